@@ -1,0 +1,224 @@
+/*
+ * csrmf.h -- C ABI of libcsrmf: CKKS arithmetic for encrypted CSR matrix
+ * factorisation on one AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the problem statement of the paper "Efficient
+ * Privacy-Preserving Recommendation on Sparse Data using Fully Homomorphic
+ * Encryption" (arXiv 2509.03024):
+ *   - the crypto service provider generates the key pair (Sec. III-B,
+ *     initialisation phase)                                  -> csrmf_keygen
+ *   - non-zero ratings are extracted in CSR order and encrypted
+ *     (Alg. 1, EncryptCsrMatrix; CSR layout of Sec. II-A.3)  -> csrmf_encrypt_csr_rows
+ *   - the server initialises and encrypts U and V (Alg. 1)   -> csrmf_init_factors
+ *   - gradient-descent epochs on encrypted data (Alg. 1 evaluated as a
+ *     synchronous epoch, with the per-entity accumulator of Alg. 2)
+ *                                                            -> csrmf_mf_epochs
+ *   - predicted ratings R_hat = U V^T on the observed set    -> csrmf_predict
+ *   - the crypto service provider decrypts (recommendation phase)
+ *                                                            -> csrmf_decrypt_*
+ * plus the homomorphic primitives of Sec. II-A.2 (Eq. 6-9: ct+ct, ct*ct,
+ * ct+pt, ct*pt), the rotations and rescale a leveled CKKS evaluation needs,
+ * and import/export hooks that let an independent implementation check the
+ * ciphertexts bit for bit.
+ *
+ * Conventions
+ *   - Every call returns 0 on success or a negative CSRMF_E_* code; the
+ *     message of the last failure on this context is csrmf_last_error().
+ *   - The caller owns every host array passed in or out.  Inputs are copied;
+ *     outputs are written into caller buffers of the documented size.
+ *   - The library owns all device memory and every ciphertext.  A ciphertext is
+ *     named by an opaque non-zero uint64_t handle, valid until csrmf_free_ct()
+ *     or csrmf_destroy().
+ *   - Ciphertexts are kept in HBM in the library's own evaluation (NTT) form.
+ *     The external form of a ciphertext (import/export) is coefficient form:
+ *     uint64 residues in [0, q_i), laid out [2][level+1][N] (polynomial c0 then
+ *     c1, limb q_0 first).
+ *   - A context is not thread safe: use one per host thread or serialise.
+ *     All device work of a context runs in order on its stream.
+ *   - A ciphertext at level l has limbs q_0..q_l; q_0 is the base prime and
+ *     q_1 > ... > q_L are the scale primes dropped by rescale, smallest first.
+ */
+#ifndef CSRMF_H
+#define CSRMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSRMF_OK         0
+#define CSRMF_E_INVAL   -1   /* invalid argument or parameter set             */
+#define CSRMF_E_NOMEM   -2   /* device or host allocation failed / budget hit  */
+#define CSRMF_E_LEVEL   -3   /* not enough levels left for the operation       */
+#define CSRMF_E_SCALE   -4   /* operand scales differ by more than 2^-30       */
+#define CSRMF_E_STATE   -5   /* call out of order (e.g. no keys yet)           */
+#define CSRMF_E_DEVICE  -6   /* HIP runtime error                              */
+#define CSRMF_E_KEY     -7   /* the rotation key the operation needs is absent */
+
+typedef struct csrmf_ctx csrmf_ctx;
+
+/* CKKS and matrix-factorisation parameters.
+ * Primes: the largest primes q < 2^bits with q = 1 (mod 2N), descending.  The
+ * base_bits list gives q_0 and, when special_bits == base_bits, the special
+ * primes after it; the scale_bits list gives q_1 > q_2 > ... > q_L.
+ * Key-switching digits: D_j = [j*g, min((j+1)*g, L+1)), g = ceil((L+1)/dnum). */
+typedef struct csrmf_params {
+    int32_t log2N;          /* ring degree N = 2^log2N, 10..16                  */
+    int32_t base_bits;      /* bits of q_0 (<= 61)                              */
+    int32_t n_scale_primes; /* L, number of scale primes                        */
+    int32_t scale_bits;     /* bits of q_1..q_L (<= 61)                         */
+    int32_t n_special;      /* alpha, number of special primes (>= 1)           */
+    int32_t special_bits;   /* bits of the special primes (<= 61)               */
+    int32_t dnum;           /* number of key-switching digits (>= 1)            */
+    int32_t log2_scale;     /* default encoding scale Delta = 2^log2_scale      */
+    /* matrix factorisation (Alg. 1 / Alg. 2) */
+    int32_t k;              /* latent factors per user / item                   */
+    double  lr;             /* learning rate alpha                              */
+    double  lambda;         /* regularisation lambda (= mu)                     */
+    double  damp;           /* dampening: alpha_t = alpha / (1 + damp * t)      */
+    int32_t rule;           /* 1 = R1 (Alg. 1 summed), 2 = R2 (degree-normalised)*/
+    int32_t refresh_mode;   /* 0 = fail with CSRMF_E_LEVEL when levels run out   */
+} csrmf_params;
+
+/* Create a context: derives the prime chain and roots, uploads the transform
+ * tables to the current HIP device.  seed is the 32-byte ChaCha20 master key
+ * from which every random polynomial is drawn.
+ * Errors: INVAL (N out of range, not enough primes, k' = 2^ceil(log2 k) too
+ * large for the slots), NOMEM, DEVICE. */
+int csrmf_create(const csrmf_params* p, const uint8_t seed[32], csrmf_ctx** out);
+
+/* Free every device and host resource of the context.  NULL is ignored. */
+void csrmf_destroy(csrmf_ctx* ctx);
+
+/* Message of the last failure on ctx (empty string if none; never NULL). */
+const char* csrmf_last_error(const csrmf_ctx* ctx);
+
+/* Run all further device work of ctx on this hipStream_t (NULL = the null
+ * stream).  The stream must outlive its use by the context. */
+int csrmf_set_stream(csrmf_ctx* ctx, void* hip_stream);
+
+/* Wait until all device work of the context has finished. */
+int csrmf_sync(csrmf_ctx* ctx);
+
+/* Query the modulus chain: q[0..L] then p[0..alpha-1] into moduli (caller
+ * array of L+1+alpha entries); any pointer may be NULL. */
+int csrmf_get_chain(const csrmf_ctx* ctx, int32_t* L, int32_t* alpha, uint64_t* moduli);
+
+/* Key generation (Sec. III-B: the crypto service provider creates the keys).
+ * Creates the secret key s, the public key, the relinearisation key (s^2 -> s)
+ * and one rotation key per entry of rot_steps (left rotation by r slots,
+ * Galois element 5^(r mod N/2) mod 2N) plus the conjugation key if conj != 0.
+ * May be called again to add rotation keys; existing keys are kept.
+ * Errors: NOMEM, DEVICE. */
+int csrmf_keygen(csrmf_ctx* ctx, const int32_t* rot_steps, int32_t n_steps, int32_t conj);
+
+/* ------------------------------------------------------------------------ */
+/* Ciphertexts and the homomorphic primitives (Sec. II-A.2, Eq. 6-9).        */
+/* ------------------------------------------------------------------------ */
+
+/* Encode a real vector (n <= N/2 slots, the rest 0) at the given scale and
+ * encrypt it at `level` with the public key.  The integer plaintext is
+ * m_n = round_half_even(scale * (2/N) * Re sum_j z_j zeta_j^-n),
+ * zeta_j = exp(i*pi*5^j/N).  Errors: INVAL, STATE (no keys). */
+int csrmf_encrypt(csrmf_ctx* ctx, const double* z, int32_t n, int32_t level, double scale,
+                  uint64_t* handle);
+
+/* Encrypt an integer plaintext polynomial m[N] (signed coefficients) at
+ * `level`; `scale` is recorded as metadata only. */
+int csrmf_encrypt_int(csrmf_ctx* ctx, const int64_t* m, int32_t level, double scale,
+                      uint64_t* handle);
+
+/* Decrypt: m = c0 + c1*s kept mod q_0 and centred, into m[N] (int64). */
+int csrmf_decrypt_int(csrmf_ctx* ctx, uint64_t handle, int64_t* m);
+
+/* Decrypt and decode the first n slots into z[n] (real parts). */
+int csrmf_decrypt(csrmf_ctx* ctx, uint64_t handle, double* z, int32_t n);
+
+/* The host encoder/decoder on their own (FP64). */
+int csrmf_encode(const csrmf_ctx* ctx, const double* z, int32_t n, double scale, int64_t* m);
+int csrmf_decode(const csrmf_ctx* ctx, const int64_t* m, double scale, double* z, int32_t n);
+
+/* Import / export a ciphertext in coefficient form ([2][level+1][N] uint64). */
+int csrmf_import_ct(csrmf_ctx* ctx, const uint64_t* coeffs, int32_t level, double scale,
+                    uint64_t* handle);
+int csrmf_export_ct(csrmf_ctx* ctx, uint64_t handle, uint64_t* coeffs, int32_t* level,
+                    double* scale);
+int csrmf_ct_info(const csrmf_ctx* ctx, uint64_t handle, int32_t* level, double* scale);
+int csrmf_free_ct(csrmf_ctx* ctx, uint64_t handle);
+
+/* Export the key material in coefficient form (test hook):
+ * which = 0: secret key s over all limbs, [L+1+alpha][N];
+ * which = 1: public key (b, a), [2][L+1][N];
+ * which = 2: relinearisation key, [dnum][2][L+1+alpha][N] (digit, b/a, limb);
+ * which = 3: rotation key of Galois element `galois`, same layout as 2.
+ * Residues in [0, q). */
+int csrmf_export_key(csrmf_ctx* ctx, int32_t which, uint32_t galois, uint64_t* out);
+
+/* Eq. 6 and its inverse.  Operands at different levels are aligned by
+ * dropping the higher one's top limbs; scales must agree to 2^-30 (SCALE);
+ * the result takes a's scale.  out receives a new handle. */
+int csrmf_add(csrmf_ctx* ctx, uint64_t a, uint64_t b, uint64_t* out);
+int csrmf_sub(csrmf_ctx* ctx, uint64_t a, uint64_t b, uint64_t* out);
+
+/* Eq. 8: add the integer plaintext polynomial m[N]. */
+int csrmf_add_plain(csrmf_ctx* ctx, uint64_t a, const int64_t* m, uint64_t* out);
+
+/* Eq. 9: multiply by the integer plaintext polynomial m[N] whose scale is
+ * pt_scale (result scale = scale * pt_scale; no rescale). */
+int csrmf_mul_plain(csrmf_ctx* ctx, uint64_t a, const int64_t* m, double pt_scale, uint64_t* out);
+
+/* Multiply by the integer constant w (result scale = scale * w). */
+int csrmf_mul_int(csrmf_ctx* ctx, uint64_t a, int64_t w, uint64_t* out);
+
+/* Eq. 7: tensor product, relinearisation (s^2 -> s key switch) and rescale,
+ * in that order.  Result level = min(level) - 1.  Errors: LEVEL, STATE. */
+int csrmf_hmult(csrmf_ctx* ctx, uint64_t a, uint64_t b, uint64_t* out);
+
+/* Tensor product + relinearisation without rescale. */
+int csrmf_mul_relin(csrmf_ctx* ctx, uint64_t a, uint64_t b, uint64_t* out);
+
+/* Rescale: divide by q_l with rounding half up, drop limb l, scale /= q_l. */
+int csrmf_rescale(csrmf_ctx* ctx, uint64_t a, uint64_t* out);
+
+/* Drop the top limbs down to `level` (scale unchanged). */
+int csrmf_mod_drop(csrmf_ctx* ctx, uint64_t a, int32_t level, uint64_t* out);
+
+/* Left rotation by r slots (slot j takes old slot j + r), non-hoisted key
+ * switch: (tau_g(c0) + u0, u1), (u0, u1) = KS_{tau_g(s) -> s}(tau_g(c1)).
+ * Errors: KEY (no key for this step). */
+int csrmf_rotate(csrmf_ctx* ctx, uint64_t a, int32_t r, uint64_t* out);
+
+/* Complex conjugation of the slots (Galois element 2N-1). */
+int csrmf_conjugate(csrmf_ctx* ctx, uint64_t a, uint64_t* out);
+
+/* Several rotations of one ciphertext sharing one ModUp of c1 (hoisting);
+ * tau_g is applied to the extended digits.  out[n] receives n handles. */
+int csrmf_rotate_hoisted(csrmf_ctx* ctx, uint64_t a, const int32_t* r, int32_t n, uint64_t* out);
+
+/* Batched forms: the same operation over n ciphertexts in as few launches as
+ * possible (all operands must share level and scale).  out[n] receives new
+ * handles; out may alias nothing. */
+int csrmf_hmult_batch(csrmf_ctx* ctx, const uint64_t* a, const uint64_t* b, int32_t n,
+                      uint64_t* out);
+int csrmf_rotate_batch(csrmf_ctx* ctx, const uint64_t* a, int32_t n, int32_t r, uint64_t* out);
+int csrmf_conjugate_batch(csrmf_ctx* ctx, const uint64_t* a, int32_t n, uint64_t* out);
+
+/* ------------------------------------------------------------------------ */
+/* Raw transforms on caller device memory (test and benchmark hooks).        */
+/* ------------------------------------------------------------------------ */
+
+/* In-place negacyclic NTT (inverse != 0: inverse NTT) of n_rows rows of N
+ * uint64 residues at device pointer `data` (row r at data + r*N), row r
+ * reduced modulo chain limb limb_idx[r % n_idx] (0..L for q_i, L+1+k for
+ * p_k).  Forward output position t holds a(psi^(2*brev(t)+1)), with brev the
+ * log2N-bit reversal and psi the smallest primitive 2N-th root mod the limb's
+ * prime.  Inputs must be reduced.  limb_idx is a host array. */
+int csrmf_ntt_rows(csrmf_ctx* ctx, uint64_t* data, int32_t n_rows, const int32_t* limb_idx,
+                   int32_t n_idx, int32_t inverse);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSRMF_H */

@@ -1,0 +1,311 @@
+"""Python binding of libcsrmf (CKKS arithmetic for encrypted CSR matrix
+factorisation on AMD Instinct MI355X).
+
+Argument marshalling only: every homomorphic operation runs in the HIP
+library.  The library must have been built (``python -m
+paper_2509_03024_amd.build`` or ``__graft_entry__.build()``); importing this
+module without it raises immediately.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcsrmf.so")
+
+CSRMF_OK = 0
+ERRORS = {-1: "INVAL", -2: "NOMEM", -3: "LEVEL", -4: "SCALE", -5: "STATE", -6: "DEVICE", -7: "KEY"}
+
+
+class CsrmfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"csrmf error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, "?")
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                      "(python -m paper_2509_03024_amd.build)")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("log2N", ctypes.c_int32), ("base_bits", ctypes.c_int32),
+                ("n_scale_primes", ctypes.c_int32), ("scale_bits", ctypes.c_int32),
+                ("n_special", ctypes.c_int32), ("special_bits", ctypes.c_int32),
+                ("dnum", ctypes.c_int32), ("log2_scale", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("lr", ctypes.c_double), ("lam", ctypes.c_double),
+                ("damp", ctypes.c_double), ("rule", ctypes.c_int32), ("refresh_mode", ctypes.c_int32)]
+
+
+_p = ctypes.c_void_p
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "csrmf_create": [ctypes.POINTER(Params), ctypes.c_char_p, ctypes.POINTER(_p)],
+    "csrmf_destroy": [_p],
+    "csrmf_last_error": [_p],
+    "csrmf_set_stream": [_p, _p],
+    "csrmf_sync": [_p],
+    "csrmf_get_chain": [_p, _i32p, _i32p, _u64p],
+    "csrmf_keygen": [_p, _i32p, ctypes.c_int32, ctypes.c_int32],
+    "csrmf_encrypt": [_p, _dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _u64p],
+    "csrmf_encrypt_int": [_p, _i64p, ctypes.c_int32, ctypes.c_double, _u64p],
+    "csrmf_decrypt_int": [_p, ctypes.c_uint64, _i64p],
+    "csrmf_decrypt": [_p, ctypes.c_uint64, _dp, ctypes.c_int32],
+    "csrmf_encode": [_p, _dp, ctypes.c_int32, ctypes.c_double, _i64p],
+    "csrmf_decode": [_p, _i64p, ctypes.c_double, _dp, ctypes.c_int32],
+    "csrmf_import_ct": [_p, _u64p, ctypes.c_int32, ctypes.c_double, _u64p],
+    "csrmf_export_ct": [_p, ctypes.c_uint64, _u64p, _i32p, _dp],
+    "csrmf_ct_info": [_p, ctypes.c_uint64, _i32p, _dp],
+    "csrmf_free_ct": [_p, ctypes.c_uint64],
+    "csrmf_export_key": [_p, ctypes.c_int32, ctypes.c_uint32, _u64p],
+    "csrmf_add": [_p, ctypes.c_uint64, ctypes.c_uint64, _u64p],
+    "csrmf_sub": [_p, ctypes.c_uint64, ctypes.c_uint64, _u64p],
+    "csrmf_add_plain": [_p, ctypes.c_uint64, _i64p, _u64p],
+    "csrmf_mul_plain": [_p, ctypes.c_uint64, _i64p, ctypes.c_double, _u64p],
+    "csrmf_mul_int": [_p, ctypes.c_uint64, ctypes.c_int64, _u64p],
+    "csrmf_hmult": [_p, ctypes.c_uint64, ctypes.c_uint64, _u64p],
+    "csrmf_mul_relin": [_p, ctypes.c_uint64, ctypes.c_uint64, _u64p],
+    "csrmf_rescale": [_p, ctypes.c_uint64, _u64p],
+    "csrmf_mod_drop": [_p, ctypes.c_uint64, ctypes.c_int32, _u64p],
+    "csrmf_rotate": [_p, ctypes.c_uint64, ctypes.c_int32, _u64p],
+    "csrmf_conjugate": [_p, ctypes.c_uint64, _u64p],
+    "csrmf_rotate_hoisted": [_p, ctypes.c_uint64, _i32p, ctypes.c_int32, _u64p],
+    "csrmf_hmult_batch": [_p, _u64p, _u64p, ctypes.c_int32, _u64p],
+    "csrmf_rotate_batch": [_p, _u64p, ctypes.c_int32, ctypes.c_int32, _u64p],
+    "csrmf_conjugate_batch": [_p, _u64p, ctypes.c_int32, _u64p],
+    "csrmf_ntt_rows": [_p, _p, ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_int32],
+}
+
+for _name, _args in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = None if _name == "csrmf_destroy" else (ctypes.c_char_p if _name == "csrmf_last_error" else ctypes.c_int)
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def params(log2N, base_bits, n_scale, scale_bits, n_special, special_bits, dnum, log2_scale=40,
+           k=0, lr=0.0, lam=0.0, damp=0.0, rule=1, refresh_mode=0):
+    return Params(log2N, base_bits, n_scale, scale_bits, n_special, special_bits, dnum, log2_scale,
+                  k, lr, lam, damp, rule, refresh_mode)
+
+
+class Context:
+    """One libcsrmf context (one modulus chain, one key set, one stream)."""
+
+    def __init__(self, prm: Params, seed: bytes):
+        assert len(seed) == 32
+        h = _p()
+        rc = lib.csrmf_create(ctypes.byref(prm), seed, ctypes.byref(h))
+        if rc != CSRMF_OK:
+            raise CsrmfError(rc, "csrmf_create failed")
+        self.h = h
+        self.prm = prm
+        self.N = 1 << prm.log2N
+        L = ctypes.c_int32()
+        a = ctypes.c_int32()
+        lib.csrmf_get_chain(self.h, ctypes.byref(L), ctypes.byref(a), None)
+        self.L, self.alpha = L.value, a.value
+        mods = np.zeros(self.L + 1 + self.alpha, np.uint64)
+        lib.csrmf_get_chain(self.h, None, None, _ptr(mods, ctypes.c_uint64))
+        self.moduli = [int(x) for x in mods]
+
+    def close(self):
+        if self.h:
+            lib.csrmf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != CSRMF_OK:
+            raise CsrmfError(rc, lib.csrmf_last_error(self.h).decode())
+
+    # ---------------------------------------------------------------- keys
+    def keygen(self, rot_steps=(), conj=False):
+        st = np.asarray(list(rot_steps), np.int32)
+        self._chk(lib.csrmf_keygen(self.h, _ptr(st, ctypes.c_int32), len(st), int(bool(conj))))
+
+    def export_key(self, which, galois=0):
+        nall = self.L + 1 + self.alpha
+        if which == 0:
+            shape = (nall, self.N)
+        elif which == 1:
+            shape = (2, self.L + 1, self.N)
+        else:
+            nd = -(-(self.L + 1) // ((self.L + 1 + self.prm.dnum - 1) // self.prm.dnum))
+            shape = (nd, 2, nall, self.N)
+        out = np.zeros(shape, np.uint64)
+        self._chk(lib.csrmf_export_key(self.h, which, galois, _ptr(out, ctypes.c_uint64)))
+        return out
+
+    def sync(self):
+        self._chk(lib.csrmf_sync(self.h))
+
+    def set_stream(self, stream_ptr):
+        self._chk(lib.csrmf_set_stream(self.h, _p(stream_ptr)))
+
+    # ---------------------------------------------------------------- ciphertexts
+    def encode(self, z, scale):
+        z = np.ascontiguousarray(z, np.float64)
+        m = np.zeros(self.N, np.int64)
+        self._chk(lib.csrmf_encode(self.h, _ptr(z, ctypes.c_double), len(z), scale, _ptr(m, ctypes.c_int64)))
+        return m
+
+    def decode(self, m, scale, n=None):
+        m = np.ascontiguousarray(m, np.int64)
+        n = self.N // 2 if n is None else n
+        z = np.zeros(n, np.float64)
+        self._chk(lib.csrmf_decode(self.h, _ptr(m, ctypes.c_int64), scale, _ptr(z, ctypes.c_double), n))
+        return z
+
+    def encrypt(self, z, level=None, scale=None):
+        z = np.ascontiguousarray(z, np.float64)
+        level = self.L if level is None else level
+        scale = float(2 ** self.prm.log2_scale) if scale is None else scale
+        h = ctypes.c_uint64()
+        self._chk(lib.csrmf_encrypt(self.h, _ptr(z, ctypes.c_double), len(z), level, scale, ctypes.byref(h)))
+        return h.value
+
+    def encrypt_int(self, m, level, scale):
+        m = np.ascontiguousarray(m, np.int64)
+        h = ctypes.c_uint64()
+        self._chk(lib.csrmf_encrypt_int(self.h, _ptr(m, ctypes.c_int64), level, scale, ctypes.byref(h)))
+        return h.value
+
+    def decrypt_int(self, h):
+        m = np.zeros(self.N, np.int64)
+        self._chk(lib.csrmf_decrypt_int(self.h, h, _ptr(m, ctypes.c_int64)))
+        return m
+
+    def decrypt(self, h, n=None):
+        n = self.N // 2 if n is None else n
+        z = np.zeros(n, np.float64)
+        self._chk(lib.csrmf_decrypt(self.h, h, _ptr(z, ctypes.c_double), n))
+        return z
+
+    def info(self, h):
+        lv = ctypes.c_int32()
+        sc = ctypes.c_double()
+        self._chk(lib.csrmf_ct_info(self.h, h, ctypes.byref(lv), ctypes.byref(sc)))
+        return lv.value, sc.value
+
+    def export_ct(self, h):
+        lv, _ = self.info(h)
+        out = np.zeros((2, lv + 1, self.N), np.uint64)
+        lvl = ctypes.c_int32()
+        sc = ctypes.c_double()
+        self._chk(lib.csrmf_export_ct(self.h, h, _ptr(out, ctypes.c_uint64), ctypes.byref(lvl), ctypes.byref(sc)))
+        return out, lvl.value, sc.value
+
+    def import_ct(self, coeffs, level, scale):
+        c = np.ascontiguousarray(coeffs, np.uint64)
+        h = ctypes.c_uint64()
+        self._chk(lib.csrmf_import_ct(self.h, _ptr(c, ctypes.c_uint64), level, scale, ctypes.byref(h)))
+        return h.value
+
+    def free(self, h):
+        self._chk(lib.csrmf_free_ct(self.h, h))
+
+    def _unary(self, fn, *args):
+        out = ctypes.c_uint64()
+        self._chk(fn(self.h, *args, ctypes.byref(out)))
+        return out.value
+
+    def add(self, a, b):
+        return self._unary(lib.csrmf_add, a, b)
+
+    def sub(self, a, b):
+        return self._unary(lib.csrmf_sub, a, b)
+
+    def add_plain(self, a, m):
+        m = np.ascontiguousarray(m, np.int64)
+        return self._unary(lib.csrmf_add_plain, a, _ptr(m, ctypes.c_int64))
+
+    def mul_plain(self, a, m, pt_scale):
+        m = np.ascontiguousarray(m, np.int64)
+        return self._unary(lib.csrmf_mul_plain, a, _ptr(m, ctypes.c_int64), pt_scale)
+
+    def mul_int(self, a, w):
+        return self._unary(lib.csrmf_mul_int, a, int(w))
+
+    def hmult(self, a, b):
+        return self._unary(lib.csrmf_hmult, a, b)
+
+    def mul_relin(self, a, b):
+        return self._unary(lib.csrmf_mul_relin, a, b)
+
+    def rescale(self, a):
+        return self._unary(lib.csrmf_rescale, a)
+
+    def mod_drop(self, a, level):
+        return self._unary(lib.csrmf_mod_drop, a, level)
+
+    def rotate(self, a, r):
+        return self._unary(lib.csrmf_rotate, a, r)
+
+    def conjugate(self, a):
+        return self._unary(lib.csrmf_conjugate, a)
+
+    def rotate_hoisted(self, a, steps):
+        st = np.asarray(list(steps), np.int32)
+        out = np.zeros(len(st), np.uint64)
+        self._chk(lib.csrmf_rotate_hoisted(self.h, a, _ptr(st, ctypes.c_int32), len(st), _ptr(out, ctypes.c_uint64)))
+        return [int(x) for x in out]
+
+    def hmult_batch(self, a, b):
+        a = np.asarray(a, np.uint64)
+        b = np.asarray(b, np.uint64)
+        out = np.zeros(len(a), np.uint64)
+        self._chk(lib.csrmf_hmult_batch(self.h, _ptr(a, ctypes.c_uint64), _ptr(b, ctypes.c_uint64), len(a),
+                                        _ptr(out, ctypes.c_uint64)))
+        return [int(x) for x in out]
+
+    def rotate_batch(self, a, r):
+        a = np.asarray(a, np.uint64)
+        out = np.zeros(len(a), np.uint64)
+        self._chk(lib.csrmf_rotate_batch(self.h, _ptr(a, ctypes.c_uint64), len(a), r, _ptr(out, ctypes.c_uint64)))
+        return [int(x) for x in out]
+
+    def conjugate_batch(self, a):
+        a = np.asarray(a, np.uint64)
+        out = np.zeros(len(a), np.uint64)
+        self._chk(lib.csrmf_conjugate_batch(self.h, _ptr(a, ctypes.c_uint64), len(a), _ptr(out, ctypes.c_uint64)))
+        return [int(x) for x in out]
+
+    def ntt_rows(self, dev_ptr, n_rows, limb_idx, inverse=False):
+        """In-place (I)NTT of rows at a device pointer (e.g. a torch tensor's data_ptr())."""
+        idx = np.asarray(limb_idx, np.int32)
+        self._chk(lib.csrmf_ntt_rows(self.h, _p(dev_ptr), n_rows, _ptr(idx, ctypes.c_int32), len(idx), int(inverse)))
+
+
+def tiny_params(k=4, lr=0.01, lam=0.02, rule=1):
+    """N = 2^12, q_0 60-bit + 3 x 40-bit scale primes, 1 x 60-bit special prime, dnum 4, scale 2^40."""
+    return params(12, 60, 3, 40, 1, 60, 4, 40, k=k, lr=lr, lam=lam, rule=rule)
+
+
+def kernel_batch_params():
+    """N = 2^16, q_0 60-bit + 24 x 40-bit, 3 x 60-bit special primes, dnum 3, scale 2^40."""
+    return params(16, 60, 24, 40, 3, 60, 3, 40)
+
+
+def mf_n15_params(k=10, lr=0.01, lam=0.02, rule=2):
+    return params(15, 60, 16, 40, 3, 60, 5, 40, k=k, lr=lr, lam=lam, rule=rule)
+
+
+def mf_n16_params(k=16, lr=0.01, lam=0.02, rule=2):
+    return params(16, 60, 24, 40, 3, 60, 7, 40, k=k, lr=lr, lam=lam, rule=rule)

@@ -1,0 +1,367 @@
+// extern "C" entry points of libcsrmf (declared in include/csrmf.h).
+#include <cstring>
+#include <new>
+
+#include "context.h"
+#include "host_math.h"
+
+using csrmf::Context;
+using csrmf::Ct;
+using csrmf::Error;
+
+#define API_BEGIN(ctx)                                   \
+    if (!(ctx)) return CSRMF_E_INVAL;                    \
+    try {
+#define API_END(ctx)                                     \
+        (ctx)->err.clear();                              \
+        return CSRMF_OK;                                 \
+    } catch (const Error& e) {                           \
+        (ctx)->err = e.what();                           \
+        return e.code;                                   \
+    } catch (const std::bad_alloc&) {                    \
+        (ctx)->err = "host allocation failed";           \
+        return CSRMF_E_NOMEM;                            \
+    } catch (const std::exception& e) {                  \
+        (ctx)->err = e.what();                           \
+        return CSRMF_E_DEVICE;                           \
+    }
+
+#define NEED(cond, msg) \
+    if (!(cond)) throw Error(CSRMF_E_INVAL, msg)
+
+extern "C" {
+
+int csrmf_create(const csrmf_params* p, const uint8_t seed[32], csrmf_ctx** out) {
+    if (!p || !seed || !out) return CSRMF_E_INVAL;
+    *out = nullptr;
+    Context* c = nullptr;
+    try {
+        c = new Context();
+        c->init(*p, seed);
+    } catch (const Error& e) {
+        delete c;
+        return e.code;
+    } catch (...) {
+        delete c;
+        return CSRMF_E_NOMEM;
+    }
+    *out = reinterpret_cast<csrmf_ctx*>(c);
+    return CSRMF_OK;
+}
+
+void csrmf_destroy(csrmf_ctx* ctx) { delete reinterpret_cast<Context*>(ctx); }
+
+const char* csrmf_last_error(const csrmf_ctx* ctx) {
+    if (!ctx) return "null context";
+    return reinterpret_cast<const Context*>(ctx)->err.c_str();
+}
+
+int csrmf_set_stream(csrmf_ctx* cx, void* s) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    CSRMF_HIP(hipStreamSynchronize(c->stream));
+    c->stream = (hipStream_t)s;
+    API_END(c)
+}
+
+int csrmf_sync(csrmf_ctx* cx) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    CSRMF_HIP(hipStreamSynchronize(c->stream));
+    API_END(c)
+}
+
+int csrmf_get_chain(const csrmf_ctx* cx, int32_t* L, int32_t* alpha, uint64_t* moduli) {
+    const Context* c = reinterpret_cast<const Context*>(cx);
+    if (!c) return CSRMF_E_INVAL;
+    if (L) *L = c->L;
+    if (alpha) *alpha = c->alpha;
+    if (moduli) std::memcpy(moduli, c->moduli.data(), c->moduli.size() * 8);
+    return CSRMF_OK;
+}
+
+int csrmf_keygen(csrmf_ctx* cx, const int32_t* steps, int32_t n, int32_t conj) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(n >= 0 && (n == 0 || steps), "rotation steps");
+    c->keygen(steps, n, conj != 0);
+    API_END(c)
+}
+
+int csrmf_encode(const csrmf_ctx* cx, const double* z, int32_t n, double scale, int64_t* m) {
+    const Context* c = reinterpret_cast<const Context*>(cx);
+    if (!c || !m || (n > 0 && !z) || n < 0 || (uint64_t)n > c->N / 2 || !(scale > 0)) return CSRMF_E_INVAL;
+    return csrmf::ckks_encode(z, n, c->logN, scale, m) ? CSRMF_OK : CSRMF_E_INVAL;
+}
+
+int csrmf_decode(const csrmf_ctx* cx, const int64_t* m, double scale, double* z, int32_t n) {
+    const Context* c = reinterpret_cast<const Context*>(cx);
+    if (!c || !m || !z || n < 0 || (uint64_t)n > c->N / 2 || !(scale > 0)) return CSRMF_E_INVAL;
+    csrmf::ckks_decode(m, c->logN, scale, z, n);
+    return CSRMF_OK;
+}
+
+int csrmf_encrypt(csrmf_ctx* cx, const double* z, int32_t n, int32_t level, double scale, uint64_t* h) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(h && (n == 0 || z) && n >= 0 && (uint64_t)n <= c->N / 2 && scale > 0, "encrypt arguments");
+    std::vector<int64_t> m(c->N);
+    NEED(csrmf::ckks_encode(z, n, c->logN, scale, m.data()), "value too large to encode");
+    *h = c->put(c->encrypt_int(m.data(), level, scale));
+    API_END(c)
+}
+
+int csrmf_encrypt_int(csrmf_ctx* cx, const int64_t* m, int32_t level, double scale, uint64_t* h) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(m && h && scale > 0, "encrypt_int arguments");
+    *h = c->put(c->encrypt_int(m, level, scale));
+    API_END(c)
+}
+
+int csrmf_decrypt_int(csrmf_ctx* cx, uint64_t h, int64_t* m) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(m, "output");
+    c->decrypt_int(c->get(h), m);
+    API_END(c)
+}
+
+int csrmf_decrypt(csrmf_ctx* cx, uint64_t h, double* z, int32_t n) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(z && n >= 0 && (uint64_t)n <= c->N / 2, "decrypt arguments");
+    const Ct& ct = c->get(h);
+    std::vector<int64_t> m(c->N);
+    c->decrypt_int(ct, m.data());
+    csrmf::ckks_decode(m.data(), c->logN, ct.scale, z, n);
+    API_END(c)
+}
+
+int csrmf_import_ct(csrmf_ctx* cx, const uint64_t* coeffs, int32_t level, double scale, uint64_t* h) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(coeffs && h && scale > 0, "import arguments");
+    *h = c->put(c->import_ct(coeffs, level, scale));
+    API_END(c)
+}
+
+int csrmf_export_ct(csrmf_ctx* cx, uint64_t h, uint64_t* coeffs, int32_t* level, double* scale) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    const Ct& ct = c->get(h);
+    if (level) *level = ct.level;
+    if (scale) *scale = ct.scale;
+    if (coeffs) c->export_ct(ct, coeffs);
+    API_END(c)
+}
+
+int csrmf_ct_info(const csrmf_ctx* cx, uint64_t h, int32_t* level, double* scale) {
+    Context* c = const_cast<Context*>(reinterpret_cast<const Context*>(cx));
+    API_BEGIN(c)
+    const Ct& ct = c->get(h);
+    if (level) *level = ct.level;
+    if (scale) *scale = ct.scale;
+    API_END(c)
+}
+
+int csrmf_free_ct(csrmf_ctx* cx, uint64_t h) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    c->free_ct(h);
+    API_END(c)
+}
+
+int csrmf_export_key(csrmf_ctx* cx, int32_t which, uint32_t galois, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(out, "output");
+    c->export_key(which, galois, out);
+    API_END(c)
+}
+
+int csrmf_add(csrmf_ctx* cx, uint64_t a, uint64_t b, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(out, "output");
+    Ct r;
+    c->add(c->get(a), c->get(b), r, false);
+    *out = c->put(r);
+    API_END(c)
+}
+
+int csrmf_sub(csrmf_ctx* cx, uint64_t a, uint64_t b, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(out, "output");
+    Ct r;
+    c->add(c->get(a), c->get(b), r, true);
+    *out = c->put(r);
+    API_END(c)
+}
+
+int csrmf_add_plain(csrmf_ctx* cx, uint64_t a, const int64_t* m, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(m && out, "arguments");
+    Ct r;
+    c->add_plain(c->get(a), m, r);
+    *out = c->put(r);
+    API_END(c)
+}
+
+int csrmf_mul_plain(csrmf_ctx* cx, uint64_t a, const int64_t* m, double pt_scale, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(m && out && pt_scale > 0, "arguments");
+    Ct r;
+    c->mul_plain(c->get(a), m, pt_scale, r);
+    *out = c->put(r);
+    API_END(c)
+}
+
+int csrmf_mul_int(csrmf_ctx* cx, uint64_t a, int64_t w, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(out && w != 0, "arguments");
+    Ct r;
+    c->mul_int(c->get(a), w, r);
+    *out = c->put(r);
+    API_END(c)
+}
+
+static void batch_mul(Context* c, const uint64_t* a, const uint64_t* b, int32_t n, uint64_t* out, bool rescale) {
+    NEED(a && b && out && n > 0, "arguments");
+    if (!c->have_keys) throw Error(CSRMF_E_STATE, "keygen first");
+    std::vector<Ct*> va, vb;
+    for (int i = 0; i < n; ++i) {
+        va.push_back(&c->get(a[i]));
+        vb.push_back(&c->get(b[i]));
+        c->check_scales(va.back()->scale, va[0]->scale);
+        if (rescale && std::min(va.back()->level, vb.back()->level) < 1) throw Error(CSRMF_E_LEVEL, "no level left");
+    }
+    std::vector<Ct> res(n);
+    std::vector<Ct*> vo;
+    for (auto& r : res) vo.push_back(&r);
+    c->mul_relin(va, vb, vo);
+    if (rescale) c->rescale(vo);
+    for (int i = 0; i < n; ++i) out[i] = c->put(res[i]);
+}
+
+int csrmf_hmult(csrmf_ctx* cx, uint64_t a, uint64_t b, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    batch_mul(c, &a, &b, 1, out, true);
+    API_END(c)
+}
+
+int csrmf_mul_relin(csrmf_ctx* cx, uint64_t a, uint64_t b, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    batch_mul(c, &a, &b, 1, out, false);
+    API_END(c)
+}
+
+int csrmf_hmult_batch(csrmf_ctx* cx, const uint64_t* a, const uint64_t* b, int32_t n, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    batch_mul(c, a, b, n, out, true);
+    API_END(c)
+}
+
+int csrmf_rescale(csrmf_ctx* cx, uint64_t a, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(out, "output");
+    const Ct& src = c->get(a);
+    if (src.level < 1) throw Error(CSRMF_E_LEVEL, "no level left to rescale");
+    Ct r = c->new_ct(src.level, src.scale);
+    CSRMF_HIP(hipMemcpyAsync(r.d, src.d, c->ct_words() * 8, hipMemcpyDeviceToDevice, c->stream));
+    std::vector<Ct*> v{&r};
+    c->rescale(v);
+    *out = c->put(r);
+    API_END(c)
+}
+
+int csrmf_mod_drop(csrmf_ctx* cx, uint64_t a, int32_t level, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(out && level >= 0, "arguments");
+    const Ct& src = c->get(a);
+    if (level > src.level) throw Error(CSRMF_E_LEVEL, "cannot raise the level");
+    Ct r = c->new_ct(level, src.scale);
+    CSRMF_HIP(hipMemcpyAsync(r.d, src.d, c->ct_words() * 8, hipMemcpyDeviceToDevice, c->stream));
+    *out = c->put(r);
+    API_END(c)
+}
+
+static void batch_rot(Context* c, const uint64_t* a, int32_t n, uint32_t g, uint64_t* out) {
+    NEED(a && out && n > 0, "arguments");
+    std::vector<Ct*> va;
+    for (int i = 0; i < n; ++i) va.push_back(&c->get(a[i]));
+    std::vector<Ct> res(n);
+    std::vector<Ct*> vo;
+    for (auto& r : res) vo.push_back(&r);
+    if (g == 1) {
+        for (int i = 0; i < n; ++i) {
+            res[i] = c->new_ct(va[i]->level, va[i]->scale);
+            CSRMF_HIP(hipMemcpyAsync(res[i].d, va[i]->d, c->ct_words() * 8, hipMemcpyDeviceToDevice, c->stream));
+        }
+    } else {
+        c->rotate(va, g, vo);
+    }
+    for (int i = 0; i < n; ++i) out[i] = c->put(res[i]);
+}
+
+int csrmf_rotate(csrmf_ctx* cx, uint64_t a, int32_t r, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    batch_rot(c, &a, 1, c->galois_for_step(r), out);
+    API_END(c)
+}
+
+int csrmf_rotate_batch(csrmf_ctx* cx, const uint64_t* a, int32_t n, int32_t r, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    batch_rot(c, a, n, c->galois_for_step(r), out);
+    API_END(c)
+}
+
+int csrmf_conjugate(csrmf_ctx* cx, uint64_t a, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    batch_rot(c, &a, 1, (uint32_t)(2 * c->N - 1), out);
+    API_END(c)
+}
+
+int csrmf_conjugate_batch(csrmf_ctx* cx, const uint64_t* a, int32_t n, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    batch_rot(c, a, n, (uint32_t)(2 * c->N - 1), out);
+    API_END(c)
+}
+
+int csrmf_rotate_hoisted(csrmf_ctx* cx, uint64_t a, const int32_t* r, int32_t n, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(r && out && n > 0, "arguments");
+    std::vector<uint32_t> gs;
+    for (int i = 0; i < n; ++i) gs.push_back(c->galois_for_step(r[i]));
+    std::vector<Ct> res(n);
+    std::vector<Ct*> vo;
+    for (auto& x : res) vo.push_back(&x);
+    c->rotate_hoisted(c->get(a), gs, vo);
+    for (int i = 0; i < n; ++i) out[i] = c->put(res[i]);
+    API_END(c)
+}
+
+int csrmf_ntt_rows(csrmf_ctx* cx, uint64_t* data, int32_t n_rows, const int32_t* idx, int32_t n_idx,
+                   int32_t inverse) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(data && idx && n_rows > 0, "arguments");
+    c->ntt_rows(data, n_rows, idx, n_idx, inverse != 0);
+    API_END(c)
+}
+
+}  // extern "C"

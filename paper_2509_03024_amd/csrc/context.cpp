@@ -1,0 +1,929 @@
+// Context set-up, keys, encryption and the evaluation primitives.
+#include "context.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "host_math.h"
+
+namespace csrmf {
+
+typedef unsigned __int128 u128;
+
+// ------------------------------------------------------------------ pool
+Pool::~Pool() { release_all(); }
+
+void* Pool::get(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    auto it = free_.find(bytes);
+    void* p = nullptr;
+    if (it != free_.end()) {
+        p = it->second;
+        free_.erase(it);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            // give cached blocks back and retry once
+            for (auto& kv : free_) { (void)hipFree(kv.second); sizes_.erase(kv.second); }
+            free_.clear();
+            (void)hipGetLastError();
+            e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                throw Error(CSRMF_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+            }
+        }
+        sizes_[p] = bytes;
+    }
+    in_use_ += bytes;
+    return p;
+}
+
+void Pool::put(void* p) {
+    if (!p) return;
+    auto it = sizes_.find(p);
+    if (it == sizes_.end()) return;
+    in_use_ -= it->second;
+    free_.emplace(it->second, p);
+}
+
+void Pool::release_all() {
+    for (auto& kv : sizes_) (void)hipFree(kv.first);
+    sizes_.clear();
+    free_.clear();
+    in_use_ = 0;
+}
+
+// ------------------------------------------------------------------ helpers
+static uint64_t mm(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
+
+static void upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    CSRMF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    CSRMF_HIP(hipStreamSynchronize(s));   // the host buffer may be reused on return
+}
+
+static uint64_t* upload_consts(Pool& pool, const std::vector<uint64_t>& v, hipStream_t s) {
+    uint64_t* d = (uint64_t*)pool.get(std::max<size_t>(8, v.size() * 8));
+    if (!v.empty()) upload(d, v.data(), v.size() * 8, s);
+    return d;
+}
+
+Context::~Context() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    else (void)hipDeviceSynchronize();
+    destroy_mf(mf);
+    mf = nullptr;
+    for (auto& kv : ptr_tables) (void)hipFree(kv.second);
+    pool.release_all();
+}
+
+// ------------------------------------------------------------------ init
+void Context::init(const csrmf_params& p, const uint8_t s[32]) {
+    prm = p;
+    std::memcpy(seed, s, 32);
+    if (p.log2N < 10 || p.log2N > 16) throw Error(CSRMF_E_INVAL, "log2N must be in [10, 16]");
+    if (p.n_scale_primes < 0 || p.n_scale_primes > 40 || p.n_special < 1 || p.n_special > 8 || p.dnum < 1)
+        throw Error(CSRMF_E_INVAL, "bad prime counts");
+    if (p.base_bits > 61 || p.scale_bits > 61 || p.special_bits > 61)
+        throw Error(CSRMF_E_INVAL, "primes must be below 2^61");
+    logN = p.log2N;
+    N = 1ull << logN;
+    L = p.n_scale_primes;
+    alpha = p.n_special;
+    dnum = p.dnum;
+    gsize = (L + 1 + dnum - 1) / dnum;
+    if (L + 1 + alpha > 64) throw Error(CSRMF_E_INVAL, "too many limbs");
+    if (p.k < 0 || (p.k > 0 && 4 * (uint64_t)p.k > N / 2)) throw Error(CSRMF_E_INVAL, "k too large for the slots");
+
+    std::vector<uint64_t> big, sc, sp;
+    const bool shared = p.special_bits == p.base_bits;
+    if (!ntt_primes(p.base_bits, N, 1 + (shared ? alpha : 0), big)) throw Error(CSRMF_E_INVAL, "not enough base primes");
+    if (!ntt_primes(p.scale_bits, N, L, sc) && L > 0) throw Error(CSRMF_E_INVAL, "not enough scale primes");
+    if (shared) sp.assign(big.begin() + 1, big.end());
+    else if (!ntt_primes(p.special_bits, N, alpha, sp)) throw Error(CSRMF_E_INVAL, "not enough special primes");
+    moduli.clear();
+    moduli.push_back(big[0]);
+    for (uint64_t q : sc) moduli.push_back(q);
+    for (uint64_t q : sp) moduli.push_back(q);
+    for (size_t i = 0; i < moduli.size(); ++i)
+        for (size_t j = 0; j < i; ++j)
+            if (moduli[i] == moduli[j]) throw Error(CSRMF_E_INVAL, "prime chain has a repeated prime");
+
+    CSRMF_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+
+    const int nm = (int)moduli.size();
+    mh.resize(nm);
+    std::vector<uint64_t> tw((size_t)nm * 4 * N);
+    for (int mi = 0; mi < nm; ++mi) {
+        const uint64_t q = moduli[mi];
+        Modulus& m = mh[mi];
+        m.q = q;
+        uint64_t inv = 1;                     // q^-1 mod 2^64 by Newton iteration
+        for (int it = 0; it < 7; ++it) inv *= 2 - q * inv;
+        m.qneg_inv = (uint64_t)0 - inv;
+        m.r_mod = (uint64_t)(((u128)1 << 64) % q);
+        m.r_mod_shoup = shoup_pre(m.r_mod, q);
+        m.r2_mod = mm(m.r_mod, m.r_mod, q);
+        m.n_inv = inv_mod(N % q, q);
+        m.n_inv_shoup = shoup_pre(m.n_inv, q);
+        m.psi = smallest_primitive_root_2n(q, N);
+        const uint64_t psi_inv = inv_mod(m.psi, q);
+        uint64_t* T = tw.data() + (size_t)mi * 4 * N;
+        // powers in natural order, then scatter to bit-reversed positions
+        uint64_t x = 1, y = 1;
+        for (uint64_t k = 0; k < N; ++k) {
+            uint64_t r = 0;
+            for (int b = 0; b < logN; ++b) r |= ((k >> b) & 1) << (logN - 1 - b);
+            T[r] = x;
+            T[2 * N + r] = y;
+            x = mm(x, m.psi, q);
+            y = mm(y, psi_inv, q);
+        }
+        for (uint64_t k = 0; k < N; ++k) {
+            T[N + k] = shoup_pre(T[k], q);
+            T[3 * N + k] = shoup_pre(T[2 * N + k], q);
+        }
+    }
+    d_mods = (Modulus*)pool.get(sizeof(Modulus) * nm);
+    upload(d_mods, mh.data(), sizeof(Modulus) * nm, stream);
+    d_tw = (uint64_t*)pool.get(tw.size() * 8);
+    upload(d_tw, tw.data(), tw.size() * 8, stream);
+    tabs.logN = logN;
+    tabs.L1 = logN / 2;
+    tabs.mods = d_mods;
+    tabs.tw = d_tw;
+
+    // per-level constants
+    lv.resize(L + 1);
+    for (int l = 0; l <= L; ++l) {
+        LevelConsts& c = lv[l];
+        const int nr = n_ext(l);
+        for (int j = 0; j < dnum; ++j) {
+            const int lo = j * gsize, hi = std::min(std::min((j + 1) * gsize, L + 1), l + 1);
+            if (lo >= hi) break;
+            DigitConsts dc;
+            dc.lo = lo;
+            dc.hi = hi;
+            std::vector<uint64_t> yc, cc;
+            std::vector<int> tg;
+            for (int t = 0; t < nr; ++t)
+                if (!(t >= lo && t < hi)) tg.push_back(gmod_ext(l, t));
+            for (int i = lo; i < hi; ++i) {
+                const uint64_t qi = moduli[i];
+                uint64_t hat = 1;
+                for (int k = lo; k < hi; ++k) if (k != i) hat = mm(hat, moduli[k] % qi, qi);
+                const uint64_t w = inv_mod(hat, qi);
+                yc.push_back(w);
+                yc.push_back(shoup_pre(w, qi));
+            }
+            for (int i = lo; i < hi; ++i) {
+                for (int tm : tg) {
+                    const uint64_t qt = moduli[tm];
+                    uint64_t hat = 1;
+                    for (int k = lo; k < hi; ++k) if (k != i) hat = mm(hat, moduli[k] % qt, qt);
+                    cc.push_back(hat);
+                    cc.push_back(shoup_pre(hat, qt));
+                }
+            }
+            dc.yc = upload_consts(pool, yc, stream);
+            dc.cc = upload_consts(pool, cc, stream);
+            c.digits.push_back(dc);
+        }
+        std::vector<uint64_t> y, cv, pinv, rs;
+        for (int k = 0; k < alpha; ++k) {
+            const uint64_t pk_ = moduli[L + 1 + k];
+            uint64_t hat = 1;
+            for (int kk = 0; kk < alpha; ++kk) if (kk != k) hat = mm(hat, moduli[L + 1 + kk] % pk_, pk_);
+            const uint64_t w = inv_mod(hat, pk_);
+            y.push_back(w);
+            y.push_back(shoup_pre(w, pk_));
+        }
+        for (int k = 0; k < alpha; ++k) {
+            for (int i = 0; i <= l; ++i) {
+                const uint64_t qi = moduli[i];
+                uint64_t hat = 1;
+                for (int kk = 0; kk < alpha; ++kk) if (kk != k) hat = mm(hat, moduli[L + 1 + kk] % qi, qi);
+                cv.push_back(hat);
+                cv.push_back(shoup_pre(hat, qi));
+            }
+        }
+        for (int i = 0; i <= l; ++i) {
+            const uint64_t qi = moduli[i];
+            uint64_t P = 1;
+            for (int k = 0; k < alpha; ++k) P = mm(P, moduli[L + 1 + k] % qi, qi);
+            const uint64_t w = inv_mod(P, qi);
+            pinv.push_back(w);
+            pinv.push_back(shoup_pre(w, qi));
+        }
+        if (l >= 1) {
+            const uint64_t ql = moduli[l];
+            for (int i = 0; i < l; ++i) {
+                const uint64_t qi = moduli[i];
+                const uint64_t w = inv_mod(ql % qi, qi);
+                rs.push_back((ql / 2) % qi);
+                rs.push_back(w);
+                rs.push_back(shoup_pre(w, qi));
+                rs.push_back(0);
+            }
+        }
+        c.md_y = upload_consts(pool, y, stream);
+        c.md_c = upload_consts(pool, cv, stream);
+        c.md_pinv = upload_consts(pool, pinv, stream);
+        c.rs = upload_consts(pool, rs, stream);
+    }
+}
+
+// ------------------------------------------------------------------ store
+Ct Context::new_ct(int level, double scale) {
+    Ct c;
+    c.d = (uint64_t*)pool.get(ct_words() * 8);
+    c.level = level;
+    c.scale = scale;
+    return c;
+}
+
+uint64_t Context::put(const Ct& c) {
+    const uint64_t h = next_handle++;
+    cts[h] = c;
+    return h;
+}
+
+Ct& Context::get(uint64_t h) {
+    auto it = cts.find(h);
+    if (it == cts.end()) throw Error(CSRMF_E_INVAL, "unknown ciphertext handle " + std::to_string(h));
+    return it->second;
+}
+
+void Context::free_ct(uint64_t h) {
+    auto it = cts.find(h);
+    if (it == cts.end()) throw Error(CSRMF_E_INVAL, "unknown ciphertext handle");
+    CSRMF_HIP(hipStreamSynchronize(stream));
+    pool.put(it->second.d);
+    cts.erase(it);
+}
+
+uint64_t** Context::ptr_table(const std::vector<uint64_t*>& v) {
+    auto it = ptr_tables.find(v);
+    if (it != ptr_tables.end()) return it->second;
+    uint64_t** d = nullptr;
+    CSRMF_HIP(hipMalloc(&d, std::max<size_t>(8, v.size() * sizeof(uint64_t*))));
+    upload(d, v.data(), v.size() * sizeof(uint64_t*), stream);
+    ptr_tables[v] = d;
+    return d;
+}
+
+RowMap Context::map_ct(uint64_t* d, int nlimbs, int first) const {
+    RowMap m;
+    m.base = d;
+    m.poly_stride = poly_stride();
+    m.batch_stride = 2 * poly_stride();
+    for (int i = 0; i < nlimbs; ++i) m.push(first + i, first + i);
+    return m;
+}
+
+RowMap Context::map_cts(const std::vector<Ct*>& v, int nlimbs, int first) {
+    RowMap m = map_ct(v.empty() ? nullptr : v[0]->d, nlimbs, first);
+    m.batch = (int)v.size();
+    if (v.size() > 1) {
+        std::vector<uint64_t*> ps;
+        for (Ct* c : v) ps.push_back(c->d);
+        m.ptrs = ptr_table(ps);
+    }
+    return m;
+}
+
+// ------------------------------------------------------------------ keys
+uint32_t Context::galois_for_step(int64_t r) const {
+    const int64_t half = (int64_t)(N / 2);
+    int64_t e = r % half;
+    if (e < 0) e += half;
+    return (uint32_t)pow_mod(5, (uint64_t)e, 2 * N);
+}
+
+const Key& Context::key_for(uint32_t g) const {
+    auto it = rot.find(g);
+    if (it == rot.end()) throw Error(CSRMF_E_KEY, "no rotation key for Galois element " + std::to_string(g));
+    return it->second;
+}
+
+void Context::keygen(const int32_t* steps, int n, bool conj) {
+    const int nall = L + 1 + alpha;
+    if (!have_keys) {
+        std::vector<int64_t> sv(N);
+        sample_ternary(seed, kSecret, 0, N, sv.data());
+        Scratch ss(pool, N);
+        upload(ss.p, sv.data(), N * 8, stream);
+        s_ntt = (uint64_t*)pool.get((size_t)nall * N * 8);
+        s_mont = (uint64_t*)pool.get((size_t)nall * N * 8);
+        RowMap ms;
+        ms.base = s_ntt;
+        for (int i = 0; i < nall; ++i) ms.push(i, i);
+        launch_expand_signed(tabs, ms, (const int64_t*)ss.p, 1, 0, stream);
+        launch_ntt(tabs, ms, false, stream);
+        RowMap mm_ = ms;
+        mm_.base = s_mont;
+        std::vector<uint64_t> rc;
+        for (int i = 0; i < nall; ++i) { rc.push_back(mh[i].r_mod); rc.push_back(mh[i].r_mod_shoup); }
+        Scratch rcd(pool, rc.size());
+        upload(rcd.p, rc.data(), rc.size() * 8, stream);
+        launch_mul_const(tabs, mm_, ms, rcd.p, false, stream);
+
+        // public key: b = -a*s + e over Q_L
+        pk = (uint64_t*)pool.get(2 * (size_t)(L + 1) * N * 8);
+        std::vector<uint64_t> av((size_t)(L + 1) * N);
+        for (int i = 0; i <= L; ++i) sample_uniform(seed, kPkA, 0, i, N, moduli[i], av.data() + (size_t)i * N);
+        std::vector<int64_t> ev(N);
+        sample_cbd21(seed, kPkE, 0, N, ev.data());
+        uint64_t* pb = pk;
+        uint64_t* pa = pk + (size_t)(L + 1) * N;
+        upload(pa, av.data(), av.size() * 8, stream);
+        Scratch es(pool, N);
+        upload(es.p, ev.data(), N * 8, stream);
+        RowMap ma, mb, msm;
+        ma.base = pa; mb.base = pb; msm.base = s_mont;
+        for (int i = 0; i <= L; ++i) { ma.push(i, i); mb.push(i, i); msm.push(i, i); }
+        launch_ntt(tabs, ma, false, stream);
+        launch_expand_signed(tabs, mb, (const int64_t*)es.p, 1, 0, stream);
+        launch_ntt(tabs, mb, false, stream);
+        Scratch as(pool, (size_t)(L + 1) * N);
+        RowMap mas = ma;
+        mas.base = as.p;
+        launch_mul_mont(tabs, mas, ma, msm, false, stream);          // a*s
+        launch_ew(tabs, EW_SUB, mb, mb, mas, stream);                // e - a*s
+        // store pk times 2^64
+        RowMap mpk;
+        mpk.base = pk;
+        mpk.poly_stride = (int64_t)(L + 1) * N;
+        for (int i = 0; i <= L; ++i) mpk.push(i, i);
+        launch_mul_const(tabs, mpk, mpk, rcd.p, true, stream);
+
+        // relinearisation key: s' = s^2
+        Scratch s2(pool, (size_t)(L + 1) * N);
+        RowMap m2 = msm;
+        m2.base = s2.p;
+        RowMap msq = msm;
+        msq.base = s_ntt;
+        launch_mul_mont(tabs, m2, msq, msm, false, stream);
+        make_switching_key(relin, s2.p, 0);
+        have_keys = true;
+    }
+    for (int i = 0; i < n; ++i) add_rotation_key(galois_for_step(steps[i]));
+    if (conj) add_rotation_key((uint32_t)(2 * N - 1));
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+void Context::add_rotation_key(uint32_t g) {
+    if (g == 1 || rot.count(g)) return;
+    Scratch sg(pool, (size_t)(L + 1) * N);
+    RowMap mi, mo;
+    mi.base = s_ntt;
+    mo.base = sg.p;
+    for (int i = 0; i <= L; ++i) { mi.push(i, i); mo.push(i, i); }
+    launch_automorphism(tabs, g, mo, mi, false, stream);
+    Key k;
+    make_switching_key(k, sg.p, g);
+    rot[g] = k;
+}
+
+void Context::make_switching_key(Key& key, const uint64_t* sprime, uint32_t key_index) {
+    const int nall = L + 1 + alpha;
+    const size_t rows_words = (size_t)nall * N;
+    key.n_digits = 0;
+    for (int j = 0; j < dnum; ++j) if (j * gsize < L + 1) key.n_digits++;
+    key.d = (uint64_t*)pool.get((size_t)key.n_digits * 2 * rows_words * 8);
+    // P mod q_i
+    std::vector<uint64_t> pc;
+    for (int i = 0; i <= L; ++i) {
+        uint64_t P = 1;
+        for (int k = 0; k < alpha; ++k) P = mm(P, moduli[L + 1 + k] % moduli[i], moduli[i]);
+        pc.push_back(P);
+        pc.push_back(shoup_pre(P, moduli[i]));
+    }
+    Scratch pcd(pool, pc.size());
+    upload(pcd.p, pc.data(), pc.size() * 8, stream);
+    std::vector<uint64_t> rc;
+    for (int i = 0; i < nall; ++i) { rc.push_back(mh[i].r_mod); rc.push_back(mh[i].r_mod_shoup); }
+    Scratch rcd(pool, rc.size());
+    upload(rcd.p, rc.data(), rc.size() * 8, stream);
+    std::vector<uint64_t> av(rows_words);
+    std::vector<int64_t> ev(N);
+    Scratch es(pool, N), tmp(pool, rows_words);
+    for (int j = 0; j < key.n_digits; ++j) {
+        const uint32_t obj = key_index * (uint32_t)dnum + (uint32_t)j;
+        for (int t = 0; t < nall; ++t) sample_uniform(seed, kKskA, obj, t, N, moduli[t], av.data() + (size_t)t * N);
+        sample_cbd21(seed, kKskE, obj, N, ev.data());
+        uint64_t* kb = key.d + (size_t)j * 2 * rows_words;
+        uint64_t* ka = kb + rows_words;
+        upload(ka, av.data(), rows_words * 8, stream);
+        upload(es.p, ev.data(), N * 8, stream);
+        RowMap ma, mb, ms, mt;
+        ma.base = ka; mb.base = kb; ms.base = s_mont; mt.base = tmp.p;
+        for (int t = 0; t < nall; ++t) { ma.push(t, t); mb.push(t, t); ms.push(t, t); mt.push(t, t); }
+        launch_ntt(tabs, ma, false, stream);
+        launch_expand_signed(tabs, mb, (const int64_t*)es.p, 1, 0, stream);
+        launch_ntt(tabs, mb, false, stream);
+        launch_mul_mont(tabs, mt, ma, ms, false, stream);   // a*s
+        launch_ew(tabs, EW_SUB, mb, mb, mt, stream);        // e - a*s
+        const int lo = j * gsize, hi = std::min((j + 1) * gsize, L + 1);
+        RowMap dq, sq, tq;
+        dq.base = kb; sq.base = (uint64_t*)sprime; tq.base = tmp.p;
+        for (int i = lo; i < hi; ++i) { dq.push(i, i); sq.push(i, i); tq.push(i, i); }
+        launch_mul_const(tabs, tq, sq, pcd.p + 2 * lo, false, stream);   // P * s'
+        launch_ew(tabs, EW_ADD, dq, dq, tq, stream);
+        // store times 2^64
+        RowMap mk = ma;
+        mk.base = kb;
+        mk.poly_stride = (int64_t)rows_words;
+        launch_mul_const(tabs, mk, mk, rcd.p, true, stream);
+    }
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+// ------------------------------------------------------------------ encrypt
+void Context::encrypt_int_batch(const int64_t* m, int count, int level, double scale, std::vector<Ct>& out) {
+    if (!have_keys) throw Error(CSRMF_E_STATE, "keygen first");
+    if (level < 0 || level > L) throw Error(CSRMF_E_INVAL, "level out of range");
+    // signed inputs: [count][4][N] = v, e0, e1, m
+    std::vector<int64_t> host((size_t)count * 4 * N);
+    for (int c = 0; c < count; ++c) {
+        const uint64_t ser = serial++;
+        int64_t* h = host.data() + (size_t)c * 4 * N;
+        sample_ternary(seed, kEncV, (uint32_t)ser, N, h);
+        sample_cbd21(seed, kEncE0, (uint32_t)ser, N, h + N);
+        sample_cbd21(seed, kEncE1, (uint32_t)ser, N, h + 2 * N);
+        std::memcpy(h + 3 * N, m + (size_t)c * N, N * 8);
+    }
+    Scratch src(pool, host.size());
+    upload(src.p, host.data(), host.size() * 8, stream);
+    const int nl = level + 1;
+    Scratch ex(pool, (size_t)count * 4 * nl * N);
+    // expand: rows [c][poly p][limb i] at off p*nl + i
+    for (int p = 0; p < 4; ++p) {
+        RowMap me;
+        me.base = ex.p + (size_t)p * nl * N;
+        me.batch = count;
+        me.batch_stride = (int64_t)4 * nl * N;
+        for (int i = 0; i < nl; ++i) me.push(i, i);
+        launch_expand_signed(tabs, me, (const int64_t*)src.p + (size_t)p * N, 1, (int64_t)4 * N, stream);
+    }
+    out.clear();
+    for (int c = 0; c < count; ++c) out.push_back(new_ct(level, scale));
+    // NTT all expanded rows
+    RowMap all;
+    all.base = ex.p;
+    all.batch = count;
+    all.batch_stride = (int64_t)4 * nl * N;
+    for (int p = 0; p < 4; ++p)
+        for (int i = 0; i < nl; ++i) all.push(p * nl + i, i);
+    launch_ntt(tabs, all, false, stream);
+    std::vector<Ct*> po;
+    for (auto& c : out) po.push_back(&c);
+    RowMap o0 = map_cts(po, nl);
+    RowMap o1 = o0;
+    for (int i = 0; i < nl; ++i) o1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+    auto vmap = [&](int p) {
+        RowMap r;
+        r.base = ex.p + (size_t)p * nl * N;
+        r.batch = count;
+        r.batch_stride = (int64_t)4 * nl * N;
+        for (int i = 0; i < nl; ++i) r.push(i, i);
+        return r;
+    };
+    RowMap pb, pa;
+    pb.base = pk;
+    pa.base = pk + (size_t)(L + 1) * N;
+    for (int i = 0; i < nl; ++i) { pb.push(i, i); pa.push(i, i); }
+    pb.batch = pa.batch = count;   // batch stride 0: the same key rows for every ciphertext
+    launch_mul_mont(tabs, o0, vmap(0), pb, false, stream);
+    launch_mul_mont(tabs, o1, vmap(0), pa, false, stream);
+    launch_ew(tabs, EW_ADD, o0, o0, vmap(3), stream);
+    launch_ew(tabs, EW_ADD, o0, o0, vmap(1), stream);
+    launch_ew(tabs, EW_ADD, o1, o1, vmap(2), stream);
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+Ct Context::encrypt_int(const int64_t* m, int level, double scale) {
+    std::vector<Ct> out;
+    encrypt_int_batch(m, 1, level, scale, out);
+    return out[0];
+}
+
+void Context::decrypt_int(const Ct& c, int64_t* m) {
+    if (!have_keys) throw Error(CSRMF_E_STATE, "keygen first");
+    Scratch x(pool, N);
+    RowMap mx, m0, m1, ms;
+    mx.base = x.p;
+    mx.push(0, 0);
+    m0.base = c.d;
+    m0.push(0, 0);
+    m1.base = c.d;
+    m1.push(L + 1, 0);
+    ms.base = s_mont;
+    ms.push(0, 0);
+    launch_mul_mont(tabs, mx, m1, ms, false, stream);
+    launch_ew(tabs, EW_ADD, mx, mx, m0, stream);
+    launch_ntt(tabs, mx, true, stream);
+    std::vector<uint64_t> h(N);
+    CSRMF_HIP(hipMemcpyAsync(h.data(), x.p, N * 8, hipMemcpyDeviceToHost, stream));
+    CSRMF_HIP(hipStreamSynchronize(stream));
+    const uint64_t q0 = moduli[0];
+    for (uint64_t i = 0; i < N; ++i) m[i] = h[i] > q0 / 2 ? -(int64_t)(q0 - h[i]) : (int64_t)h[i];
+}
+
+void Context::export_ct(const Ct& c, uint64_t* coeffs) {
+    const int nl = c.level + 1;
+    Scratch x(pool, 2 * (size_t)nl * N);
+    RowMap src = map_ct(c.d, nl), dst;
+    dst.base = x.p;
+    dst.poly_stride = (int64_t)nl * N;
+    for (int i = 0; i < nl; ++i) dst.push(i, i);
+    RowMap src1 = src, dst1 = dst;
+    for (int i = 0; i < nl; ++i) {
+        src1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+        dst1.e[i] = ((uint32_t)(nl + i) << 8) | (uint32_t)i;
+    }
+    launch_ew(tabs, EW_COPY, dst, src, src, stream);
+    launch_ew(tabs, EW_COPY, dst1, src1, src1, stream);
+    RowMap both = dst;
+    for (int i = 0; i < nl; ++i) both.push(nl + i, i);
+    launch_ntt(tabs, both, true, stream);
+    CSRMF_HIP(hipMemcpyAsync(coeffs, x.p, 2 * (size_t)nl * N * 8, hipMemcpyDeviceToHost, stream));
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+Ct Context::import_ct(const uint64_t* coeffs, int level, double scale) {
+    if (level < 0 || level > L) throw Error(CSRMF_E_INVAL, "level out of range");
+    const int nl = level + 1;
+    for (int p = 0; p < 2; ++p)
+        for (int i = 0; i < nl; ++i)
+            for (uint64_t n = 0; n < N; ++n)
+                if (coeffs[((size_t)p * nl + i) * N + n] >= moduli[i]) throw Error(CSRMF_E_INVAL, "residue not reduced");
+    Ct c = new_ct(level, scale);
+    for (int p = 0; p < 2; ++p)
+        CSRMF_HIP(hipMemcpyAsync(c.d + (size_t)p * poly_stride(), coeffs + (size_t)p * nl * N, (size_t)nl * N * 8,
+                                 hipMemcpyHostToDevice, stream));
+    RowMap m = map_ct(c.d, nl);
+    for (int i = 0; i < nl; ++i) m.push(L + 1 + i, i);
+    launch_ntt(tabs, m, false, stream);
+    CSRMF_HIP(hipStreamSynchronize(stream));
+    return c;
+}
+
+void Context::export_key(int which, uint32_t g, uint64_t* out) {
+    if (!have_keys) throw Error(CSRMF_E_STATE, "keygen first");
+    const int nall = L + 1 + alpha;
+    std::vector<uint64_t> h;
+    auto pull = [&](const uint64_t* d, int rows, const std::vector<int>& mods, bool mont) {
+        Scratch x(pool, (size_t)rows * N);
+        CSRMF_HIP(hipMemcpyAsync(x.p, d, (size_t)rows * N * 8, hipMemcpyDeviceToDevice, stream));
+        RowMap m;
+        m.base = x.p;
+        for (int r = 0; r < rows; ++r) m.push(r, mods[r]);
+        launch_ntt(tabs, m, true, stream);
+        std::vector<uint64_t> v((size_t)rows * N);
+        CSRMF_HIP(hipMemcpyAsync(v.data(), x.p, v.size() * 8, hipMemcpyDeviceToHost, stream));
+        CSRMF_HIP(hipStreamSynchronize(stream));
+        if (mont) {
+            for (int r = 0; r < rows; ++r) {
+                const uint64_t q = moduli[mods[r]];
+                const uint64_t rinv = inv_mod(mh[mods[r]].r_mod, q);
+                for (uint64_t n = 0; n < N; ++n) v[(size_t)r * N + n] = mm(v[(size_t)r * N + n], rinv, q);
+            }
+        }
+        h.insert(h.end(), v.begin(), v.end());
+    };
+    std::vector<int> all_mods, q_mods;
+    for (int i = 0; i < nall; ++i) all_mods.push_back(i);
+    for (int i = 0; i <= L; ++i) q_mods.push_back(i);
+    if (which == 0) {
+        pull(s_ntt, nall, all_mods, false);
+    } else if (which == 1) {
+        std::vector<int> m2 = q_mods;
+        m2.insert(m2.end(), q_mods.begin(), q_mods.end());
+        pull(pk, 2 * (L + 1), m2, true);
+    } else if (which == 2 || which == 3) {
+        const Key& k = which == 2 ? relin : key_for(g);
+        for (int j = 0; j < k.n_digits; ++j) {
+            pull(k.d + (size_t)j * 2 * nall * N, nall, all_mods, true);
+            pull(k.d + (size_t)j * 2 * nall * N + (size_t)nall * N, nall, all_mods, true);
+        }
+    } else {
+        throw Error(CSRMF_E_INVAL, "unknown key selector");
+    }
+    std::memcpy(out, h.data(), h.size() * 8);
+}
+
+// ------------------------------------------------------------------ evaluation
+void Context::check_scales(double a, double b) const {
+    if (std::fabs(a / b - 1.0) > std::ldexp(1.0, -30))
+        throw Error(CSRMF_E_SCALE, "operand scales differ: " + std::to_string(a) + " vs " + std::to_string(b));
+}
+
+void Context::add(const Ct& a, const Ct& b, Ct& out, bool sub) {
+    check_scales(a.scale, b.scale);
+    const int lvl = std::min(a.level, b.level);
+    out = new_ct(lvl, a.scale);
+    RowMap ma = map_ct(a.d, lvl + 1), mb = map_ct(b.d, lvl + 1), mo = map_ct(out.d, lvl + 1);
+    for (int i = 0; i <= lvl; ++i) {
+        ma.push(L + 1 + i, i);
+        mb.push(L + 1 + i, i);
+        mo.push(L + 1 + i, i);
+    }
+    launch_ew(tabs, sub ? EW_SUB : EW_ADD, mo, ma, mb, stream);
+}
+
+void Context::add_plain(const Ct& a, const int64_t* m, Ct& out) {
+    const int nl = a.level + 1;
+    Scratch src(pool, N), ex(pool, (size_t)nl * N);
+    upload(src.p, m, N * 8, stream);
+    RowMap me;
+    me.base = ex.p;
+    for (int i = 0; i < nl; ++i) me.push(i, i);
+    launch_expand_signed(tabs, me, (const int64_t*)src.p, 1, 0, stream);
+    launch_ntt(tabs, me, false, stream);
+    out = new_ct(a.level, a.scale);
+    RowMap ma = map_ct(a.d, nl), mo = map_ct(out.d, nl);
+    launch_ew(tabs, EW_ADD, mo, ma, me, stream);
+    RowMap ma1 = ma, mo1 = mo;
+    for (int i = 0; i < nl; ++i) {
+        ma1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+        mo1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+    }
+    launch_ew(tabs, EW_COPY, mo1, ma1, ma1, stream);
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+void Context::mul_plain(const Ct& a, const int64_t* m, double pt_scale, Ct& out) {
+    const int nl = a.level + 1;
+    Scratch src(pool, N), ex(pool, (size_t)nl * N);
+    upload(src.p, m, N * 8, stream);
+    RowMap me;
+    me.base = ex.p;
+    for (int i = 0; i < nl; ++i) me.push(i, i);
+    launch_expand_signed(tabs, me, (const int64_t*)src.p, 1, 0, stream);
+    launch_ntt(tabs, me, false, stream);
+    std::vector<uint64_t> rc;
+    for (int i = 0; i < nl; ++i) { rc.push_back(mh[i].r_mod); rc.push_back(mh[i].r_mod_shoup); }
+    Scratch rcd(pool, rc.size());
+    upload(rcd.p, rc.data(), rc.size() * 8, stream);
+    launch_mul_const(tabs, me, me, rcd.p, false, stream);   // plaintext times 2^64
+    out = new_ct(a.level, a.scale * pt_scale);
+    RowMap ma = map_ct(a.d, nl), mo = map_ct(out.d, nl);
+    launch_mul_mont(tabs, mo, ma, me, false, stream);
+    for (int i = 0; i < nl; ++i) {
+        ma.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+        mo.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+    }
+    launch_mul_mont(tabs, mo, ma, me, false, stream);
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+void Context::mul_int(const Ct& a, int64_t w, Ct& out) {
+    const int nl = a.level + 1;
+    std::vector<uint64_t> c;
+    for (int i = 0; i < nl; ++i) {
+        const uint64_t r = from_signed(w, moduli[i]);
+        c.push_back(r);
+        c.push_back(shoup_pre(r, moduli[i]));
+    }
+    Scratch cd(pool, c.size());
+    upload(cd.p, c.data(), c.size() * 8, stream);
+    out = new_ct(a.level, a.scale * (double)w);
+    launch_mul_const(tabs, map_ct(out.d, nl), map_ct(a.d, nl), cd.p, true, stream);
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+void Context::mod_drop(Ct& c, int level) {
+    if (level > c.level) throw Error(CSRMF_E_LEVEL, "cannot raise the level");
+    c.level = level;
+}
+
+// ModUp of every digit of d (evaluation form, B ciphertext rows of level+1
+// limbs) into ext [B][n_digits][l+1+alpha][N] (evaluation form).
+void Context::ks_modup(const RowMap& d_in, int level, int B, uint64_t* ext, uint64_t* coef) {
+    const int nl = level + 1, nr = n_ext(level);
+    const LevelConsts& c = lv[level];
+    const int nd = (int)c.digits.size();
+    RowMap mc;
+    mc.base = coef;
+    mc.batch = B;
+    mc.batch_stride = (int64_t)nl * N;
+    for (int i = 0; i < nl; ++i) mc.push(i, i);
+    launch_ew(tabs, EW_COPY, mc, d_in, d_in, stream);
+    launch_ntt(tabs, mc, true, stream);
+    for (int jj = 0; jj < nd; ++jj) {
+        const DigitConsts& dc = c.digits[jj];
+        RowMap src, dst, cpy_src, cpy_dst;
+        src.base = coef;
+        src.batch = B;
+        src.batch_stride = (int64_t)nl * N;
+        for (int i = dc.lo; i < dc.hi; ++i) src.push(i, i);
+        dst.base = ext;
+        dst.batch = B;
+        dst.batch_stride = (int64_t)nd * nr * N;
+        for (int t = 0; t < nr; ++t)
+            if (!(t >= dc.lo && t < dc.hi)) dst.push(jj * nr + t, gmod_ext(level, t));
+        launch_basis_convert(tabs, dst, src, dc.yc, dc.cc, stream);
+        launch_ntt(tabs, dst, false, stream);
+        cpy_src = d_in;
+        cpy_src.n = 0;
+        cpy_dst = dst;
+        cpy_dst.n = 0;
+        for (int i = dc.lo; i < dc.hi; ++i) {
+            cpy_src.push(d_in.e[i] >> 8, i);
+            cpy_dst.push(jj * nr + i, i);
+        }
+        launch_ew(tabs, EW_COPY, cpy_dst, cpy_src, cpy_src, stream);
+    }
+}
+
+void Context::ks_inner(const uint64_t* ext, int level, int B, const Key& key, uint32_t g, uint64_t* u) {
+    const int nr = n_ext(level);
+    const int nd = (int)lv[level].digits.size();
+    const int nall = L + 1 + alpha;
+    RowMap mu;
+    mu.base = u;
+    mu.batch = B;
+    mu.batch_stride = 2 * (int64_t)nr * N;
+    mu.poly_stride = (int64_t)nr * N;
+    for (int t = 0; t < nr; ++t) mu.push(t, gmod_ext(level, t));
+    KsArgs a;
+    a.ext = ext;
+    a.ext_batch_stride = (int64_t)nd * nr * N;
+    a.ext_digit_stride = (int64_t)nr * N;
+    a.key = key.d;
+    a.key_digit_stride = 2 * (int64_t)nall * N;
+    a.key_poly_stride = (int64_t)nall * N;
+    a.n_q = level + 1;
+    a.key_shift = L - level;
+    a.n_digits = nd;
+    launch_ks_inner(tabs, mu, a, g, stream);
+}
+
+void Context::ks_moddown(uint64_t* u, int level, int B, const RowMap& out, const RowMap& addend,
+                         uint32_t g_add, bool addend_both) {
+    const int nl = level + 1, nr = n_ext(level);
+    const LevelConsts& c = lv[level];
+    RowMap mp;   // P rows of u0 and u1: 2B groups of alpha rows
+    mp.base = u;
+    mp.batch = 2 * B;
+    mp.batch_stride = (int64_t)nr * N;
+    for (int k = 0; k < alpha; ++k) mp.push(nl + k, L + 1 + k);
+    launch_ntt(tabs, mp, true, stream);
+    Scratch conv(pool, 2 * (size_t)B * nl * N);
+    RowMap mcv;
+    mcv.base = conv.p;
+    mcv.batch = 2 * B;
+    mcv.batch_stride = (int64_t)nl * N;
+    for (int i = 0; i < nl; ++i) mcv.push(i, i);
+    launch_basis_convert(tabs, mcv, mp, c.md_y, c.md_c, stream);
+    launch_ntt(tabs, mcv, false, stream);
+    RowMap mu;
+    mu.base = u;
+    mu.batch = B;
+    mu.batch_stride = 2 * (int64_t)nr * N;
+    mu.poly_stride = (int64_t)nr * N;
+    for (int i = 0; i < nl; ++i) mu.push(i, i);
+    RowMap mc2;
+    mc2.base = conv.p;
+    mc2.batch = B;
+    mc2.batch_stride = 2 * (int64_t)nl * N;
+    mc2.poly_stride = (int64_t)nl * N;
+    for (int i = 0; i < nl; ++i) mc2.push(i, i);
+    launch_moddown_combine(tabs, out, mu, mc2, addend, g_add, addend_both, c.md_pinv, stream);
+}
+
+void Context::mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, std::vector<Ct*>& out) {
+    const int B = (int)a.size();
+    if (B == 0) return;
+    if (!have_keys) throw Error(CSRMF_E_STATE, "keygen first");
+    const int lvl = std::min(a[0]->level, b[0]->level);
+    for (int i = 0; i < B; ++i)
+        if (std::min(a[i]->level, b[i]->level) != lvl) throw Error(CSRMF_E_INVAL, "batch operands must share a level");
+    const int nl = lvl + 1, nr = n_ext(lvl);
+    const int nd = (int)lv[lvl].digits.size();
+    Scratch d(pool, (size_t)B * 3 * nl * N);
+    RowMap md;
+    md.base = d.p;
+    md.batch = B;
+    md.batch_stride = 3 * (int64_t)nl * N;
+    md.poly_stride = (int64_t)nl * N;
+    for (int i = 0; i < nl; ++i) md.push(i, i);
+    launch_tensor(tabs, md, map_cts(a, nl), map_cts(b, nl), stream);
+    RowMap d2 = md;
+    for (int i = 0; i < nl; ++i) d2.e[i] = ((uint32_t)(2 * nl + i) << 8) | (uint32_t)i;
+    Scratch ext(pool, (size_t)B * nd * nr * N), coef(pool, (size_t)B * nl * N), u(pool, (size_t)B * 2 * nr * N);
+    ks_modup(d2, lvl, B, ext.p, coef.p);
+    ks_inner(ext.p, lvl, B, relin, 1, u.p);
+    for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, a[i]->scale * b[i]->scale);
+    ks_moddown(u.p, lvl, B, map_cts(out, nl), md, 1, true);
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+void Context::rescale(const std::vector<Ct*>& v) {
+    const int B = (int)v.size();
+    if (B == 0) return;
+    const int l = v[0]->level;
+    for (Ct* c : v)
+        if (c->level != l) throw Error(CSRMF_E_INVAL, "batch operands must share a level");
+    if (l < 1) throw Error(CSRMF_E_LEVEL, "no level left to rescale");
+    Scratch top(pool, 2 * (size_t)B * N), T(pool, 2 * (size_t)B * l * N);
+    RowMap src = map_cts(v, 1, l);
+    src.push(L + 1 + l, l);
+    RowMap mt;
+    mt.base = top.p;
+    mt.batch = B;
+    mt.batch_stride = 2 * (int64_t)N;
+    mt.poly_stride = (int64_t)N;
+    mt.push(0, l);
+    mt.push(1, l);
+    launch_ew(tabs, EW_COPY, mt, src, src, stream);
+    launch_ntt(tabs, mt, true, stream);
+    RowMap mt1 = mt;
+    mt1.n = 1;
+    RowMap mT;
+    mT.base = T.p;
+    mT.batch = B;
+    mT.batch_stride = 2 * (int64_t)l * N;
+    mT.poly_stride = (int64_t)l * N;
+    for (int i = 0; i < l; ++i) mT.push(i, i);
+    launch_rescale_spread(tabs, mT, mt1, (uint32_t)l, stream);
+    RowMap mTall = mT;
+    for (int i = 0; i < l; ++i) mTall.push(l + i, i);
+    launch_ntt(tabs, mTall, false, stream);
+    RowMap mc = map_cts(v, l);
+    launch_rescale_combine(tabs, mc, mc, mT, lv[l].rs, stream);
+    const double ql = (double)moduli[l];
+    for (Ct* c : v) {
+        c->level = l - 1;
+        c->scale = c->scale / ql;
+    }
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out) {
+    const int B = (int)in.size();
+    if (B == 0) return;
+    const Key& key = key_for(g);
+    const int lvl = in[0]->level;
+    for (Ct* c : in)
+        if (c->level != lvl) throw Error(CSRMF_E_INVAL, "batch operands must share a level");
+    const int nl = lvl + 1, nr = n_ext(lvl);
+    const int nd = (int)lv[lvl].digits.size();
+    Scratch d(pool, (size_t)B * nl * N);
+    RowMap md;
+    md.base = d.p;
+    md.batch = B;
+    md.batch_stride = (int64_t)nl * N;
+    for (int i = 0; i < nl; ++i) md.push(i, i);
+    RowMap c1 = map_cts(in, nl);
+    for (int i = 0; i < nl; ++i) c1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+    launch_automorphism(tabs, g, md, c1, false, stream);
+    Scratch ext(pool, (size_t)B * nd * nr * N), coef(pool, (size_t)B * nl * N), u(pool, (size_t)B * 2 * nr * N);
+    ks_modup(md, lvl, B, ext.p, coef.p);
+    ks_inner(ext.p, lvl, B, key, 1, u.p);
+    for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, in[i]->scale);
+    ks_moddown(u.p, lvl, B, map_cts(out, nl), map_cts(in, nl), g, false);
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+void Context::rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std::vector<Ct*>& out) {
+    const int lvl = in.level;
+    const int nl = lvl + 1, nr = n_ext(lvl);
+    const int nd = (int)lv[lvl].digits.size();
+    for (uint32_t g : gs) if (g != 1) key_for(g);
+    Scratch ext(pool, (size_t)nd * nr * N), coef(pool, (size_t)nl * N), u(pool, 2 * (size_t)nr * N);
+    RowMap c1 = map_ct(in.d, nl);
+    for (int i = 0; i < nl; ++i) c1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+    ks_modup(c1, lvl, 1, ext.p, coef.p);
+    for (size_t k = 0; k < gs.size(); ++k) {
+        const uint32_t g = gs[k];
+        *out[k] = new_ct(lvl, in.scale);
+        if (g == 1) {
+            RowMap a = map_ct(in.d, nl), o = map_ct(out[k]->d, nl);
+            for (int i = 0; i < nl; ++i) { a.push(L + 1 + i, i); o.push(L + 1 + i, i); }
+            launch_ew(tabs, EW_COPY, o, a, a, stream);
+            continue;
+        }
+        ks_inner(ext.p, lvl, 1, key_for(g), g, u.p);
+        ks_moddown(u.p, lvl, 1, map_ct(out[k]->d, nl), map_ct(in.d, nl), g, false);
+    }
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+void Context::ntt_rows(uint64_t* data, int n_rows, const int32_t* idx, int n_idx, bool inverse) {
+    if (n_idx <= 0 || n_idx > kMaxMapRows || n_rows % n_idx) throw Error(CSRMF_E_INVAL, "bad row map");
+    RowMap m;
+    m.base = data;
+    m.batch = n_rows / n_idx;
+    m.batch_stride = (int64_t)n_idx * N;
+    for (int i = 0; i < n_idx; ++i) {
+        if (idx[i] < 0 || idx[i] >= (int)moduli.size()) throw Error(CSRMF_E_INVAL, "bad limb index");
+        m.push(i, idx[i]);
+    }
+    launch_ntt(tabs, m, inverse, stream);
+    CSRMF_HIP(hipStreamSynchronize(stream));
+}
+
+}  // namespace csrmf

@@ -1,0 +1,173 @@
+// Host-side context of libcsrmf: modulus chain, device tables, keys,
+// ciphertext store and the orchestration of the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/csrmf.h"
+#include "kernels.h"
+
+namespace csrmf {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define CSRMF_HIP(x)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            throw ::csrmf::Error(CSRMF_E_DEVICE, std::string(#x ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device ciphertext: polynomials c0, c1 in evaluation form, each with room
+// for L+1 limbs (poly stride (L+1)*N words); limbs 0..level are valid.
+struct Ct {
+    uint64_t* d = nullptr;
+    int level = 0;
+    double scale = 1.0;
+};
+
+// A switching key: [n_digits][2 (b, a)][L+1+alpha][N], stored times 2^64 mod q.
+struct Key {
+    uint64_t* d = nullptr;
+    int n_digits = 0;
+};
+
+struct DigitConsts {
+    int lo, hi;                 // limbs [lo, hi) of the digit at this level
+    uint64_t* yc = nullptr;     // [|D|][2]
+    uint64_t* cc = nullptr;     // [|D|][n_tgt][2]
+};
+
+struct LevelConsts {
+    std::vector<DigitConsts> digits;
+    uint64_t* md_y = nullptr;       // [alpha][2]  (P/p_k)^-1 mod p_k
+    uint64_t* md_c = nullptr;       // [alpha][l+1][2]  (P/p_k) mod q_i
+    uint64_t* md_pinv = nullptr;    // [l+1][2]  P^-1 mod q_i
+    uint64_t* rs = nullptr;         // [l][4]  h mod q_i, q_l^-1 mod q_i, shoup, 0
+};
+
+class Pool {  // caching device allocator
+public:
+    ~Pool();
+    void* get(size_t bytes);
+    void put(void* p);
+    void release_all();
+    size_t bytes_in_use() const { return in_use_; }
+
+private:
+    std::multimap<size_t, void*> free_;
+    std::unordered_map<void*, size_t> sizes_;
+    size_t in_use_ = 0;
+};
+
+// Scratch buffer that returns itself to the pool.
+struct Scratch {
+    Pool* pool = nullptr;
+    uint64_t* p = nullptr;
+    Scratch(Pool& pl, size_t words) : pool(&pl), p((uint64_t*)pl.get(words * 8)) {}
+    ~Scratch() { if (p) pool->put(p); }
+    Scratch(const Scratch&) = delete;
+    Scratch& operator=(const Scratch&) = delete;
+};
+
+struct MfState;  // encrypted matrix-factorisation program (mf_program.cpp)
+void destroy_mf(MfState* m);
+
+struct Context {
+    csrmf_params prm{};
+    uint8_t seed[32];
+    int logN = 0;
+    uint64_t N = 0;
+    int L = 0, alpha = 0, dnum = 0, gsize = 0;
+    std::vector<uint64_t> moduli;      // q_0..q_L, p_0..p_{alpha-1}
+    std::vector<Modulus> mh;
+    Modulus* d_mods = nullptr;
+    uint64_t* d_tw = nullptr;
+    DevTables tabs{};
+    std::vector<LevelConsts> lv;
+    hipStream_t stream = nullptr;
+    Pool pool;
+    std::string err;
+
+    uint64_t serial = 0;
+    bool have_keys = false;
+    uint64_t* s_ntt = nullptr;      // [L+1+alpha][N] plain
+    uint64_t* s_mont = nullptr;     // s * 2^64
+    uint64_t* pk = nullptr;         // [2][L+1][N] times 2^64
+    Key relin;
+    std::map<uint32_t, Key> rot;
+
+    std::unordered_map<uint64_t, Ct> cts;
+    uint64_t next_handle = 1;
+    std::map<std::vector<uint64_t*>, uint64_t**> ptr_tables;
+    MfState* mf = nullptr;
+
+    Context() = default;
+    ~Context();
+    void init(const csrmf_params& p, const uint8_t s[32]);
+
+    // --- geometry
+    int n_ext(int level) const { return level + 1 + alpha; }
+    int gmod_ext(int level, int t) const { return t <= level ? t : L + 1 + (t - level - 1); }
+    int64_t poly_stride() const { return (int64_t)(L + 1) * (int64_t)N; }
+    size_t ct_words() const { return 2 * (size_t)(L + 1) * N; }
+
+    // --- ciphertext store
+    Ct new_ct(int level, double scale);
+    uint64_t put(const Ct& c);
+    Ct& get(uint64_t h);
+    void free_ct(uint64_t h);
+    uint64_t** ptr_table(const std::vector<uint64_t*>& v);
+
+    RowMap map_ct(uint64_t* d, int nlimbs, int first = 0) const;
+    RowMap map_cts(const std::vector<Ct*>& v, int nlimbs, int first = 0);
+
+    // --- keys
+    void keygen(const int32_t* steps, int n, bool conj);
+    void add_rotation_key(uint32_t g);
+    void make_switching_key(Key& k, const uint64_t* sprime_ntt, uint32_t key_index);
+    bool has_key(uint32_t g) const { return rot.count(g) != 0; }
+    const Key& key_for(uint32_t g) const;
+    uint32_t galois_for_step(int64_t r) const;
+
+    // --- encryption
+    Ct encrypt_int(const int64_t* m, int level, double scale);
+    void encrypt_int_batch(const int64_t* m, int count, int level, double scale, std::vector<Ct>& out);
+    void decrypt_int(const Ct& c, int64_t* m);
+    void export_ct(const Ct& c, uint64_t* coeffs);
+    Ct import_ct(const uint64_t* coeffs, int level, double scale);
+    void export_key(int which, uint32_t g, uint64_t* out);
+
+    // --- evaluation (batched; every vector holds ciphertexts of equal level)
+    void add(const Ct& a, const Ct& b, Ct& out, bool sub);
+    void add_plain(const Ct& a, const int64_t* m, Ct& out);
+    void mul_plain(const Ct& a, const int64_t* m, double pt_scale, Ct& out);
+    void mul_int(const Ct& a, int64_t w, Ct& out);
+    void mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, std::vector<Ct*>& out);
+    void rescale(const std::vector<Ct*>& v);          // in place
+    void mod_drop(Ct& c, int level);                   // in place
+    void rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out);
+    void rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std::vector<Ct*>& out);
+    void check_scales(double a, double b) const;
+
+    // --- key-switching pieces
+    void ks_modup(const RowMap& d_in, int level, int B, uint64_t* ext, uint64_t* coef);
+    void ks_inner(const uint64_t* ext, int level, int B, const Key& key, uint32_t g, uint64_t* u);
+    void ks_moddown(uint64_t* u, int level, int B, const RowMap& out, const RowMap& addend,
+                    uint32_t g_add, bool addend_both);
+
+    // --- raw NTT hook
+    void ntt_rows(uint64_t* data, int n_rows, const int32_t* idx, int n_idx, bool inverse);
+};
+
+}  // namespace csrmf

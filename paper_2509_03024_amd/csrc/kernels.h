@@ -1,0 +1,124 @@
+// Launch wrappers of the gfx950 kernels (implemented in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modarith.h"
+
+namespace csrmf {
+
+constexpr int kMaxMapRows = 64;
+
+// A set of polynomial rows (each N uint64 residues) addressed as `batch`
+// groups of `n` rows.  Row (b, k) starts at
+//     P(b) + off(k) * N,   P(b) = ptrs ? ptrs[b] : base + b * batch_stride
+// and is reduced modulo chain modulus mod(k); entry k packs (off << 8) | mod.
+// Kernels that touch both polynomials of a ciphertext find c1's row at
+// c0's row + poly_stride words.
+struct RowMap {
+    uint64_t* base = nullptr;
+    uint64_t* const* ptrs = nullptr;   // device array of `batch` pointers, or null
+    int64_t batch_stride = 0;          // words
+    int64_t poly_stride = 0;           // words
+    int32_t n = 0;
+    int32_t batch = 1;
+    uint32_t e[kMaxMapRows];
+
+    void push(uint32_t off, uint32_t mod) { e[n++] = (off << 8) | mod; }
+    int rows() const { return n * batch; }
+};
+
+// Device-resident tables of the modulus chain.
+struct DevTables {
+    int logN;
+    int L1;                      // stages done by the column pass
+    const Modulus* mods;         // [n_mod]
+    const uint64_t* tw;          // [n_mod][4][N]: psi^brev, shoup, psi^-brev, shoup
+};
+
+void launch_ntt(const DevTables& t, const RowMap& rows, bool inverse, hipStream_t s);
+
+// out row (b, k) = from_signed(src + b*src_batch_stride + (k % n_src)*N), int64
+// coefficients (n_src = 1 broadcasts one signed polynomial to every limb).
+void launch_expand_signed(const DevTables& t, const RowMap& out, const int64_t* src, int n_src,
+                          int64_t src_batch_stride, hipStream_t s);
+
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_NEG = 2, EW_COPY = 3 };
+// out = a (op) b (EW_NEG: out = -a; EW_COPY: out = a); maps share (n, batch).
+void launch_ew(const DevTables& t, EwOp op, const RowMap& out, const RowMap& a, const RowMap& b,
+               hipStream_t s);
+
+// out = mont(a, b) = a*b*2^-64 mod q; with b stored as x*2^64 this is a*x.
+// If acc != 0, out += mont(a, b) instead.
+void launch_mul_mont(const DevTables& t, const RowMap& out, const RowMap& a, const RowMap& b,
+                     bool acc, hipStream_t s);
+
+// out = a * c(k), one constant per map entry k: consts[2k] = c, consts[2k+1] = shoup(c)
+// (device array).  With both_polys, rows at +poly_stride are treated too.
+void launch_mul_const(const DevTables& t, const RowMap& out, const RowMap& a,
+                      const uint64_t* consts, bool both_polys, hipStream_t s);
+
+// Tensor product per limb of ciphertexts a and b (evaluation form):
+// d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.  Maps describe the c0 rows; c1
+// rows at +poly_stride; d has three polys at +poly_stride steps.
+void launch_tensor(const DevTables& t, const RowMap& d, const RowMap& a, const RowMap& b,
+                   hipStream_t s);
+
+// Automorphism tau_g in evaluation form: out[k] = in[perm_g(k)] with
+// perm_g(k) = brev(((2 brev(k) + 1) g mod 2N - 1) / 2).  both_polys: also rows at +poly_stride.
+// If add_to != 0 the permuted row is added into out instead of stored.
+void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, const RowMap& in,
+                         bool both_polys, hipStream_t s);
+
+// Fast basis conversion (coefficient form), per batch element:
+//   y_i = x_i * [Qhat_i^-1]_{q_i},   out_t = sum_i y_i * [Qhat_i]_t  (mod t)
+// src map: n_src rows; dst map: n_tgt rows.  Device constants:
+//   yc[2i], yc[2i+1]            = Qhat_i^-1 mod src_i and its shoup
+//   cc[2(i*n_tgt+t)], +1        = Qhat_i mod tgt_t and its shoup
+void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src,
+                          const uint64_t* yc, const uint64_t* cc, hipStream_t s);
+
+// Key-switching inner product over the extended basis Q_l u P (n_rows = l+1+alpha
+// rows): u0[t] = sum_j mont(ext_j[t][perm(k)], kb_j[row(t)]), u1 likewise with
+// the key's a part.  ext row (j, t) = ext + b*ext_batch_stride + j*ext_digit_stride
+// + t*N; key row (j, t) = key + j*key_digit_stride + row(t)*N with
+// row(t) = t for t < n_q and t + key_shift otherwise (special primes); the a
+// part is at +key_poly_stride.  Keys are stored times 2^64 (Montgomery form).
+// u: map with n = n_rows (u0 rows), u1 rows at +poly_stride.  g != 1 applies
+// tau_g to the ext rows on the fly (hoisted rotation).
+struct KsArgs {
+    const uint64_t* ext;
+    int64_t ext_batch_stride;
+    int64_t ext_digit_stride;
+    const uint64_t* key;
+    int64_t key_digit_stride;
+    int64_t key_poly_stride;
+    int32_t n_q;
+    int32_t key_shift;
+    int32_t n_digits;
+};
+void launch_ks_inner(const DevTables& t, const RowMap& u, const KsArgs& a, uint32_t g, hipStream_t s);
+
+// ModDown combine over q_0..q_l:  out_i = (u_i - conv_i) * P^-1 (mod q_i)
+// [+ tau_g(addend_i) if addend.n > 0].  consts[2i], +1 = P^-1 mod q_i, shoup.
+// All maps have n = number of Q limbs; both polys (+poly_stride) are processed
+// when both_polys; the addend is applied to poly 0 only when add_poly0_only.
+void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap& u,
+                            const RowMap& conv, const RowMap& addend, uint32_t g_add,
+                            bool addend_both_polys, const uint64_t* consts, hipStream_t s);
+
+// Rescale step 1 (coefficient form top limb, one row per batch element and
+// poly): t = (c_l + h) mod q_l with h = floor(q_l/2), then dst row k =
+// (t - h) mod q_{mod(k)}; rounding adds h to every coefficient, so it is
+// folded in here, in coefficient form.
+// top: map with n = 1 (poly 0 row; poly 1 at +poly_stride); dst: n = l rows
+// for poly 0 (poly 1 at +poly_stride).
+void launch_rescale_spread(const DevTables& t, const RowMap& dst, const RowMap& top,
+                           uint32_t top_mod, hipStream_t s);
+// Rescale step 2 (evaluation form): out_i = (c_i - T_i) * q_l^-1 mod q_i with
+// T_i the transform of step 1's output; consts[4i+1], [4i+2] = q_l^-1 mod q_i
+// and its shoup.  Both polys.
+void launch_rescale_combine(const DevTables& t, const RowMap& out, const RowMap& c,
+                            const RowMap& T, const uint64_t* consts, hipStream_t s);
+
+}  // namespace csrmf

@@ -1,0 +1,44 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol include/csrmf.h declares, and the binding declares matching calls."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "csrmf.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(csrmf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_calls():
+    names = declared()
+    for n in ["csrmf_create", "csrmf_keygen", "csrmf_hmult", "csrmf_rotate", "csrmf_rescale", "csrmf_destroy"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2509_03024_amd as pk
+    lib = ctypes.CDLL(pk.LIB_PATH)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    import paper_2509_03024_amd as pk
+    missing = [n for n in declared() if n not in pk._SIGS]
+    assert not missing, missing
+
+
+def test_create_rejects_bad_params_without_gpu_work():
+    import paper_2509_03024_amd as pk
+    h = ctypes.c_void_p()
+    bad = pk.params(9, 60, 3, 40, 1, 60, 4)          # N = 2^9 is below the supported range
+    assert pk.lib.csrmf_create(ctypes.byref(bad), bytes(32), ctypes.byref(h)) == -1
+    bad = pk.params(12, 62, 3, 40, 1, 62, 4)         # primes must be below 2^61
+    assert pk.lib.csrmf_create(ctypes.byref(bad), bytes(32), ctypes.byref(h)) == -1
+    assert pk.lib.csrmf_create(None, bytes(32), ctypes.byref(h)) == -1
+    assert pk.lib.csrmf_last_error(None) == b"null context"
