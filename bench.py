@@ -1,0 +1,183 @@
+"""Benchmark: batched CKKS key switching at N = 2^16 on one MI355X.
+
+Workload (the kernel-batch configuration): 64 ciphertexts of uniform random
+residues at N = 2^16 with q_0 (60-bit) + 24 x 40-bit scale primes, 3 x 60-bit
+special primes, dnum = 3.  One step is one pass of the whole batched path:
+  (i)   forward + inverse NTT of all 64 x 2 x 25 limbs,
+  (ii)  64 HMult (tensor, relinearise, rescale) ct_i x ct_{i+1 mod 64},
+  (iii) per ciphertext a rotate-and-sum chain over steps 2^0 .. 2^14 plus a
+        conjugation: 16 key switches per ciphertext, 1024 per step.
+value = key-switch rotations per second over whole steps (1024 * K / time of
+the K timed steps, phases (i) and (ii) included).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_CT = 64
+LOGN = 16
+CHAIN = [1 << a for a in range(15)]
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline():
+    """The oracle (numpy, one host thread) on a bounded sample: one non-hoisted
+    rotation of one 25-limb ciphertext at N = 2^16 (key generation untimed)."""
+    import numpy as np
+    from oracle import ckks, params
+    import workloads
+    prm = params.config_kernel_batch()
+    orc = ckks.Context(prm, workloads.CRYPTO_SEED)
+    t0 = time.perf_counter()
+    orc.keygen(rot_steps=[1])
+    t_key = time.perf_counter() - t0
+    x = workloads.random_residues(prm.q, prm.N, 2, seed=99)
+    ct = ckks.Ciphertext(x[0], x[1], 2.0 ** 40)
+    t0 = time.perf_counter()
+    orc.rotate(ct, 1)
+    t_rot = time.perf_counter() - t0
+    return {"value": 1.0 / t_rot, "unit": "key-switch rotations/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 non-hoisted rotation of one ciphertext, N=2^16, 25 limbs, dnum=3 "
+                      f"({t_rot:.1f} s; key generation {t_key:.1f} s untimed)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    import paper_2509_03024_amd as pk
+    import workloads
+
+    t0 = time.perf_counter()
+    ctx = pk.Context(pk.kernel_batch_params(), workloads.CRYPTO_SEED)
+    ctx.keygen(CHAIN, conj=True)
+    log(f"context + keys {time.perf_counter() - t0:.1f} s")
+    N = ctx.N
+    L = ctx.L
+    t0 = time.perf_counter()
+    cts = []
+    for i in range(N_CT):
+        x = workloads.random_residues(ctx.moduli[: L + 1], N, 2, seed=1000 + i)
+        cts.append(ctx.import_ct(x, L, 2.0 ** 40))
+    rows = np.arange(L + 1, dtype=np.int32)
+    ntt_buf = torch.empty((N_CT * 2 * (L + 1), N), dtype=torch.int64, device="cuda")
+    for i in range(N_CT):
+        x = workloads.random_residues(ctx.moduli[: L + 1], N, 2, seed=1000 + i)
+        ntt_buf[i * 2 * (L + 1):(i + 1) * 2 * (L + 1)] = torch.from_numpy(x.reshape(-1, N).view(np.int64))
+    torch.cuda.synchronize()
+    log(f"inputs resident in HBM {time.perf_counter() - t0:.1f} s")
+
+    phase = {"ntt_intt": 0.0, "hmult": 0.0, "rotations": 0.0}
+
+    def step(timed):
+        t = time.perf_counter()
+        ctx.ntt_rows(ntt_buf.data_ptr(), ntt_buf.shape[0], rows, inverse=False)
+        ctx.ntt_rows(ntt_buf.data_ptr(), ntt_buf.shape[0], rows, inverse=True)
+        ctx.sync()
+        t1 = time.perf_counter()
+        prods = ctx.hmult_batch(cts, cts[1:] + cts[:1])
+        ctx.sync()
+        t2 = time.perf_counter()
+        for p in prods:
+            ctx.free(p)
+        cur = list(cts)
+        owned = []
+        for r in CHAIN:
+            rot = ctx.rotate_batch(cur, r)
+            nxt = [ctx.add(a, b) for a, b in zip(cur, rot)]
+            for h in rot + owned:
+                ctx.free(h)
+            cur = owned = nxt
+        conj = ctx.conjugate_batch(cur)
+        for h in conj + owned:
+            ctx.free(h)
+        ctx.sync()
+        t3 = time.perf_counter()
+        if timed:
+            phase["ntt_intt"] += t1 - t
+            phase["hmult"] += t2 - t1
+            phase["rotations"] += t3 - t2
+
+    for w in range(args.warmup):
+        step(False)
+        log(f"warmup step {w} done")
+    torch.cuda.synchronize()
+    ctx.sync()
+    pk.profile_enable(True)
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(True)
+        log(f"timed step {s} done")
+    ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = pk.profile_report()
+    pk.profile_enable(False)
+
+    n_rot = N_CT * (len(CHAIN) + 1)
+    value = n_rot * args.steps / elapsed
+    dom = max(prof.items(), key=lambda kv: kv[1][1])
+    name, (launches, total_ms, total_bytes) = dom
+    avg_ms = total_ms / launches
+    achieved = (total_bytes / launches) / (avg_ms * 1e-3) / 1e9
+    kernel_table = {k: {"launches": v[0], "total_ms": round(v[1], 3), "avg_us": round(1e3 * v[1] / v[0], 2),
+                        "alg_GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+                    for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    out = {
+        "metric": "key-switch rotations/s at N=2^16",
+        "value": round(value, 2),
+        "unit": "rotations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "kernel batch: 64 ciphertexts, N=2^16, q0 60-bit + 24 x 40-bit, "
+                               "3 x 60-bit special primes, dnum=3; per step NTT+INTT of 3200 limbs, "
+                               "64 HMult, 64 x 16 rotate-and-sum key switches",
+                   "ciphertexts": N_CT, "log2N": LOGN, "limbs": L + 1, "special": ctx.alpha, "dnum": 3},
+        "phase_ms_per_step": {k: round(1e3 * v / args.steps, 3) for k, v in phase.items()},
+        "rotation_phase_rotations_per_s": round(n_rot * args.steps / phase["rotations"], 2),
+        "roofline": {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": round(1e3 * avg_ms, 2)},
+        "kernels": kernel_table,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -65,7 +65,7 @@ typedef struct csrmf_ctx csrmf_ctx;
  * primes after it; the scale_bits list gives q_1 > q_2 > ... > q_L.
  * Key-switching digits: D_j = [j*g, min((j+1)*g, L+1)), g = ceil((L+1)/dnum). */
 typedef struct csrmf_params {
-    int32_t log2N;          /* ring degree N = 2^log2N, 10..16                  */
+    int32_t log2N;          /* ring degree N = 2^log2N, 12..16                  */
     int32_t base_bits;      /* bits of q_0 (<= 61)                              */
     int32_t n_scale_primes; /* L, number of scale primes                        */
     int32_t scale_bits;     /* bits of q_1..q_L (<= 61)                         */
@@ -217,6 +217,19 @@ int csrmf_conjugate_batch(csrmf_ctx* ctx, const uint64_t* a, int32_t n, uint64_t
  * prime.  Inputs must be reduced.  limb_idx is a host array. */
 int csrmf_ntt_rows(csrmf_ctx* ctx, uint64_t* data, int32_t n_rows, const int32_t* limb_idx,
                    int32_t n_idx, int32_t inverse);
+
+/* ------------------------------------------------------------------------ */
+/* Per-kernel timing (benchmark hook; process-wide).                         */
+/* ------------------------------------------------------------------------ */
+
+/* enable != 0: clear the records and bracket every later kernel launch of the
+ * library with two HIP events on the launch stream; 0: stop recording. */
+int csrmf_profile_enable(int32_t enable);
+
+/* Write {"kernel": [launches, total_ms], ...} for the recorded launches into
+ * buf (NUL-terminated, truncated to cap bytes).  Synchronises on the recorded
+ * events.  Returns the length of the full report. */
+int csrmf_profile_report(char* buf, int32_t cap);
 
 #ifdef __cplusplus
 }

@@ -82,6 +82,8 @@ _SIGS = {
     "csrmf_rotate_batch": [_p, _u64p, ctypes.c_int32, ctypes.c_int32, _u64p],
     "csrmf_conjugate_batch": [_p, _u64p, ctypes.c_int32, _u64p],
     "csrmf_ntt_rows": [_p, _p, ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_int32],
+    "csrmf_profile_enable": [ctypes.c_int32],
+    "csrmf_profile_report": [ctypes.c_char_p, ctypes.c_int32],
 }
 
 for _name, _args in _SIGS.items():
@@ -291,6 +293,19 @@ class Context:
         """In-place (I)NTT of rows at a device pointer (e.g. a torch tensor's data_ptr())."""
         idx = np.asarray(limb_idx, np.int32)
         self._chk(lib.csrmf_ntt_rows(self.h, _p(dev_ptr), n_rows, _ptr(idx, ctypes.c_int32), len(idx), int(inverse)))
+
+
+def profile_enable(on=True):
+    lib.csrmf_profile_enable(int(bool(on)))
+
+
+def profile_report():
+    """{kernel: (launches, total_ms, algorithmic_bytes)} recorded since profile_enable()."""
+    import json
+    n = lib.csrmf_profile_report(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib.csrmf_profile_report(buf, n + 1)
+    return {k: (int(v[0]), float(v[1]), float(v[2])) for k, v in json.loads(buf.value.decode()).items()}
 
 
 def tiny_params(k=4, lr=0.01, lam=0.02, rule=1):

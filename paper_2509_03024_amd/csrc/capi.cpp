@@ -1,9 +1,11 @@
 // extern "C" entry points of libcsrmf (declared in include/csrmf.h).
+#include <algorithm>
 #include <cstring>
 #include <new>
 
 #include "context.h"
 #include "host_math.h"
+#include "prof.h"
 
 using csrmf::Context;
 using csrmf::Ct;
@@ -362,6 +364,21 @@ int csrmf_ntt_rows(csrmf_ctx* cx, uint64_t* data, int32_t n_rows, const int32_t*
     NEED(data && idx && n_rows > 0, "arguments");
     c->ntt_rows(data, n_rows, idx, n_idx, inverse != 0);
     API_END(c)
+}
+
+int csrmf_profile_enable(int32_t enable) {
+    csrmf::prof_enable(enable != 0);
+    return CSRMF_OK;
+}
+
+int csrmf_profile_report(char* buf, int32_t cap) {
+    const std::string s = csrmf::prof_report_json();
+    if (buf && cap > 0) {
+        const size_t n = std::min<size_t>(s.size(), (size_t)cap - 1);
+        std::memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return (int)s.size();
 }
 
 }  // extern "C"

@@ -82,7 +82,7 @@ Context::~Context() {
 void Context::init(const csrmf_params& p, const uint8_t s[32]) {
     prm = p;
     std::memcpy(seed, s, 32);
-    if (p.log2N < 10 || p.log2N > 16) throw Error(CSRMF_E_INVAL, "log2N must be in [10, 16]");
+    if (p.log2N < 12 || p.log2N > 16) throw Error(CSRMF_E_INVAL, "log2N must be in [12, 16]");
     if (p.n_scale_primes < 0 || p.n_scale_primes > 40 || p.n_special < 1 || p.n_special > 8 || p.dnum < 1)
         throw Error(CSRMF_E_INVAL, "bad prime counts");
     if (p.base_bits > 61 || p.scale_bits > 61 || p.special_bits > 61)
@@ -140,9 +140,21 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
             x = mm(x, m.psi, q);
             y = mm(y, psi_inv, q);
         }
-        for (uint64_t k = 0; k < N; ++k) {
-            T[N + k] = shoup_pre(T[k], q);
-            T[3 * N + k] = shoup_pre(T[2 * N + k], q);
+        if (q < kFp64PrimeBound) {
+            // exact FP64 transform: w and fl(w/q) as doubles
+            for (uint64_t k = 0; k < N; ++k) {
+                for (int part = 0; part < 2; ++part) {
+                    const double w = (double)T[2 * part * N + k];
+                    const double wq = w / (double)q;
+                    std::memcpy(&T[2 * part * N + k], &w, 8);
+                    std::memcpy(&T[(2 * part + 1) * N + k], &wq, 8);
+                }
+            }
+        } else {
+            for (uint64_t k = 0; k < N; ++k) {
+                T[N + k] = shoup_pre(T[k], q);
+                T[3 * N + k] = shoup_pre(T[2 * N + k], q);
+            }
         }
     }
     d_mods = (Modulus*)pool.get(sizeof(Modulus) * nm);
@@ -258,8 +270,7 @@ Ct& Context::get(uint64_t h) {
 void Context::free_ct(uint64_t h) {
     auto it = cts.find(h);
     if (it == cts.end()) throw Error(CSRMF_E_INVAL, "unknown ciphertext handle");
-    CSRMF_HIP(hipStreamSynchronize(stream));
-    pool.put(it->second.d);
+    pool.put(it->second.d);   // later users of the block are ordered after this on the stream
     cts.erase(it);
 }
 

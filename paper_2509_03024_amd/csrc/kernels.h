@@ -28,12 +28,17 @@ struct RowMap {
     int rows() const { return n * batch; }
 };
 
+// Primes below this bound use the exact FP64 transform; their twiddle tables
+// hold doubles: w and fl(w/q) in place of w and shoup(w).
+constexpr uint64_t kFp64PrimeBound = 1ull << 44;
+
 // Device-resident tables of the modulus chain.
 struct DevTables {
     int logN;
     int L1;                      // stages done by the column pass
     const Modulus* mods;         // [n_mod]
     const uint64_t* tw;          // [n_mod][4][N]: psi^brev, shoup, psi^-brev, shoup
+                                 // (FP64 primes: as doubles, w then fl(w/q))
 };
 
 void launch_ntt(const DevTables& t, const RowMap& rows, bool inverse, hipStream_t s);

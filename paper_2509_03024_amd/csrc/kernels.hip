@@ -7,15 +7,16 @@
 // batch (consecutive blocks share a modulus and its tables in L2).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
+#include "prof.h"
 
 namespace csrmf {
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kNttTile = 4096;    // residues staged in LDS per block (32 KiB)
-constexpr int kColTile = 16;      // columns per block in the column pass (128-byte runs)
 constexpr int kEwPerThread = 2;
 
 __device__ __forceinline__ uint64_t* map_row(const RowMap& m, int b, int k, int logN, int& mod) {
@@ -45,114 +46,283 @@ __device__ __forceinline__ uint32_t galois_perm(uint32_t k, uint32_t g, int logN
 
 // ------------------------------------------------------------------ NTT
 // Forward negacyclic transform (Cooley-Tukey, psi folded into the twiddles,
-// bit-reversed output).  Stage s (0-based) pairs j and j + N/2^(s+1) inside
-// block i = j / (N/2^s) with twiddle psi^brev(2^s + i).  Pass A (columns)
-// runs stages 0..L1-1 on the 2^L1 residues sharing j mod 2^L2; pass B (rows)
-// runs stages L1..logN-1 on contiguous runs of 2^L2 residues.
+// bit-reversed output).  Stage s (0-based) pairs positions j and j + N/2^(s+1)
+// inside block i = j / (N/2^s) with twiddle psi^brev(2^s + i); the inverse
+// runs the Gentleman-Sande butterflies in reverse with psi^-brev(...) and a
+// final N^-1.  Pass A ("columns") runs stages 0..L1-1 on the 2^L1 residues
+// sharing j mod 2^L2; pass B ("rows") runs stages L1..logN-1 on contiguous
+// runs of 2^L2 residues.
+//
+// Inside a pass each sub-transform of S = 2^SL residues is held by S/8
+// threads with 8 residues each.  Stages are grouped in rounds of three
+// (radix-8 in registers); the first round takes SL mod 3 stages (or three),
+// so every later round is a full radix-8.  Rounds exchange residues through
+// LDS.  Residues stay lazily reduced (Harvey): forward values in [0, 4q),
+// inverse values in [0, 2q); the pass that ends the transform reduces fully.
 
-__global__ void __launch_bounds__(kThreads) k_ntt_cols(DevTables t, RowMap m, int inverse) {
-    __shared__ uint64_t lds[kNttTile];
-    const int logN = t.logN, L1 = t.L1, L2 = logN - L1;
-    const int R = 1 << L1, C = kColTile;
-    const int chunks = (1 << L2) / C;
-    int b, k, chunk, mod;
-    block_coords(blockIdx.x, chunks, m.batch, b, k, chunk);
-    uint64_t* data = map_row(m, b, k, logN, mod);
-    const Modulus md = t.mods[mod];
-    const uint64_t q = md.q;
-    const size_t N = (size_t)1 << logN;
-    const uint64_t* W = t.tw + (size_t)mod * 4 * N + (inverse ? 2 * N : 0);
-    const uint64_t* Wp = W + N;
-    const int c0 = chunk * C;
-    for (int e = threadIdx.x; e < C * R; e += kThreads) {
-        const int r = e / C, c = e % C;
-        lds[e] = data[((size_t)r << L2) + c0 + c];
-    }
-    __syncthreads();
-    if (!inverse) {
-        for (int s = 0; s < L1; ++s) {
-            const int tl = R >> (s + 1);
-            const int m0 = 1 << s;
-            for (int bf = threadIdx.x; bf < C * R / 2; bf += kThreads) {
-                const int c = bf % C, bb = bf / C;
-                const int i = bb / tl, jj = bb % tl;
-                const int r = 2 * i * tl + jj;
-                const uint64_t x = lds[r * C + c];
-                const uint64_t v = mul_shoup(lds[(r + tl) * C + c], W[m0 + i], Wp[m0 + i], q);
-                lds[r * C + c] = add_mod(x, v, q);
-                lds[(r + tl) * C + c] = sub_mod(x, v, q);
+constexpr int kNttThreads = 256;
+constexpr int kNttPerThread = 8;
+constexpr int kNttBlockElems = kNttThreads * kNttPerThread;   // 2048 residues, 16 KiB of LDS
+
+__device__ __forceinline__ void bfly_fwd(uint64_t& x, uint64_t& y, uint64_t w, uint64_t wp, uint64_t q, uint64_t q2) {
+    uint64_t a = x >= q2 ? x - q2 : x;
+    const uint64_t v = y * w - mulhi64(y, wp) * q;   // [0, 2q)
+    x = a + v;
+    y = a - v + q2;
+}
+
+__device__ __forceinline__ void bfly_inv(uint64_t& x, uint64_t& y, uint64_t w, uint64_t wp, uint64_t q, uint64_t q2) {
+    uint64_t s = x + y;
+    s = s >= q2 ? s - q2 : s;
+    const uint64_t d = x - y + q2;
+    y = d * w - mulhi64(d, wp) * q;                  // [0, 2q)
+    x = s;
+}
+
+// One round of NS (<= 3) stages on the 8 registers of a thread.  The thread's
+// residues sit at positions j0 + kk*2^ld; round stage s pairs kk and kk + (4>>s)
+// and needs 2^s distinct twiddles: index (c0 << (a+s)) + (blk << s) + u,
+// u = kk >> (3-s), with blk = j0 >> (ld+3) (c0 = 1 in the column pass,
+// 2^L1 + run index in the row pass, a = first local stage of the round).
+template <typename T> __device__ __forceinline__ T load_tw(const uint64_t* p);
+template <> __device__ __forceinline__ uint64_t load_tw<uint64_t>(const uint64_t* p) { return *p; }
+template <> __device__ __forceinline__ double load_tw<double>(const uint64_t* p) { return __longlong_as_double((long long)*p); }
+
+// Exact FP64 arithmetic for primes q < 2^44 (the 40-bit scale primes).
+// Residues are integers held in doubles, kept centred and unreduced.  For
+// |y| < 2^48 and an integer twiddle w < q with wq = fl(w/q):
+//   h = fl(y*w), l = fma(y, w, -h) = y*w - h exactly (integers),
+//   t = rint(y*wq) is within 0.5 + 2^-4 of y*w/q,
+//   r = fma(-t, q, h) + l = y*w - t*q exactly, so r = y*w (mod q), |r| <= 0.57 q.
+struct ModF { double q, qinv; };
+
+__device__ __forceinline__ double fmul_centred(double y, double w, double wq, double q) {
+    const double h = y * w;
+    const double l = fma(y, w, -h);
+    const double t = rint(y * wq);
+    return fma(-t, q, h) + l;
+}
+
+__device__ __forceinline__ void bfly_fwd(double& x, double& y, double w, double wq, const ModF& m) {
+    const double v = fmul_centred(y, w, wq, m.q);   // inputs stay below ~10 q over 16 stages
+    const double a = x;
+    x = a + v;
+    y = a - v;
+}
+
+__device__ __forceinline__ void bfly_inv(double& x, double& y, double w, double wq, const ModF& m) {
+    const double s = x + y;
+    const double d = x - y;
+    y = fmul_centred(d, w, wq, m.q);
+    x = fma(-rint(s * m.qinv), m.q, s);              // centred reduction of the sum
+}
+
+__device__ __forceinline__ void bfly_fwd(uint64_t& x, uint64_t& y, uint64_t w, uint64_t wp, const Modulus& m) {
+    bfly_fwd(x, y, w, wp, m.q, 2 * m.q);
+}
+
+__device__ __forceinline__ void bfly_inv(uint64_t& x, uint64_t& y, uint64_t w, uint64_t wp, const Modulus& m) {
+    bfly_inv(x, y, w, wp, m.q, 2 * m.q);
+}
+
+__device__ __forceinline__ double as_f64(uint64_t v) { return __longlong_as_double((long long)v); }
+__device__ __forceinline__ uint64_t f64_bits(double v) { return (uint64_t)__double_as_longlong(v); }
+
+// centred double (|v| < 2^50) -> canonical residue in [0, q)
+__device__ __forceinline__ uint64_t f64_canon(double v, const ModF& m) {
+    double r = fma(-floor(v * m.qinv), m.q, v);
+    r = r < 0.0 ? r + m.q : r;
+    r = r >= m.q ? r - m.q : r;
+    return (uint64_t)r;
+}
+
+template <int NS, bool kInverse, typename T, typename M>
+__device__ __forceinline__ void ntt_round(T (&x)[8], const uint64_t* W, const uint64_t* Wp, int c0, int a,
+                                          int blk, const M& md) {
+    if (!kInverse) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int h = 4 >> s;
+            const int wb = (c0 << (a + s)) + (blk << s);
+            T w[4], wp[4];
+#pragma unroll
+            for (int u = 0; u < (1 << s); ++u) { w[u] = load_tw<T>(W + wb + u); wp[u] = load_tw<T>(Wp + wb + u); }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                if (kk & h) continue;
+                const int u = kk >> (3 - s);
+                bfly_fwd(x[kk], x[kk + h], w[u], wp[u], md);
             }
-            __syncthreads();
-        }
-        for (int e = threadIdx.x; e < C * R; e += kThreads) {
-            const int r = e / C, c = e % C;
-            data[((size_t)r << L2) + c0 + c] = lds[e];
         }
     } else {
-        for (int s = L1 - 1; s >= 0; --s) {
-            const int tl = R >> (s + 1);
-            const int m0 = 1 << s;
-            for (int bf = threadIdx.x; bf < C * R / 2; bf += kThreads) {
-                const int c = bf % C, bb = bf / C;
-                const int i = bb / tl, jj = bb % tl;
-                const int r = 2 * i * tl + jj;
-                const uint64_t x = lds[r * C + c];
-                const uint64_t y = lds[(r + tl) * C + c];
-                lds[r * C + c] = add_mod(x, y, q);
-                lds[(r + tl) * C + c] = mul_shoup(sub_mod(x, y, q), W[m0 + i], Wp[m0 + i], q);
+#pragma unroll
+        for (int s = NS - 1; s >= 0; --s) {
+            const int h = 4 >> s;
+            const int wb = (c0 << (a + s)) + (blk << s);
+            T w[4], wp[4];
+#pragma unroll
+            for (int u = 0; u < (1 << s); ++u) { w[u] = load_tw<T>(W + wb + u); wp[u] = load_tw<T>(Wp + wb + u); }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                if (kk & h) continue;
+                const int u = kk >> (3 - s);
+                bfly_inv(x[kk], x[kk + h], w[u], wp[u], md);
             }
-            __syncthreads();
-        }
-        for (int e = threadIdx.x; e < C * R; e += kThreads) {
-            const int r = e / C, c = e % C;
-            data[((size_t)r << L2) + c0 + c] = mul_shoup(lds[e], md.n_inv, md.n_inv_shoup, q);
         }
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_ntt_rows(DevTables t, RowMap m, int inverse) {
-    __shared__ uint64_t lds[kNttTile];
+// Element access of the two representations.  The integer path keeps
+// canonical uint64 residues in memory.  The FP64 path reads canonical
+// residues in the first pass of a transform, keeps the centred doubles (as
+// raw bits) between its two passes, and writes canonical residues at the end.
+template <typename T, typename M> struct NttIo;
+template <> struct NttIo<uint64_t, Modulus> {
+    static __device__ __forceinline__ uint64_t in(uint64_t v, bool, const Modulus&) { return v; }
+    static __device__ __forceinline__ uint64_t out_mid(uint64_t v, const Modulus&) { return v; }
+    static __device__ __forceinline__ uint64_t out_fwd_end(uint64_t v, const Modulus& m) {
+        const uint64_t q2 = 2 * m.q;
+        v = v >= q2 ? v - q2 : v;
+        return v >= m.q ? v - m.q : v;
+    }
+    static __device__ __forceinline__ uint64_t out_inv_end(uint64_t v, const Modulus& m) {
+        return mul_shoup(v, m.n_inv, m.n_inv_shoup, m.q);
+    }
+};
+template <> struct NttIo<double, ModF> {
+    static __device__ __forceinline__ double in(uint64_t v, bool canonical, const ModF&) {
+        return canonical ? (double)v : as_f64(v);
+    }
+    static __device__ __forceinline__ uint64_t out_mid(double v, const ModF&) { return f64_bits(v); }
+    static __device__ __forceinline__ uint64_t out_fwd_end(double v, const ModF& m) { return f64_canon(v, m); }
+    static __device__ __forceinline__ uint64_t out_inv_end(double v, const ModF& m, double ninv, double ninvq) {
+        return f64_canon(fmul_centred(v, ninv, ninvq, m.q), m);
+    }
+};
+
+template <int SL, bool kCols, bool kInverse, typename T, typename M>
+__device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data, const uint64_t* W, const uint64_t* Wp,
+                                              const M& md, const Modulus& mi, int L1, int L2, int chunk, int tid) {
+    T* lds = reinterpret_cast<T*>(lds_raw);
+    constexpr int TPS_L = SL - 3;
+    constexpr int SPB_L = 11 - SL;
+    constexpr int R0 = (SL % 3) ? (SL % 3) : 3;
+    constexpr bool kFirstPass = kCols != kInverse;   // forward starts with columns, inverse with rows
+    int sub, tt;
+    if (kCols) { sub = tid & ((1 << SPB_L) - 1); tt = tid >> SPB_L; }
+    else       { sub = tid >> TPS_L;              tt = tid & ((1 << TPS_L) - 1); }
+    const size_t col0 = kCols ? ((size_t)chunk << SPB_L) + sub : 0;
+    const size_t run0 = kCols ? 0 : ((size_t)chunk << 11) + ((size_t)sub << SL);
+    auto gaddr = [&](int p) -> size_t { return kCols ? col0 + ((size_t)p << L2) : run0 + p; };
+    auto laddr = [&](int p) -> int { return kCols ? (p << SPB_L) + sub : (sub << SL) + p; };
+    const int c0 = kCols ? 1 : (1 << L1) + (chunk << SPB_L) + sub;
+    typedef NttIo<T, M> Io;
+
+    T x[8];
+    int j0, ld;
+    if (!kInverse) {
+        ld = SL - 3;
+        j0 = tt;
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(data[gaddr(tt + (kk << ld))], kFirstPass, md);
+        ntt_round<R0, false>(x, W, Wp, c0, 0, 0, md);
+#pragma unroll
+        for (int a = R0; a < SL; a += 3) {
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) lds[laddr(j0 + (kk << ld))] = x[kk];
+            __syncthreads();
+            ld = SL - a - 3;
+            j0 = ((tt >> ld) << (ld + 3)) | (tt & ((1 << ld) - 1));
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) x[kk] = lds[laddr(j0 + (kk << ld))];
+            __syncthreads();
+            ntt_round<3, false>(x, W, Wp, c0, a, tt >> ld, md);
+        }
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+            data[gaddr(j0 + (kk << ld))] = kCols ? Io::out_mid(x[kk], md) : Io::out_fwd_end(x[kk], md);
+    } else {
+        ld = 0;
+        j0 = tt << 3;
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(data[gaddr(j0 + kk)], kFirstPass, md);
+        ntt_round<3, true>(x, W, Wp, c0, SL - 3, tt, md);
+#pragma unroll
+        for (int a = SL - 6; a >= R0; a -= 3) {
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) lds[laddr(j0 + (kk << ld))] = x[kk];
+            __syncthreads();
+            ld = SL - a - 3;
+            j0 = ((tt >> ld) << (ld + 3)) | (tt & ((1 << ld) - 1));
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) x[kk] = lds[laddr(j0 + (kk << ld))];
+            __syncthreads();
+            ntt_round<3, true>(x, W, Wp, c0, a, tt >> ld, md);
+        }
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) lds[laddr(j0 + (kk << ld))] = x[kk];
+        __syncthreads();
+        ld = SL - 3;
+        j0 = tt;
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) x[kk] = lds[laddr(j0 + (kk << ld))];
+        ntt_round<R0, true>(x, W, Wp, c0, 0, 0, md);
+        if (kCols) {
+            if constexpr (std::is_same<T, double>::value) {
+                const double ninv = (double)mi.n_inv, ninvq = ninv / (double)mi.q;
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) data[gaddr(j0 + (kk << ld))] = Io::out_inv_end(x[kk], md, ninv, ninvq);
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) data[gaddr(j0 + (kk << ld))] = NttIo<uint64_t, Modulus>::out_inv_end((uint64_t)x[kk], mi);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) data[gaddr(j0 + (kk << ld))] = Io::out_mid(x[kk], md);
+        }
+    }
+}
+
+template <int SL, bool kCols, bool kInverse>
+__global__ void __launch_bounds__(kNttThreads) k_ntt_pass(DevTables t, RowMap m) {
+    __shared__ uint64_t lds[kNttBlockElems];
+    constexpr int SPB_L = 11 - SL;
     const int logN = t.logN, L1 = t.L1, L2 = logN - L1;
     const size_t N = (size_t)1 << logN;
-    const int BL = 1 << L2;
-    const int TILE = (int)(N < (size_t)kNttTile ? N : (size_t)kNttTile);
-    const int chunks = (int)(N / TILE);
-    const int bpt = TILE / BL;           // runs per tile
+    const int chunks = kCols ? ((1 << L2) >> SPB_L) : (int)(N >> 11);
     int b, k, chunk, mod;
     block_coords(blockIdx.x, chunks, m.batch, b, k, chunk);
-    uint64_t* data = map_row(m, b, k, logN, mod) + (size_t)chunk * TILE;
-    const uint64_t q = t.mods[mod].q;
-    const uint64_t* W = t.tw + (size_t)mod * 4 * N + (inverse ? 2 * N : 0);
+    uint64_t* data = map_row(m, b, k, logN, mod);
+    const Modulus md = t.mods[mod];
+    const uint64_t* W = t.tw + (size_t)mod * 4 * N + (kInverse ? 2 * N : 0);
     const uint64_t* Wp = W + N;
-    for (int e = threadIdx.x; e < TILE; e += kThreads) lds[e] = data[e];
-    __syncthreads();
-    const int half_mask = (BL >> 1) - 1;
-    for (int st = 0; st < L2; ++st) {
-        const int s2 = inverse ? (L2 - 1 - st) : st;
-        const int s = L1 + s2;
-        const int m0 = 1 << s;
-        const int tt = BL >> (s2 + 1);
-        for (int bf = threadIdx.x; bf < TILE / 2; bf += kThreads) {
-            const int bl = bf >> (L2 - 1);
-            const int kk = bf & half_mask;
-            const int ip = kk / tt, jj = kk % tt;
-            const int jl = 2 * ip * tt + jj;
-            const int gb = chunk * bpt + bl;
-            const int i = gb * (BL / (2 * tt)) + ip;
-            const int a0 = bl * BL + jl;
-            const uint64_t x = lds[a0], y = lds[a0 + tt];
-            if (!inverse) {
-                const uint64_t v = mul_shoup(y, W[m0 + i], Wp[m0 + i], q);
-                lds[a0] = add_mod(x, v, q);
-                lds[a0 + tt] = sub_mod(x, v, q);
-            } else {
-                lds[a0] = add_mod(x, y, q);
-                lds[a0 + tt] = mul_shoup(sub_mod(x, y, q), W[m0 + i], Wp[m0 + i], q);
-            }
-        }
-        __syncthreads();
+    if (md.q < kFp64PrimeBound) {
+        const ModF mf{(double)md.q, 1.0 / (double)md.q};
+        ntt_pass_body<SL, kCols, kInverse, double, ModF>(lds, data, W, Wp, mf, md, L1, L2, chunk, threadIdx.x);
+    } else {
+        ntt_pass_body<SL, kCols, kInverse, uint64_t, Modulus>(lds, data, W, Wp, md, md, L1, L2, chunk, threadIdx.x);
     }
-    for (int e = threadIdx.x; e < TILE; e += kThreads) data[e] = lds[e];
+}
+
+template <int SL>
+void launch_ntt_pass(const DevTables& t, const RowMap& m, bool cols, bool inverse, int blocks, hipStream_t s) {
+    if (cols) {
+        if (inverse) hipLaunchKernelGGL((k_ntt_pass<SL, true, true>), dim3(blocks), dim3(kNttThreads), 0, s, t, m);
+        else hipLaunchKernelGGL((k_ntt_pass<SL, true, false>), dim3(blocks), dim3(kNttThreads), 0, s, t, m);
+    } else {
+        if (inverse) hipLaunchKernelGGL((k_ntt_pass<SL, false, true>), dim3(blocks), dim3(kNttThreads), 0, s, t, m);
+        else hipLaunchKernelGGL((k_ntt_pass<SL, false, false>), dim3(blocks), dim3(kNttThreads), 0, s, t, m);
+    }
+}
+
+void dispatch_ntt_pass(const DevTables& t, const RowMap& m, bool cols, bool inverse, int blocks, hipStream_t s) {
+    const int SL = cols ? t.L1 : t.logN - t.L1;
+    switch (SL) {
+        case 6: launch_ntt_pass<6>(t, m, cols, inverse, blocks, s); break;
+        case 7: launch_ntt_pass<7>(t, m, cols, inverse, blocks, s); break;
+        case 8: launch_ntt_pass<8>(t, m, cols, inverse, blocks, s); break;
+        default: break;   // log2N is validated to [12, 16] at context creation
+    }
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -365,6 +535,9 @@ __global__ void __launch_bounds__(kThreads) k_rescale_combine(DevTables t, RowMa
     }
 }
 
+// bytes of `rows` polynomial rows (algorithmic traffic accounting for the profiler)
+#define NB(rows) ((double)(rows) * (double)(1 << t.logN) * 8.0)
+
 inline int ew_blocks(const DevTables& t, const RowMap& m) {
     return m.rows() * ((1 << t.logN) / (kThreads * kEwPerThread));
 }
@@ -374,79 +547,77 @@ inline int ew_blocks(const DevTables& t, const RowMap& m) {
 // ------------------------------------------------------------------ launchers
 void launch_ntt(const DevTables& t, const RowMap& m, bool inverse, hipStream_t s) {
     if (m.rows() == 0) return;
-    const int L2 = t.logN - t.L1;
-    const int col_blocks = m.rows() * ((1 << L2) / kColTile);
-    const int tile = (1 << t.logN) < kNttTile ? (1 << t.logN) : kNttTile;
-    const int row_blocks = m.rows() * ((1 << t.logN) / tile);
+    const int blocks = m.rows() * (int)(((size_t)1 << t.logN) / kNttBlockElems);
+    const double bytes = NB(m.rows()) * 2;
     if (!inverse) {
-        hipLaunchKernelGGL(k_ntt_cols, dim3(col_blocks), dim3(kThreads), 0, s, t, m, 0);
-        hipLaunchKernelGGL(k_ntt_rows, dim3(row_blocks), dim3(kThreads), 0, s, t, m, 0);
+        { ProfScope ps_("k_ntt_cols", s, bytes); dispatch_ntt_pass(t, m, true, false, blocks, s); }
+        { ProfScope ps_("k_ntt_rows", s, bytes); dispatch_ntt_pass(t, m, false, false, blocks, s); }
     } else {
-        hipLaunchKernelGGL(k_ntt_rows, dim3(row_blocks), dim3(kThreads), 0, s, t, m, 1);
-        hipLaunchKernelGGL(k_ntt_cols, dim3(col_blocks), dim3(kThreads), 0, s, t, m, 1);
+        { ProfScope ps_("k_ntt_rows", s, bytes); dispatch_ntt_pass(t, m, false, true, blocks, s); }
+        { ProfScope ps_("k_ntt_cols", s, bytes); dispatch_ntt_pass(t, m, true, true, blocks, s); }
     }
 }
 
 void launch_expand_signed(const DevTables& t, const RowMap& out, const int64_t* src, int n_src, int64_t sbs,
                           hipStream_t s) {
     if (!out.rows()) return;
-    hipLaunchKernelGGL(k_expand_signed, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, src, n_src, sbs);
+    { ProfScope ps_("k_expand_signed", s, NB(out.rows()) * 2); hipLaunchKernelGGL(k_expand_signed, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, src, n_src, sbs); }
 }
 
 void launch_ew(const DevTables& t, EwOp op, const RowMap& out, const RowMap& a, const RowMap& b, hipStream_t s) {
     if (!out.rows()) return;
-    hipLaunchKernelGGL(k_ew, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, (int)op, out, a, b);
+    { ProfScope ps_("k_ew", s, NB(out.rows()) * 3); hipLaunchKernelGGL(k_ew, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, (int)op, out, a, b); }
 }
 
 void launch_mul_mont(const DevTables& t, const RowMap& out, const RowMap& a, const RowMap& b, bool acc, hipStream_t s) {
     if (!out.rows()) return;
-    hipLaunchKernelGGL(k_mul_mont, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, a, b, acc ? 1 : 0);
+    { ProfScope ps_("k_mul_mont", s, NB(out.rows()) * 3); hipLaunchKernelGGL(k_mul_mont, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, a, b, acc ? 1 : 0); }
 }
 
 void launch_mul_const(const DevTables& t, const RowMap& out, const RowMap& a, const uint64_t* consts, bool both, hipStream_t s) {
     if (!out.rows()) return;
-    hipLaunchKernelGGL(k_mul_const, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, a, consts, both ? 1 : 0);
+    { ProfScope ps_("k_mul_const", s, NB(out.rows()) * (both ? 4 : 2)); hipLaunchKernelGGL(k_mul_const, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, a, consts, both ? 1 : 0); }
 }
 
 void launch_tensor(const DevTables& t, const RowMap& d, const RowMap& a, const RowMap& b, hipStream_t s) {
     if (!d.rows()) return;
-    hipLaunchKernelGGL(k_tensor, dim3(ew_blocks(t, d)), dim3(kThreads), 0, s, t, d, a, b);
+    { ProfScope ps_("k_tensor", s, NB(d.rows()) * 7); hipLaunchKernelGGL(k_tensor, dim3(ew_blocks(t, d)), dim3(kThreads), 0, s, t, d, a, b); }
 }
 
 void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, const RowMap& in, bool both, hipStream_t s) {
     if (!out.rows()) return;
-    hipLaunchKernelGGL(k_automorphism, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, g, out, in, both ? 1 : 0);
+    { ProfScope ps_("k_automorphism", s, NB(out.rows()) * (both ? 4 : 2)); hipLaunchKernelGGL(k_automorphism, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, g, out, in, both ? 1 : 0); }
 }
 
 void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src, const uint64_t* yc,
                           const uint64_t* cc, hipStream_t s) {
     if (!dst.n || !src.n) return;
     const int blocks = dst.batch * ((1 << t.logN) / kThreads);
-    hipLaunchKernelGGL(k_basis_convert, dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc);
+    { ProfScope ps_("k_basis_convert", s, NB(dst.batch) * (src.n + dst.n)); hipLaunchKernelGGL(k_basis_convert, dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc); }
 }
 
 void launch_ks_inner(const DevTables& t, const RowMap& u, const KsArgs& a, uint32_t g, hipStream_t s) {
     if (!u.rows()) return;
-    hipLaunchKernelGGL(k_ks_inner, dim3(ew_blocks(t, u)), dim3(kThreads), 0, s, t, u, a, g);
+    { ProfScope ps_("k_ks_inner", s, NB(u.rows()) * (a.n_digits + 2) + NB(u.n) * 2 * a.n_digits); hipLaunchKernelGGL(k_ks_inner, dim3(ew_blocks(t, u)), dim3(kThreads), 0, s, t, u, a, g); }
 }
 
 void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap& u, const RowMap& conv,
                             const RowMap& addend, uint32_t g_add, bool addend_both, const uint64_t* consts,
                             hipStream_t s) {
     if (!out.rows()) return;
-    hipLaunchKernelGGL(k_moddown_combine, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, u, conv,
-                       addend, g_add, addend_both ? 1 : 0, consts);
+    { ProfScope ps_("k_moddown_combine", s, NB(out.rows()) * (6 + (addend.n ? (addend_both ? 2 : 1) : 0))); hipLaunchKernelGGL(k_moddown_combine, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, u, conv,
+                       addend, g_add, addend_both ? 1 : 0, consts); }
 }
 
 void launch_rescale_spread(const DevTables& t, const RowMap& dst, const RowMap& top, uint32_t top_mod, hipStream_t s) {
     if (!dst.rows()) return;
-    hipLaunchKernelGGL(k_rescale_spread, dim3(ew_blocks(t, dst)), dim3(kThreads), 0, s, t, dst, top, top_mod);
+    { ProfScope ps_("k_rescale_spread", s, NB(dst.rows()) * 3); hipLaunchKernelGGL(k_rescale_spread, dim3(ew_blocks(t, dst)), dim3(kThreads), 0, s, t, dst, top, top_mod); }
 }
 
 void launch_rescale_combine(const DevTables& t, const RowMap& out, const RowMap& c, const RowMap& T,
                             const uint64_t* consts, hipStream_t s) {
     if (!out.rows()) return;
-    hipLaunchKernelGGL(k_rescale_combine, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, c, T, consts);
+    { ProfScope ps_("k_rescale_combine", s, NB(out.rows()) * 6); hipLaunchKernelGGL(k_rescale_combine, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, c, T, consts); }
 }
 
 }  // namespace csrmf
