@@ -109,7 +109,7 @@ def main():
         owned = []
         for r in CHAIN:
             rot = ctx.rotate_batch(cur, r)
-            nxt = [ctx.add(a, b) for a, b in zip(cur, rot)]
+            nxt = ctx.add_batch(cur, rot)
             for h in rot + owned:
                 ctx.free(h)
             cur = owned = nxt

@@ -66,11 +66,11 @@ typedef struct csrmf_ctx csrmf_ctx;
  * Key-switching digits: D_j = [j*g, min((j+1)*g, L+1)), g = ceil((L+1)/dnum). */
 typedef struct csrmf_params {
     int32_t log2N;          /* ring degree N = 2^log2N, 12..16                  */
-    int32_t base_bits;      /* bits of q_0 (<= 61)                              */
+    int32_t base_bits;      /* bits of q_0 (<= 60)                              */
     int32_t n_scale_primes; /* L, number of scale primes                        */
-    int32_t scale_bits;     /* bits of q_1..q_L (<= 61)                         */
+    int32_t scale_bits;     /* bits of q_1..q_L (<= 60)                         */
     int32_t n_special;      /* alpha, number of special primes (>= 1)           */
-    int32_t special_bits;   /* bits of the special primes (<= 61)               */
+    int32_t special_bits;   /* bits of the special primes (<= 60)               */
     int32_t dnum;           /* number of key-switching digits (>= 1)            */
     int32_t log2_scale;     /* default encoding scale Delta = 2^log2_scale      */
     /* matrix factorisation (Alg. 1 / Alg. 2) */
@@ -161,6 +161,11 @@ int csrmf_export_key(csrmf_ctx* ctx, int32_t which, uint32_t galois, uint64_t* o
  * the result takes a's scale.  out receives a new handle. */
 int csrmf_add(csrmf_ctx* ctx, uint64_t a, uint64_t b, uint64_t* out);
 int csrmf_sub(csrmf_ctx* ctx, uint64_t a, uint64_t b, uint64_t* out);
+
+/* Batched Eq. 6: out[i] = a[i] + b[i] (or a[i] - b[i] if subtract != 0) in
+ * one launch; all operands at one level after alignment. */
+int csrmf_add_batch(csrmf_ctx* ctx, const uint64_t* a, const uint64_t* b, int32_t n, int32_t subtract,
+                    uint64_t* out);
 
 /* Eq. 8: add the integer plaintext polynomial m[N]. */
 int csrmf_add_plain(csrmf_ctx* ctx, uint64_t a, const int64_t* m, uint64_t* out);

@@ -1,0 +1,459 @@
+"""Encrypted CSR matrix-factorisation epoch (oracle; test infrastructure only).
+
+What it computes: the synchronous gradient epoch of ``oracle.mf`` (Eq. 2-5,
+Alg. 1 with the per-entity accumulator of Alg. 2) on CKKS ciphertexts whose
+slots hold the CSR ratings (Sec. III-C: non-zero ratings packed in CSR order,
+profile vectors of k factors packed together).
+
+Layout (k' = 2^ceil(log2 k), block width B = 2k', D = N/(2B) blocks per
+ciphertext):
+* rating ciphertexts: rows packed greedily in CSR order; a row that does not
+  fit in the current ciphertext starts a new one; a row longer than D is cut
+  into chunks of D.  Block t of rating ciphertext c holding rating (i, j)
+  carries r_ij (R), u_i (Ug) and v_j (Vg) in slots tB .. tB+k-1; other slots 0.
+* factor tables: table ciphertext a holds user (item) a*D + b at block b.
+
+One epoch, Ug and Vg at level l:
+ 1. P = HMult(Ug, Vg)
+ 2. windowed block sum: T_0 = P, T_{s+1} = T_s + Rot(T_s, 2^s) for s < log2 B,
+    Sdot = Rot(T_{log2 B}, -k'); slot tB+f (f < k) now holds <u_i, v_j>
+ 3. R_e = Rescale(R * W_R), W_R = rint((S_P * q_L) / S_R), dropped to Sdot's
+    level; E = R_e - Sdot
+ 4. G_U = HMult(E, Vg), G_V = HMult(E, Ug)
+ 5. scatter: table <- BlockPermute(G -> table layout, learning-rate weights)
+    plus the self term (1 - a_t*lambda*d) * table, one rescale
+ 6. gather (not after the last epoch): Ug, Vg <- BlockPermute(tables ->
+    rating layout, weight 1), one rescale.
+
+BlockPermute: a move (source ciphertext c, source block a -> destination
+block b, weight w) has delta = (a - b) mod D = gamma*G + beta with
+G = 2^ceil(log2(D)/2).  For destination d:
+    acc_d = sum_gamma Rot_{gamma G B}( sum_{c, beta} HRot_{beta B}(src_c) (.) M_{d,c,gamma,beta} )
+with HRot hoisted per source, the giant rotation applied once per (d, gamma)
+after the inner sum, zero steps skipped, and the plaintext mask
+    M_{d,c,gamma,beta} = sum_{moves in the group} W * I_{(b + gamma G) mod D},
+    I_p = tau_{g_p}(I_0), g_p = 5^((-p B) mod N/2) mod 2N,
+I_0 the encoding of the indicator of slots 0..k-1 at scale S_I = 2^20, and
+the integer weight W = rint((w * S_t * q_ell) / (S_src * S_I)) for a target
+scale S_t = Delta (q_ell the top prime of the accumulator).  Every term then
+carries scale S_t * q_ell and the accumulator is rescaled once.
+
+The same program runs on two back ends: ``CkksBackend`` (the oracle CKKS
+context) and ``ClearBackend`` (plain slot vectors with exact 0/1 masks and
+exact weights), which pins the rotation and mask index algebra.
+"""
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+import numpy as np
+
+from . import ckks, ring
+
+S_I = 2.0 ** 20
+
+
+def next_pow2(k):
+    p = 1
+    while p < k:
+        p *= 2
+    return p
+
+
+@dataclass
+class Layout:
+    N: int
+    k: int
+    kp: int
+    B: int
+    D: int
+    G: int
+    n_users: int
+    n_items: int
+    n_ct: int = 0
+    # per rating (CSR order): rating ciphertext and block
+    ct_of: np.ndarray = None
+    blk_of: np.ndarray = None
+    rows: np.ndarray = None      # user of each rating
+    cols: np.ndarray = None      # item of each rating
+
+    @property
+    def n_utab(self):
+        return -(-self.n_users // self.D)
+
+    @property
+    def n_vtab(self):
+        return -(-self.n_items // self.D)
+
+
+def make_layout(N, k, n_users, n_items, row_ptr, col_idx):
+    kp = next_pow2(k)
+    B = 2 * kp
+    D = N // (2 * B)
+    logD = D.bit_length() - 1
+    G = 1 << ((logD + 1) // 2)
+    row_ptr = np.asarray(row_ptr, np.int64)
+    nnz = int(row_ptr[-1])
+    ct_of = np.zeros(nnz, np.int64)
+    blk_of = np.zeros(nnz, np.int64)
+    c, used = 0, 0
+    started = False
+    for i in range(n_users):
+        s, e = int(row_ptr[i]), int(row_ptr[i + 1])
+        pos = s
+        while pos < e:
+            chunk = min(D, e - pos)
+            if not started:
+                started = True
+            elif used + chunk > D:
+                c += 1
+                used = 0
+            ct_of[pos:pos + chunk] = c
+            blk_of[pos:pos + chunk] = used + np.arange(chunk)
+            used += chunk
+            pos += chunk
+    lay = Layout(N, k, kp, B, D, G, n_users, n_items)
+    lay.n_ct = c + 1 if started else 0
+    lay.ct_of, lay.blk_of = ct_of, blk_of
+    lay.rows = np.repeat(np.arange(n_users), np.diff(row_ptr))
+    lay.cols = np.asarray(col_idx, np.int64)
+    return lay
+
+
+def slot_vectors(lay, values_per_rating=None, users=None, items=None, which="R"):
+    """Cleartext slot contents of the rating-layout ciphertexts ([n_ct][N/2])."""
+    out = np.zeros((lay.n_ct, lay.N // 2))
+    for r in range(len(lay.rows)):
+        c, t = lay.ct_of[r], lay.blk_of[r]
+        sl = slice(t * lay.B, t * lay.B + lay.k)
+        if which == "R":
+            out[c, sl] = values_per_rating[r]
+        elif which == "U":
+            out[c, sl] = users[lay.rows[r]]
+        else:
+            out[c, sl] = items[lay.cols[r]]
+    return out
+
+
+def table_vectors(lay, F, n_tab):
+    out = np.zeros((n_tab, lay.N // 2))
+    for e in range(F.shape[0]):
+        a, b = divmod(e, lay.D)
+        out[a, b * lay.B: b * lay.B + lay.k] = F[e]
+    return out
+
+
+def rotation_steps(lay):
+    """Every rotation the program uses (left steps)."""
+    st = set()
+    s = 1
+    while s < lay.B:
+        st.add(s)
+        s *= 2
+    st.add(-lay.kp)
+    for beta in range(1, lay.G):
+        st.add(beta * lay.B)
+    for gamma in range(1, lay.D // lay.G):
+        st.add(gamma * lay.G * lay.B)
+    return sorted(st)
+
+
+# ---------------------------------------------------------------- back ends
+class CkksBackend:
+    """Evaluates the program on oracle ciphertexts."""
+
+    def __init__(self, ctx: ckks.Context, mask0):
+        self.ctx = ctx
+        self.mask0 = np.asarray(mask0, np.int64)   # encoded indicator, integer coefficients
+        self.N = ctx.N
+
+    def level(self, x):
+        return x.level
+
+    def scale(self, x):
+        return x.scale
+
+    def top_prime(self, level):
+        return self.ctx.prm.q[level]
+
+    def hmult(self, a, b):
+        return self.ctx.hmult(a, b)
+
+    def add(self, a, b):
+        return self.ctx.add(a, b)
+
+    def sub(self, a, b):
+        return self.ctx.sub(a, b)
+
+    def rotate(self, a, r):
+        return self.ctx.rotate(a, r)
+
+    def hoisted(self, a, steps):
+        return self.ctx.hoisted_rotations(a, steps)
+
+    def mul_int(self, a, w):
+        return self.ctx.mul_int(a, w)
+
+    def rescale(self, a):
+        return self.ctx.rescale(a)
+
+    def drop(self, a, level):
+        return self.ctx.mod_drop(a, level)
+
+    def mask_mul(self, a, terms, scale):
+        """a (.) sum_m W_m * I_{p_m}; the result carries the given scale."""
+        N = self.N
+        m = np.zeros(N, dtype=object)
+        for p, W in terms:
+            m = m + int(W) * self._mask(p)
+        qm = self.ctx.qmods(a.level)
+        mm = np.stack([np.array([int(v) % q for v in m], dtype=np.uint64) for q in qm])
+        idx = list(range(a.level + 1))
+        return ckks.Ciphertext(self.ctx.mul(a.c0, mm, idx), self.ctx.mul(a.c1, mm, idx), scale)
+
+    def set_block(self, B):
+        self.B = B
+        self._cache = {}
+
+    def _mask(self, p):
+        if p not in self._cache:
+            N = self.N
+            g = pow(5, (-p * self.B) % (N // 2), 2 * N)
+            dst, neg = ring.automorphism_map(g, N)
+            v = np.zeros(N, dtype=object)
+            src = self.mask0.astype(object)
+            v[dst] = np.where(neg, -src, src)
+            self._cache[p] = v
+        return self._cache[p]
+
+
+class ClearBackend:
+    """Plain slot vectors: exact 0/1 block masks and exact weights."""
+
+    @dataclass
+    class V:
+        z: np.ndarray
+        level: int
+        scale: float
+
+    def __init__(self, N, q_chain, B, k):
+        self.N = N
+        self.q = q_chain
+        self.B = B
+        self.k = k
+
+    def wrap(self, z, level, scale):
+        return ClearBackend.V(np.asarray(z, np.float64), level, scale)
+
+    def level(self, x):
+        return x.level
+
+    def scale(self, x):
+        return x.scale
+
+    def top_prime(self, level):
+        return self.q[level]
+
+    def hmult(self, a, b):
+        lv = min(a.level, b.level)
+        return self.V(a.z * b.z, lv - 1, a.scale * b.scale / float(self.q[lv]))
+
+    def add(self, a, b):
+        return self.V(a.z + b.z, min(a.level, b.level), a.scale)
+
+    def sub(self, a, b):
+        return self.V(a.z - b.z, min(a.level, b.level), a.scale)
+
+    def rotate(self, a, r):
+        return self.V(np.roll(a.z, -r), a.level, a.scale)
+
+    def hoisted(self, a, steps):
+        return {r: self.rotate(a, r) for r in steps}
+
+    def mul_int(self, a, w):
+        return self.V(a.z, a.level, a.scale * float(w))   # value unchanged; scale absorbs w
+
+    def rescale(self, a):
+        return self.V(a.z, a.level - 1, a.scale / float(self.q[a.level]))
+
+    def drop(self, a, level):
+        return self.V(a.z, level, a.scale)
+
+    def mask_mul(self, a, terms, scale):
+        m = np.zeros(self.N // 2)
+        for p, w in terms:            # here the weight is the exact real w, not the integer W
+            m[p * self.B: p * self.B + self.k] += w
+        return self.V(a.z * m, a.level, scale)
+
+    def set_block(self, B):
+        pass
+
+
+# ---------------------------------------------------------------- the program
+@dataclass
+class Move:
+    src: int      # source ciphertext
+    a: int        # source block
+    b: int        # destination block
+    w: float      # real weight
+
+
+def block_permute(be, lay, srcs, dests_moves, self_terms, level, exact_weights=False):
+    """dests_moves[d] = list of Move; self_terms[d] = (ciphertext, [(block, w)]) or None.
+    All sources share level and scale.  Returns the rescaled accumulators."""
+    D, G, B = lay.D, lay.G, lay.B
+    S_t = float(2 ** 40) if not exact_weights else None
+    src_scale = be.scale(srcs[0]) if srcs else None
+    q_acc = float(be.top_prime(level))
+    # hoisted baby rotations per source, only the betas that are used
+    need = {}
+    for d, moves in enumerate(dests_moves):
+        for mv in moves:
+            beta = ((mv.a - mv.b) % D) % G
+            need.setdefault(mv.src, set()).add(beta)
+    baby = {}
+    for c, betas in need.items():
+        src = be.drop(srcs[c], level)
+        steps = sorted(b * B for b in betas if b)
+        rots = be.hoisted(src, steps) if steps else {}
+        baby[c] = {0: src}
+        for b in betas:
+            if b:
+                baby[c][b] = rots[b * B]
+    out = []
+    acc_scale = S_T_Q(lay, level, be)
+    for d, moves in enumerate(dests_moves):
+        groups = {}
+        for mv in moves:
+            delta = (mv.a - mv.b) % D
+            gamma, beta = divmod(delta, G)
+            groups.setdefault(gamma, {}).setdefault((mv.src, beta), []).append(mv)
+        acc = None
+        for gamma in sorted(groups):
+            inner = None
+            for (c, beta) in sorted(groups[gamma]):
+                terms = []
+                for mv in groups[gamma][(c, beta)]:
+                    p = (mv.b + gamma * G) % D
+                    terms.append((p, weight(be, mv.w, src_scale, q_acc, exact_weights)))
+                t = be.mask_mul(baby[c][beta], terms, acc_scale)
+                inner = t if inner is None else be.add(inner, t)
+            if gamma:
+                inner = be.rotate(inner, gamma * G * B)
+            acc = inner if acc is None else be.add(acc, inner)
+        st = self_terms[d] if self_terms else None
+        if st is not None:
+            ct, blocks = st
+            ctd = be.drop(ct, level)
+            terms = [(b, weight(be, w, be.scale(ctd), q_acc, exact_weights)) for b, w in blocks]
+            t = be.mask_mul(ctd, terms, acc_scale)
+            acc = t if acc is None else be.add(acc, t)
+        out.append(be.rescale(acc))
+    return out
+
+
+def S_T_Q(lay, level, be):
+    return float(2 ** 40) * float(be.top_prime(level))
+
+
+def weight(be, w, s_src, q_acc, exact):
+    if exact:
+        return w
+    return int(np.rint((w * float(2 ** 40) * q_acc) / (s_src * S_I)))
+
+
+@dataclass
+class EpochResult:
+    utab: list
+    vtab: list
+    ug: list = None
+    vg: list = None
+    sdot: list = None
+
+
+def run_epochs(be, lay, R, Ug, Vg, Utab, Vtab, n_epochs, alpha, lam, damp=0.0, rule="R1",
+               exact_weights=False):
+    """Run n_epochs; returns the final tables, the last forward dot products."""
+    be.set_block(lay.B)
+    d_user = np.bincount(lay.rows, minlength=lay.n_users)
+    c_item = np.bincount(lay.cols, minlength=lay.n_items)
+    sdot = None
+    for t in range(n_epochs):
+        a_t = alpha / (1.0 + damp * t)
+        lvl = be.level(Ug[0])
+        # 1-3: block dot products and errors
+        E, sdot = [], []
+        for c in range(lay.n_ct):
+            P = be.hmult(Ug[c], Vg[c])
+            T = P
+            s = 1
+            while s < lay.B:
+                T = be.add(T, be.rotate(T, s))
+                s *= 2
+            S = be.rotate(T, -lay.kp)
+            sdot.append(S)
+            SP = be.scale(P)
+            WR = int(np.rint((SP * float(be.top_prime(be.level(R[c])))) / be.scale(R[c])))
+            Re = be.rescale(be.mul_int(R[c], WR))
+            Re = be.drop(Re, be.level(S))
+            E.append(be.sub(Re, S))
+        # 4: gradient terms
+        GU = [be.hmult(E[c], be.drop(Vg[c], be.level(E[c]))) for c in range(lay.n_ct)]
+        GV = [be.hmult(E[c], be.drop(Ug[c], be.level(E[c]))) for c in range(lay.n_ct)]
+        glevel = be.level(GU[0])
+        # 5: scatter into the tables
+        Utab = _scatter(be, lay, GU, Utab, lay.rows, d_user, lay.n_users, a_t, lam, rule, glevel, exact_weights)
+        Vtab = _scatter(be, lay, GV, Vtab, lay.cols, c_item, lay.n_items, a_t, lam, rule, glevel, exact_weights)
+        # 6: gather for the next epoch
+        if t + 1 < n_epochs:
+            Ug = _gather(be, lay, Utab, lay.rows, exact_weights)
+            Vg = _gather(be, lay, Vtab, lay.cols, exact_weights)
+    return EpochResult(Utab, Vtab, Ug, Vg, sdot)
+
+
+def _scatter(be, lay, Gs, tabs, owner, deg, n_ent, a_t, lam, rule, level, exact):
+    D = lay.D
+    moves = [[] for _ in tabs]
+    for r in range(len(owner)):
+        e = int(owner[r])
+        d, b = divmod(e, D)
+        w = a_t if rule == "R1" else a_t / deg[e]
+        moves[d].append(Move(int(lay.ct_of[r]), int(lay.blk_of[r]), b, w))
+    selfs = []
+    for d in range(len(tabs)):
+        blocks = []
+        for b in range(D):
+            e = d * D + b
+            if e >= n_ent:
+                continue
+            if rule == "R1":
+                w = 1.0 - a_t * lam * deg[e]
+            else:
+                w = (1.0 - a_t * lam) if deg[e] > 0 else 1.0
+            blocks.append((b, w))
+        selfs.append((tabs[d], blocks))
+    return block_permute(be, lay, Gs, moves, selfs, level, exact)
+
+
+def _gather(be, lay, tabs, owner, exact):
+    D = lay.D
+    moves = [[] for _ in range(lay.n_ct)]
+    for r in range(len(owner)):
+        e = int(owner[r])
+        a_ct, a = divmod(e, D)
+        moves[int(lay.ct_of[r])].append(Move(a_ct, a, int(lay.blk_of[r]), 1.0))
+    level = be.level(tabs[0])
+    return block_permute(be, lay, tabs, moves, None, level, exact)
+
+
+def decode_tables(vals, lay, n_ent):
+    """Slot vectors of table ciphertexts -> factor matrix [n_ent][k]."""
+    F = np.zeros((n_ent, lay.k))
+    for e in range(n_ent):
+        a, b = divmod(e, lay.D)
+        F[e] = vals[a][b * lay.B: b * lay.B + lay.k]
+    return F
+
+
+def decode_predictions(vals, lay):
+    """Slot vectors of the forward dot products -> r_hat per rating (CSR order)."""
+    return np.array([vals[int(c)][int(t) * lay.B] for c, t in zip(lay.ct_of, lay.blk_of)])

@@ -69,6 +69,7 @@ _SIGS = {
     "csrmf_add": [_p, ctypes.c_uint64, ctypes.c_uint64, _u64p],
     "csrmf_sub": [_p, ctypes.c_uint64, ctypes.c_uint64, _u64p],
     "csrmf_add_plain": [_p, ctypes.c_uint64, _i64p, _u64p],
+    "csrmf_add_batch": [_p, _u64p, _u64p, ctypes.c_int32, ctypes.c_int32, _u64p],
     "csrmf_mul_plain": [_p, ctypes.c_uint64, _i64p, ctypes.c_double, _u64p],
     "csrmf_mul_int": [_p, ctypes.c_uint64, ctypes.c_int64, _u64p],
     "csrmf_hmult": [_p, ctypes.c_uint64, ctypes.c_uint64, _u64p],
@@ -233,6 +234,14 @@ class Context:
 
     def sub(self, a, b):
         return self._unary(lib.csrmf_sub, a, b)
+
+    def add_batch(self, a, b, subtract=False):
+        a = np.asarray(a, np.uint64)
+        b = np.asarray(b, np.uint64)
+        out = np.zeros(len(a), np.uint64)
+        self._chk(lib.csrmf_add_batch(self.h, _ptr(a, ctypes.c_uint64), _ptr(b, ctypes.c_uint64), len(a),
+                                      int(bool(subtract)), _ptr(out, ctypes.c_uint64)))
+        return [int(x) for x in out]
 
     def add_plain(self, a, m):
         m = np.ascontiguousarray(m, np.int64)

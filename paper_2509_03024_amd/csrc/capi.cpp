@@ -202,6 +202,24 @@ int csrmf_sub(csrmf_ctx* cx, uint64_t a, uint64_t b, uint64_t* out) {
     API_END(c)
 }
 
+int csrmf_add_batch(csrmf_ctx* cx, const uint64_t* a, const uint64_t* b, int32_t n, int32_t subtract,
+                    uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(a && b && out && n > 0, "arguments");
+    std::vector<Ct*> va, vb;
+    for (int i = 0; i < n; ++i) {
+        va.push_back(&c->get(a[i]));
+        vb.push_back(&c->get(b[i]));
+    }
+    std::vector<Ct> res(n);
+    std::vector<Ct*> vo;
+    for (auto& r : res) vo.push_back(&r);
+    c->add_batch(va, vb, vo, subtract != 0);
+    for (int i = 0; i < n; ++i) out[i] = c->put(res[i]);
+    API_END(c)
+}
+
 int csrmf_add_plain(csrmf_ctx* cx, uint64_t a, const int64_t* m, uint64_t* out) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)

@@ -85,14 +85,15 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
     if (p.log2N < 12 || p.log2N > 16) throw Error(CSRMF_E_INVAL, "log2N must be in [12, 16]");
     if (p.n_scale_primes < 0 || p.n_scale_primes > 40 || p.n_special < 1 || p.n_special > 8 || p.dnum < 1)
         throw Error(CSRMF_E_INVAL, "bad prime counts");
-    if (p.base_bits > 61 || p.scale_bits > 61 || p.special_bits > 61)
-        throw Error(CSRMF_E_INVAL, "primes must be below 2^61");
+    if (p.base_bits > 60 || p.scale_bits > 60 || p.special_bits > 60)
+        throw Error(CSRMF_E_INVAL, "primes must be below 2^60");
     logN = p.log2N;
     N = 1ull << logN;
     L = p.n_scale_primes;
     alpha = p.n_special;
     dnum = p.dnum;
     gsize = (L + 1 + dnum - 1) / dnum;
+    if (gsize > 16 || alpha > 16) throw Error(CSRMF_E_INVAL, "key-switching digits hold at most 16 limbs");
     if (L + 1 + alpha > 64) throw Error(CSRMF_E_INVAL, "too many limbs");
     if (p.k < 0 || (p.k > 0 && 4 * (uint64_t)p.k > N / 2)) throw Error(CSRMF_E_INVAL, "k too large for the slots");
 
@@ -194,8 +195,7 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
                     const uint64_t qt = moduli[tm];
                     uint64_t hat = 1;
                     for (int k = lo; k < hi; ++k) if (k != i) hat = mm(hat, moduli[k] % qt, qt);
-                    cc.push_back(hat);
-                    cc.push_back(shoup_pre(hat, qt));
+                    cc.push_back(mm(hat, mh[tm].r_mod, qt));
                 }
             }
             dc.yc = upload_consts(pool, yc, stream);
@@ -216,8 +216,7 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
                 const uint64_t qi = moduli[i];
                 uint64_t hat = 1;
                 for (int kk = 0; kk < alpha; ++kk) if (kk != k) hat = mm(hat, moduli[L + 1 + kk] % qi, qi);
-                cv.push_back(hat);
-                cv.push_back(shoup_pre(hat, qi));
+                cv.push_back(mm(hat, mh[i].r_mod, qi));
             }
         }
         for (int i = 0; i <= l; ++i) {
@@ -277,6 +276,11 @@ void Context::free_ct(uint64_t h) {
 uint64_t** Context::ptr_table(const std::vector<uint64_t*>& v) {
     auto it = ptr_tables.find(v);
     if (it != ptr_tables.end()) return it->second;
+    if (ptr_tables.size() >= 4096) {   // bound the cache; earlier launches may still read the tables
+        CSRMF_HIP(hipStreamSynchronize(stream));
+        for (auto& kv : ptr_tables) (void)hipFree(kv.second);
+        ptr_tables.clear();
+    }
     uint64_t** d = nullptr;
     CSRMF_HIP(hipMalloc(&d, std::max<size_t>(8, v.size() * sizeof(uint64_t*))));
     upload(d, v.data(), v.size() * sizeof(uint64_t*), stream);
@@ -636,6 +640,24 @@ void Context::add(const Ct& a, const Ct& b, Ct& out, bool sub) {
     const int lvl = std::min(a.level, b.level);
     out = new_ct(lvl, a.scale);
     RowMap ma = map_ct(a.d, lvl + 1), mb = map_ct(b.d, lvl + 1), mo = map_ct(out.d, lvl + 1);
+    for (int i = 0; i <= lvl; ++i) {
+        ma.push(L + 1 + i, i);
+        mb.push(L + 1 + i, i);
+        mo.push(L + 1 + i, i);
+    }
+    launch_ew(tabs, sub ? EW_SUB : EW_ADD, mo, ma, mb, stream);
+}
+
+void Context::add_batch(const std::vector<Ct*>& a, const std::vector<Ct*>& b, std::vector<Ct*>& out, bool sub) {
+    const int B = (int)a.size();
+    if (B == 0) return;
+    const int lvl = std::min(a[0]->level, b[0]->level);
+    for (int i = 0; i < B; ++i) {
+        check_scales(a[i]->scale, b[i]->scale);
+        if (std::min(a[i]->level, b[i]->level) != lvl) throw Error(CSRMF_E_INVAL, "batch operands must share a level");
+    }
+    for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, a[i]->scale);
+    RowMap ma = map_cts(a, lvl + 1), mb = map_cts(b, lvl + 1), mo = map_cts(out, lvl + 1);
     for (int i = 0; i <= lvl; ++i) {
         ma.push(L + 1 + i, i);
         mb.push(L + 1 + i, i);

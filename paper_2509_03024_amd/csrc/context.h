@@ -45,13 +45,13 @@ struct Key {
 struct DigitConsts {
     int lo, hi;                 // limbs [lo, hi) of the digit at this level
     uint64_t* yc = nullptr;     // [|D|][2]
-    uint64_t* cc = nullptr;     // [|D|][n_tgt][2]
+    uint64_t* cc = nullptr;     // [|D|][n_tgt]  Qhat_i * 2^64 mod target
 };
 
 struct LevelConsts {
     std::vector<DigitConsts> digits;
     uint64_t* md_y = nullptr;       // [alpha][2]  (P/p_k)^-1 mod p_k
-    uint64_t* md_c = nullptr;       // [alpha][l+1][2]  (P/p_k) mod q_i
+    uint64_t* md_c = nullptr;       // [alpha][l+1]  (P/p_k) * 2^64 mod q_i
     uint64_t* md_pinv = nullptr;    // [l+1][2]  P^-1 mod q_i
     uint64_t* rs = nullptr;         // [l][4]  h mod q_i, q_l^-1 mod q_i, shoup, 0
 };
@@ -150,6 +150,7 @@ struct Context {
 
     // --- evaluation (batched; every vector holds ciphertexts of equal level)
     void add(const Ct& a, const Ct& b, Ct& out, bool sub);
+    void add_batch(const std::vector<Ct*>& a, const std::vector<Ct*>& b, std::vector<Ct*>& out, bool sub);
     void add_plain(const Ct& a, const int64_t* m, Ct& out);
     void mul_plain(const Ct& a, const int64_t* m, double pt_scale, Ct& out);
     void mul_int(const Ct& a, int64_t w, Ct& out);

@@ -77,9 +77,9 @@ void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, cons
 
 // Fast basis conversion (coefficient form), per batch element:
 //   y_i = x_i * [Qhat_i^-1]_{q_i},   out_t = sum_i y_i * [Qhat_i]_t  (mod t)
-// src map: n_src rows; dst map: n_tgt rows.  Device constants:
+// src map: n_src (1..16) rows; dst map: n_tgt rows.  Device constants:
 //   yc[2i], yc[2i+1]            = Qhat_i^-1 mod src_i and its shoup
-//   cc[2(i*n_tgt+t)], +1        = Qhat_i mod tgt_t and its shoup
+//   cc[i*n_tgt+t]               = Qhat_i * 2^64 mod tgt_t (Montgomery form)
 void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src,
                           const uint64_t* yc, const uint64_t* cc, hipStream_t s);
 

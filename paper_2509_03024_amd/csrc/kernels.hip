@@ -427,17 +427,23 @@ __global__ void __launch_bounds__(kThreads) k_automorphism(DevTables t, uint32_t
     }
 }
 
-// Basis conversion: one thread per coefficient, loops over source and target limbs.
-__global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap dst, RowMap src, const uint64_t* yc, const uint64_t* cc) {
+// Basis conversion: one thread per coefficient.  y_i = x_i * [Qhat_i^-1]_{q_i}
+// (Shoup, canonical), then for every target t the products y_i * (Qhat_i 2^64
+// mod t) are summed exactly in 128 bits and reduced once by Montgomery REDC:
+// sum < NS * 2^60 * t <= t * 2^64, so REDC returns sum * 2^-64 mod t in [0, 2t).
+template <int NS>
+__global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap dst, RowMap src, const uint64_t* yc,
+                                                            const uint64_t* cc) {
     const int logN = t.logN;
     const int N = 1 << logN;
     const int chunks = N / kThreads;
     const int chunk = blockIdx.x % chunks;
     const int b = blockIdx.x / chunks;
     const int i = chunk * kThreads + threadIdx.x;
-    const int ns = src.n, nt = dst.n;
-    uint64_t y[16];
-    for (int s = 0; s < ns; ++s) {
+    const int nt = dst.n;
+    uint64_t y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
         int mod;
         const uint64_t* p = map_row(src, b, s, logN, mod);
         y[s] = mul_shoup(p[i], yc[2 * s], yc[2 * s + 1], t.mods[mod].q);
@@ -445,13 +451,19 @@ __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap 
     for (int tt = 0; tt < nt; ++tt) {
         int mod;
         uint64_t* o = map_row(dst, b, tt, logN, mod);
-        const uint64_t q = t.mods[mod].q;
-        uint64_t acc = 0;
-        for (int s = 0; s < ns; ++s) {
-            const uint64_t* c = cc + 2 * (s * nt + tt);
-            acc = add_mod(acc, mul_shoup(y[s], c[0], c[1], q), q);
+        const Modulus md = t.mods[mod];
+        uint64_t lo = 0, hi = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const uint64_t c = cc[s * nt + tt];
+            const uint64_t pl = y[s] * c;
+            const uint64_t ph = mulhi64(y[s], c);
+            lo += pl;
+            hi += ph + (lo < pl ? 1u : 0u);
         }
-        o[i] = acc;
+        const uint64_t m = lo * md.qneg_inv;
+        uint64_t r = hi + mulhi64(m, md.q) + (lo != 0 ? 1u : 0u);
+        o[i] = r >= md.q ? r - md.q : r;
     }
 }
 
@@ -589,11 +601,36 @@ void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, cons
     { ProfScope ps_("k_automorphism", s, NB(out.rows()) * (both ? 4 : 2)); hipLaunchKernelGGL(k_automorphism, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, g, out, in, both ? 1 : 0); }
 }
 
+template <int NS>
+static void launch_bc(const DevTables& t, const RowMap& dst, const RowMap& src, const uint64_t* yc,
+                      const uint64_t* cc, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_basis_convert<NS>, dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc);
+}
+
 void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src, const uint64_t* yc,
                           const uint64_t* cc, hipStream_t s) {
     if (!dst.n || !src.n) return;
     const int blocks = dst.batch * ((1 << t.logN) / kThreads);
-    { ProfScope ps_("k_basis_convert", s, NB(dst.batch) * (src.n + dst.n)); hipLaunchKernelGGL(k_basis_convert, dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc); }
+    ProfScope ps_("k_basis_convert", s, NB(dst.batch) * (src.n + dst.n));
+    switch (src.n) {
+        case 1: launch_bc<1>(t, dst, src, yc, cc, blocks, s); break;
+        case 2: launch_bc<2>(t, dst, src, yc, cc, blocks, s); break;
+        case 3: launch_bc<3>(t, dst, src, yc, cc, blocks, s); break;
+        case 4: launch_bc<4>(t, dst, src, yc, cc, blocks, s); break;
+        case 5: launch_bc<5>(t, dst, src, yc, cc, blocks, s); break;
+        case 6: launch_bc<6>(t, dst, src, yc, cc, blocks, s); break;
+        case 7: launch_bc<7>(t, dst, src, yc, cc, blocks, s); break;
+        case 8: launch_bc<8>(t, dst, src, yc, cc, blocks, s); break;
+        case 9: launch_bc<9>(t, dst, src, yc, cc, blocks, s); break;
+        case 10: launch_bc<10>(t, dst, src, yc, cc, blocks, s); break;
+        case 11: launch_bc<11>(t, dst, src, yc, cc, blocks, s); break;
+        case 12: launch_bc<12>(t, dst, src, yc, cc, blocks, s); break;
+        case 13: launch_bc<13>(t, dst, src, yc, cc, blocks, s); break;
+        case 14: launch_bc<14>(t, dst, src, yc, cc, blocks, s); break;
+        case 15: launch_bc<15>(t, dst, src, yc, cc, blocks, s); break;
+        case 16: launch_bc<16>(t, dst, src, yc, cc, blocks, s); break;
+        default: break;   // digit sizes are validated at context creation
+    }
 }
 
 void launch_ks_inner(const DevTables& t, const RowMap& u, const KsArgs& a, uint32_t g, hipStream_t s) {

@@ -38,7 +38,7 @@ def test_create_rejects_bad_params_without_gpu_work():
     h = ctypes.c_void_p()
     bad = pk.params(9, 60, 3, 40, 1, 60, 4)          # N = 2^9 is below the supported range
     assert pk.lib.csrmf_create(ctypes.byref(bad), bytes(32), ctypes.byref(h)) == -1
-    bad = pk.params(12, 62, 3, 40, 1, 62, 4)         # primes must be below 2^61
+    bad = pk.params(12, 61, 3, 40, 1, 61, 4)         # primes must be below 2^60
     assert pk.lib.csrmf_create(ctypes.byref(bad), bytes(32), ctypes.byref(h)) == -1
     assert pk.lib.csrmf_create(None, bytes(32), ctypes.byref(h)) == -1
     assert pk.lib.csrmf_last_error(None) == b"null context"

@@ -154,6 +154,11 @@ def test_batched_equals_single(pair):
     rots = lib.rotate_batch(prods, 2)
     for i in range(4):
         _same(lib, rots[i], orc.rotate(orc.hmult(hs[i][1], hs[(i + 1) % 4][1]), 2))
+    sums = lib.add_batch(a, b)
+    diffs = lib.add_batch(a, b, subtract=True)
+    for i in range(4):
+        _same(lib, sums[i], orc.add(hs[i][1], hs[(i + 1) % 4][1]))
+        _same(lib, diffs[i], orc.sub(hs[i][1], hs[(i + 1) % 4][1]))
     conj = lib.conjugate_batch(a)
     for i in range(4):
         _same(lib, conj[i], orc.conjugate(hs[i][1]))

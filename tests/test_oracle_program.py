@@ -1,0 +1,117 @@
+"""Pins for the encrypted MF program of the oracle.
+
+* ClearBackend: the program's rotations, block masks and weights applied to
+  plain slot vectors reproduce the FP64 synchronous epoch exactly (pure index
+  algebra: layout, windowed block sum, BlockPermute grouping, self terms).
+* CkksBackend at the tiny configuration: decrypted factors and forward
+  predictions within 1e-4 of FP64 MF (the value contract).
+"""
+import numpy as np
+import pytest
+
+from oracle import ckks, mf, params, program
+import workloads
+
+
+def _layout_for(csr, N, k):
+    return program.make_layout(N, k, csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx)
+
+
+def test_layout_packing_rules():
+    # rows of lengths 3, 0, 5, 2 with D = 4 blocks: row 0 -> ct0 blocks 0..2; row 2 is
+    # longer than D -> chunks 4 + 1, the first starts ct1 (does not fit in ct0), the
+    # second continues in ct2 (ct1 full); row 3 fits after it in ct2.
+    row_ptr = np.array([0, 3, 3, 8, 10])
+    col_idx = np.array([0, 1, 2, 0, 1, 2, 3, 4, 1, 3])
+    lay = program.make_layout(32, 4, 4, 5, row_ptr, col_idx)   # k'=4, B=8, D=32/16=2? -> N/2B
+    assert lay.B == 8 and lay.D == 2
+    lay = program.make_layout(64, 4, 4, 5, row_ptr, col_idx)
+    assert lay.D == 4
+    assert list(lay.ct_of) == [0, 0, 0, 1, 1, 1, 1, 2, 2, 2]
+    assert list(lay.blk_of) == [0, 1, 2, 0, 1, 2, 3, 0, 1, 2]
+    assert lay.n_ct == 3
+
+
+def _clear_run(csr, N, k, U0, V0, epochs, alpha, lam, rule, damp=0.0):
+    lay = _layout_for(csr, N, k)
+    q = params.config_tiny().q if N == 4096 else [2 ** 40] * 30
+    qchain = [1] + [2 ** 40 + 7] * 29      # scales are irrelevant for the exact back end
+    be = program.ClearBackend(N, qchain, lay.B, k)
+    L = 4 * epochs + 2
+    R = [be.wrap(z, L, 2.0 ** 40) for z in program.slot_vectors(lay, csr.values, which="R")]
+    Ug = [be.wrap(z, L, 2.0 ** 40) for z in program.slot_vectors(lay, users=U0, which="U")]
+    Vg = [be.wrap(z, L, 2.0 ** 40) for z in program.slot_vectors(lay, items=V0, which="V")]
+    Ut = [be.wrap(z, L, 2.0 ** 40) for z in program.table_vectors(lay, U0, lay.n_utab)]
+    Vt = [be.wrap(z, L, 2.0 ** 40) for z in program.table_vectors(lay, V0, lay.n_vtab)]
+    res = program.run_epochs(be, lay, R, Ug, Vg, Ut, Vt, epochs, alpha, lam, damp=damp, rule=rule,
+                             exact_weights=True)
+    U = program.decode_tables([v.z for v in res.utab], lay, csr.n_rows)
+    V = program.decode_tables([v.z for v in res.vtab], lay, csr.n_cols)
+    rhat = program.decode_predictions([v.z for v in res.sdot], lay)
+    return U, V, rhat, lay
+
+
+@pytest.mark.parametrize("rule,epochs", [("R1", 1), ("R1", 3), ("R2", 2)])
+def test_clear_program_equals_fp64_epochs(rule, epochs):
+    csr = workloads.tiny_ratings()
+    U0, V0 = workloads.init_factors(32, 64, 4)
+    U, V, rhat, lay = _clear_run(csr, 4096, 4, U0, V0, epochs, 0.01, 0.02, rule, damp=0.1)
+    Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, 0.01, 0.02, epochs, damp=0.1, rule=rule)
+    assert np.max(np.abs(U - Uf)) < 1e-12 and np.max(np.abs(V - Vf)) < 1e-12
+    assert np.max(np.abs(rhat - rf)) < 1e-12
+
+
+def test_clear_program_multi_ciphertext_layout():
+    """Small N so the 205 ratings span several rating and table ciphertexts,
+    with rows split across ciphertexts, k not a power of two."""
+    csr = workloads.tiny_ratings()
+    U0, V0 = workloads.init_factors(32, 64, 3, seed=4)
+    U, V, rhat, lay = _clear_run(csr, 128, 3, U0, V0, 2, 0.02, 0.05, "R2")
+    assert lay.n_ct > 10 and lay.n_utab > 1 and lay.n_vtab > 1
+    Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, 0.02, 0.05, 2, rule="R2")
+    assert np.max(np.abs(U - Uf)) < 1e-12 and np.max(np.abs(V - Vf)) < 1e-12
+    assert np.max(np.abs(rhat - rf)) < 1e-12
+
+
+def run_encrypted_tiny(ctx, csr, U0, V0, mask0, epochs=1, alpha=0.01, lam=0.02, rule="R1"):
+    """Encrypt the tiny workload with the oracle (serial order: R, Utab, Vtab, Ug, Vg)
+    and run the program on CkksBackend; returns (layout, result, plaintexts)."""
+    N = ctx.N
+    lay = _layout_for(csr, N, U0.shape[1])
+    L = ctx.prm.L
+    D40 = 2.0 ** 40
+    enc = lambda Z: [ctx.encode(z, D40) for z in Z]
+    pt = {
+        "R": enc(program.slot_vectors(lay, csr.values, which="R")),
+        "Utab": enc(program.table_vectors(lay, U0, lay.n_utab)),
+        "Vtab": enc(program.table_vectors(lay, V0, lay.n_vtab)),
+        "Ug": enc(program.slot_vectors(lay, users=U0, which="U")),
+        "Vg": enc(program.slot_vectors(lay, items=V0, which="V")),
+    }
+    cts = {key: [ctx.encrypt_int(m, L, D40) for m in pt[key]] for key in ["R", "Utab", "Vtab", "Ug", "Vg"]}
+    be = program.CkksBackend(ctx, mask0)
+    res = program.run_epochs(be, lay, cts["R"], cts["Ug"], cts["Vg"], cts["Utab"], cts["Vtab"], epochs,
+                             alpha, lam, rule=rule)
+    return lay, res, pt
+
+
+@pytest.mark.slow
+def test_encrypted_program_tiny_within_1e4_of_fp64():
+    prm = params.config_tiny()
+    csr = workloads.tiny_ratings()
+    U0, V0 = workloads.init_factors(32, 64, 4)
+    ctx = ckks.Context(prm, workloads.CRYPTO_SEED)
+    lay0 = _layout_for(csr, prm.N, 4)
+    ctx.keygen(rot_steps=program.rotation_steps(lay0))
+    ind = np.zeros(prm.N // 2)
+    ind[:4] = 1.0
+    mask0 = ctx.encode(ind, program.S_I)
+    lay, res, _ = run_encrypted_tiny(ctx, csr, U0, V0, mask0)
+    U = program.decode_tables([ctx.decrypt(c) for c in res.utab], lay, 32)
+    V = program.decode_tables([ctx.decrypt(c) for c in res.vtab], lay, 64)
+    rhat = program.decode_predictions([ctx.decrypt(c) for c in res.sdot], lay)
+    Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, 0.01, 0.02, 1, rule="R1")
+    assert np.max(np.abs(U - Uf)) < 1e-4
+    assert np.max(np.abs(V - Vf)) < 1e-4
+    assert np.max(np.abs(rhat - rf)) < 1e-4
+    assert res.utab[0].level == 0
