@@ -236,6 +236,80 @@ int csrmf_profile_enable(int32_t enable);
  * events.  Returns the length of the full report. */
 int csrmf_profile_report(char* buf, int32_t cap);
 
+/* ------------------------------------------------------------------------ */
+/* Encrypted CSR matrix factorisation (Alg. 1 / Alg. 2).                     */
+/* ------------------------------------------------------------------------ */
+
+/* Pack the CSR rating matrix (n_rows users x n_cols items; row_ptr[n_rows+1],
+ * col_idx[nnz] sorted within a row, values[nnz]) into block layout and encrypt
+ * it (Alg. 1 EncryptCsrMatrix).  With k' = 2^ceil(log2 k), block width B = 2k'
+ * and D = N/(2B) blocks per ciphertext, rows are packed greedily in CSR order;
+ * a row that does not fit in the current ciphertext starts a new one and a
+ * row longer than D is split into chunks of D.  Block t of a rating
+ * ciphertext holds r_ij in slots tB..tB+k-1.  n_ct receives the number of
+ * rating ciphertexts.  Errors: INVAL (row_ptr not monotone, columns unsorted,
+ * duplicated or out of range, NaN), STATE (no keys). */
+int csrmf_encrypt_csr_rows(csrmf_ctx* ctx, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr,
+                           const int32_t* col_idx, const double* values, int32_t* n_ct);
+
+/* Same as csrmf_encrypt_csr_rows but each rating ciphertext's plaintext is
+ * supplied already encoded: plain[n_ct][N] (int64).  Used to check the
+ * evaluation bit for bit independently of floating-point encoding. */
+int csrmf_encrypt_csr_rows_int(csrmf_ctx* ctx, int32_t n_rows, int32_t n_cols,
+                               const int64_t* row_ptr, const int32_t* col_idx,
+                               const int64_t* plain, int32_t n_plain, int32_t* n_ct);
+
+/* Encrypt the initial factors (Alg. 1: the server draws and encrypts U and V):
+ * U0[n_rows*k], V0[n_cols*k] row-major.  Creates the factor tables (user a*D+b
+ * at block b of table ciphertext a, likewise items) and the gathered copies
+ * in the rating layout (u_i and v_j in the slots of every rating (i, j)).
+ * Errors: STATE (no ratings encrypted yet). */
+int csrmf_init_factors(csrmf_ctx* ctx, const double* U0, const double* V0);
+
+/* Integer-plaintext form of csrmf_init_factors plus the block indicator mask:
+ * utab[n_utab][N], vtab[n_vtab][N], ug[n_ct][N], vg[n_ct][N] and
+ * mask0[N] = encoding of the indicator of slots 0..k-1 at scale 2^20.
+ * Counts are reported by csrmf_mf_layout. */
+int csrmf_init_factors_int(csrmf_ctx* ctx, const int64_t* utab, const int64_t* vtab,
+                           const int64_t* ug, const int64_t* vg, const int64_t* mask0);
+
+/* Layout counts: rating ciphertexts, user-table and item-table ciphertexts,
+ * blocks per ciphertext D and block width B. */
+int csrmf_mf_layout(const csrmf_ctx* ctx, int32_t* n_ct, int32_t* n_utab, int32_t* n_vtab,
+                    int32_t* D, int32_t* B);
+
+/* Run n_epochs synchronous encrypted gradient-descent epochs.  Each epoch
+ * computes for every rating ciphertext P = Ug*Vg, the block dot products by a
+ * windowed rotate-and-sum, E = R - <u,v>, the gradient terms E*Vg and E*Ug,
+ * scatters them into the factor tables with the learning-rate weights and the
+ * (1 - alpha*lambda*...) self term, and gathers the new factors back into the
+ * rating layout for the next epoch (not after the last one; a later call
+ * gathers first).  The first epoch on gathered factors costs 3 levels, each
+ * further one 4.  Rule 1: weights alpha_t and self term 1 - alpha_t*lambda*d;
+ * rule 2: alpha_t/d and 1 - alpha_t*lambda (entities without ratings are
+ * left unchanged).  alpha_t = lr / (1 + damp * t), t = epochs run so far.
+ * Errors: LEVEL (not enough levels), STATE, DEVICE. */
+int csrmf_mf_epochs(csrmf_ctx* ctx, int32_t n_epochs);
+
+/* Encrypted predictions r_hat = <u_i, v_j> on the observed ratings from the
+ * current factor tables (gather + product + windowed sum).  Errors: LEVEL. */
+int csrmf_predict(csrmf_ctx* ctx);
+
+/* Decrypt the factor tables: U[n_rows*k], V[n_cols*k] row-major. */
+int csrmf_decrypt_factors(csrmf_ctx* ctx, double* U, double* V);
+
+/* Decrypt predictions on the observed ratings, in CSR order, into rhat[nnz]:
+ * which = 0: the forward predictions of the last epoch (epoch-start factors);
+ * which = 1: the output of csrmf_predict. */
+int csrmf_decrypt_predictions(csrmf_ctx* ctx, double* rhat, int32_t which);
+
+/* Handles of the program's ciphertexts (test hook; owned by the program, do
+ * not free): which = 0 rating ciphertexts, 1 user tables, 2 item tables,
+ * 3 gathered users, 4 gathered items, 5 forward dot products of the last
+ * epoch, 6 the output of csrmf_predict.  Writes up to `cap` handles into out
+ * and the count into n. */
+int csrmf_mf_handles(const csrmf_ctx* ctx, int32_t which, uint64_t* out, int32_t cap, int32_t* n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,16 @@ _SIGS = {
     "csrmf_rotate_batch": [_p, _u64p, ctypes.c_int32, ctypes.c_int32, _u64p],
     "csrmf_conjugate_batch": [_p, _u64p, ctypes.c_int32, _u64p],
     "csrmf_ntt_rows": [_p, _p, ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_int32],
+    "csrmf_encrypt_csr_rows": [_p, ctypes.c_int32, ctypes.c_int32, _i64p, _i32p, _dp, _i32p],
+    "csrmf_encrypt_csr_rows_int": [_p, ctypes.c_int32, ctypes.c_int32, _i64p, _i32p, _i64p, ctypes.c_int32, _i32p],
+    "csrmf_init_factors": [_p, _dp, _dp],
+    "csrmf_init_factors_int": [_p, _i64p, _i64p, _i64p, _i64p, _i64p],
+    "csrmf_mf_layout": [_p, _i32p, _i32p, _i32p, _i32p, _i32p],
+    "csrmf_mf_epochs": [_p, ctypes.c_int32],
+    "csrmf_predict": [_p],
+    "csrmf_decrypt_factors": [_p, _dp, _dp],
+    "csrmf_decrypt_predictions": [_p, _dp, ctypes.c_int32],
+    "csrmf_mf_handles": [_p, ctypes.c_int32, _u64p, ctypes.c_int32, _i32p],
     "csrmf_profile_enable": [ctypes.c_int32],
     "csrmf_profile_report": [ctypes.c_char_p, ctypes.c_int32],
 }
@@ -302,6 +312,74 @@ class Context:
         """In-place (I)NTT of rows at a device pointer (e.g. a torch tensor's data_ptr())."""
         idx = np.asarray(limb_idx, np.int32)
         self._chk(lib.csrmf_ntt_rows(self.h, _p(dev_ptr), n_rows, _ptr(idx, ctypes.c_int32), len(idx), int(inverse)))
+
+
+class MF:
+    """Encrypted CSR matrix factorisation on a Context (the calls of Alg. 1)."""
+
+    def __init__(self, ctx: "Context"):
+        self.ctx = ctx
+
+    def encrypt_csr_rows(self, n_rows, n_cols, row_ptr, col_idx, values):
+        rp = np.ascontiguousarray(row_ptr, np.int64)
+        ci = np.ascontiguousarray(col_idx, np.int32)
+        v = np.ascontiguousarray(values, np.float64)
+        n = ctypes.c_int32()
+        self.ctx._chk(lib.csrmf_encrypt_csr_rows(self.ctx.h, n_rows, n_cols, _ptr(rp, ctypes.c_int64),
+                                                 _ptr(ci, ctypes.c_int32), _ptr(v, ctypes.c_double), ctypes.byref(n)))
+        self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, len(ci)
+        return n.value
+
+    def encrypt_csr_rows_int(self, n_rows, n_cols, row_ptr, col_idx, plain):
+        rp = np.ascontiguousarray(row_ptr, np.int64)
+        ci = np.ascontiguousarray(col_idx, np.int32)
+        pl = np.ascontiguousarray(plain, np.int64)
+        n = ctypes.c_int32()
+        self.ctx._chk(lib.csrmf_encrypt_csr_rows_int(self.ctx.h, n_rows, n_cols, _ptr(rp, ctypes.c_int64),
+                                                     _ptr(ci, ctypes.c_int32), _ptr(pl, ctypes.c_int64),
+                                                     pl.shape[0], ctypes.byref(n)))
+        self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, len(ci)
+        return n.value
+
+    def layout(self):
+        v = [ctypes.c_int32() for _ in range(5)]
+        self.ctx._chk(lib.csrmf_mf_layout(self.ctx.h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["n_ct", "n_utab", "n_vtab", "D", "B"], [x.value for x in v]))
+
+    def init_factors(self, U0, V0):
+        U = np.ascontiguousarray(U0, np.float64)
+        V = np.ascontiguousarray(V0, np.float64)
+        self.k = U.shape[1]
+        self.ctx._chk(lib.csrmf_init_factors(self.ctx.h, _ptr(U, ctypes.c_double), _ptr(V, ctypes.c_double)))
+
+    def init_factors_int(self, utab, vtab, ug, vg, mask0, k):
+        arrs = [np.ascontiguousarray(a, np.int64) for a in (utab, vtab, ug, vg, mask0)]
+        self.k = k
+        self.ctx._chk(lib.csrmf_init_factors_int(self.ctx.h, *[_ptr(a, ctypes.c_int64) for a in arrs]))
+
+    def epochs(self, n):
+        self.ctx._chk(lib.csrmf_mf_epochs(self.ctx.h, n))
+
+    def predict(self):
+        self.ctx._chk(lib.csrmf_predict(self.ctx.h))
+
+    def decrypt_factors(self):
+        U = np.zeros((self.n_rows, self.k))
+        V = np.zeros((self.n_cols, self.k))
+        self.ctx._chk(lib.csrmf_decrypt_factors(self.ctx.h, _ptr(U, ctypes.c_double), _ptr(V, ctypes.c_double)))
+        return U, V
+
+    def decrypt_predictions(self, which=0):
+        r = np.zeros(self.nnz)
+        self.ctx._chk(lib.csrmf_decrypt_predictions(self.ctx.h, _ptr(r, ctypes.c_double), which))
+        return r
+
+    def handles(self, which):
+        n = ctypes.c_int32()
+        self.ctx._chk(lib.csrmf_mf_handles(self.ctx.h, which, None, 0, ctypes.byref(n)))
+        out = np.zeros(max(1, n.value), np.uint64)
+        self.ctx._chk(lib.csrmf_mf_handles(self.ctx.h, which, _ptr(out, ctypes.c_uint64), n.value, ctypes.byref(n)))
+        return [int(x) for x in out[: n.value]]
 
 
 def profile_enable(on=True):

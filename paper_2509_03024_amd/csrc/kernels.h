@@ -112,6 +112,15 @@ void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap&
                             const RowMap& conv, const RowMap& addend, uint32_t g_add,
                             bool addend_both_polys, const uint64_t* consts, hipStream_t s);
 
+// acc (+)= src (.) M for both polynomials (rows of acc/src: c0, c1 at
+// +poly_stride), where M = sum_m W_m tau_{g_m}(I0) is formed on the fly from
+// the evaluation-form plaintext I0 (limb k at i0 + k*N): gs[m] = g_m,
+// cw[2*(m*cw_stride + k)], +1 = W_m * 2^64 mod q_k and its shoup.  first:
+// overwrite acc instead of accumulating.
+void launch_mask_mac(const DevTables& t, const RowMap& acc, const RowMap& src, const uint64_t* i0,
+                     const uint32_t* gs, const uint64_t* cw, int n_terms, int cw_stride, bool first,
+                     hipStream_t s);
+
 // Rescale step 1 (coefficient form top limb, one row per batch element and
 // poly): t = (c_l + h) mod q_l with h = floor(q_l/2), then dst row k =
 // (t - h) mod q_{mod(k)}; rounding adds h to every coefficient, so it is

@@ -550,6 +550,38 @@ __global__ void __launch_bounds__(kThreads) k_rescale_combine(DevTables t, RowMa
 // bytes of `rows` polynomial rows (algorithmic traffic accounting for the profiler)
 #define NB(rows) ((double)(rows) * (double)(1 << t.logN) * 8.0)
 
+// Masked plaintext multiply-accumulate for block permutations.  For each
+// element x of limb k the plaintext mask is formed on the fly in Montgomery
+// form from the evaluation-form indicator I0 (rows [L+1][N]):
+//     M[x] = sum_m cw[m][k] * I0_k[perm_{g_m}(x)]     (cw = W_m * 2^64 mod q_k, Shoup)
+// and acc_p[x] (+)= mont(src_p[x], M[x]) for both polynomials p.
+__global__ void __launch_bounds__(kThreads) k_mask_mac(DevTables t, RowMap acc, RowMap src, const uint64_t* i0,
+                                                       const uint32_t* gs, const uint64_t* cw, int n_terms,
+                                                       int cw_stride, int first) {
+    EW_PROLOGUE(acc)
+    int mod, ms;
+    uint64_t* pa = map_row(acc, b, k, logN, mod);
+    const uint64_t* ps = map_row(src, b, k, logN, ms);
+    const Modulus md = t.mods[mod];
+    const uint64_t* row = i0 + ((size_t)k << logN);
+    for (int uu = 0; uu < kEwPerThread; ++uu) {
+        const int i = base_i + uu * kThreads;
+        uint64_t M = 0;
+        for (int m = 0; m < n_terms; ++m) {
+            const uint64_t* c = cw + 2 * ((size_t)m * cw_stride + k);
+            M = add_mod(M, mul_shoup(row[galois_perm((uint32_t)i, gs[m], logN)], c[0], c[1], md.q), md.q);
+        }
+        uint64_t r0 = mul_mont(ps[i], M, md.q, md.qneg_inv);
+        uint64_t r1 = mul_mont(ps[i + src.poly_stride], M, md.q, md.qneg_inv);
+        if (!first) {
+            r0 = add_mod(r0, pa[i], md.q);
+            r1 = add_mod(r1, pa[i + acc.poly_stride], md.q);
+        }
+        pa[i] = r0;
+        pa[i + acc.poly_stride] = r1;
+    }
+}
+
 inline int ew_blocks(const DevTables& t, const RowMap& m) {
     return m.rows() * ((1 << t.logN) / (kThreads * kEwPerThread));
 }
@@ -562,11 +594,11 @@ void launch_ntt(const DevTables& t, const RowMap& m, bool inverse, hipStream_t s
     const int blocks = m.rows() * (int)(((size_t)1 << t.logN) / kNttBlockElems);
     const double bytes = NB(m.rows()) * 2;
     if (!inverse) {
-        { ProfScope ps_("k_ntt_cols", s, bytes); dispatch_ntt_pass(t, m, true, false, blocks, s); }
-        { ProfScope ps_("k_ntt_rows", s, bytes); dispatch_ntt_pass(t, m, false, false, blocks, s); }
+        { ProfScope ps_("k_ntt_pass<cols,fwd>", s, bytes); dispatch_ntt_pass(t, m, true, false, blocks, s); }
+        { ProfScope ps_("k_ntt_pass<rows,fwd>", s, bytes); dispatch_ntt_pass(t, m, false, false, blocks, s); }
     } else {
-        { ProfScope ps_("k_ntt_rows", s, bytes); dispatch_ntt_pass(t, m, false, true, blocks, s); }
-        { ProfScope ps_("k_ntt_cols", s, bytes); dispatch_ntt_pass(t, m, true, true, blocks, s); }
+        { ProfScope ps_("k_ntt_pass<rows,inv>", s, bytes); dispatch_ntt_pass(t, m, false, true, blocks, s); }
+        { ProfScope ps_("k_ntt_pass<cols,inv>", s, bytes); dispatch_ntt_pass(t, m, true, true, blocks, s); }
     }
 }
 
@@ -644,6 +676,14 @@ void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap&
     if (!out.rows()) return;
     { ProfScope ps_("k_moddown_combine", s, NB(out.rows()) * (6 + (addend.n ? (addend_both ? 2 : 1) : 0))); hipLaunchKernelGGL(k_moddown_combine, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, u, conv,
                        addend, g_add, addend_both ? 1 : 0, consts); }
+}
+
+void launch_mask_mac(const DevTables& t, const RowMap& acc, const RowMap& src, const uint64_t* i0, const uint32_t* gs,
+                     const uint64_t* cw, int n_terms, int cw_stride, bool first, hipStream_t s) {
+    if (!acc.rows() || n_terms <= 0) return;
+    ProfScope ps_("k_mask_mac", s, NB(acc.rows()) * (first ? 4 : 6) + NB(acc.rows()) * n_terms);
+    hipLaunchKernelGGL(k_mask_mac, dim3(ew_blocks(t, acc)), dim3(kThreads), 0, s, t, acc, src, i0, gs, cw, n_terms,
+                       cw_stride, first ? 1 : 0);
 }
 
 void launch_rescale_spread(const DevTables& t, const RowMap& dst, const RowMap& top, uint32_t top_mod, hipStream_t s) {

@@ -1,10 +1,739 @@
-// Encrypted CSR matrix-factorisation program.
+// Encrypted CSR matrix-factorisation program: Alg. 1 of the paper evaluated
+// as a synchronous epoch (every rating's error uses the epoch-start factors,
+// the per-entity gradient terms are accumulated and applied once, as the
+// accumulator of Alg. 2 does), over block-packed CSR rating ciphertexts.
+//
+// Layout (k' = 2^ceil(log2 k), B = 2k', D = N/(2B) blocks per ciphertext):
+//   rating ciphertexts: rows packed greedily in CSR order (a row that does not
+//   fit starts a new ciphertext, a row longer than D is cut into chunks of D);
+//   block t holding rating (i, j) carries r_ij / u_i / v_j in slots tB..tB+k-1.
+//   factor tables: table ciphertext a holds entity a*D + b at block b.
+// Epoch (gathered factors at level l):
+//   P = HMult(Ug, Vg); T_{s+1} = T_s + Rot(T_s, 2^s), s < log2 B;
+//   Sdot = Rot(T, -k') (slot tB+f holds <u_i, v_j>);
+//   E = drop(Rescale(R * W_R)) - Sdot, W_R = rint((S_P * q_L) / S_R);
+//   G_U = HMult(E, Vg), G_V = HMult(E, Ug);
+//   tables <- BlockPermute(G -> tables, learning-rate weights) + self term;
+//   gathered factors <- BlockPermute(tables -> rating layout, weight 1).
+// BlockPermute (move: source c, block a -> destination block b, weight w;
+// (a - b) mod D = gamma*G + beta, G = 2^ceil(log2(D)/2)):
+//   acc_d = sum_gamma Rot_{gamma G B}( sum_{c,beta} HRot_{beta B}(src_c) (.) M_{d,c,gamma,beta} )
+//   M = sum_moves W * tau_{g_p}(I0), p = (b + gamma G) mod D, g_p = 5^((-pB) mod N/2),
+//   W = rint((w * 2^40 * q_ell) / (S_src * 2^20)); one rescale per destination.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
 #include "context.h"
+#include "host_math.h"
 
 namespace csrmf {
 
-struct MfState {};
+namespace {
+constexpr double kMaskScale = 1048576.0;           // 2^20
+constexpr double kTargetScale = 1099511627776.0;   // 2^40
+}  // namespace
+
+struct MfState {
+    int k = 0, kp = 0, B = 0, D = 0, G = 0;
+    int n_users = 0, n_items = 0, nnz = 0;
+    int n_ct = 0, n_utab = 0, n_vtab = 0;
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col_idx;
+    std::vector<int32_t> rows, ct_of, blk_of;
+    std::vector<double> deg_u, deg_v;
+    std::vector<uint64_t> R, Utab, Vtab, Ug, Vg, Sdot, Pred;   // handles
+    uint64_t* mask0 = nullptr;                                  // I0, evaluation form [L+1][N]
+    int epochs_done = 0;
+    bool factors = false;
+};
 
 void destroy_mf(MfState* m) { delete m; }
 
+namespace {
+
+struct Move {
+    int src, a, b;
+    double w;
+};
+
+void free_handles(Context* c, std::vector<uint64_t>& v) {
+    for (uint64_t h : v) c->free_ct(h);
+    v.clear();
+}
+
+std::vector<Ct*> cts_of(Context* c, const std::vector<uint64_t>& v) {
+    std::vector<Ct*> out;
+    for (uint64_t h : v) out.push_back(&c->get(h));
+    return out;
+}
+
+MfState& state(Context* c) {
+    if (!c->mf) throw Error(CSRMF_E_STATE, "no rating matrix has been encrypted");
+    return *c->mf;
+}
+
+// Validate the CSR arrays and compute the block layout.
+MfState* make_layout(Context* c, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr, const int32_t* col_idx) {
+    if (n_rows <= 0 || n_cols <= 0 || !row_ptr || !col_idx) throw Error(CSRMF_E_INVAL, "empty or null CSR matrix");
+    const int k = c->prm.k;
+    if (k <= 0) throw Error(CSRMF_E_INVAL, "params.k must be positive for the MF program");
+    if (row_ptr[0] != 0) throw Error(CSRMF_E_INVAL, "row_ptr[0] must be 0");
+    for (int i = 0; i < n_rows; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i]) throw Error(CSRMF_E_INVAL, "row_ptr is not monotone");
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            if (col_idx[p] < 0 || col_idx[p] >= n_cols) throw Error(CSRMF_E_INVAL, "column index out of range");
+            if (p > row_ptr[i] && col_idx[p] <= col_idx[p - 1])
+                throw Error(CSRMF_E_INVAL, "column indices unsorted or duplicated within a row");
+        }
+    }
+    const int64_t nnz = row_ptr[n_rows];
+    if (nnz <= 0 || nnz > (int64_t)1 << 30) throw Error(CSRMF_E_INVAL, "bad number of ratings");
+    MfState* m = new MfState();
+    m->k = k;
+    m->kp = 1;
+    while (m->kp < k) m->kp *= 2;
+    m->B = 2 * m->kp;
+    m->D = (int)(c->N / (2 * (uint64_t)m->B));
+    int logD = 0;
+    while ((1 << (logD + 1)) <= m->D) ++logD;
+    m->G = 1 << ((logD + 1) / 2);
+    m->n_users = n_rows;
+    m->n_items = n_cols;
+    m->nnz = (int)nnz;
+    m->row_ptr.assign(row_ptr, row_ptr + n_rows + 1);
+    m->col_idx.assign(col_idx, col_idx + nnz);
+    m->rows.resize(nnz);
+    m->ct_of.resize(nnz);
+    m->blk_of.resize(nnz);
+    m->deg_u.assign(n_rows, 0.0);
+    m->deg_v.assign(n_cols, 0.0);
+    int ct = 0, used = 0;
+    bool started = false;
+    for (int i = 0; i < n_rows; ++i) {
+        int64_t pos = row_ptr[i];
+        const int64_t e = row_ptr[i + 1];
+        while (pos < e) {
+            const int chunk = (int)std::min<int64_t>(m->D, e - pos);
+            if (!started) started = true;
+            else if (used + chunk > m->D) { ++ct; used = 0; }
+            for (int q = 0; q < chunk; ++q) {
+                m->ct_of[pos + q] = ct;
+                m->blk_of[pos + q] = used + q;
+                m->rows[pos + q] = i;
+            }
+            used += chunk;
+            pos += chunk;
+        }
+        m->deg_u[i] = (double)(e - row_ptr[i]);
+    }
+    for (int64_t p = 0; p < nnz; ++p) m->deg_v[col_idx[p]] += 1.0;
+    m->n_ct = ct + 1;
+    m->n_utab = (n_rows + m->D - 1) / m->D;
+    m->n_vtab = (n_cols + m->D - 1) / m->D;
+    return m;
+}
+
+// slot vectors of all rating-layout ciphertexts in one pass over the ratings
+// (which: 0 ratings, 1 users, 2 items)
+void fill_rating_slots(const MfState& m, int which, const double* values, const double* U, const double* V,
+                       std::vector<std::vector<double>>& zs) {
+    for (auto& z : zs) std::fill(z.begin(), z.end(), 0.0);
+    for (int r = 0; r < m.nnz; ++r) {
+        double* dst = zs[m.ct_of[r]].data() + (size_t)m.blk_of[r] * m.B;
+        for (int f = 0; f < m.k; ++f) {
+            if (which == 0) dst[f] = values[r];
+            else if (which == 1) dst[f] = U[(size_t)m.rows[r] * m.k + f];
+            else dst[f] = V[(size_t)m.col_idx[r] * m.k + f];
+        }
+    }
+}
+
+void fill_table_slots(const MfState& m, int a, int n_ent, const double* F, std::vector<double>& z) {
+    std::fill(z.begin(), z.end(), 0.0);
+    for (int b = 0; b < m.D; ++b) {
+        const int e = a * m.D + b;
+        if (e >= n_ent) break;
+        for (int f = 0; f < m.k; ++f) z[(size_t)b * m.B + f] = F[(size_t)e * m.k + f];
+    }
+}
+
+std::vector<int64_t> encode_all(Context* c, const std::vector<std::vector<double>>& zs, double scale) {
+    std::vector<int64_t> out(zs.size() * c->N);
+    for (size_t i = 0; i < zs.size(); ++i)
+        if (!ckks_encode(zs[i].data(), (int)zs[i].size(), c->logN, scale, out.data() + i * c->N))
+            throw Error(CSRMF_E_INVAL, "value too large to encode");
+    return out;
+}
+
+std::vector<uint64_t> encrypt_list(Context* c, const int64_t* m, int count, double scale) {
+    std::vector<Ct> cts;
+    c->encrypt_int_batch(m, count, c->L, scale, cts);
+    std::vector<uint64_t> h;
+    for (auto& x : cts) h.push_back(c->put(x));
+    return h;
+}
+
+void upload_mask(Context* c, MfState& m, const int64_t* mask) {
+    if (!m.mask0) m.mask0 = (uint64_t*)c->pool.get((size_t)(c->L + 1) * c->N * 8);
+    Scratch src(c->pool, c->N);
+    CSRMF_HIP(hipMemcpyAsync(src.p, mask, c->N * 8, hipMemcpyHostToDevice, c->stream));
+    RowMap mm;
+    mm.base = m.mask0;
+    for (int i = 0; i <= c->L; ++i) mm.push(i, i);
+    launch_expand_signed(c->tabs, mm, (const int64_t*)src.p, 1, 0, c->stream);
+    launch_ntt(c->tabs, mm, false, c->stream);
+    CSRMF_HIP(hipStreamSynchronize(c->stream));
+}
+
+// Ct views at a lower level (same device buffer)
+std::vector<Ct> dropped(const std::vector<Ct*>& v, int level) {
+    std::vector<Ct> out;
+    for (Ct* x : v) {
+        if (x->level < level) throw Error(CSRMF_E_LEVEL, "cannot raise a level");
+        Ct y = *x;
+        y.level = level;
+        out.push_back(y);
+    }
+    return out;
+}
+
+std::vector<Ct*> ptrs(std::vector<Ct>& v) {
+    std::vector<Ct*> out;
+    for (auto& x : v) out.push_back(&x);
+    return out;
+}
+
+void release(Context* c, std::vector<Ct>& v) {
+    for (auto& x : v) c->pool.put(x.d);
+    v.clear();
+}
+
+std::vector<Ct> hmult_all(Context* c, const std::vector<Ct*>& a, const std::vector<Ct*>& b) {
+    std::vector<Ct> out(a.size());
+    std::vector<Ct*> po = ptrs(out);
+    c->mul_relin(a, b, po);
+    c->rescale(po);
+    return out;
+}
+
+std::vector<Ct> rotate_all(Context* c, const std::vector<Ct*>& a, int64_t r) {
+    std::vector<Ct> out(a.size());
+    std::vector<Ct*> po = ptrs(out);
+    c->rotate(a, c->galois_for_step(r), po);
+    return out;
+}
+
+std::vector<Ct> add_all(Context* c, const std::vector<Ct*>& a, const std::vector<Ct*>& b, bool sub) {
+    std::vector<Ct> out(a.size());
+    std::vector<Ct*> po = ptrs(out);
+    c->add_batch(a, b, po, sub);
+    return out;
+}
+
+int64_t weight_int(double w, double s_src, double q_acc) {
+    return (int64_t)std::nearbyint((w * kTargetScale * q_acc) / (s_src * kMaskScale));
+}
+
+// srcs: source ciphertexts (viewed at `level`); dests[d]: moves into destination d;
+// selfs[d]: optional (table ciphertext, [(block, w)]) term.
+std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& srcs,
+                              const std::vector<std::vector<Move>>& dests,
+                              const std::vector<std::pair<Ct*, std::vector<std::pair<int, double>>>>* selfs,
+                              int level) {
+    const int D = m.D, G = m.G, B = m.B;
+    const int nl = level + 1;
+    const double s_src = srcs.empty() ? 1.0 : srcs[0]->scale;
+    const uint64_t q_top = c->moduli[level];
+    const double q_acc = (double)q_top;
+    const double acc_scale = kTargetScale * q_acc;
+    // hoisted baby rotations of every source that is used
+    std::map<int, std::map<int, Ct>> baby;      // source -> beta -> ciphertext (beta 0 = the source view)
+    std::map<int, std::vector<int>> need;
+    for (auto& mv : dests)
+        for (const Move& x : mv) {
+            const int beta = ((x.a - x.b) % D + D) % D % G;
+            auto& v = need[x.src];
+            if (std::find(v.begin(), v.end(), beta) == v.end()) v.push_back(beta);
+        }
+    for (auto& kv : need) {
+        Ct src = *srcs[kv.first];
+        src.level = level;
+        std::vector<uint32_t> gs;
+        std::vector<int> betas;
+        for (int beta : kv.second)
+            if (beta) { betas.push_back(beta); gs.push_back(c->galois_for_step((int64_t)beta * B)); }
+        baby[kv.first][0] = src;   // view, not owned
+        if (!gs.empty()) {
+            std::vector<Ct> outs(gs.size());
+            std::vector<Ct*> po = ptrs(outs);
+            c->rotate_hoisted(src, gs, po);
+            for (size_t i = 0; i < betas.size(); ++i) baby[kv.first][betas[i]] = outs[i];
+        }
+    }
+    // per-limb Montgomery constants of an integer weight
+    auto wconst = [&](int64_t W, std::vector<uint64_t>& out) {
+        for (int i = 0; i < nl; ++i) {
+            const uint64_t q = c->moduli[i];
+            const uint64_t r = mul_mod_host(from_signed(W, q), c->mh[i].r_mod, q);
+            out.push_back(r);
+            out.push_back(shoup_pre(r, q));
+        }
+    };
+    auto gal = [&](int p) { return c->galois_for_step(-(int64_t)p * B); };
+    RowMap mask_rows;   // unused placeholder for clarity
+    (void)mask_rows;
+    std::vector<Ct> outs;
+    const int n_dest = (int)dests.size();
+    for (int d = 0; d < n_dest; ++d) {
+        // group the moves: gamma -> (source, beta) -> terms
+        std::map<int, std::map<std::pair<int, int>, std::vector<std::pair<int, int64_t>>>> groups;
+        for (const Move& x : dests[d]) {
+            const int delta = ((x.a - x.b) % D + D) % D;
+            const int gamma = delta / G, beta = delta % G;
+            const int p = (x.b + gamma * G) % D;
+            groups[gamma][{x.src, beta}].push_back({p, weight_int(x.w, s_src, q_acc)});
+        }
+        std::vector<std::pair<int, int64_t>> self_terms;
+        Ct self_src;
+        const bool has_self = selfs && (*selfs)[d].first;
+        if (has_self) {
+            self_src = *(*selfs)[d].first;
+            self_src.level = level;
+            for (auto& bw : (*selfs)[d].second) self_terms.push_back({bw.first, weight_int(bw.second, self_src.scale, q_acc)});
+        }
+        // upload all terms of this destination at once
+        std::vector<uint32_t> gs;
+        std::vector<uint64_t> cw;
+        struct Launch { int gamma; Ct* src; int first_term; int n_terms; };
+        std::vector<Launch> launches;
+        for (auto& g : groups)
+            for (auto& cb : g.second) {
+                Launch L{g.first, &baby[cb.first.first][cb.first.second], (int)gs.size(), (int)cb.second.size()};
+                for (auto& t : cb.second) { gs.push_back(gal(t.first)); wconst(t.second, cw); }
+                launches.push_back(L);
+            }
+        const int self_first = (int)gs.size();
+        for (auto& t : self_terms) { gs.push_back(gal(t.first)); wconst(t.second, cw); }
+        Scratch dgs(c->pool, (gs.size() + 1) / 2 + 1), dcw(c->pool, cw.size() + 1);
+        if (!gs.empty()) {
+            CSRMF_HIP(hipMemcpyAsync(dgs.p, gs.data(), gs.size() * 4, hipMemcpyHostToDevice, c->stream));
+            CSRMF_HIP(hipMemcpyAsync(dcw.p, cw.data(), cw.size() * 8, hipMemcpyHostToDevice, c->stream));
+            CSRMF_HIP(hipStreamSynchronize(c->stream));
+        }
+        Ct acc = c->new_ct(level, acc_scale);
+        bool acc_empty = true;
+        for (auto& g : groups) {
+            const int gamma = g.first;
+            Ct inner = gamma ? c->new_ct(level, acc_scale) : acc;
+            bool first = gamma ? true : acc_empty;
+            for (const Launch& L : launches) {
+                if (L.gamma != gamma) continue;
+                launch_mask_mac(c->tabs, c->map_ct(inner.d, nl), c->map_ct(L.src->d, nl), m.mask0,
+                                (const uint32_t*)dgs.p + L.first_term, dcw.p + 2 * (size_t)L.first_term * nl,
+                                L.n_terms, nl, first, c->stream);
+                first = false;
+            }
+            if (gamma) {
+                std::vector<Ct*> in{&inner};
+                Ct rot;
+                std::vector<Ct*> out{&rot};
+                c->rotate(in, c->galois_for_step((int64_t)gamma * G * B), out);
+                c->pool.put(inner.d);
+                if (acc_empty) {
+                    c->pool.put(acc.d);
+                    acc = rot;
+                    acc.scale = acc_scale;
+                } else {
+                    std::vector<Ct*> a{&acc}, b{&rot};
+                    Ct sum;
+                    std::vector<Ct*> o{&sum};
+                    c->add_batch(a, b, o, false);
+                    c->pool.put(acc.d);
+                    c->pool.put(rot.d);
+                    acc = sum;
+                }
+            }
+            acc_empty = false;
+        }
+        if (has_self && !self_terms.empty()) {
+            launch_mask_mac(c->tabs, c->map_ct(acc.d, nl), c->map_ct(self_src.d, nl), m.mask0,
+                            (const uint32_t*)dgs.p + self_first, dcw.p + 2 * (size_t)self_first * nl,
+                            (int)self_terms.size(), nl, acc_empty, c->stream);
+            acc_empty = false;
+        }
+        if (acc_empty) throw Error(CSRMF_E_INVAL, "block permutation with an empty destination");
+        acc.scale = acc_scale;
+        std::vector<Ct*> v{&acc};
+        c->rescale(v);
+        outs.push_back(acc);
+    }
+    for (auto& kv : baby)
+        for (auto& bc : kv.second)
+            if (bc.first) c->pool.put(bc.second.d);
+    return outs;
+}
+
+std::vector<Ct> scatter(Context* c, MfState& m, const std::vector<Ct*>& Gs, const std::vector<uint64_t>& tabs,
+                        bool users, double a_t, int level) {
+    const double lam = c->prm.lambda;
+    const int n_ent = users ? m.n_users : m.n_items;
+    const std::vector<double>& deg = users ? m.deg_u : m.deg_v;
+    std::vector<std::vector<Move>> moves(tabs.size());
+    for (int r = 0; r < m.nnz; ++r) {
+        const int e = users ? m.rows[r] : m.col_idx[r];
+        const double w = c->prm.rule == 2 ? a_t / deg[e] : a_t;
+        moves[e / m.D].push_back({m.ct_of[r], m.blk_of[r], e % m.D, w});
+    }
+    std::vector<std::pair<Ct*, std::vector<std::pair<int, double>>>> selfs(tabs.size());
+    for (size_t d = 0; d < tabs.size(); ++d) {
+        selfs[d].first = &c->get(tabs[d]);
+        for (int b = 0; b < m.D; ++b) {
+            const int e = (int)d * m.D + b;
+            if (e >= n_ent) break;
+            double w;
+            if (c->prm.rule == 2) w = deg[e] > 0 ? (1.0 - a_t * lam) : 1.0;
+            else w = 1.0 - a_t * lam * deg[e];
+            selfs[d].second.push_back({b, w});
+        }
+    }
+    return block_permute(c, m, Gs, moves, &selfs, level);
+}
+
+std::vector<Ct> gather(Context* c, MfState& m, const std::vector<uint64_t>& tabs, bool users) {
+    std::vector<std::vector<Move>> moves(m.n_ct);
+    for (int r = 0; r < m.nnz; ++r) {
+        const int e = users ? m.rows[r] : m.col_idx[r];
+        moves[m.ct_of[r]].push_back({e / m.D, e % m.D, m.blk_of[r], 1.0});
+    }
+    std::vector<Ct*> srcs = cts_of(c, tabs);
+    return block_permute(c, m, srcs, moves, nullptr, srcs[0]->level);
+}
+
+std::vector<uint64_t> put_all(Context* c, std::vector<Ct>& v) {
+    std::vector<uint64_t> h;
+    for (auto& x : v) h.push_back(c->put(x));
+    v.clear();
+    return h;
+}
+
+// Forward dot products of gathered factors: HMult + windowed block sum.
+std::vector<Ct> dot_products(Context* c, MfState& m, const std::vector<Ct*>& ug, const std::vector<Ct*>& vg,
+                             double* sp_out) {
+    std::vector<Ct> T = hmult_all(c, ug, vg);
+    if (sp_out) *sp_out = T[0].scale;
+    for (int s = 1; s < m.B; s *= 2) {
+        std::vector<Ct*> pt = ptrs(T);
+        std::vector<Ct> rot = rotate_all(c, pt, s);
+        std::vector<Ct*> pr = ptrs(rot);
+        std::vector<Ct> sum = add_all(c, pt, pr, false);
+        release(c, T);
+        release(c, rot);
+        T = std::move(sum);
+    }
+    std::vector<Ct*> pt = ptrs(T);
+    std::vector<Ct> S = rotate_all(c, pt, -(int64_t)m.kp);
+    release(c, T);
+    return S;
+}
+
+void run_epoch(Context* c, MfState& m, bool last) {
+    const double a_t = c->prm.lr / (1.0 + c->prm.damp * (double)m.epochs_done);
+    std::vector<Ct*> ug = cts_of(c, m.Ug), vg = cts_of(c, m.Vg), R = cts_of(c, m.R);
+    const int lvl = ug[0]->level;
+    if (lvl < 3 + (last ? 0 : 1)) throw Error(CSRMF_E_LEVEL, "not enough levels left for an epoch");
+    double sp = 0;
+    std::vector<Ct> S = dot_products(c, m, ug, vg, &sp);
+    const int slv = S[0].level;
+    // R_e = drop(Rescale(R * W_R)); E = R_e - Sdot
+    const double q_R = (double)c->moduli[R[0]->level];
+    const int64_t WR = (int64_t)std::nearbyint((sp * q_R) / R[0]->scale);
+    std::vector<Ct> Re(m.n_ct);
+    for (int i = 0; i < m.n_ct; ++i) c->mul_int(*R[i], WR, Re[i]);
+    std::vector<Ct*> pre = ptrs(Re);
+    c->rescale(pre);
+    for (auto& x : Re) x.level = slv;
+    std::vector<Ct*> ps = ptrs(S);
+    std::vector<Ct> E = add_all(c, pre, ps, true);
+    release(c, Re);
+    const int elv = E[0].level;
+    std::vector<Ct*> pe = ptrs(E);
+    std::vector<Ct> vgd = dropped(vg, elv), ugd = dropped(ug, elv);
+    std::vector<Ct*> pvgd = ptrs(vgd), pugd = ptrs(ugd);
+    std::vector<Ct> GU = hmult_all(c, pe, pvgd);
+    std::vector<Ct> GV = hmult_all(c, pe, pugd);
+    release(c, E);
+    const int glv = GU[0].level;
+    std::vector<Ct*> pgu = ptrs(GU), pgv = ptrs(GV);
+    std::vector<Ct> nu = scatter(c, m, pgu, m.Utab, true, a_t, glv);
+    std::vector<Ct> nv = scatter(c, m, pgv, m.Vtab, false, a_t, glv);
+    release(c, GU);
+    release(c, GV);
+    free_handles(c, m.Utab);
+    free_handles(c, m.Vtab);
+    m.Utab = put_all(c, nu);
+    m.Vtab = put_all(c, nv);
+    free_handles(c, m.Sdot);
+    m.Sdot = put_all(c, S);
+    if (!last) {
+        std::vector<Ct> gu = gather(c, m, m.Utab, true);
+        std::vector<Ct> gv = gather(c, m, m.Vtab, false);
+        free_handles(c, m.Ug);
+        free_handles(c, m.Vg);
+        m.Ug = put_all(c, gu);
+        m.Vg = put_all(c, gv);
+    }
+    m.epochs_done++;
+}
+
+void decrypt_slots(Context* c, uint64_t h, std::vector<double>& z) {
+    const Ct& ct = c->get(h);
+    std::vector<int64_t> mm(c->N);
+    c->decrypt_int(ct, mm.data());
+    z.assign(c->N / 2, 0.0);
+    ckks_decode(mm.data(), c->logN, ct.scale, z.data(), (int)(c->N / 2));
+}
+
+}  // namespace
+
 }  // namespace csrmf
+
+using csrmf::Context;
+using csrmf::Error;
+using csrmf::MfState;
+
+#define API_BEGIN(ctx)                 \
+    if (!(ctx)) return CSRMF_E_INVAL;  \
+    try {
+#define API_END_EARLY                  \
+    { c->err.clear(); return CSRMF_OK; }
+#define API_END(ctx)                   \
+        (ctx)->err.clear();            \
+        return CSRMF_OK;               \
+    } catch (const Error& e) {         \
+        (ctx)->err = e.what();         \
+        return e.code;                 \
+    } catch (const std::bad_alloc&) {  \
+        (ctx)->err = "host allocation failed"; \
+        return CSRMF_E_NOMEM;          \
+    } catch (const std::exception& e) { \
+        (ctx)->err = e.what();         \
+        return CSRMF_E_DEVICE;         \
+    }
+
+static void install_layout(Context* c, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr, const int32_t* col_idx) {
+    if (!c->have_keys) throw Error(CSRMF_E_STATE, "keygen first");
+    MfState* m = csrmf::make_layout(c, n_rows, n_cols, row_ptr, col_idx);
+    if (c->mf) {
+        csrmf::free_handles(c, c->mf->R);
+        csrmf::free_handles(c, c->mf->Utab);
+        csrmf::free_handles(c, c->mf->Vtab);
+        csrmf::free_handles(c, c->mf->Ug);
+        csrmf::free_handles(c, c->mf->Vg);
+        csrmf::free_handles(c, c->mf->Sdot);
+        csrmf::free_handles(c, c->mf->Pred);
+        if (c->mf->mask0) c->pool.put(c->mf->mask0);
+        delete c->mf;
+    }
+    c->mf = m;
+}
+
+extern "C" {
+
+int csrmf_encrypt_csr_rows(csrmf_ctx* cx, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr,
+                           const int32_t* col_idx, const double* values, int32_t* n_ct) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    if (!values) throw Error(CSRMF_E_INVAL, "values");
+    for (int64_t p = 0; row_ptr && n_rows > 0 && p < row_ptr[n_rows]; ++p)
+        if (!std::isfinite(values[p])) throw Error(CSRMF_E_INVAL, "non-finite rating");
+    install_layout(c, n_rows, n_cols, row_ptr, col_idx);
+    MfState& m = *c->mf;
+    std::vector<std::vector<double>> zs(m.n_ct, std::vector<double>(c->N / 2));
+    csrmf::fill_rating_slots(m, 0, values, nullptr, nullptr, zs);
+    const double scale = std::ldexp(1.0, c->prm.log2_scale);
+    std::vector<int64_t> pt = csrmf::encode_all(c, zs, scale);
+    m.R = csrmf::encrypt_list(c, pt.data(), m.n_ct, scale);
+    if (n_ct) *n_ct = m.n_ct;
+    API_END(c)
+}
+
+int csrmf_encrypt_csr_rows_int(csrmf_ctx* cx, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr,
+                               const int32_t* col_idx, const int64_t* plain, int32_t n_plain, int32_t* n_ct) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    if (!plain) throw Error(CSRMF_E_INVAL, "plaintexts");
+    install_layout(c, n_rows, n_cols, row_ptr, col_idx);
+    MfState& m = *c->mf;
+    if (n_plain != m.n_ct) throw Error(CSRMF_E_INVAL, "number of plaintexts differs from the layout's ciphertexts");
+    m.R = csrmf::encrypt_list(c, plain, m.n_ct, std::ldexp(1.0, c->prm.log2_scale));
+    if (n_ct) *n_ct = m.n_ct;
+    API_END(c)
+}
+
+int csrmf_mf_layout(const csrmf_ctx* cx, int32_t* n_ct, int32_t* n_utab, int32_t* n_vtab, int32_t* D, int32_t* B) {
+    Context* c = const_cast<Context*>(reinterpret_cast<const Context*>(cx));
+    API_BEGIN(c)
+    MfState& m = csrmf::state(c);
+    if (n_ct) *n_ct = m.n_ct;
+    if (n_utab) *n_utab = m.n_utab;
+    if (n_vtab) *n_vtab = m.n_vtab;
+    if (D) *D = m.D;
+    if (B) *B = m.B;
+    API_END(c)
+}
+
+int csrmf_init_factors(csrmf_ctx* cx, const double* U0, const double* V0) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    MfState& m = csrmf::state(c);
+    if (!U0 || !V0) throw Error(CSRMF_E_INVAL, "factors");
+    const double scale = std::ldexp(1.0, c->prm.log2_scale);
+    std::vector<std::vector<double>> zu(m.n_utab, std::vector<double>(c->N / 2)), zv(m.n_vtab, std::vector<double>(c->N / 2));
+    std::vector<std::vector<double>> gu(m.n_ct, std::vector<double>(c->N / 2)), gv(m.n_ct, std::vector<double>(c->N / 2));
+    for (int a = 0; a < m.n_utab; ++a) csrmf::fill_table_slots(m, a, m.n_users, U0, zu[a]);
+    for (int a = 0; a < m.n_vtab; ++a) csrmf::fill_table_slots(m, a, m.n_items, V0, zv[a]);
+    csrmf::fill_rating_slots(m, 1, nullptr, U0, V0, gu);
+    csrmf::fill_rating_slots(m, 2, nullptr, U0, V0, gv);
+    std::vector<int64_t> pu = csrmf::encode_all(c, zu, scale), pv = csrmf::encode_all(c, zv, scale);
+    std::vector<int64_t> pgu = csrmf::encode_all(c, gu, scale), pgv = csrmf::encode_all(c, gv, scale);
+    std::vector<double> ind(c->N / 2, 0.0);
+    for (int f = 0; f < m.k; ++f) ind[f] = 1.0;
+    std::vector<int64_t> mask(c->N);
+    csrmf::ckks_encode(ind.data(), (int)ind.size(), c->logN, csrmf::kMaskScale, mask.data());
+    for (auto* v : {&m.Utab, &m.Vtab, &m.Ug, &m.Vg}) csrmf::free_handles(c, *v);
+    m.Utab = csrmf::encrypt_list(c, pu.data(), m.n_utab, scale);
+    m.Vtab = csrmf::encrypt_list(c, pv.data(), m.n_vtab, scale);
+    m.Ug = csrmf::encrypt_list(c, pgu.data(), m.n_ct, scale);
+    m.Vg = csrmf::encrypt_list(c, pgv.data(), m.n_ct, scale);
+    csrmf::upload_mask(c, m, mask.data());
+    m.factors = true;
+    m.epochs_done = 0;
+    API_END(c)
+}
+
+int csrmf_init_factors_int(csrmf_ctx* cx, const int64_t* utab, const int64_t* vtab, const int64_t* ug,
+                           const int64_t* vg, const int64_t* mask0) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    MfState& m = csrmf::state(c);
+    if (!utab || !vtab || !ug || !vg || !mask0) throw Error(CSRMF_E_INVAL, "plaintexts");
+    const double scale = std::ldexp(1.0, c->prm.log2_scale);
+    for (auto* v : {&m.Utab, &m.Vtab, &m.Ug, &m.Vg}) csrmf::free_handles(c, *v);
+    m.Utab = csrmf::encrypt_list(c, utab, m.n_utab, scale);
+    m.Vtab = csrmf::encrypt_list(c, vtab, m.n_vtab, scale);
+    m.Ug = csrmf::encrypt_list(c, ug, m.n_ct, scale);
+    m.Vg = csrmf::encrypt_list(c, vg, m.n_ct, scale);
+    csrmf::upload_mask(c, m, mask0);
+    m.factors = true;
+    m.epochs_done = 0;
+    API_END(c)
+}
+
+int csrmf_mf_epochs(csrmf_ctx* cx, int32_t n_epochs) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    MfState& m = csrmf::state(c);
+    if (!m.factors) throw Error(CSRMF_E_STATE, "init_factors first");
+    if (n_epochs < 0) throw Error(CSRMF_E_INVAL, "n_epochs");
+    if (n_epochs == 0) API_END_EARLY;
+    // Level budget of the whole request: an epoch on gathered factors uses 3
+    // levels, every further one 4 (its gather included).  After a previous
+    // call the factors are only in the tables, so they are gathered first.
+    const bool regather = m.Ug.empty();
+    const int lvl = regather ? c->get(m.Utab[0]).level - 1 : c->get(m.Ug[0]).level;
+    if (lvl < 3 + 4 * (n_epochs - 1)) throw Error(CSRMF_E_LEVEL, "not enough levels for the requested epochs");
+    if (regather) {
+        std::vector<csrmf::Ct> gu = csrmf::gather(c, m, m.Utab, true);
+        std::vector<csrmf::Ct> gv = csrmf::gather(c, m, m.Vtab, false);
+        m.Ug = csrmf::put_all(c, gu);
+        m.Vg = csrmf::put_all(c, gv);
+    }
+    for (int t = 0; t < n_epochs; ++t) csrmf::run_epoch(c, m, t + 1 == n_epochs);
+    if (n_epochs > 0) {
+        csrmf::free_handles(c, m.Ug);
+        csrmf::free_handles(c, m.Vg);
+    }
+    CSRMF_HIP(hipStreamSynchronize(c->stream));
+    API_END(c)
+}
+
+int csrmf_predict(csrmf_ctx* cx) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    MfState& m = csrmf::state(c);
+    if (!m.factors) throw Error(CSRMF_E_STATE, "init_factors first");
+    if (c->get(m.Utab[0]).level < 2) throw Error(CSRMF_E_LEVEL, "predict needs 2 levels (gather + product)");
+    std::vector<csrmf::Ct> gu = csrmf::gather(c, m, m.Utab, true);
+    std::vector<csrmf::Ct> gv = csrmf::gather(c, m, m.Vtab, false);
+    std::vector<csrmf::Ct*> pu = csrmf::ptrs(gu), pv = csrmf::ptrs(gv);
+    std::vector<csrmf::Ct> S = csrmf::dot_products(c, m, pu, pv, nullptr);
+    csrmf::release(c, gu);
+    csrmf::release(c, gv);
+    csrmf::free_handles(c, m.Pred);
+    m.Pred = csrmf::put_all(c, S);
+    API_END(c)
+}
+
+int csrmf_decrypt_factors(csrmf_ctx* cx, double* U, double* V) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    MfState& m = csrmf::state(c);
+    if (!m.factors) throw Error(CSRMF_E_STATE, "init_factors first");
+    if (!U || !V) throw Error(CSRMF_E_INVAL, "outputs");
+    std::vector<double> z;
+    for (int a = 0; a < m.n_utab; ++a) {
+        csrmf::decrypt_slots(c, m.Utab[a], z);
+        for (int b = 0; b < m.D && a * m.D + b < m.n_users; ++b)
+            for (int f = 0; f < m.k; ++f) U[(size_t)(a * m.D + b) * m.k + f] = z[(size_t)b * m.B + f];
+    }
+    for (int a = 0; a < m.n_vtab; ++a) {
+        csrmf::decrypt_slots(c, m.Vtab[a], z);
+        for (int b = 0; b < m.D && a * m.D + b < m.n_items; ++b)
+            for (int f = 0; f < m.k; ++f) V[(size_t)(a * m.D + b) * m.k + f] = z[(size_t)b * m.B + f];
+    }
+    API_END(c)
+}
+
+int csrmf_decrypt_predictions(csrmf_ctx* cx, double* rhat, int32_t which) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    MfState& m = csrmf::state(c);
+    if (!rhat) throw Error(CSRMF_E_INVAL, "output");
+    const std::vector<uint64_t>& src = which == 0 ? m.Sdot : m.Pred;
+    if (which != 0 && which != 1) throw Error(CSRMF_E_INVAL, "which must be 0 or 1");
+    if (src.empty()) throw Error(CSRMF_E_STATE, which == 0 ? "no epoch has run" : "csrmf_predict has not run");
+    std::vector<double> z;
+    int cur = -1;
+    for (int r = 0; r < m.nnz; ++r) {
+        if (m.ct_of[r] != cur) {
+            cur = m.ct_of[r];
+            csrmf::decrypt_slots(c, src[cur], z);
+        }
+        rhat[r] = z[(size_t)m.blk_of[r] * m.B];
+    }
+    API_END(c)
+}
+
+int csrmf_mf_handles(const csrmf_ctx* cx, int32_t which, uint64_t* out, int32_t cap, int32_t* n) {
+    Context* c = const_cast<Context*>(reinterpret_cast<const Context*>(cx));
+    API_BEGIN(c)
+    MfState& m = csrmf::state(c);
+    const std::vector<uint64_t>* v;
+    switch (which) {
+        case 0: v = &m.R; break;
+        case 1: v = &m.Utab; break;
+        case 2: v = &m.Vtab; break;
+        case 3: v = &m.Ug; break;
+        case 4: v = &m.Vg; break;
+        case 5: v = &m.Sdot; break;
+        case 6: v = &m.Pred; break;
+        default: throw Error(CSRMF_E_INVAL, "which");
+    }
+    if (n) *n = (int32_t)v->size();
+    for (int32_t i = 0; out && i < cap && i < (int32_t)v->size(); ++i) out[i] = (*v)[i];
+    API_END(c)
+}
+
+}  // extern "C"

@@ -14,8 +14,13 @@ from collections import defaultdict
 
 
 def short(name):
-    m = re.search(r"(k_[a-z_]+)(<[^>]*>)?", name)
-    return (m.group(1) + (m.group(2) or "")) if m else name[:60]
+    """Kernel name as bench.py's per-kernel profile reports it."""
+    m = re.search(r"k_ntt_pass<\d+, (true|false), (true|false)>", name)
+    if m:
+        return "k_ntt_pass<%s,%s>" % ("cols" if m.group(1) == "true" else "rows",
+                                      "inv" if m.group(2) == "true" else "fwd")
+    m = re.search(r"(k_[a-z_]+)", name)
+    return m.group(1) if m else name[:60]
 
 
 def main(argv):
@@ -38,11 +43,8 @@ def main(argv):
     print(f"{'kernel':42s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s}")
     for tot, k, n, avg in rows:
         print(f"{k:42s} {n:7d} {tot / 1e6:10.3f} {avg / 1e3:10.2f}")
-    groups = defaultdict(list)
-    for k, v in per.items():
-        groups[re.sub(r"<.*", "", k)].extend(v)
     for k, n in last.items():
-        v = sorted(groups.get(k, []))[-n:]
+        v = sorted(per.get(k, []))[-n:]
         if v:
             print(f"timed-step average of {k} over its last {len(v)} dispatches: "
                   f"{sum(d for _, d in v) / len(v) / 1e3:.2f} us")
