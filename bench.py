@@ -25,6 +25,10 @@ N_CT = 64
 LOGN = 16
 CHAIN = [1 << a for a in range(15)]
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of a kernel in the timed step, from rocprofv3 FETCH_SIZE +
+# WRITE_SIZE counters scaled by a plain copy of known size (see profiles/); only
+# valid for the kernel code the counters were taken on.
+TRAFFIC = {}
 
 
 def parse():
@@ -33,6 +37,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="copy a 512 MiB device buffer once before the timed steps (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -77,6 +83,8 @@ def main():
     ctx = pk.Context(pk.kernel_batch_params(), workloads.CRYPTO_SEED)
     ctx.keygen(CHAIN, conj=True)
     log(f"context + keys {time.perf_counter() - t0:.1f} s")
+    tune = ctx.autotune()
+    log(f"autotune {tune}")
     N = ctx.N
     L = ctx.L
     t0 = time.perf_counter()
@@ -123,6 +131,13 @@ def main():
             phase["hmult"] += t2 - t1
             phase["rotations"] += t3 - t2
 
+    if args.calib_copy:
+        src = torch.zeros(64 << 20, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy of 512 MiB done")
     for w in range(args.warmup):
         step(False)
         log(f"warmup step {w} done")
@@ -166,10 +181,11 @@ def main():
                                "64 HMult, 64 x 16 rotate-and-sum key switches",
                    "ciphertexts": N_CT, "log2N": LOGN, "limbs": L + 1, "special": ctx.alpha, "dnum": 3},
         "phase_ms_per_step": {k: round(1e3 * v / args.steps, 3) for k, v in phase.items()},
+        "autotune_ms": tune,
         "rotation_phase_rotations_per_s": round(n_rot * args.steps / phase["rotations"], 2),
         "roofline": {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "avg_launch_us": round(1e3 * avg_ms, 2)},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(name),
+                     "avg_launch_us": round(1e3 * avg_ms, 2), "launches_in_timed_steps": launches},
         "kernels": kernel_table,
     }
     if not args.no_cpu_baseline:

@@ -224,6 +224,18 @@ int csrmf_ntt_rows(csrmf_ctx* ctx, uint64_t* data, int32_t n_rows, const int32_t
                    int32_t n_idx, int32_t inverse);
 
 /* ------------------------------------------------------------------------ */
+/* Schedule autotuning.                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Time the candidate NTT schedules (rows transformed per pair of passes) on
+ * `rows` limbs of this context's ring (0: 64 ciphertexts x 2 x (L+1) limbs,
+ * the batched key-switching shape) with HIP events, and keep the fastest for
+ * all later work in the process.  Writes a JSON report of the timings into
+ * report (NUL-terminated, truncated to cap bytes; may be NULL).
+ * Errors: NOMEM, DEVICE. */
+int csrmf_autotune(csrmf_ctx* ctx, int32_t rows, char* report, int32_t cap);
+
+/* ------------------------------------------------------------------------ */
 /* Per-kernel timing (benchmark hook; process-wide).                         */
 /* ------------------------------------------------------------------------ */
 

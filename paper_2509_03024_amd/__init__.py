@@ -93,6 +93,7 @@ _SIGS = {
     "csrmf_decrypt_factors": [_p, _dp, _dp],
     "csrmf_decrypt_predictions": [_p, _dp, ctypes.c_int32],
     "csrmf_mf_handles": [_p, ctypes.c_int32, _u64p, ctypes.c_int32, _i32p],
+    "csrmf_autotune": [_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32],
     "csrmf_profile_enable": [ctypes.c_int32],
     "csrmf_profile_report": [ctypes.c_char_p, ctypes.c_int32],
 }
@@ -307,6 +308,13 @@ class Context:
         out = np.zeros(len(a), np.uint64)
         self._chk(lib.csrmf_conjugate_batch(self.h, _ptr(a, ctypes.c_uint64), len(a), _ptr(out, ctypes.c_uint64)))
         return [int(x) for x in out]
+
+    def autotune(self, rows=0):
+        """Pick the fastest NTT schedule for this ring on `rows` limbs; returns the timings."""
+        import json
+        buf = ctypes.create_string_buffer(4096)
+        self._chk(lib.csrmf_autotune(self.h, rows, buf, 4096))
+        return json.loads(buf.value.decode())
 
     def ntt_rows(self, dev_ptr, n_rows, limb_idx, inverse=False):
         """In-place (I)NTT of rows at a device pointer (e.g. a torch tensor's data_ptr())."""

@@ -384,6 +384,18 @@ int csrmf_ntt_rows(csrmf_ctx* cx, uint64_t* data, int32_t n_rows, const int32_t*
     API_END(c)
 }
 
+int csrmf_autotune(csrmf_ctx* cx, int32_t rows, char* report, int32_t cap) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    const std::string s = c->autotune(rows);
+    if (report && cap > 0) {
+        const size_t n = std::min<size_t>(s.size(), (size_t)cap - 1);
+        std::memcpy(report, s.data(), n);
+        report[n] = 0;
+    }
+    API_END(c)
+}
+
 int csrmf_profile_enable(int32_t enable) {
     csrmf::prof_enable(enable != 0);
     return CSRMF_OK;

@@ -945,6 +945,50 @@ void Context::rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std:
     CSRMF_HIP(hipStreamSynchronize(stream));
 }
 
+std::string Context::autotune(int rows) {
+    // Time forward + inverse transforms of `rows` limbs (a key-switching batch
+    // shape) under each candidate schedule; keep the fastest.
+    if (rows <= 0) rows = 64 * 2 * (L + 1);
+    const int n_idx = L + 1;
+    rows = (rows + n_idx - 1) / n_idx * n_idx;
+    Scratch buf(pool, (size_t)rows * N);
+    CSRMF_HIP(hipMemsetAsync(buf.p, 0, (size_t)rows * N * 8, stream));
+    RowMap m;
+    m.base = buf.p;
+    m.batch = rows / n_idx;
+    m.batch_stride = (int64_t)n_idx * N;
+    for (int i = 0; i < n_idx; ++i) m.push(i, i);
+    hipEvent_t a, b;
+    CSRMF_HIP(hipEventCreate(&a));
+    CSRMF_HIP(hipEventCreate(&b));
+    const int cands[] = {0, 64, 128, 256, 512, 1024, 2048};
+    int best = 0;
+    float best_ms = 1e30f;
+    std::string rep = "{";
+    for (int cnd : cands) {
+        set_ntt_chunk_rows(cnd);
+        launch_ntt(tabs, m, false, stream);     // warm
+        launch_ntt(tabs, m, true, stream);
+        CSRMF_HIP(hipEventRecord(a, stream));
+        for (int r = 0; r < 3; ++r) {
+            launch_ntt(tabs, m, false, stream);
+            launch_ntt(tabs, m, true, stream);
+        }
+        CSRMF_HIP(hipEventRecord(b, stream));
+        CSRMF_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        CSRMF_HIP(hipEventElapsedTime(&ms, a, b));
+        ms /= 3;
+        rep += (rep.size() > 1 ? ", " : "") + std::string("\"ntt_chunk_rows=") + std::to_string(cnd) + "\": " + std::to_string(ms);
+        if (ms < best_ms) { best_ms = ms; best = cnd; }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    set_ntt_chunk_rows(best);
+    rep += ", \"chosen\": " + std::to_string(best) + "}";
+    return rep;
+}
+
 void Context::ntt_rows(uint64_t* data, int n_rows, const int32_t* idx, int n_idx, bool inverse) {
     if (n_idx <= 0 || n_idx > kMaxMapRows || n_rows % n_idx) throw Error(CSRMF_E_INVAL, "bad row map");
     RowMap m;

@@ -167,6 +167,9 @@ struct Context {
     void ks_moddown(uint64_t* u, int level, int B, const RowMap& out, const RowMap& addend,
                     uint32_t g_add, bool addend_both);
 
+    // --- schedule autotuning (returns a JSON report)
+    std::string autotune(int rows);
+
     // --- raw NTT hook
     void ntt_rows(uint64_t* data, int n_rows, const int32_t* idx, int n_idx, bool inverse);
 };

@@ -43,6 +43,10 @@ struct DevTables {
 
 void launch_ntt(const DevTables& t, const RowMap& rows, bool inverse, hipStream_t s);
 
+// NTT schedule tunable: rows per pair of passes (0 = whole batch), process-wide.
+void set_ntt_chunk_rows(int rows);
+int ntt_chunk_rows();
+
 // out row (b, k) = from_signed(src + b*src_batch_stride + (k % n_src)*N), int64
 // coefficients (n_src = 1 broadcasts one signed polynomial to every limb).
 void launch_expand_signed(const DevTables& t, const RowMap& out, const int64_t* src, int n_src,

@@ -60,9 +60,11 @@ __device__ __forceinline__ uint32_t galois_perm(uint32_t k, uint32_t g, int logN
 // LDS.  Residues stay lazily reduced (Harvey): forward values in [0, 4q),
 // inverse values in [0, 2q); the pass that ends the transform reduces fully.
 
-constexpr int kNttThreads = 256;
+constexpr int kNttThreads = 512;
 constexpr int kNttPerThread = 8;
-constexpr int kNttBlockElems = kNttThreads * kNttPerThread;   // 2048 residues, 16 KiB of LDS
+constexpr int kNttBlockLog = 12;
+constexpr int kNttBlockElems = kNttThreads * kNttPerThread;   // 4096 residues, 32 KiB of LDS
+static_assert(kNttBlockElems == 1 << kNttBlockLog, "block size");
 
 __device__ __forceinline__ void bfly_fwd(uint64_t& x, uint64_t& y, uint64_t w, uint64_t wp, uint64_t q, uint64_t q2) {
     uint64_t a = x >= q2 ? x - q2 : x;
@@ -205,14 +207,14 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data,
                                               const M& md, const Modulus& mi, int L1, int L2, int chunk, int tid) {
     T* lds = reinterpret_cast<T*>(lds_raw);
     constexpr int TPS_L = SL - 3;
-    constexpr int SPB_L = 11 - SL;
+    constexpr int SPB_L = kNttBlockLog - SL;        // log2(sub-transforms per block)
     constexpr int R0 = (SL % 3) ? (SL % 3) : 3;
     constexpr bool kFirstPass = kCols != kInverse;   // forward starts with columns, inverse with rows
     int sub, tt;
     if (kCols) { sub = tid & ((1 << SPB_L) - 1); tt = tid >> SPB_L; }
     else       { sub = tid >> TPS_L;              tt = tid & ((1 << TPS_L) - 1); }
     const size_t col0 = kCols ? ((size_t)chunk << SPB_L) + sub : 0;
-    const size_t run0 = kCols ? 0 : ((size_t)chunk << 11) + ((size_t)sub << SL);
+    const size_t run0 = kCols ? 0 : ((size_t)chunk << kNttBlockLog) + ((size_t)sub << SL);
     auto gaddr = [&](int p) -> size_t { return kCols ? col0 + ((size_t)p << L2) : run0 + p; };
     auto laddr = [&](int p) -> int { return kCols ? (p << SPB_L) + sub : (sub << SL) + p; };
     const int c0 = kCols ? 1 : (1 << L1) + (chunk << SPB_L) + sub;
@@ -286,10 +288,10 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data,
 template <int SL, bool kCols, bool kInverse>
 __global__ void __launch_bounds__(kNttThreads) k_ntt_pass(DevTables t, RowMap m) {
     __shared__ uint64_t lds[kNttBlockElems];
-    constexpr int SPB_L = 11 - SL;
+    constexpr int SPB_L = kNttBlockLog - SL;
     const int logN = t.logN, L1 = t.L1, L2 = logN - L1;
     const size_t N = (size_t)1 << logN;
-    const int chunks = kCols ? ((1 << L2) >> SPB_L) : (int)(N >> 11);
+    const int chunks = kCols ? ((1 << L2) >> SPB_L) : (int)(N >> kNttBlockLog);
     int b, k, chunk, mod;
     block_coords(blockIdx.x, chunks, m.batch, b, k, chunk);
     uint64_t* data = map_row(m, b, k, logN, mod);
@@ -589,16 +591,33 @@ inline int ew_blocks(const DevTables& t, const RowMap& m) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+// Rows per pair of passes (0: the whole batch at once).  With a chunk, both
+// passes of a sub-batch run back to back so the second pass can find the
+// first pass's output in the last-level cache.  Chosen by the autotuner.
+static int g_ntt_chunk_rows = 0;
+void set_ntt_chunk_rows(int rows) { g_ntt_chunk_rows = rows < 0 ? 0 : rows; }
+int ntt_chunk_rows() { return g_ntt_chunk_rows; }
+
 void launch_ntt(const DevTables& t, const RowMap& m, bool inverse, hipStream_t s) {
     if (m.rows() == 0) return;
-    const int blocks = m.rows() * (int)(((size_t)1 << t.logN) / kNttBlockElems);
-    const double bytes = NB(m.rows()) * 2;
-    if (!inverse) {
-        { ProfScope ps_("k_ntt_pass<cols,fwd>", s, bytes); dispatch_ntt_pass(t, m, true, false, blocks, s); }
-        { ProfScope ps_("k_ntt_pass<rows,fwd>", s, bytes); dispatch_ntt_pass(t, m, false, false, blocks, s); }
-    } else {
-        { ProfScope ps_("k_ntt_pass<rows,inv>", s, bytes); dispatch_ntt_pass(t, m, false, true, blocks, s); }
-        { ProfScope ps_("k_ntt_pass<cols,inv>", s, bytes); dispatch_ntt_pass(t, m, true, true, blocks, s); }
+    const int per_b = m.n;
+    int bchunk = m.batch;
+    if (g_ntt_chunk_rows > 0) bchunk = per_b >= g_ntt_chunk_rows ? 1 : g_ntt_chunk_rows / per_b;
+    if (bchunk > m.batch) bchunk = m.batch;
+    for (int b0 = 0; b0 < m.batch; b0 += bchunk) {
+        RowMap sub = m;
+        sub.batch = (m.batch - b0) < bchunk ? (m.batch - b0) : bchunk;
+        if (m.ptrs) sub.ptrs = m.ptrs + b0;
+        else sub.base = m.base + (int64_t)b0 * m.batch_stride;
+        const int blocks = sub.rows() * (int)(((size_t)1 << t.logN) / kNttBlockElems);
+        const double bytes = NB(sub.rows()) * 2;
+        if (!inverse) {
+            { ProfScope ps_("k_ntt_pass<cols,fwd>", s, bytes); dispatch_ntt_pass(t, sub, true, false, blocks, s); }
+            { ProfScope ps_("k_ntt_pass<rows,fwd>", s, bytes); dispatch_ntt_pass(t, sub, false, false, blocks, s); }
+        } else {
+            { ProfScope ps_("k_ntt_pass<rows,inv>", s, bytes); dispatch_ntt_pass(t, sub, false, true, blocks, s); }
+            { ProfScope ps_("k_ntt_pass<cols,inv>", s, bytes); dispatch_ntt_pass(t, sub, true, true, blocks, s); }
+        }
     }
 }
 
