@@ -259,8 +259,11 @@ int csrmf_profile_report(char* buf, int32_t cap);
  * a row that does not fit in the current ciphertext starts a new one and a
  * row longer than D is split into chunks of D.  Block t of a rating
  * ciphertext holds r_ij in slots tB..tB+k-1.  n_ct receives the number of
- * rating ciphertexts.  Errors: INVAL (row_ptr not monotone, columns unsorted,
- * duplicated or out of range, NaN), STATE (no keys). */
+ * rating ciphertexts.  The rotation keys the program needs (windowed sum:
+ * 1, 2, .., B/2 and -k'; block permutations: beta*B and gamma*G*B with
+ * G = 2^ceil(log2(D)/2)) are generated here if missing.  Errors: INVAL
+ * (row_ptr not monotone, columns unsorted, duplicated or out of range, NaN),
+ * STATE (no keys). */
 int csrmf_encrypt_csr_rows(csrmf_ctx* ctx, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr,
                            const int32_t* col_idx, const double* values, int32_t* n_ct);
 

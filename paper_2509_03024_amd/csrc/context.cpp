@@ -484,13 +484,12 @@ void Context::encrypt_int_batch(const int64_t* m, int count, int level, double s
     }
     out.clear();
     for (int c = 0; c < count; ++c) out.push_back(new_ct(level, scale));
-    // NTT all expanded rows
+    // NTT all expanded rows: count*4 polynomials of nl limbs, contiguous
     RowMap all;
     all.base = ex.p;
-    all.batch = count;
-    all.batch_stride = (int64_t)4 * nl * N;
-    for (int p = 0; p < 4; ++p)
-        for (int i = 0; i < nl; ++i) all.push(p * nl + i, i);
+    all.batch = count * 4;
+    all.batch_stride = (int64_t)nl * N;
+    for (int i = 0; i < nl; ++i) all.push(i, i);
     launch_ntt(tabs, all, false, stream);
     std::vector<Ct*> po;
     for (auto& c : out) po.push_back(&c);
@@ -987,6 +986,40 @@ std::string Context::autotune(int rows) {
     set_ntt_chunk_rows(best);
     rep += ", \"chosen\": " + std::to_string(best) + "}";
     return rep;
+}
+
+Context::Hoist::~Hoist() {
+    if (ctx) {
+        ctx->pool.put(ext);
+        ctx->pool.put(coef);
+    }
+}
+
+void Context::hoist_begin(Hoist& h, const std::vector<Ct*>& in) {
+    const int B = (int)in.size();
+    if (B == 0) throw Error(CSRMF_E_INVAL, "empty hoisting batch");
+    const int lvl = in[0]->level;
+    for (Ct* x : in)
+        if (x->level != lvl) throw Error(CSRMF_E_INVAL, "batch operands must share a level");
+    const int nl = lvl + 1, nr = n_ext(lvl), nd = (int)lv[lvl].digits.size();
+    h.ctx = this;
+    h.in = in;
+    h.level = lvl;
+    h.ext = (uint64_t*)pool.get((size_t)B * nd * nr * N * 8);
+    h.coef = (uint64_t*)pool.get((size_t)B * nl * N * 8);
+    RowMap c1 = map_cts(in, nl);
+    for (int i = 0; i < nl; ++i) c1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+    ks_modup(c1, lvl, B, h.ext, h.coef);
+}
+
+void Context::hoist_rotate(Hoist& h, uint32_t g, std::vector<Ct*>& out) {
+    const int B = (int)h.in.size();
+    const int lvl = h.level, nl = lvl + 1, nr = n_ext(lvl);
+    const Key& key = key_for(g);
+    Scratch u(pool, (size_t)B * 2 * nr * N);
+    ks_inner(h.ext, lvl, B, key, g, u.p);
+    for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, h.in[i]->scale);
+    ks_moddown(u.p, lvl, B, map_cts(out, nl), map_cts(h.in, nl), g, false);
 }
 
 void Context::ntt_rows(uint64_t* data, int n_rows, const int32_t* idx, int n_idx, bool inverse) {

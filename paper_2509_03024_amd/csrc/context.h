@@ -161,6 +161,18 @@ struct Context {
     void rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std::vector<Ct*>& out);
     void check_scales(double a, double b) const;
 
+    // --- hoisted rotations of a batch: ModUp once, then any number of Galois elements
+    struct Hoist {
+        Context* ctx = nullptr;
+        std::vector<Ct*> in;
+        int level = 0;
+        uint64_t* ext = nullptr;
+        uint64_t* coef = nullptr;
+        ~Hoist();
+    };
+    void hoist_begin(Hoist& h, const std::vector<Ct*>& in);
+    void hoist_rotate(Hoist& h, uint32_t g, std::vector<Ct*>& out);
+
     // --- key-switching pieces
     void ks_modup(const RowMap& d_in, int level, int B, uint64_t* ext, uint64_t* coef);
     void ks_inner(const uint64_t* ext, int level, int B, const Key& key, uint32_t g, uint64_t* u);

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <stdexcept>
+
 #include "modarith.h"
 
 namespace csrmf {
@@ -24,7 +26,10 @@ struct RowMap {
     int32_t batch = 1;
     uint32_t e[kMaxMapRows];
 
-    void push(uint32_t off, uint32_t mod) { e[n++] = (off << 8) | mod; }
+    void push(uint32_t off, uint32_t mod) {
+        if (n >= kMaxMapRows || mod > 0xffu || off > 0xffffffu) throw std::length_error("RowMap capacity exceeded");
+        e[n++] = (off << 8) | mod;
+    }
     int rows() const { return n * batch; }
 };
 
@@ -124,6 +129,24 @@ void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap&
 void launch_mask_mac(const DevTables& t, const RowMap& acc, const RowMap& src, const uint64_t* i0,
                      const uint32_t* gs, const uint64_t* cw, int n_terms, int cw_stride, bool first,
                      hipStream_t s);
+
+// Multi-task masked MAC (the inner sums of block permutations): task t
+// accumulates into acc[t] (both polynomials, limbs 0..n_limbs-1) its groups
+// [grp_begin[t], grp_begin[t+1]), each src[g] (.) sum_{m} W_m tau_{gs[m]}(I0) over
+// the group's terms [term_begin[g], term_begin[g+1]); cw as for launch_mask_mac.
+// first[t] != 0: the accumulator starts at zero.  All pointers are device arrays.
+struct MaskTasks {
+    uint64_t* const* acc;       // [n_tasks] ciphertext base pointers
+    const int32_t* grp_begin;   // [n_tasks + 1]
+    const int32_t* first;       // [n_tasks]
+    const uint64_t* const* src; // [n_groups]
+    const int32_t* term_begin;  // [n_groups + 1]
+    const uint32_t* gs;         // [n_terms]
+    const uint64_t* cw;         // [n_terms][cw_stride][2]
+    int32_t n_tasks, n_limbs, cw_stride;
+    int64_t poly_stride;
+};
+void launch_mask_mac_tasks(const DevTables& t, const MaskTasks& T, const uint64_t* i0, double bytes, hipStream_t s);
 
 // Rescale step 1 (coefficient form top limb, one row per batch element and
 // poly): t = (c_l + h) mod q_l with h = floor(q_l/2), then dst row k =

@@ -584,6 +584,48 @@ __global__ void __launch_bounds__(kThreads) k_mask_mac(DevTables t, RowMap acc, 
     }
 }
 
+// Multi-task masked MAC: task t accumulates into acc_t (both polynomials,
+// limbs 0..n_limbs-1) the groups [grp_begin[t], grp_begin[t+1]) of
+//     src_g (.) sum_{m in group} W_m tau_{g_m}(I0);
+// group g reads src_ptr[g] (c1 at +poly_stride) and its terms
+// [term_begin[g], term_begin[g+1]).  If first[t] != 0 the accumulator starts at 0.
+
+
+__global__ void __launch_bounds__(kThreads) k_mask_mac_tasks(DevTables t, MaskTasks T, const uint64_t* i0) {
+    const int logN = t.logN;
+    const int N = 1 << logN;
+    const int chunks = N / (kThreads * kEwPerThread);
+    const int chunk = blockIdx.x % chunks;
+    const int r = blockIdx.x / chunks;
+    const int k = r % T.n_limbs;             // limb
+    const int task = r / T.n_limbs;
+    const int base_i = chunk * kThreads * kEwPerThread + threadIdx.x;
+    const Modulus md = t.mods[k];
+    const uint64_t* row = i0 + ((size_t)k << logN);
+    uint64_t* pa = T.acc[task] + ((size_t)k << logN);
+    const int g0 = T.grp_begin[task], g1 = T.grp_begin[task + 1];
+    for (int uu = 0; uu < kEwPerThread; ++uu) {
+        const int i = base_i + uu * kThreads;
+        uint64_t a0 = 0, a1 = 0;
+        if (!T.first[task]) {
+            a0 = pa[i];
+            a1 = pa[i + T.poly_stride];
+        }
+        for (int g = g0; g < g1; ++g) {
+            uint64_t M = 0;
+            for (int m = T.term_begin[g]; m < T.term_begin[g + 1]; ++m) {
+                const uint64_t* c = T.cw + 2 * ((size_t)m * T.cw_stride + k);
+                M = add_mod(M, mul_shoup(row[galois_perm((uint32_t)i, T.gs[m], logN)], c[0], c[1], md.q), md.q);
+            }
+            const uint64_t* ps = T.src[g] + ((size_t)k << logN);
+            a0 = add_mod(a0, mul_mont(ps[i], M, md.q, md.qneg_inv), md.q);
+            a1 = add_mod(a1, mul_mont(ps[i + T.poly_stride], M, md.q, md.qneg_inv), md.q);
+        }
+        pa[i] = a0;
+        pa[i + T.poly_stride] = a1;
+    }
+}
+
 inline int ew_blocks(const DevTables& t, const RowMap& m) {
     return m.rows() * ((1 << t.logN) / (kThreads * kEwPerThread));
 }
@@ -703,6 +745,13 @@ void launch_mask_mac(const DevTables& t, const RowMap& acc, const RowMap& src, c
     ProfScope ps_("k_mask_mac", s, NB(acc.rows()) * (first ? 4 : 6) + NB(acc.rows()) * n_terms);
     hipLaunchKernelGGL(k_mask_mac, dim3(ew_blocks(t, acc)), dim3(kThreads), 0, s, t, acc, src, i0, gs, cw, n_terms,
                        cw_stride, first ? 1 : 0);
+}
+
+void launch_mask_mac_tasks(const DevTables& t, const MaskTasks& T, const uint64_t* i0, double bytes, hipStream_t s) {
+    if (T.n_tasks <= 0) return;
+    ProfScope ps_("k_mask_mac_tasks", s, bytes);
+    const int blocks = T.n_tasks * T.n_limbs * ((1 << t.logN) / (kThreads * kEwPerThread));
+    hipLaunchKernelGGL(k_mask_mac_tasks, dim3(blocks), dim3(kThreads), 0, s, t, T, i0);
 }
 
 void launch_rescale_spread(const DevTables& t, const RowMap& dst, const RowMap& top, uint32_t top_mod, hipStream_t s) {

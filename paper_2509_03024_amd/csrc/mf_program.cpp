@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 
 #include "context.h"
 #include "host_math.h"
@@ -236,8 +237,24 @@ int64_t weight_int(double w, double s_src, double q_acc) {
     return (int64_t)std::nearbyint((w * kTargetScale * q_acc) / (s_src * kMaskScale));
 }
 
+// Upload a host vector into a pool scratch block (synchronous).
+template <typename T>
+uint64_t* upload_vec(Context* c, const std::vector<T>& v, std::vector<uint64_t*>& owned) {
+    uint64_t* d = (uint64_t*)c->pool.get(std::max<size_t>(8, v.size() * sizeof(T)));
+    if (!v.empty()) CSRMF_HIP(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    owned.push_back(d);
+    return d;
+}
+
+constexpr int kHoistChunk = 128;   // sources whose digits are extended together
+
 // srcs: source ciphertexts (viewed at `level`); dests[d]: moves into destination d;
-// selfs[d]: optional (table ciphertext, [(block, w)]) term.
+// selfs[d]: optional (table ciphertext, [(block, w)]) term.  Schedule: the sources
+// are extended (ModUp) once per chunk; for every baby step beta one batched
+// inner product + ModDown gives HRot_beta of all sources of the chunk, and one
+// multi-task launch accumulates every (destination, gamma) inner sum that uses
+// them; then one batched giant rotation per gamma, the self terms, and one
+// batched rescale.  Sums are exact, so this order gives the defined result.
 std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& srcs,
                               const std::vector<std::vector<Move>>& dests,
                               const std::vector<std::pair<Ct*, std::vector<std::pair<int, double>>>>* selfs,
@@ -245,34 +262,10 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
     const int D = m.D, G = m.G, B = m.B;
     const int nl = level + 1;
     const double s_src = srcs.empty() ? 1.0 : srcs[0]->scale;
-    const uint64_t q_top = c->moduli[level];
-    const double q_acc = (double)q_top;
+    const double q_acc = (double)c->moduli[level];
     const double acc_scale = kTargetScale * q_acc;
-    // hoisted baby rotations of every source that is used
-    std::map<int, std::map<int, Ct>> baby;      // source -> beta -> ciphertext (beta 0 = the source view)
-    std::map<int, std::vector<int>> need;
-    for (auto& mv : dests)
-        for (const Move& x : mv) {
-            const int beta = ((x.a - x.b) % D + D) % D % G;
-            auto& v = need[x.src];
-            if (std::find(v.begin(), v.end(), beta) == v.end()) v.push_back(beta);
-        }
-    for (auto& kv : need) {
-        Ct src = *srcs[kv.first];
-        src.level = level;
-        std::vector<uint32_t> gs;
-        std::vector<int> betas;
-        for (int beta : kv.second)
-            if (beta) { betas.push_back(beta); gs.push_back(c->galois_for_step((int64_t)beta * B)); }
-        baby[kv.first][0] = src;   // view, not owned
-        if (!gs.empty()) {
-            std::vector<Ct> outs(gs.size());
-            std::vector<Ct*> po = ptrs(outs);
-            c->rotate_hoisted(src, gs, po);
-            for (size_t i = 0; i < betas.size(); ++i) baby[kv.first][betas[i]] = outs[i];
-        }
-    }
-    // per-limb Montgomery constants of an integer weight
+    const int n_dest = (int)dests.size();
+    const int n_gamma = D / G;
     auto wconst = [&](int64_t W, std::vector<uint64_t>& out) {
         for (int i = 0; i < nl; ++i) {
             const uint64_t q = c->moduli[i];
@@ -282,97 +275,199 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
         }
     };
     auto gal = [&](int p) { return c->galois_for_step(-(int64_t)p * B); };
-    RowMap mask_rows;   // unused placeholder for clarity
-    (void)mask_rows;
-    std::vector<Ct> outs;
-    const int n_dest = (int)dests.size();
-    for (int d = 0; d < n_dest; ++d) {
-        // group the moves: gamma -> (source, beta) -> terms
-        std::map<int, std::map<std::pair<int, int>, std::vector<std::pair<int, int64_t>>>> groups;
+
+    // groups keyed by (beta, source, destination, gamma) -> terms (p, W)
+    std::map<std::tuple<int, int, int, int>, std::vector<std::pair<int, int64_t>>> groups;
+    std::map<int, std::vector<int>> betas_of_src;
+    for (int d = 0; d < n_dest; ++d)
         for (const Move& x : dests[d]) {
             const int delta = ((x.a - x.b) % D + D) % D;
             const int gamma = delta / G, beta = delta % G;
-            const int p = (x.b + gamma * G) % D;
-            groups[gamma][{x.src, beta}].push_back({p, weight_int(x.w, s_src, q_acc)});
+            groups[{beta, x.src, d, gamma}].push_back({(x.b + gamma * G) % D, weight_int(x.w, s_src, q_acc)});
+            auto& v = betas_of_src[x.src];
+            if (std::find(v.begin(), v.end(), beta) == v.end()) v.push_back(beta);
         }
-        std::vector<std::pair<int, int64_t>> self_terms;
-        Ct self_src;
-        const bool has_self = selfs && (*selfs)[d].first;
-        if (has_self) {
-            self_src = *(*selfs)[d].first;
-            self_src.level = level;
-            for (auto& bw : (*selfs)[d].second) self_terms.push_back({bw.first, weight_int(bw.second, self_src.scale, q_acc)});
+    // accumulators: gamma 0 sums go straight into acc[d]; inner[d][gamma] otherwise
+    std::vector<Ct> acc(n_dest);
+    std::vector<char> acc_init(n_dest, 0);
+    for (int d = 0; d < n_dest; ++d) acc[d] = c->new_ct(level, acc_scale);
+    std::vector<std::vector<Ct>> inner(n_dest, std::vector<Ct>(n_gamma));
+    std::vector<std::vector<char>> inner_init(n_dest, std::vector<char>(n_gamma, 0));
+    for (auto& kv : groups) {
+        const int d = std::get<2>(kv.first), gamma = std::get<3>(kv.first);
+        if (gamma && !inner[d][gamma].d) inner[d][gamma] = c->new_ct(level, acc_scale);
+    }
+    std::vector<int> src_list;
+    for (auto& kv : betas_of_src) src_list.push_back(kv.first);
+
+    for (size_t c0 = 0; c0 < src_list.size(); c0 += kHoistChunk) {
+        const size_t c1 = std::min(src_list.size(), c0 + kHoistChunk);
+        std::vector<Ct> views;
+        std::vector<int> ids;
+        std::vector<int> betas;
+        for (size_t i = c0; i < c1; ++i) {
+            Ct v = *srcs[src_list[i]];
+            v.level = level;
+            views.push_back(v);
+            ids.push_back(src_list[i]);
+            for (int b : betas_of_src[src_list[i]])
+                if (std::find(betas.begin(), betas.end(), b) == betas.end()) betas.push_back(b);
         }
-        // upload all terms of this destination at once
-        std::vector<uint32_t> gs;
-        std::vector<uint64_t> cw;
-        struct Launch { int gamma; Ct* src; int first_term; int n_terms; };
-        std::vector<Launch> launches;
-        for (auto& g : groups)
-            for (auto& cb : g.second) {
-                Launch L{g.first, &baby[cb.first.first][cb.first.second], (int)gs.size(), (int)cb.second.size()};
-                for (auto& t : cb.second) { gs.push_back(gal(t.first)); wconst(t.second, cw); }
-                launches.push_back(L);
+        std::sort(betas.begin(), betas.end());
+        std::map<int, int> pos;   // source id -> index in the chunk
+        for (size_t i = 0; i < ids.size(); ++i) pos[ids[i]] = (int)i;
+        std::vector<Ct*> pviews = ptrs(views);
+        Context::Hoist hs;
+        const bool any_rot = betas.size() > 1 || (betas.size() == 1 && betas[0] != 0);
+        if (any_rot) c->hoist_begin(hs, pviews);
+        for (int beta : betas) {
+            std::vector<Ct> babies;
+            if (beta) {
+                babies.resize(views.size());
+                std::vector<Ct*> pb = ptrs(babies);
+                c->hoist_rotate(hs, c->galois_for_step((int64_t)beta * B), pb);
             }
-        const int self_first = (int)gs.size();
-        for (auto& t : self_terms) { gs.push_back(gal(t.first)); wconst(t.second, cw); }
-        Scratch dgs(c->pool, (gs.size() + 1) / 2 + 1), dcw(c->pool, cw.size() + 1);
-        if (!gs.empty()) {
-            CSRMF_HIP(hipMemcpyAsync(dgs.p, gs.data(), gs.size() * 4, hipMemcpyHostToDevice, c->stream));
-            CSRMF_HIP(hipMemcpyAsync(dcw.p, cw.data(), cw.size() * 8, hipMemcpyHostToDevice, c->stream));
-            CSRMF_HIP(hipStreamSynchronize(c->stream));
-        }
-        Ct acc = c->new_ct(level, acc_scale);
-        bool acc_empty = true;
-        for (auto& g : groups) {
-            const int gamma = g.first;
-            Ct inner = gamma ? c->new_ct(level, acc_scale) : acc;
-            bool first = gamma ? true : acc_empty;
-            for (const Launch& L : launches) {
-                if (L.gamma != gamma) continue;
-                launch_mask_mac(c->tabs, c->map_ct(inner.d, nl), c->map_ct(L.src->d, nl), m.mask0,
-                                (const uint32_t*)dgs.p + L.first_term, dcw.p + 2 * (size_t)L.first_term * nl,
-                                L.n_terms, nl, first, c->stream);
-                first = false;
+            // tasks: one per (destination, gamma) receiving groups of this beta from this chunk
+            std::map<std::pair<int, int>, std::vector<std::pair<int, const std::vector<std::pair<int, int64_t>>*>>> tasks;
+            auto lo = groups.lower_bound({beta, ids.front(), -1, -1});
+            for (auto it = lo; it != groups.end() && std::get<0>(it->first) == beta; ++it) {
+                const int src = std::get<1>(it->first);
+                auto pit = pos.find(src);
+                if (pit == pos.end()) continue;
+                tasks[{std::get<2>(it->first), std::get<3>(it->first)}].push_back({pit->second, &it->second});
             }
-            if (gamma) {
-                std::vector<Ct*> in{&inner};
-                Ct rot;
-                std::vector<Ct*> out{&rot};
-                c->rotate(in, c->galois_for_step((int64_t)gamma * G * B), out);
-                c->pool.put(inner.d);
-                if (acc_empty) {
-                    c->pool.put(acc.d);
-                    acc = rot;
-                    acc.scale = acc_scale;
-                } else {
-                    std::vector<Ct*> a{&acc}, b{&rot};
-                    Ct sum;
-                    std::vector<Ct*> o{&sum};
-                    c->add_batch(a, b, o, false);
-                    c->pool.put(acc.d);
-                    c->pool.put(rot.d);
-                    acc = sum;
+            if (tasks.empty()) continue;
+            std::vector<uint64_t*> acc_ptr, src_ptr;
+            std::vector<int32_t> grp_begin, first, term_begin;
+            std::vector<uint32_t> gs;
+            std::vector<uint64_t> cw;
+            for (auto& tk : tasks) {
+                const int d = tk.first.first, gamma = tk.first.second;
+                Ct& tgt = gamma ? inner[d][gamma] : acc[d];
+                char& init = gamma ? inner_init[d][gamma] : acc_init[d];
+                acc_ptr.push_back(tgt.d);
+                first.push_back(init ? 0 : 1);
+                init = 1;
+                grp_begin.push_back((int32_t)src_ptr.size());
+                for (auto& gr : tk.second) {
+                    src_ptr.push_back(beta ? babies[gr.first].d : views[gr.first].d);
+                    term_begin.push_back((int32_t)gs.size());
+                    for (auto& t : *gr.second) {
+                        gs.push_back(gal(t.first));
+                        wconst(t.second, cw);
+                    }
                 }
             }
-            acc_empty = false;
+            grp_begin.push_back((int32_t)src_ptr.size());
+            term_begin.push_back((int32_t)gs.size());
+            std::vector<uint64_t*> owned;
+            MaskTasks T;
+            T.acc = (uint64_t* const*)upload_vec(c, acc_ptr, owned);
+            T.grp_begin = (const int32_t*)upload_vec(c, grp_begin, owned);
+            T.first = (const int32_t*)upload_vec(c, first, owned);
+            T.src = (const uint64_t* const*)upload_vec(c, src_ptr, owned);
+            T.term_begin = (const int32_t*)upload_vec(c, term_begin, owned);
+            T.gs = (const uint32_t*)upload_vec(c, gs, owned);
+            T.cw = upload_vec(c, cw, owned);
+            T.n_tasks = (int32_t)acc_ptr.size();
+            T.n_limbs = nl;
+            T.cw_stride = nl;
+            T.poly_stride = c->poly_stride();
+            CSRMF_HIP(hipStreamSynchronize(c->stream));   // host vectors go out of scope
+            const double bytes = (double)c->N * 8.0 * nl * (2.0 * src_ptr.size() + 4.0 * acc_ptr.size() + gs.size());
+            launch_mask_mac_tasks(c->tabs, T, m.mask0, bytes, c->stream);
+            for (uint64_t* p : owned) c->pool.put(p);
+            release(c, babies);
         }
-        if (has_self && !self_terms.empty()) {
-            launch_mask_mac(c->tabs, c->map_ct(acc.d, nl), c->map_ct(self_src.d, nl), m.mask0,
-                            (const uint32_t*)dgs.p + self_first, dcw.p + 2 * (size_t)self_first * nl,
-                            (int)self_terms.size(), nl, acc_empty, c->stream);
-            acc_empty = false;
-        }
-        if (acc_empty) throw Error(CSRMF_E_INVAL, "block permutation with an empty destination");
-        acc.scale = acc_scale;
-        std::vector<Ct*> v{&acc};
-        c->rescale(v);
-        outs.push_back(acc);
     }
-    for (auto& kv : baby)
-        for (auto& bc : kv.second)
-            if (bc.first) c->pool.put(bc.second.d);
-    return outs;
+    // giant steps: one batched rotation per gamma over the destinations that use it
+    for (int gamma = 1; gamma < n_gamma; ++gamma) {
+        std::vector<int> ds;
+        for (int d = 0; d < n_dest; ++d)
+            if (inner[d][gamma].d) ds.push_back(d);
+        if (ds.empty()) continue;
+        std::vector<Ct*> in;
+        for (int d : ds) in.push_back(&inner[d][gamma]);
+        std::vector<Ct> rot(ds.size());
+        std::vector<Ct*> prot = ptrs(rot);
+        c->rotate(in, c->galois_for_step((int64_t)gamma * G * B), prot);
+        std::vector<Ct*> a, b;
+        std::vector<int> add_d;
+        for (size_t i = 0; i < ds.size(); ++i) {
+            const int d = ds[i];
+            c->pool.put(inner[d][gamma].d);
+            inner[d][gamma].d = nullptr;
+            if (acc_init[d]) {
+                a.push_back(&acc[d]);
+                b.push_back(&rot[i]);
+                add_d.push_back(d);
+            } else {
+                c->pool.put(acc[d].d);
+                acc[d] = rot[i];
+                rot[i].d = nullptr;
+                acc_init[d] = 1;
+            }
+        }
+        if (!a.empty()) {
+            std::vector<Ct> sum(a.size());
+            std::vector<Ct*> ps = ptrs(sum);
+            c->add_batch(a, b, ps, false);
+            for (size_t i = 0; i < add_d.size(); ++i) {
+                c->pool.put(acc[add_d[i]].d);
+                acc[add_d[i]] = sum[i];
+            }
+        }
+        for (auto& r : rot)
+            if (r.d) c->pool.put(r.d);
+    }
+    // self terms: one task per destination
+    if (selfs) {
+        std::vector<uint64_t*> acc_ptr, src_ptr;
+        std::vector<int32_t> grp_begin, first, term_begin;
+        std::vector<uint32_t> gs;
+        std::vector<uint64_t> cw;
+        for (int d = 0; d < n_dest; ++d) {
+            if (!(*selfs)[d].first || (*selfs)[d].second.empty()) continue;
+            const double s_self = (*selfs)[d].first->scale;
+            acc_ptr.push_back(acc[d].d);
+            first.push_back(acc_init[d] ? 0 : 1);
+            acc_init[d] = 1;
+            grp_begin.push_back((int32_t)src_ptr.size());
+            src_ptr.push_back((*selfs)[d].first->d);
+            term_begin.push_back((int32_t)gs.size());
+            for (auto& bw : (*selfs)[d].second) {
+                gs.push_back(gal(bw.first));
+                wconst(weight_int(bw.second, s_self, q_acc), cw);
+            }
+        }
+        if (!acc_ptr.empty()) {
+            grp_begin.push_back((int32_t)src_ptr.size());
+            term_begin.push_back((int32_t)gs.size());
+            std::vector<uint64_t*> owned;
+            MaskTasks T;
+            T.acc = (uint64_t* const*)upload_vec(c, acc_ptr, owned);
+            T.grp_begin = (const int32_t*)upload_vec(c, grp_begin, owned);
+            T.first = (const int32_t*)upload_vec(c, first, owned);
+            T.src = (const uint64_t* const*)upload_vec(c, src_ptr, owned);
+            T.term_begin = (const int32_t*)upload_vec(c, term_begin, owned);
+            T.gs = (const uint32_t*)upload_vec(c, gs, owned);
+            T.cw = upload_vec(c, cw, owned);
+            T.n_tasks = (int32_t)acc_ptr.size();
+            T.n_limbs = nl;
+            T.cw_stride = nl;
+            T.poly_stride = c->poly_stride();
+            CSRMF_HIP(hipStreamSynchronize(c->stream));
+            const double bytes = (double)c->N * 8.0 * nl * (6.0 * acc_ptr.size() + gs.size());
+            launch_mask_mac_tasks(c->tabs, T, m.mask0, bytes, c->stream);
+            for (uint64_t* p : owned) c->pool.put(p);
+        }
+    }
+    for (int d = 0; d < n_dest; ++d)
+        if (!acc_init[d]) throw Error(CSRMF_E_INVAL, "block permutation with an empty destination");
+    for (auto& a : acc) a.scale = acc_scale;
+    std::vector<Ct*> pacc = ptrs(acc);
+    c->rescale(pacc);
+    return acc;
 }
 
 std::vector<Ct> scatter(Context* c, MfState& m, const std::vector<Ct*>& Gs, const std::vector<uint64_t>& tabs,
@@ -525,6 +620,19 @@ using csrmf::MfState;
 static void install_layout(Context* c, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr, const int32_t* col_idx) {
     if (!c->have_keys) throw Error(CSRMF_E_STATE, "keygen first");
     MfState* m = csrmf::make_layout(c, n_rows, n_cols, row_ptr, col_idx);
+    // rotation keys the program uses: windowed sum 1, 2, .., B/2 and -k'; baby
+    // steps beta*B (beta < G); giant steps gamma*G*B (gamma < D/G)
+    std::vector<int32_t> steps;
+    for (int s = 1; s < m->B; s *= 2) steps.push_back(s);
+    steps.push_back(-m->kp);
+    for (int b = 1; b < m->G; ++b) steps.push_back(b * m->B);
+    for (int g = 1; g < m->D / m->G; ++g) steps.push_back(g * m->G * m->B);
+    try {
+        c->keygen(steps.data(), (int)steps.size(), false);
+    } catch (...) {
+        delete m;
+        throw;
+    }
     if (c->mf) {
         csrmf::free_handles(c, c->mf->R);
         csrmf::free_handles(c, c->mf->Utab);

@@ -35,7 +35,7 @@ def tiny_run():
     lay, ores, pt = run_encrypted_tiny(orc, csr, U0, V0, mask0)
 
     ctx = pk.Context(pk.tiny_params(k=4, lr=0.01, lam=0.02, rule=1), workloads.CRYPTO_SEED)
-    ctx.keygen(steps)
+    ctx.keygen([])            # the program generates its rotation keys itself
     m = pk.MF(ctx)
     n_ct = m.encrypt_csr_rows_int(32, 64, csr.row_ptr, csr.col_idx, np.stack(pt["R"]))
     assert n_ct == lay.n_ct
