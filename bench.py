@@ -37,10 +37,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="ks", choices=["ks", "mf100k", "mf1m"],
+    ap.add_argument("--workload", default="ks", choices=["ks", "mf100k", "mf1m", "serve"],
                     help="ks: batched key switching (default); mf100k / mf1m: encrypted MF epochs on the "
                          "MovieLens-100K / -1M shaped synthetic matrices")
     ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--rates", default="10,25,50,100,200", help="serve: Poisson arrival rates (requests/s)")
+    ap.add_argument("--requests", type=int, default=60, help="serve: requests per rate")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy a 512 MiB device buffer once before the timed steps (reference for HBM counters)")
     return ap.parse_args()
@@ -121,11 +123,88 @@ def bench_mf(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """Poisson stream of encrypted per-user PREDICT / UPDATE requests (50/50) over the
+    MovieLens-1M-shaped tables (6040 x 3706, k = 16): rows of lognormal(4.5, 1) length
+    clipped to [5, 2000], items Zipf(1.1); rows of <= 512 items go to the N = 2^15
+    server, longer ones to the N = 2^16 server.  Reports p50/p99 latency per rate."""
+    import threading
+    import numpy as np
+    import paper_2509_03024_amd as pk
+    import workloads
+    k = 16
+    U0, V0 = workloads.init_factors(6040, 3706, k)
+    t0 = time.perf_counter()
+    servers = {}
+    for name, prm in (("n15", pk.mf_n15_params(k=k, lr=0.01, lam=0.02, rule=2)),
+                      ("n16", pk.mf_n16_params(k=k, lr=0.01, lam=0.02, rule=2))):
+        ctx = pk.Context(prm, workloads.CRYPTO_SEED)
+        ctx.keygen([])
+        ctx.autotune()
+        servers[name] = (ctx, pk.Server(ctx, U0, V0, hbm_budget_bytes=40e9, max_batch=64))
+        log(f"server {name} ready ({time.perf_counter() - t0:.1f} s)")
+    rng = np.random.default_rng(7)
+    weights = np.arange(1, 3707, dtype=np.float64) ** -1.1
+    perm = rng.permutation(3706)
+    w = np.empty(3706)
+    w[perm] = weights
+    w /= w.sum()
+    results = []
+    serial = 0
+    for rate in [float(x) for x in args.rates.split(",")]:
+        reqs = []
+        for _ in range(args.requests):
+            d = int(np.clip(np.rint(rng.lognormal(4.5, 1.0)), 5, 2000))
+            items = np.sort(rng.choice(3706, size=d, replace=False, p=w)).astype(np.int32)
+            r = np.rint(np.clip(rng.normal(3.5, 1.1, d), 1, 5))
+            reqs.append((int(rng.integers(0, 6040)), items, r, int(rng.integers(0, 2))))
+        gaps = rng.exponential(1.0 / rate, len(reqs))
+        ids = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for (user, items, r, op), g in zip(reqs, gaps):
+            t_next += g
+            delay = t_next - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            srv = servers["n15" if len(items) <= 512 else "n16"][1]
+            serial += 1
+            ids.append((srv, srv.submit(op, user, items, r if op else None, client_serial=serial), len(items)))
+        lats = []
+        n_ratings = 0
+        for srv, rid, d in ids:
+            st, res, lat = srv.poll(rid, wait=True)
+            lats.append(lat)
+            n_ratings += d
+            for h in res:
+                srv.ctx.free(h)
+        wall = time.perf_counter() - t_start
+        lats = np.array(lats)
+        results.append({"rate": rate, "requests": len(ids), "p50_ms": round(1e3 * float(np.percentile(lats, 50)), 2),
+                        "p99_ms": round(1e3 * float(np.percentile(lats, 99)), 2),
+                        "ratings_per_s": round(n_ratings / wall, 1)})
+        log(f"rate {rate}: {results[-1]}")
+    stats = {n: s[1].stats() for n, s in servers.items()}
+    for ctx, srv in servers.values():
+        srv.close()
+        ctx.close()
+    top = results[-1]
+    print(json.dumps({
+        "metric": "p99 latency of encrypted per-user requests", "value": top["p99_ms"], "unit": "ms",
+        "n_gpus": 1, "steps": len(results), "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "serving: Poisson PREDICT/UPDATE requests over 6040 x 3706 tables, k=16, "
+                               "N=2^15 (rows <= 512) / 2^16"},
+        "sweep": results, "servers": stats}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "serve":
+        return bench_serve(args)
     if args.workload != "ks":
         return bench_mf(args)
     import numpy as np

@@ -224,6 +224,53 @@ int csrmf_ntt_rows(csrmf_ctx* ctx, uint64_t* data, int32_t n_rows, const int32_t
                    int32_t n_idx, int32_t inverse);
 
 /* ------------------------------------------------------------------------ */
+/* Serving: encrypted per-user requests against resident factor tables.     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct csrmf_server csrmf_server;
+
+/* Create a request server on ctx (keys must exist).  The factor tables U[n_users*k]
+ * and V[n_items*k] (row-major) are encrypted once and stay resident in HBM with
+ * the baby-step rotations of the gathers; the rotation keys the requests need
+ * are generated if missing.  A worker thread admits queued requests while
+ * their ciphertext footprint (about 16 ciphertexts per row chunk) fits in
+ * hbm_budget_bytes and runs everything admitted as one batch (at most
+ * max_batch requests); requests arriving meanwhile join the next batch.
+ * Errors: INVAL, STATE, NOMEM, DEVICE, LEVEL (a chain of fewer than 2 levels). */
+int csrmf_server_create(csrmf_ctx* ctx, int32_t n_users, int32_t n_items, const double* U, const double* V,
+                        double hbm_budget_bytes, int32_t max_batch, csrmf_server** out);
+
+/* Queue a request: op 0 = PREDICT (r_hat = <u_user, v_j> for the row's items),
+ * op 1 = UPDATE (one R2 gradient step of u_user on the row:
+ * u' = (1 - lr*lambda) u + (lr/d) sum_j (r_j - <u, v_j>) v_j; items stay fixed).
+ * items[n]: the row's item ids, increasing; ratings[n]: the row's ratings
+ * (UPDATE only; encrypted on admission with randomness derived from
+ * client_serial < 2^27, so equal requests give equal ciphertexts).  Rows longer
+ * than D blocks are cut into up to 8 chunks.  id receives the request id.
+ * A PREDICT uses 2 levels of the chain, an UPDATE 4.
+ * Errors: INVAL, NOMEM (the request alone exceeds the budget), LEVEL (an
+ * UPDATE on a chain of fewer than 4 levels). */
+int csrmf_server_submit(csrmf_server* s, int32_t op, int32_t user, int32_t n, const int32_t* items,
+                        const double* ratings, uint32_t client_serial, uint64_t* id);
+
+/* Status of a request (wait != 0: block until it finishes): 0 queued,
+ * 1 running, 2 done, or a negative error code (also returned).  When done,
+ * the result handles (owned by the caller, freed with csrmf_free_ct) go to
+ * results[cap]: PREDICT one ciphertext per row chunk, slot t*B holding
+ * r_hat of the chunk's t-th item; UPDATE one ciphertext with u' in slots
+ * 0..k-1.  latency_s = completion - submission time. */
+int csrmf_server_poll(csrmf_server* s, uint64_t id, int32_t wait, int32_t* status, uint64_t* results,
+                      int32_t cap, int32_t* n_results, double* latency_s);
+
+/* JSON counters (batches, processed, largest batch, queue length, bytes in
+ * flight, budget) into buf (NUL-terminated, truncated to cap); returns the
+ * full length. */
+int csrmf_server_stats(csrmf_server* s, char* buf, int32_t cap);
+
+/* Stop the worker (finishing the batch on the device) and free the server. */
+void csrmf_server_destroy(csrmf_server* s);
+
+/* ------------------------------------------------------------------------ */
 /* Schedule autotuning.                                                      */
 /* ------------------------------------------------------------------------ */
 
@@ -281,12 +328,14 @@ int csrmf_encrypt_csr_rows_int(csrmf_ctx* ctx, int32_t n_rows, int32_t n_cols,
  * Errors: STATE (no ratings encrypted yet). */
 int csrmf_init_factors(csrmf_ctx* ctx, const double* U0, const double* V0);
 
-/* Integer-plaintext form of csrmf_init_factors plus the block indicator mask:
- * utab[n_utab][N], vtab[n_vtab][N], ug[n_ct][N], vg[n_ct][N] and
- * mask0[N] = encoding of the indicator of slots 0..k-1 at scale 2^20.
- * Counts are reported by csrmf_mf_layout. */
+/* Integer-plaintext form of csrmf_init_factors plus the block indicator masks:
+ * utab[n_utab][N], vtab[n_vtab][N], ug[n_ct][N], vg[n_ct][N];
+ * mask_scatter[N] and mask_gather[N] = encodings of the indicator of slots
+ * 0..k-1 at scales 2^20 (scatters) and 2^30 (gathers, whose weights are all 1).
+ * Counts are reported by csrmf_mf_layout.  Errors: INVAL (null pointer), STATE. */
 int csrmf_init_factors_int(csrmf_ctx* ctx, const int64_t* utab, const int64_t* vtab,
-                           const int64_t* ug, const int64_t* vg, const int64_t* mask0);
+                           const int64_t* ug, const int64_t* vg, const int64_t* mask_scatter,
+                           const int64_t* mask_gather);
 
 /* Layout counts: rating ciphertexts, user-table and item-table ciphertexts,
  * blocks per ciphertext D and block width B. */

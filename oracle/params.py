@@ -185,6 +185,13 @@ def config_tiny():
     return make_params(12, 60, 3, 40, 1, 60, 4, 40, name="tiny")
 
 
+def config_tiny_two_epochs():
+    """N = 2^12, q_0 60-bit + 7 x 40-bit, 2 x 60-bit special, dnum 4 (2-limb digits,
+    each below P ~ 2^120), scale 2^40: room for two MF epochs (3 + 4 levels), so a
+    gather runs encrypted."""
+    return make_params(12, 60, 7, 40, 2, 60, 4, 40, name="tiny2")
+
+
 def config_kernel_batch():
     """N = 2^16, q_0 60-bit + 24 x 40-bit, 3 x 60-bit special, dnum = 3 (digits 9, 9, 7)."""
     return make_params(16, 60, 24, 40, 3, 60, 3, 40, name="kernel_batch")

@@ -29,14 +29,31 @@ BlockPermute: a move (source ciphertext c, source block a -> destination
 block b, weight w) has delta = (a - b) mod D = gamma*G + beta with
 G = 2^ceil(log2(D)/2).  For destination d:
     acc_d = sum_gamma Rot_{gamma G B}( sum_{c, beta} HRot_{beta B}(src_c) (.) M_{d,c,gamma,beta} )
+            + T_d (.) (W_c + sum_{b in C_d} W_b I_b)                  (scatter only)
 with HRot hoisted per source, the giant rotation applied once per (d, gamma)
 after the inner sum, zero steps skipped, and the plaintext mask
     M_{d,c,gamma,beta} = sum_{moves in the group} W * I_{(b + gamma G) mod D},
     I_p = tau_{g_p}(I_0), g_p = 5^((-p B) mod N/2) mod 2N,
-I_0 the encoding of the indicator of slots 0..k-1 at scale S_I = 2^20, and
-the integer weight W = rint((w * S_t * q_ell) / (S_src * S_I)) for a target
-scale S_t = Delta (q_ell the top prime of the accumulator).  Every term then
-carries scale S_t * q_ell and the accumulator is rescaled once.
+I_0 the encoding of the indicator of slots 0..k-1 at the call's mask scale S_I
+and the integer weight W = rint((w * S_t * q_ell) / (S_src * S_I)) for the
+target scale S_t = Delta (q_ell the top prime of the accumulator).  One
+rescale per destination.
+
+Mask precision.  Encoding I_0 rounds its N coefficients, so every slot of I_p
+is off by about sqrt(N/24)/S_I (5e-5 at N = 2^15, S_I = 2^20) and a sum of D
+masks with weight ~1 is off by sqrt(D) times that.  Two choices keep the
+result within the 1e-4 value contract at N = 2^15 and 2^16:
+* gather (every weight 1, one source scale): I_0 at S_I = 2^30; the
+  accumulator's scale is declared as S_src * S_I * W_1 with
+  W_1 = rint((S_t * q_ell) / (S_src * S_I)), the exact scale of every term,
+  so no weight is rounded and the result's scale is within 2^-10 of S_t;
+* scatter: I_0 at S_I = 2^20.  The self term's weights w_b (one per table
+  entry) are split into a constant c, the lower median of the w_b of the
+  present entries, applied as the constant polynomial
+  W_c = rint((c * S_t * q_ell) / S_T), plus masked corrections w_b - c for the
+  entries whose weight differs (C_d).  Mask rounding then scales with the
+  correction, not with the weight ~1.  Slots of absent entries and the
+  padding slots of a table are multiplied by c (they hold no data).
 
 The same program runs on two back ends: ``CkksBackend`` (the oracle CKKS
 context) and ``ClearBackend`` (plain slot vectors with exact 0/1 masks and
@@ -49,7 +66,16 @@ import numpy as np
 
 from . import ckks, ring
 
-S_I = 2.0 ** 20
+S_I = 2.0 ** 20      # mask scale of a scatter
+S_IG = 2.0 ** 30     # mask scale of a gather
+S_T = 2.0 ** 40      # target scale of every permuted result
+
+
+def block_masks(ctx, k):
+    """{mask scale: I_0 encoded at that scale} for the scatter and gather scales."""
+    ind = np.zeros(ctx.N // 2)
+    ind[:k] = 1.0
+    return {S_I: ctx.encode(ind, S_I), S_IG: ctx.encode(ind, S_IG)}
 
 
 def next_pow2(k):
@@ -161,9 +187,10 @@ def rotation_steps(lay):
 class CkksBackend:
     """Evaluates the program on oracle ciphertexts."""
 
-    def __init__(self, ctx: ckks.Context, mask0):
+    def __init__(self, ctx: ckks.Context, masks):
+        """masks: {mask scale: integer coefficients of I_0 encoded at that scale}."""
         self.ctx = ctx
-        self.mask0 = np.asarray(mask0, np.int64)   # encoded indicator, integer coefficients
+        self.masks = {float(s): np.asarray(m, np.int64) for s, m in masks.items()}
         self.N = ctx.N
 
     def level(self, x):
@@ -199,12 +226,14 @@ class CkksBackend:
     def drop(self, a, level):
         return self.ctx.mod_drop(a, level)
 
-    def mask_mul(self, a, terms, scale):
-        """a (.) sum_m W_m * I_{p_m}; the result carries the given scale."""
+    def mask_mul(self, a, terms, scale, mask_scale, const=0):
+        """a (.) (const + sum_m W_m * I_{p_m}), I_0 encoded at mask_scale; the
+        result carries the given scale."""
         N = self.N
         m = np.zeros(N, dtype=object)
+        m[0] = int(const)
         for p, W in terms:
-            m = m + int(W) * self._mask(p)
+            m = m + int(W) * self._mask(p, mask_scale)
         qm = self.ctx.qmods(a.level)
         mm = np.stack([np.array([int(v) % q for v in m], dtype=np.uint64) for q in qm])
         idx = list(range(a.level + 1))
@@ -214,16 +243,17 @@ class CkksBackend:
         self.B = B
         self._cache = {}
 
-    def _mask(self, p):
-        if p not in self._cache:
+    def _mask(self, p, mask_scale):
+        key = (float(mask_scale), p)
+        if key not in self._cache:
             N = self.N
             g = pow(5, (-p * self.B) % (N // 2), 2 * N)
             dst, neg = ring.automorphism_map(g, N)
             v = np.zeros(N, dtype=object)
-            src = self.mask0.astype(object)
+            src = self.masks[float(mask_scale)].astype(object)
             v[dst] = np.where(neg, -src, src)
-            self._cache[p] = v
-        return self._cache[p]
+            self._cache[key] = v
+        return self._cache[key]
 
 
 class ClearBackend:
@@ -278,9 +308,9 @@ class ClearBackend:
     def drop(self, a, level):
         return self.V(a.z, level, a.scale)
 
-    def mask_mul(self, a, terms, scale):
-        m = np.zeros(self.N // 2)
-        for p, w in terms:            # here the weight is the exact real w, not the integer W
+    def mask_mul(self, a, terms, scale, mask_scale, const=0.0):
+        m = np.full(self.N // 2, float(const))
+        for p, w in terms:            # here the weights are the exact reals, not the integers W
             m[p * self.B: p * self.B + self.k] += w
         return self.V(a.z * m, a.level, scale)
 
@@ -297,13 +327,21 @@ class Move:
     w: float      # real weight
 
 
-def block_permute(be, lay, srcs, dests_moves, self_terms, level, exact_weights=False):
-    """dests_moves[d] = list of Move; self_terms[d] = (ciphertext, [(block, w)]) or None.
-    All sources share level and scale.  Returns the rescaled accumulators."""
+def block_permute(be, lay, srcs, dests_moves, self_terms, level, mask_scale, unit=False,
+                  exact_weights=False):
+    """dests_moves[d] = list of Move; self_terms[d] = (table ciphertext, c,
+    [(block, w_b - c)]) or None.  All sources share level and scale.  unit:
+    every move has weight 1 and the accumulator takes the exact scale of the
+    terms.  Returns the rescaled accumulators."""
     D, G, B = lay.D, lay.G, lay.B
-    S_t = float(2 ** 40) if not exact_weights else None
     src_scale = be.scale(srcs[0]) if srcs else None
     q_acc = float(be.top_prime(level))
+    if unit:
+        assert all(mv.w == 1.0 for moves in dests_moves for mv in moves)
+        W1 = weight(1.0, src_scale, q_acc, mask_scale, False)
+        acc_scale = src_scale * mask_scale * float(W1)
+    else:
+        acc_scale = S_T * q_acc
     # hoisted baby rotations per source, only the betas that are used
     need = {}
     for d, moves in enumerate(dests_moves):
@@ -320,7 +358,6 @@ def block_permute(be, lay, srcs, dests_moves, self_terms, level, exact_weights=F
             if b:
                 baby[c][b] = rots[b * B]
     out = []
-    acc_scale = S_T_Q(lay, level, be)
     for d, moves in enumerate(dests_moves):
         groups = {}
         for mv in moves:
@@ -334,31 +371,30 @@ def block_permute(be, lay, srcs, dests_moves, self_terms, level, exact_weights=F
                 terms = []
                 for mv in groups[gamma][(c, beta)]:
                     p = (mv.b + gamma * G) % D
-                    terms.append((p, weight(be, mv.w, src_scale, q_acc, exact_weights)))
-                t = be.mask_mul(baby[c][beta], terms, acc_scale)
+                    terms.append((p, weight(mv.w, src_scale, q_acc, mask_scale, exact_weights)))
+                t = be.mask_mul(baby[c][beta], terms, acc_scale, mask_scale)
                 inner = t if inner is None else be.add(inner, t)
             if gamma:
                 inner = be.rotate(inner, gamma * G * B)
             acc = inner if acc is None else be.add(acc, inner)
         st = self_terms[d] if self_terms else None
         if st is not None:
-            ct, blocks = st
+            ct, cst, blocks = st
             ctd = be.drop(ct, level)
-            terms = [(b, weight(be, w, be.scale(ctd), q_acc, exact_weights)) for b, w in blocks]
-            t = be.mask_mul(ctd, terms, acc_scale)
+            s_self = be.scale(ctd)
+            Wc = weight(cst, s_self, q_acc, 1.0, exact_weights)
+            terms = [(b, weight(w, s_self, q_acc, mask_scale, exact_weights)) for b, w in blocks]
+            t = be.mask_mul(ctd, terms, acc_scale, mask_scale, const=Wc)
             acc = t if acc is None else be.add(acc, t)
         out.append(be.rescale(acc))
     return out
 
 
-def S_T_Q(lay, level, be):
-    return float(2 ** 40) * float(be.top_prime(level))
-
-
-def weight(be, w, s_src, q_acc, exact):
+def weight(w, s_src, q_acc, mask_scale, exact):
+    """The integer W that carries weight w from scale s_src to S_t * q_acc."""
     if exact:
         return w
-    return int(np.rint((w * float(2 ** 40) * q_acc) / (s_src * S_I)))
+    return int(np.rint((w * S_T * q_acc) / (s_src * mask_scale)))
 
 
 @dataclass
@@ -418,20 +454,31 @@ def _scatter(be, lay, Gs, tabs, owner, deg, n_ent, a_t, lam, rule, level, exact)
         d, b = divmod(e, D)
         w = a_t if rule == "R1" else a_t / deg[e]
         moves[d].append(Move(int(lay.ct_of[r]), int(lay.blk_of[r]), b, w))
-    selfs = []
+    return block_permute(be, lay, Gs, moves, self_terms(lay, tabs, deg, n_ent, a_t, lam, rule), level,
+                         S_I, False, exact)
+
+
+def self_terms(lay, tabs, deg, n_ent, a_t, lam, rule):
+    """Per table ciphertext: (ciphertext, c, [(block, w_b - c)]) with w_b the
+    entry's weight (R1: 1 - a_t*lambda*d; R2: 1 - a_t*lambda, 1 for an empty
+    entry), c the lower median of the w_b, corrections where w_b != c."""
+    D = lay.D
+    out = []
     for d in range(len(tabs)):
-        blocks = []
+        ws = []
         for b in range(D):
             e = d * D + b
             if e >= n_ent:
-                continue
+                break
             if rule == "R1":
                 w = 1.0 - a_t * lam * deg[e]
             else:
                 w = (1.0 - a_t * lam) if deg[e] > 0 else 1.0
-            blocks.append((b, w))
-        selfs.append((tabs[d], blocks))
-    return block_permute(be, lay, Gs, moves, selfs, level, exact)
+            ws.append((b, w))
+        srt = sorted(w for _, w in ws)
+        c = srt[(len(srt) - 1) // 2]
+        out.append((tabs[d], c, [(b, w - c) for b, w in ws if w != c]))
+    return out
 
 
 def _gather(be, lay, tabs, owner, exact):
@@ -442,7 +489,7 @@ def _gather(be, lay, tabs, owner, exact):
         a_ct, a = divmod(e, D)
         moves[int(lay.ct_of[r])].append(Move(a_ct, a, int(lay.blk_of[r]), 1.0))
     level = be.level(tabs[0])
-    return block_permute(be, lay, tabs, moves, None, level, exact)
+    return block_permute(be, lay, tabs, moves, None, level, S_IG, True, exact)
 
 
 def decode_tables(vals, lay, n_ent):

@@ -86,7 +86,7 @@ _SIGS = {
     "csrmf_encrypt_csr_rows": [_p, ctypes.c_int32, ctypes.c_int32, _i64p, _i32p, _dp, _i32p],
     "csrmf_encrypt_csr_rows_int": [_p, ctypes.c_int32, ctypes.c_int32, _i64p, _i32p, _i64p, ctypes.c_int32, _i32p],
     "csrmf_init_factors": [_p, _dp, _dp],
-    "csrmf_init_factors_int": [_p, _i64p, _i64p, _i64p, _i64p, _i64p],
+    "csrmf_init_factors_int": [_p, _i64p, _i64p, _i64p, _i64p, _i64p, _i64p],
     "csrmf_mf_layout": [_p, _i32p, _i32p, _i32p, _i32p, _i32p],
     "csrmf_mf_epochs": [_p, ctypes.c_int32],
     "csrmf_predict": [_p],
@@ -94,6 +94,12 @@ _SIGS = {
     "csrmf_decrypt_predictions": [_p, _dp, ctypes.c_int32],
     "csrmf_mf_handles": [_p, ctypes.c_int32, _u64p, ctypes.c_int32, _i32p],
     "csrmf_autotune": [_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32],
+    "csrmf_server_create": [_p, ctypes.c_int32, ctypes.c_int32, _dp, _dp, ctypes.c_double, ctypes.c_int32,
+                            ctypes.POINTER(_p)],
+    "csrmf_server_submit": [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _dp, ctypes.c_uint32, _u64p],
+    "csrmf_server_poll": [_p, ctypes.c_uint64, ctypes.c_int32, _i32p, _u64p, ctypes.c_int32, _i32p, _dp],
+    "csrmf_server_stats": [_p, ctypes.c_char_p, ctypes.c_int32],
+    "csrmf_server_destroy": [_p],
     "csrmf_profile_enable": [ctypes.c_int32],
     "csrmf_profile_report": [ctypes.c_char_p, ctypes.c_int32],
 }
@@ -101,7 +107,8 @@ _SIGS = {
 for _name, _args in _SIGS.items():
     _f = getattr(lib, _name)
     _f.argtypes = _args
-    _f.restype = None if _name == "csrmf_destroy" else (ctypes.c_char_p if _name == "csrmf_last_error" else ctypes.c_int)
+    _f.restype = None if _name in ("csrmf_destroy", "csrmf_server_destroy") else (
+        ctypes.c_char_p if _name == "csrmf_last_error" else ctypes.c_int)
 
 
 def _ptr(a, ct):
@@ -136,6 +143,8 @@ class Context:
 
     def close(self):
         if self.h:
+            for srv in list(getattr(self, "_servers", [])):
+                srv._detach()
             lib.csrmf_destroy(self.h)
             self.h = None
 
@@ -360,8 +369,8 @@ class MF:
         self.k = U.shape[1]
         self.ctx._chk(lib.csrmf_init_factors(self.ctx.h, _ptr(U, ctypes.c_double), _ptr(V, ctypes.c_double)))
 
-    def init_factors_int(self, utab, vtab, ug, vg, mask0, k):
-        arrs = [np.ascontiguousarray(a, np.int64) for a in (utab, vtab, ug, vg, mask0)]
+    def init_factors_int(self, utab, vtab, ug, vg, mask_scatter, mask_gather, k):
+        arrs = [np.ascontiguousarray(a, np.int64) for a in (utab, vtab, ug, vg, mask_scatter, mask_gather)]
         self.k = k
         self.ctx._chk(lib.csrmf_init_factors_int(self.ctx.h, *[_ptr(a, ctypes.c_int64) for a in arrs]))
 
@@ -388,6 +397,70 @@ class MF:
         out = np.zeros(max(1, n.value), np.uint64)
         self.ctx._chk(lib.csrmf_mf_handles(self.ctx.h, which, _ptr(out, ctypes.c_uint64), n.value, ctypes.byref(n)))
         return [int(x) for x in out[: n.value]]
+
+
+class Server:
+    """Request server (continuous batching) on a Context; see csrmf_server_*."""
+    PREDICT, UPDATE = 0, 1
+
+    def __init__(self, ctx: "Context", U, V, hbm_budget_bytes, max_batch=64):
+        U = np.ascontiguousarray(U, np.float64)
+        V = np.ascontiguousarray(V, np.float64)
+        self.ctx = ctx
+        h = _p()
+        ctx._chk(lib.csrmf_server_create(ctx.h, U.shape[0], V.shape[0], _ptr(U, ctypes.c_double),
+                                         _ptr(V, ctypes.c_double), float(hbm_budget_bytes), max_batch,
+                                         ctypes.byref(h)))
+        self.h = h
+        if not hasattr(ctx, "_servers"):
+            ctx._servers = []
+        ctx._servers.append(self)
+
+    def _detach(self):
+        """The context is being destroyed; it stops and frees this server itself."""
+        self.h = None
+
+    def submit(self, op, user, items, ratings=None, client_serial=0):
+        it = np.ascontiguousarray(items, np.int32)
+        r = None if ratings is None else np.ascontiguousarray(ratings, np.float64)
+        rid = ctypes.c_uint64()
+        rc = lib.csrmf_server_submit(self.h, op, user, len(it), _ptr(it, ctypes.c_int32),
+                                     None if r is None else _ptr(r, ctypes.c_double), client_serial,
+                                     ctypes.byref(rid))
+        if rc != CSRMF_OK:
+            raise CsrmfError(rc, "submit rejected")
+        return rid.value
+
+    def poll(self, rid, wait=False):
+        """(status, [result handles], latency_s)."""
+        st = ctypes.c_int32()
+        n = ctypes.c_int32(0)
+        lat = ctypes.c_double(0)
+        out = np.zeros(16, np.uint64)
+        rc = lib.csrmf_server_poll(self.h, rid, int(bool(wait)), ctypes.byref(st), _ptr(out, ctypes.c_uint64), 16,
+                                   ctypes.byref(n), ctypes.byref(lat))
+        if rc != CSRMF_OK:
+            raise CsrmfError(rc, "request failed")
+        return st.value, [int(x) for x in out[: n.value]], lat.value
+
+    def stats(self):
+        import json
+        buf = ctypes.create_string_buffer(1024)
+        lib.csrmf_server_stats(self.h, buf, 1024)
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self.h:
+            lib.csrmf_server_destroy(self.h)
+            self.h = None
+            if self in getattr(self.ctx, "_servers", []):
+                self.ctx._servers.remove(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_enable(on=True):

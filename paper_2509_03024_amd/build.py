@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcsrmf.so")
-SOURCES = ["kernels.hip", "context.cpp", "capi.cpp", "host_math.cpp", "mf_program.cpp", "prof.cpp"]
+SOURCES = ["kernels.hip", "context.cpp", "capi.cpp", "host_math.cpp", "mf_program.cpp", "prof.cpp", "serving.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -25,7 +25,7 @@ def build(verbose=False):
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs, check=True)
+    subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-pthread", "-o", tmp] + objs, check=True)
     os.replace(tmp, LIB)
     return LIB
 

@@ -13,6 +13,7 @@ using csrmf::Error;
 
 #define API_BEGIN(ctx)                                   \
     if (!(ctx)) return CSRMF_E_INVAL;                    \
+    std::lock_guard<std::recursive_mutex> lk_((ctx)->mu); \
     try {
 #define API_END(ctx)                                     \
         (ctx)->err.clear();                              \

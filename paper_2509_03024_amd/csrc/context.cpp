@@ -70,6 +70,7 @@ static uint64_t* upload_consts(Pool& pool, const std::vector<uint64_t>& v, hipSt
 }
 
 Context::~Context() {
+    while (!servers.empty()) destroy_server(servers.back());   // joins the worker threads
     if (stream) (void)hipStreamSynchronize(stream);
     else (void)hipDeviceSynchronize();
     destroy_mf(mf);
@@ -456,13 +457,14 @@ void Context::make_switching_key(Key& key, const uint64_t* sprime, uint32_t key_
 }
 
 // ------------------------------------------------------------------ encrypt
-void Context::encrypt_int_batch(const int64_t* m, int count, int level, double scale, std::vector<Ct>& out) {
+void Context::encrypt_int_batch(const int64_t* m, int count, int level, double scale, std::vector<Ct>& out,
+                                const uint32_t* serials) {
     if (!have_keys) throw Error(CSRMF_E_STATE, "keygen first");
     if (level < 0 || level > L) throw Error(CSRMF_E_INVAL, "level out of range");
     // signed inputs: [count][4][N] = v, e0, e1, m
     std::vector<int64_t> host((size_t)count * 4 * N);
     for (int c = 0; c < count; ++c) {
-        const uint64_t ser = serial++;
+        const uint64_t ser = serials ? serials[c] : serial++;
         int64_t* h = host.data() + (size_t)c * 4 * N;
         sample_ternary(seed, kEncV, (uint32_t)ser, N, h);
         sample_cbd21(seed, kEncE0, (uint32_t)ser, N, h + N);
@@ -711,7 +713,7 @@ void Context::mul_plain(const Ct& a, const int64_t* m, double pt_scale, Ct& out)
     CSRMF_HIP(hipStreamSynchronize(stream));
 }
 
-void Context::mul_int(const Ct& a, int64_t w, Ct& out) {
+void Context::mul_int(const Ct& a, int64_t w, Ct& out, double declared) {
     const int nl = a.level + 1;
     std::vector<uint64_t> c;
     for (int i = 0; i < nl; ++i) {
@@ -721,7 +723,7 @@ void Context::mul_int(const Ct& a, int64_t w, Ct& out) {
     }
     Scratch cd(pool, c.size());
     upload(cd.p, c.data(), c.size() * 8, stream);
-    out = new_ct(a.level, a.scale * (double)w);
+    out = new_ct(a.level, declared != 0.0 ? declared : a.scale * (double)w);
     launch_mul_const(tabs, map_ct(out.d, nl), map_ct(a.d, nl), cd.p, true, stream);
     CSRMF_HIP(hipStreamSynchronize(stream));
 }

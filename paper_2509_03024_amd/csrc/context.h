@@ -6,6 +6,7 @@
 
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
@@ -82,6 +83,8 @@ struct Scratch {
 
 struct MfState;  // encrypted matrix-factorisation program (mf_program.cpp)
 void destroy_mf(MfState* m);
+struct Server;   // request server (serving.cpp)
+void destroy_server(Server* s);
 
 struct Context {
     csrmf_params prm{};
@@ -98,6 +101,7 @@ struct Context {
     hipStream_t stream = nullptr;
     Pool pool;
     std::string err;
+    std::recursive_mutex mu;        // serialises API calls and the serving worker
 
     uint64_t serial = 0;
     bool have_keys = false;
@@ -111,6 +115,7 @@ struct Context {
     uint64_t next_handle = 1;
     std::map<std::vector<uint64_t*>, uint64_t**> ptr_tables;
     MfState* mf = nullptr;
+    std::vector<Server*> servers;   // stopped and freed before the context
 
     Context() = default;
     ~Context();
@@ -142,7 +147,8 @@ struct Context {
 
     // --- encryption
     Ct encrypt_int(const int64_t* m, int level, double scale);
-    void encrypt_int_batch(const int64_t* m, int count, int level, double scale, std::vector<Ct>& out);
+    void encrypt_int_batch(const int64_t* m, int count, int level, double scale, std::vector<Ct>& out,
+                           const uint32_t* serials = nullptr);
     void decrypt_int(const Ct& c, int64_t* m);
     void export_ct(const Ct& c, uint64_t* coeffs);
     Ct import_ct(const uint64_t* coeffs, int level, double scale);
@@ -153,7 +159,8 @@ struct Context {
     void add_batch(const std::vector<Ct*>& a, const std::vector<Ct*>& b, std::vector<Ct*>& out, bool sub);
     void add_plain(const Ct& a, const int64_t* m, Ct& out);
     void mul_plain(const Ct& a, const int64_t* m, double pt_scale, Ct& out);
-    void mul_int(const Ct& a, int64_t w, Ct& out);
+    // multiply by the integer w; the result's scale is scale * w, or `declared` if non-zero
+    void mul_int(const Ct& a, int64_t w, Ct& out, double declared = 0.0);
     void mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, std::vector<Ct*>& out);
     void rescale(const std::vector<Ct*>& v);          // in place
     void mod_drop(Ct& c, int level);                   // in place

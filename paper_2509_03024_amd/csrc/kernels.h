@@ -121,19 +121,13 @@ void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap&
                             const RowMap& conv, const RowMap& addend, uint32_t g_add,
                             bool addend_both_polys, const uint64_t* consts, hipStream_t s);
 
-// acc (+)= src (.) M for both polynomials (rows of acc/src: c0, c1 at
-// +poly_stride), where M = sum_m W_m tau_{g_m}(I0) is formed on the fly from
-// the evaluation-form plaintext I0 (limb k at i0 + k*N): gs[m] = g_m,
-// cw[2*(m*cw_stride + k)], +1 = W_m * 2^64 mod q_k and its shoup.  first:
-// overwrite acc instead of accumulating.
-void launch_mask_mac(const DevTables& t, const RowMap& acc, const RowMap& src, const uint64_t* i0,
-                     const uint32_t* gs, const uint64_t* cw, int n_terms, int cw_stride, bool first,
-                     hipStream_t s);
-
 // Multi-task masked MAC (the inner sums of block permutations): task t
 // accumulates into acc[t] (both polynomials, limbs 0..n_limbs-1) its groups
-// [grp_begin[t], grp_begin[t+1]), each src[g] (.) sum_{m} W_m tau_{gs[m]}(I0) over
-// the group's terms [term_begin[g], term_begin[g+1]); cw as for launch_mask_mac.
+// [grp_begin[t], grp_begin[t+1]), each src[g] (.) M_g with
+// M_g = sum_m W_m tau_{gs[m]}(I0) over the group's terms
+// [term_begin[g], term_begin[g+1]) (a term with gs[m] = 0 adds the constant W_m),
+// formed on the fly from the evaluation-form plaintext I0 (limb k at i0 + k*N);
+// cw[2*(m*cw_stride + k)], +1 = W_m * 2^64 mod q_k and its shoup.
 // first[t] != 0: the accumulator starts at zero.  All pointers are device arrays.
 struct MaskTasks {
     uint64_t* const* acc;       // [n_tasks] ciphertext base pointers
@@ -141,7 +135,7 @@ struct MaskTasks {
     const int32_t* first;       // [n_tasks]
     const uint64_t* const* src; // [n_groups]
     const int32_t* term_begin;  // [n_groups + 1]
-    const uint32_t* gs;         // [n_terms]
+    const uint32_t* gs;         // [n_terms] Galois element of I_p, or 0 for a constant term
     const uint64_t* cw;         // [n_terms][cw_stride][2]
     int32_t n_tasks, n_limbs, cw_stride;
     int64_t poly_stride;

@@ -552,41 +552,11 @@ __global__ void __launch_bounds__(kThreads) k_rescale_combine(DevTables t, RowMa
 // bytes of `rows` polynomial rows (algorithmic traffic accounting for the profiler)
 #define NB(rows) ((double)(rows) * (double)(1 << t.logN) * 8.0)
 
-// Masked plaintext multiply-accumulate for block permutations.  For each
-// element x of limb k the plaintext mask is formed on the fly in Montgomery
-// form from the evaluation-form indicator I0 (rows [L+1][N]):
-//     M[x] = sum_m cw[m][k] * I0_k[perm_{g_m}(x)]     (cw = W_m * 2^64 mod q_k, Shoup)
-// and acc_p[x] (+)= mont(src_p[x], M[x]) for both polynomials p.
-__global__ void __launch_bounds__(kThreads) k_mask_mac(DevTables t, RowMap acc, RowMap src, const uint64_t* i0,
-                                                       const uint32_t* gs, const uint64_t* cw, int n_terms,
-                                                       int cw_stride, int first) {
-    EW_PROLOGUE(acc)
-    int mod, ms;
-    uint64_t* pa = map_row(acc, b, k, logN, mod);
-    const uint64_t* ps = map_row(src, b, k, logN, ms);
-    const Modulus md = t.mods[mod];
-    const uint64_t* row = i0 + ((size_t)k << logN);
-    for (int uu = 0; uu < kEwPerThread; ++uu) {
-        const int i = base_i + uu * kThreads;
-        uint64_t M = 0;
-        for (int m = 0; m < n_terms; ++m) {
-            const uint64_t* c = cw + 2 * ((size_t)m * cw_stride + k);
-            M = add_mod(M, mul_shoup(row[galois_perm((uint32_t)i, gs[m], logN)], c[0], c[1], md.q), md.q);
-        }
-        uint64_t r0 = mul_mont(ps[i], M, md.q, md.qneg_inv);
-        uint64_t r1 = mul_mont(ps[i + src.poly_stride], M, md.q, md.qneg_inv);
-        if (!first) {
-            r0 = add_mod(r0, pa[i], md.q);
-            r1 = add_mod(r1, pa[i + acc.poly_stride], md.q);
-        }
-        pa[i] = r0;
-        pa[i + acc.poly_stride] = r1;
-    }
-}
-
-// Multi-task masked MAC: task t accumulates into acc_t (both polynomials,
-// limbs 0..n_limbs-1) the groups [grp_begin[t], grp_begin[t+1]) of
-//     src_g (.) sum_{m in group} W_m tau_{g_m}(I0);
+// Multi-task masked MAC for block permutations: task t accumulates into acc_t
+// (both polynomials, limbs 0..n_limbs-1) the groups [grp_begin[t], grp_begin[t+1]) of
+//     src_g (.) M_g,   M_g[x] = sum_{m in group} cw[m][k] * I0_k[perm_{g_m}(x)]
+// (cw = W_m * 2^64 mod q_k with its Shoup factor, so the product with src is a
+// Montgomery multiply; g_m = 0 adds cw[m][k] itself, a constant plaintext);
 // group g reads src_ptr[g] (c1 at +poly_stride) and its terms
 // [term_begin[g], term_begin[g+1]).  If first[t] != 0 the accumulator starts at 0.
 
@@ -615,7 +585,9 @@ __global__ void __launch_bounds__(kThreads) k_mask_mac_tasks(DevTables t, MaskTa
             uint64_t M = 0;
             for (int m = T.term_begin[g]; m < T.term_begin[g + 1]; ++m) {
                 const uint64_t* c = T.cw + 2 * ((size_t)m * T.cw_stride + k);
-                M = add_mod(M, mul_shoup(row[galois_perm((uint32_t)i, T.gs[m], logN)], c[0], c[1], md.q), md.q);
+                const uint32_t g = T.gs[m];
+                // Galois element 0 marks a constant term (the plaintext W, no mask)
+                M = add_mod(M, g ? mul_shoup(row[galois_perm((uint32_t)i, g, logN)], c[0], c[1], md.q) : c[0], md.q);
             }
             const uint64_t* ps = T.src[g] + ((size_t)k << logN);
             a0 = add_mod(a0, mul_mont(ps[i], M, md.q, md.qneg_inv), md.q);
@@ -737,14 +709,6 @@ void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap&
     if (!out.rows()) return;
     { ProfScope ps_("k_moddown_combine", s, NB(out.rows()) * (6 + (addend.n ? (addend_both ? 2 : 1) : 0))); hipLaunchKernelGGL(k_moddown_combine, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, u, conv,
                        addend, g_add, addend_both ? 1 : 0, consts); }
-}
-
-void launch_mask_mac(const DevTables& t, const RowMap& acc, const RowMap& src, const uint64_t* i0, const uint32_t* gs,
-                     const uint64_t* cw, int n_terms, int cw_stride, bool first, hipStream_t s) {
-    if (!acc.rows() || n_terms <= 0) return;
-    ProfScope ps_("k_mask_mac", s, NB(acc.rows()) * (first ? 4 : 6) + NB(acc.rows()) * n_terms);
-    hipLaunchKernelGGL(k_mask_mac, dim3(ew_blocks(t, acc)), dim3(kThreads), 0, s, t, acc, src, i0, gs, cw, n_terms,
-                       cw_stride, first ? 1 : 0);
 }
 
 void launch_mask_mac_tasks(const DevTables& t, const MaskTasks& T, const uint64_t* i0, double bytes, hipStream_t s) {

@@ -1,0 +1,76 @@
+// Internal pieces of the encrypted MF program shared with the serving loop.
+#pragma once
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "context.h"
+
+namespace csrmf {
+
+struct MfState {
+    int k = 0, kp = 0, B = 0, D = 0, G = 0;
+    int n_users = 0, n_items = 0, nnz = 0;
+    int n_ct = 0, n_utab = 0, n_vtab = 0;
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col_idx;
+    std::vector<int32_t> rows, ct_of, blk_of;
+    std::vector<double> deg_u, deg_v;
+    std::vector<uint64_t> R, Utab, Vtab, Ug, Vg, Sdot, Pred;   // handles
+    uint64_t* mask0 = nullptr;      // I0 at the scatter mask scale, evaluation form [L+1][N]
+    uint64_t* maskg = nullptr;      // I0 at the gather mask scale, evaluation form [L+1][N]
+    int epochs_done = 0;
+    bool factors = false;
+};
+
+namespace mfp {
+
+// Scales of the block indicator I0.  Rounding I0's coefficients puts an error
+// of about sqrt(N/24)/S_I on every slot of every mask; a gather (all weights 1)
+// sums D masks, so it takes the larger scale and declares the exact scale of
+// its terms instead of rounding a weight; a scatter needs room for small
+// integer weights (learning rate over degree) and keeps 2^20, with the self
+// term's common weight applied as a constant so only corrections are masked.
+constexpr double kMaskScale = 1048576.0;           // 2^20, scatter
+constexpr double kGatherMaskScale = 1073741824.0;  // 2^30, gather
+constexpr double kTargetScale = 1099511627776.0;   // 2^40, scale of every permuted result
+
+// A block move: source ciphertext `src`, block a -> destination block b, weight w.
+struct Move {
+    int src, a, b;
+    double w;
+};
+
+// Self term of a scatter destination: T (.) (c + sum_b (w_b - c) I_b).
+struct SelfTerm {
+    Ct* t = nullptr;
+    double c = 1.0;
+    std::vector<std::pair<int, double>> corr;   // (block, w_b - c), w_b != c
+};
+
+// (source index, baby step beta) -> HRot_{beta B}(source) at the permutation's level
+typedef std::map<std::pair<int, int>, Ct> BabyCache;
+
+void free_handles(Context* c, std::vector<uint64_t>& v);
+void release(Context* c, std::vector<Ct>& v);
+std::vector<Ct*> ptrs(std::vector<Ct>& v);
+std::vector<Ct> dropped(const std::vector<Ct*>& v, int level);
+std::vector<Ct> hmult_all(Context* c, const std::vector<Ct*>& a, const std::vector<Ct*>& b);
+std::vector<Ct> rotate_all(Context* c, const std::vector<Ct*>& a, int64_t r);
+std::vector<Ct> add_all(Context* c, const std::vector<Ct*>& a, const std::vector<Ct*>& b, bool sub);
+int64_t weight_int(double w, double s_src, double q_acc, double mask_scale);
+std::vector<int64_t> encode_all(Context* c, const std::vector<std::vector<double>>& zs, double scale);
+std::vector<uint64_t> put_all(Context* c, std::vector<Ct>& v);
+void upload_masks(Context* c, MfState& m, const int64_t* mask_scatter, const int64_t* mask_gather);
+void encode_masks(Context* c, int k, std::vector<int64_t>& mask_scatter, std::vector<int64_t>& mask_gather);
+void free_masks(Context* c, MfState& m);
+// unit: every move has weight 1 (a gather): I0 at the gather scale and the
+// accumulator declared at the exact scale of its terms.
+std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& srcs,
+                              const std::vector<std::vector<Move>>& dests, const std::vector<SelfTerm>* selfs,
+                              int level, const BabyCache* cache, bool unit);
+std::vector<Ct> dot_products(Context* c, MfState& m, const std::vector<Ct*>& ug, const std::vector<Ct*>& vg,
+                             double* sp_out);
+
+}  // namespace mfp
+}  // namespace csrmf

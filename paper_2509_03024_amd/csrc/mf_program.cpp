@@ -26,38 +26,14 @@
 #include <map>
 #include <tuple>
 
-#include "context.h"
+#include "mf_internal.h"
 #include "host_math.h"
 
 namespace csrmf {
 
-namespace {
-constexpr double kMaskScale = 1048576.0;           // 2^20
-constexpr double kTargetScale = 1099511627776.0;   // 2^40
-}  // namespace
-
-struct MfState {
-    int k = 0, kp = 0, B = 0, D = 0, G = 0;
-    int n_users = 0, n_items = 0, nnz = 0;
-    int n_ct = 0, n_utab = 0, n_vtab = 0;
-    std::vector<int64_t> row_ptr;
-    std::vector<int32_t> col_idx;
-    std::vector<int32_t> rows, ct_of, blk_of;
-    std::vector<double> deg_u, deg_v;
-    std::vector<uint64_t> R, Utab, Vtab, Ug, Vg, Sdot, Pred;   // handles
-    uint64_t* mask0 = nullptr;                                  // I0, evaluation form [L+1][N]
-    int epochs_done = 0;
-    bool factors = false;
-};
-
 void destroy_mf(MfState* m) { delete m; }
 
-namespace {
-
-struct Move {
-    int src, a, b;
-    double w;
-};
+namespace mfp {
 
 void free_handles(Context* c, std::vector<uint64_t>& v) {
     for (uint64_t h : v) c->free_ct(h);
@@ -176,16 +152,36 @@ std::vector<uint64_t> encrypt_list(Context* c, const int64_t* m, int count, doub
     return h;
 }
 
-void upload_mask(Context* c, MfState& m, const int64_t* mask) {
-    if (!m.mask0) m.mask0 = (uint64_t*)c->pool.get((size_t)(c->L + 1) * c->N * 8);
+static void upload_one(Context* c, uint64_t*& dst, const int64_t* mask) {
+    if (!dst) dst = (uint64_t*)c->pool.get((size_t)(c->L + 1) * c->N * 8);
     Scratch src(c->pool, c->N);
     CSRMF_HIP(hipMemcpyAsync(src.p, mask, c->N * 8, hipMemcpyHostToDevice, c->stream));
     RowMap mm;
-    mm.base = m.mask0;
+    mm.base = dst;
     for (int i = 0; i <= c->L; ++i) mm.push(i, i);
     launch_expand_signed(c->tabs, mm, (const int64_t*)src.p, 1, 0, c->stream);
     launch_ntt(c->tabs, mm, false, c->stream);
     CSRMF_HIP(hipStreamSynchronize(c->stream));
+}
+
+void upload_masks(Context* c, MfState& m, const int64_t* mask_scatter, const int64_t* mask_gather) {
+    upload_one(c, m.mask0, mask_scatter);
+    upload_one(c, m.maskg, mask_gather);
+}
+
+void encode_masks(Context* c, int k, std::vector<int64_t>& mask_scatter, std::vector<int64_t>& mask_gather) {
+    std::vector<double> ind(c->N / 2, 0.0);
+    for (int f = 0; f < k; ++f) ind[f] = 1.0;
+    mask_scatter.assign(c->N, 0);
+    mask_gather.assign(c->N, 0);
+    ckks_encode(ind.data(), (int)ind.size(), c->logN, kMaskScale, mask_scatter.data());
+    ckks_encode(ind.data(), (int)ind.size(), c->logN, kGatherMaskScale, mask_gather.data());
+}
+
+void free_masks(Context* c, MfState& m) {
+    if (m.mask0) c->pool.put(m.mask0);
+    if (m.maskg) c->pool.put(m.maskg);
+    m.mask0 = m.maskg = nullptr;
 }
 
 // Ct views at a lower level (same device buffer)
@@ -233,8 +229,8 @@ std::vector<Ct> add_all(Context* c, const std::vector<Ct*>& a, const std::vector
     return out;
 }
 
-int64_t weight_int(double w, double s_src, double q_acc) {
-    return (int64_t)std::nearbyint((w * kTargetScale * q_acc) / (s_src * kMaskScale));
+int64_t weight_int(double w, double s_src, double q_acc, double mask_scale) {
+    return (int64_t)std::nearbyint((w * kTargetScale * q_acc) / (s_src * mask_scale));
 }
 
 // Upload a host vector into a pool scratch block (synchronous).
@@ -249,21 +245,30 @@ uint64_t* upload_vec(Context* c, const std::vector<T>& v, std::vector<uint64_t*>
 constexpr int kHoistChunk = 128;   // sources whose digits are extended together
 
 // srcs: source ciphertexts (viewed at `level`); dests[d]: moves into destination d;
-// selfs[d]: optional (table ciphertext, [(block, w)]) term.  Schedule: the sources
+// selfs[d]: optional self term (constant plus masked corrections).  Schedule: the sources
 // are extended (ModUp) once per chunk; for every baby step beta one batched
 // inner product + ModDown gives HRot_beta of all sources of the chunk, and one
 // multi-task launch accumulates every (destination, gamma) inner sum that uses
 // them; then one batched giant rotation per gamma, the self terms, and one
 // batched rescale.  Sums are exact, so this order gives the defined result.
 std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& srcs,
-                              const std::vector<std::vector<Move>>& dests,
-                              const std::vector<std::pair<Ct*, std::vector<std::pair<int, double>>>>* selfs,
-                              int level) {
+                              const std::vector<std::vector<Move>>& dests, const std::vector<SelfTerm>* selfs,
+                              int level, const BabyCache* cache, bool unit) {
     const int D = m.D, G = m.G, B = m.B;
     const int nl = level + 1;
     const double s_src = srcs.empty() ? 1.0 : srcs[0]->scale;
     const double q_acc = (double)c->moduli[level];
-    const double acc_scale = kTargetScale * q_acc;
+    const double mask_scale = unit ? kGatherMaskScale : kMaskScale;
+    const uint64_t* mask = unit ? m.maskg : m.mask0;
+    if (!mask) throw Error(CSRMF_E_STATE, "block masks not uploaded");
+    double acc_scale = kTargetScale * q_acc;
+    if (unit) {
+        for (const auto& dv : dests)
+            for (const Move& x : dv)
+                if (x.w != 1.0) throw Error(CSRMF_E_INVAL, "unit permutation with a weight other than 1");
+        if (selfs) throw Error(CSRMF_E_INVAL, "unit permutation with self terms");
+        acc_scale = s_src * mask_scale * (double)weight_int(1.0, s_src, q_acc, mask_scale);
+    }
     const int n_dest = (int)dests.size();
     const int n_gamma = D / G;
     auto wconst = [&](int64_t W, std::vector<uint64_t>& out) {
@@ -283,7 +288,7 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
         for (const Move& x : dests[d]) {
             const int delta = ((x.a - x.b) % D + D) % D;
             const int gamma = delta / G, beta = delta % G;
-            groups[{beta, x.src, d, gamma}].push_back({(x.b + gamma * G) % D, weight_int(x.w, s_src, q_acc)});
+            groups[{beta, x.src, d, gamma}].push_back({(x.b + gamma * G) % D, weight_int(x.w, s_src, q_acc, mask_scale)});
             auto& v = betas_of_src[x.src];
             if (std::find(v.begin(), v.end(), beta) == v.end()) v.push_back(beta);
         }
@@ -319,13 +324,21 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
         std::vector<Ct*> pviews = ptrs(views);
         Context::Hoist hs;
         const bool any_rot = betas.size() > 1 || (betas.size() == 1 && betas[0] != 0);
-        if (any_rot) c->hoist_begin(hs, pviews);
+        if (any_rot && !cache) c->hoist_begin(hs, pviews);
         for (int beta : betas) {
             std::vector<Ct> babies;
-            if (beta) {
+            std::vector<uint64_t*> baby_ptr(views.size());
+            for (size_t i = 0; i < views.size(); ++i) baby_ptr[i] = views[i].d;
+            if (beta && cache) {
+                for (size_t i = 0; i < views.size(); ++i) {
+                    auto it = cache->find({ids[i], beta});
+                    baby_ptr[i] = it == cache->end() ? nullptr : it->second.d;
+                }
+            } else if (beta) {
                 babies.resize(views.size());
                 std::vector<Ct*> pb = ptrs(babies);
                 c->hoist_rotate(hs, c->galois_for_step((int64_t)beta * B), pb);
+                for (size_t i = 0; i < views.size(); ++i) baby_ptr[i] = babies[i].d;
             }
             // tasks: one per (destination, gamma) receiving groups of this beta from this chunk
             std::map<std::pair<int, int>, std::vector<std::pair<int, const std::vector<std::pair<int, int64_t>>*>>> tasks;
@@ -350,7 +363,8 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
                 init = 1;
                 grp_begin.push_back((int32_t)src_ptr.size());
                 for (auto& gr : tk.second) {
-                    src_ptr.push_back(beta ? babies[gr.first].d : views[gr.first].d);
+                    if (!baby_ptr[gr.first]) throw Error(CSRMF_E_STATE, "missing cached baby-step rotation");
+                    src_ptr.push_back(baby_ptr[gr.first]);
                     term_begin.push_back((int32_t)gs.size());
                     for (auto& t : *gr.second) {
                         gs.push_back(gal(t.first));
@@ -375,7 +389,7 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
             T.poly_stride = c->poly_stride();
             CSRMF_HIP(hipStreamSynchronize(c->stream));   // host vectors go out of scope
             const double bytes = (double)c->N * 8.0 * nl * (2.0 * src_ptr.size() + 4.0 * acc_ptr.size() + gs.size());
-            launch_mask_mac_tasks(c->tabs, T, m.mask0, bytes, c->stream);
+            launch_mask_mac_tasks(c->tabs, T, mask, bytes, c->stream);
             for (uint64_t* p : owned) c->pool.put(p);
             release(c, babies);
         }
@@ -420,24 +434,28 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
         for (auto& r : rot)
             if (r.d) c->pool.put(r.d);
     }
-    // self terms: one task per destination
+    // self terms: one task per destination; the constant c is a term with
+    // Galois element 0 (no mask), the corrections are masked terms
     if (selfs) {
         std::vector<uint64_t*> acc_ptr, src_ptr;
         std::vector<int32_t> grp_begin, first, term_begin;
         std::vector<uint32_t> gs;
         std::vector<uint64_t> cw;
         for (int d = 0; d < n_dest; ++d) {
-            if (!(*selfs)[d].first || (*selfs)[d].second.empty()) continue;
-            const double s_self = (*selfs)[d].first->scale;
+            const SelfTerm& st = (*selfs)[d];
+            if (!st.t) continue;
+            const double s_self = st.t->scale;
             acc_ptr.push_back(acc[d].d);
             first.push_back(acc_init[d] ? 0 : 1);
             acc_init[d] = 1;
             grp_begin.push_back((int32_t)src_ptr.size());
-            src_ptr.push_back((*selfs)[d].first->d);
+            src_ptr.push_back(st.t->d);
             term_begin.push_back((int32_t)gs.size());
-            for (auto& bw : (*selfs)[d].second) {
+            gs.push_back(0);
+            wconst(weight_int(st.c, s_self, q_acc, 1.0), cw);
+            for (auto& bw : st.corr) {
                 gs.push_back(gal(bw.first));
-                wconst(weight_int(bw.second, s_self, q_acc), cw);
+                wconst(weight_int(bw.second, s_self, q_acc, mask_scale), cw);
             }
         }
         if (!acc_ptr.empty()) {
@@ -457,8 +475,8 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
             T.cw_stride = nl;
             T.poly_stride = c->poly_stride();
             CSRMF_HIP(hipStreamSynchronize(c->stream));
-            const double bytes = (double)c->N * 8.0 * nl * (6.0 * acc_ptr.size() + gs.size());
-            launch_mask_mac_tasks(c->tabs, T, m.mask0, bytes, c->stream);
+            const double bytes = (double)c->N * 8.0 * nl * (6.0 * acc_ptr.size() + (gs.size() - acc_ptr.size()));
+            launch_mask_mac_tasks(c->tabs, T, mask, bytes, c->stream);
             for (uint64_t* p : owned) c->pool.put(p);
         }
     }
@@ -481,19 +499,27 @@ std::vector<Ct> scatter(Context* c, MfState& m, const std::vector<Ct*>& Gs, cons
         const double w = c->prm.rule == 2 ? a_t / deg[e] : a_t;
         moves[e / m.D].push_back({m.ct_of[r], m.blk_of[r], e % m.D, w});
     }
-    std::vector<std::pair<Ct*, std::vector<std::pair<int, double>>>> selfs(tabs.size());
+    std::vector<SelfTerm> selfs(tabs.size());
     for (size_t d = 0; d < tabs.size(); ++d) {
-        selfs[d].first = &c->get(tabs[d]);
+        selfs[d].t = &c->get(tabs[d]);
+        std::vector<std::pair<int, double>> ws;
         for (int b = 0; b < m.D; ++b) {
             const int e = (int)d * m.D + b;
             if (e >= n_ent) break;
             double w;
             if (c->prm.rule == 2) w = deg[e] > 0 ? (1.0 - a_t * lam) : 1.0;
             else w = 1.0 - a_t * lam * deg[e];
-            selfs[d].second.push_back({b, w});
+            ws.push_back({b, w});
         }
+        // c: the lower median of the entries' weights
+        std::vector<double> srt;
+        for (auto& bw : ws) srt.push_back(bw.second);
+        std::sort(srt.begin(), srt.end());
+        selfs[d].c = srt[(srt.size() - 1) / 2];
+        for (auto& bw : ws)
+            if (bw.second != selfs[d].c) selfs[d].corr.push_back({bw.first, bw.second - selfs[d].c});
     }
-    return block_permute(c, m, Gs, moves, &selfs, level);
+    return block_permute(c, m, Gs, moves, &selfs, level, nullptr, false);
 }
 
 std::vector<Ct> gather(Context* c, MfState& m, const std::vector<uint64_t>& tabs, bool users) {
@@ -503,7 +529,7 @@ std::vector<Ct> gather(Context* c, MfState& m, const std::vector<uint64_t>& tabs
         moves[m.ct_of[r]].push_back({e / m.D, e % m.D, m.blk_of[r], 1.0});
     }
     std::vector<Ct*> srcs = cts_of(c, tabs);
-    return block_permute(c, m, srcs, moves, nullptr, srcs[0]->level);
+    return block_permute(c, m, srcs, moves, nullptr, srcs[0]->level, nullptr, true);
 }
 
 std::vector<uint64_t> put_all(Context* c, std::vector<Ct>& v) {
@@ -590,7 +616,7 @@ void decrypt_slots(Context* c, uint64_t h, std::vector<double>& z) {
     ckks_decode(mm.data(), c->logN, ct.scale, z.data(), (int)(c->N / 2));
 }
 
-}  // namespace
+}  // namespace mfp
 
 }  // namespace csrmf
 
@@ -600,6 +626,7 @@ using csrmf::MfState;
 
 #define API_BEGIN(ctx)                 \
     if (!(ctx)) return CSRMF_E_INVAL;  \
+    std::lock_guard<std::recursive_mutex> lk_((ctx)->mu); \
     try {
 #define API_END_EARLY                  \
     { c->err.clear(); return CSRMF_OK; }
@@ -619,7 +646,7 @@ using csrmf::MfState;
 
 static void install_layout(Context* c, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr, const int32_t* col_idx) {
     if (!c->have_keys) throw Error(CSRMF_E_STATE, "keygen first");
-    MfState* m = csrmf::make_layout(c, n_rows, n_cols, row_ptr, col_idx);
+    MfState* m = csrmf::mfp::make_layout(c, n_rows, n_cols, row_ptr, col_idx);
     // rotation keys the program uses: windowed sum 1, 2, .., B/2 and -k'; baby
     // steps beta*B (beta < G); giant steps gamma*G*B (gamma < D/G)
     std::vector<int32_t> steps;
@@ -634,14 +661,14 @@ static void install_layout(Context* c, int32_t n_rows, int32_t n_cols, const int
         throw;
     }
     if (c->mf) {
-        csrmf::free_handles(c, c->mf->R);
-        csrmf::free_handles(c, c->mf->Utab);
-        csrmf::free_handles(c, c->mf->Vtab);
-        csrmf::free_handles(c, c->mf->Ug);
-        csrmf::free_handles(c, c->mf->Vg);
-        csrmf::free_handles(c, c->mf->Sdot);
-        csrmf::free_handles(c, c->mf->Pred);
-        if (c->mf->mask0) c->pool.put(c->mf->mask0);
+        csrmf::mfp::free_handles(c, c->mf->R);
+        csrmf::mfp::free_handles(c, c->mf->Utab);
+        csrmf::mfp::free_handles(c, c->mf->Vtab);
+        csrmf::mfp::free_handles(c, c->mf->Ug);
+        csrmf::mfp::free_handles(c, c->mf->Vg);
+        csrmf::mfp::free_handles(c, c->mf->Sdot);
+        csrmf::mfp::free_handles(c, c->mf->Pred);
+        csrmf::mfp::free_masks(c, *c->mf);
         delete c->mf;
     }
     c->mf = m;
@@ -659,10 +686,10 @@ int csrmf_encrypt_csr_rows(csrmf_ctx* cx, int32_t n_rows, int32_t n_cols, const 
     install_layout(c, n_rows, n_cols, row_ptr, col_idx);
     MfState& m = *c->mf;
     std::vector<std::vector<double>> zs(m.n_ct, std::vector<double>(c->N / 2));
-    csrmf::fill_rating_slots(m, 0, values, nullptr, nullptr, zs);
+    csrmf::mfp::fill_rating_slots(m, 0, values, nullptr, nullptr, zs);
     const double scale = std::ldexp(1.0, c->prm.log2_scale);
-    std::vector<int64_t> pt = csrmf::encode_all(c, zs, scale);
-    m.R = csrmf::encrypt_list(c, pt.data(), m.n_ct, scale);
+    std::vector<int64_t> pt = csrmf::mfp::encode_all(c, zs, scale);
+    m.R = csrmf::mfp::encrypt_list(c, pt.data(), m.n_ct, scale);
     if (n_ct) *n_ct = m.n_ct;
     API_END(c)
 }
@@ -675,7 +702,7 @@ int csrmf_encrypt_csr_rows_int(csrmf_ctx* cx, int32_t n_rows, int32_t n_cols, co
     install_layout(c, n_rows, n_cols, row_ptr, col_idx);
     MfState& m = *c->mf;
     if (n_plain != m.n_ct) throw Error(CSRMF_E_INVAL, "number of plaintexts differs from the layout's ciphertexts");
-    m.R = csrmf::encrypt_list(c, plain, m.n_ct, std::ldexp(1.0, c->prm.log2_scale));
+    m.R = csrmf::mfp::encrypt_list(c, plain, m.n_ct, std::ldexp(1.0, c->prm.log2_scale));
     if (n_ct) *n_ct = m.n_ct;
     API_END(c)
 }
@@ -683,7 +710,7 @@ int csrmf_encrypt_csr_rows_int(csrmf_ctx* cx, int32_t n_rows, int32_t n_cols, co
 int csrmf_mf_layout(const csrmf_ctx* cx, int32_t* n_ct, int32_t* n_utab, int32_t* n_vtab, int32_t* D, int32_t* B) {
     Context* c = const_cast<Context*>(reinterpret_cast<const Context*>(cx));
     API_BEGIN(c)
-    MfState& m = csrmf::state(c);
+    MfState& m = csrmf::mfp::state(c);
     if (n_ct) *n_ct = m.n_ct;
     if (n_utab) *n_utab = m.n_utab;
     if (n_vtab) *n_vtab = m.n_vtab;
@@ -695,45 +722,43 @@ int csrmf_mf_layout(const csrmf_ctx* cx, int32_t* n_ct, int32_t* n_utab, int32_t
 int csrmf_init_factors(csrmf_ctx* cx, const double* U0, const double* V0) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
-    MfState& m = csrmf::state(c);
+    MfState& m = csrmf::mfp::state(c);
     if (!U0 || !V0) throw Error(CSRMF_E_INVAL, "factors");
     const double scale = std::ldexp(1.0, c->prm.log2_scale);
     std::vector<std::vector<double>> zu(m.n_utab, std::vector<double>(c->N / 2)), zv(m.n_vtab, std::vector<double>(c->N / 2));
     std::vector<std::vector<double>> gu(m.n_ct, std::vector<double>(c->N / 2)), gv(m.n_ct, std::vector<double>(c->N / 2));
-    for (int a = 0; a < m.n_utab; ++a) csrmf::fill_table_slots(m, a, m.n_users, U0, zu[a]);
-    for (int a = 0; a < m.n_vtab; ++a) csrmf::fill_table_slots(m, a, m.n_items, V0, zv[a]);
-    csrmf::fill_rating_slots(m, 1, nullptr, U0, V0, gu);
-    csrmf::fill_rating_slots(m, 2, nullptr, U0, V0, gv);
-    std::vector<int64_t> pu = csrmf::encode_all(c, zu, scale), pv = csrmf::encode_all(c, zv, scale);
-    std::vector<int64_t> pgu = csrmf::encode_all(c, gu, scale), pgv = csrmf::encode_all(c, gv, scale);
-    std::vector<double> ind(c->N / 2, 0.0);
-    for (int f = 0; f < m.k; ++f) ind[f] = 1.0;
-    std::vector<int64_t> mask(c->N);
-    csrmf::ckks_encode(ind.data(), (int)ind.size(), c->logN, csrmf::kMaskScale, mask.data());
-    for (auto* v : {&m.Utab, &m.Vtab, &m.Ug, &m.Vg}) csrmf::free_handles(c, *v);
-    m.Utab = csrmf::encrypt_list(c, pu.data(), m.n_utab, scale);
-    m.Vtab = csrmf::encrypt_list(c, pv.data(), m.n_vtab, scale);
-    m.Ug = csrmf::encrypt_list(c, pgu.data(), m.n_ct, scale);
-    m.Vg = csrmf::encrypt_list(c, pgv.data(), m.n_ct, scale);
-    csrmf::upload_mask(c, m, mask.data());
+    for (int a = 0; a < m.n_utab; ++a) csrmf::mfp::fill_table_slots(m, a, m.n_users, U0, zu[a]);
+    for (int a = 0; a < m.n_vtab; ++a) csrmf::mfp::fill_table_slots(m, a, m.n_items, V0, zv[a]);
+    csrmf::mfp::fill_rating_slots(m, 1, nullptr, U0, V0, gu);
+    csrmf::mfp::fill_rating_slots(m, 2, nullptr, U0, V0, gv);
+    std::vector<int64_t> pu = csrmf::mfp::encode_all(c, zu, scale), pv = csrmf::mfp::encode_all(c, zv, scale);
+    std::vector<int64_t> pgu = csrmf::mfp::encode_all(c, gu, scale), pgv = csrmf::mfp::encode_all(c, gv, scale);
+    std::vector<int64_t> mask_s, mask_g;
+    csrmf::mfp::encode_masks(c, m.k, mask_s, mask_g);
+    for (auto* v : {&m.Utab, &m.Vtab, &m.Ug, &m.Vg}) csrmf::mfp::free_handles(c, *v);
+    m.Utab = csrmf::mfp::encrypt_list(c, pu.data(), m.n_utab, scale);
+    m.Vtab = csrmf::mfp::encrypt_list(c, pv.data(), m.n_vtab, scale);
+    m.Ug = csrmf::mfp::encrypt_list(c, pgu.data(), m.n_ct, scale);
+    m.Vg = csrmf::mfp::encrypt_list(c, pgv.data(), m.n_ct, scale);
+    csrmf::mfp::upload_masks(c, m, mask_s.data(), mask_g.data());
     m.factors = true;
     m.epochs_done = 0;
     API_END(c)
 }
 
 int csrmf_init_factors_int(csrmf_ctx* cx, const int64_t* utab, const int64_t* vtab, const int64_t* ug,
-                           const int64_t* vg, const int64_t* mask0) {
+                           const int64_t* vg, const int64_t* mask_scatter, const int64_t* mask_gather) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
-    MfState& m = csrmf::state(c);
-    if (!utab || !vtab || !ug || !vg || !mask0) throw Error(CSRMF_E_INVAL, "plaintexts");
+    MfState& m = csrmf::mfp::state(c);
+    if (!utab || !vtab || !ug || !vg || !mask_scatter || !mask_gather) throw Error(CSRMF_E_INVAL, "plaintexts");
     const double scale = std::ldexp(1.0, c->prm.log2_scale);
-    for (auto* v : {&m.Utab, &m.Vtab, &m.Ug, &m.Vg}) csrmf::free_handles(c, *v);
-    m.Utab = csrmf::encrypt_list(c, utab, m.n_utab, scale);
-    m.Vtab = csrmf::encrypt_list(c, vtab, m.n_vtab, scale);
-    m.Ug = csrmf::encrypt_list(c, ug, m.n_ct, scale);
-    m.Vg = csrmf::encrypt_list(c, vg, m.n_ct, scale);
-    csrmf::upload_mask(c, m, mask0);
+    for (auto* v : {&m.Utab, &m.Vtab, &m.Ug, &m.Vg}) csrmf::mfp::free_handles(c, *v);
+    m.Utab = csrmf::mfp::encrypt_list(c, utab, m.n_utab, scale);
+    m.Vtab = csrmf::mfp::encrypt_list(c, vtab, m.n_vtab, scale);
+    m.Ug = csrmf::mfp::encrypt_list(c, ug, m.n_ct, scale);
+    m.Vg = csrmf::mfp::encrypt_list(c, vg, m.n_ct, scale);
+    csrmf::mfp::upload_masks(c, m, mask_scatter, mask_gather);
     m.factors = true;
     m.epochs_done = 0;
     API_END(c)
@@ -742,7 +767,7 @@ int csrmf_init_factors_int(csrmf_ctx* cx, const int64_t* utab, const int64_t* vt
 int csrmf_mf_epochs(csrmf_ctx* cx, int32_t n_epochs) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
-    MfState& m = csrmf::state(c);
+    MfState& m = csrmf::mfp::state(c);
     if (!m.factors) throw Error(CSRMF_E_STATE, "init_factors first");
     if (n_epochs < 0) throw Error(CSRMF_E_INVAL, "n_epochs");
     if (n_epochs == 0) API_END_EARLY;
@@ -753,15 +778,15 @@ int csrmf_mf_epochs(csrmf_ctx* cx, int32_t n_epochs) {
     const int lvl = regather ? c->get(m.Utab[0]).level - 1 : c->get(m.Ug[0]).level;
     if (lvl < 3 + 4 * (n_epochs - 1)) throw Error(CSRMF_E_LEVEL, "not enough levels for the requested epochs");
     if (regather) {
-        std::vector<csrmf::Ct> gu = csrmf::gather(c, m, m.Utab, true);
-        std::vector<csrmf::Ct> gv = csrmf::gather(c, m, m.Vtab, false);
-        m.Ug = csrmf::put_all(c, gu);
-        m.Vg = csrmf::put_all(c, gv);
+        std::vector<csrmf::Ct> gu = csrmf::mfp::gather(c, m, m.Utab, true);
+        std::vector<csrmf::Ct> gv = csrmf::mfp::gather(c, m, m.Vtab, false);
+        m.Ug = csrmf::mfp::put_all(c, gu);
+        m.Vg = csrmf::mfp::put_all(c, gv);
     }
-    for (int t = 0; t < n_epochs; ++t) csrmf::run_epoch(c, m, t + 1 == n_epochs);
+    for (int t = 0; t < n_epochs; ++t) csrmf::mfp::run_epoch(c, m, t + 1 == n_epochs);
     if (n_epochs > 0) {
-        csrmf::free_handles(c, m.Ug);
-        csrmf::free_handles(c, m.Vg);
+        csrmf::mfp::free_handles(c, m.Ug);
+        csrmf::mfp::free_handles(c, m.Vg);
     }
     CSRMF_HIP(hipStreamSynchronize(c->stream));
     API_END(c)
@@ -770,34 +795,34 @@ int csrmf_mf_epochs(csrmf_ctx* cx, int32_t n_epochs) {
 int csrmf_predict(csrmf_ctx* cx) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
-    MfState& m = csrmf::state(c);
+    MfState& m = csrmf::mfp::state(c);
     if (!m.factors) throw Error(CSRMF_E_STATE, "init_factors first");
     if (c->get(m.Utab[0]).level < 2) throw Error(CSRMF_E_LEVEL, "predict needs 2 levels (gather + product)");
-    std::vector<csrmf::Ct> gu = csrmf::gather(c, m, m.Utab, true);
-    std::vector<csrmf::Ct> gv = csrmf::gather(c, m, m.Vtab, false);
-    std::vector<csrmf::Ct*> pu = csrmf::ptrs(gu), pv = csrmf::ptrs(gv);
-    std::vector<csrmf::Ct> S = csrmf::dot_products(c, m, pu, pv, nullptr);
-    csrmf::release(c, gu);
-    csrmf::release(c, gv);
-    csrmf::free_handles(c, m.Pred);
-    m.Pred = csrmf::put_all(c, S);
+    std::vector<csrmf::Ct> gu = csrmf::mfp::gather(c, m, m.Utab, true);
+    std::vector<csrmf::Ct> gv = csrmf::mfp::gather(c, m, m.Vtab, false);
+    std::vector<csrmf::Ct*> pu = csrmf::mfp::ptrs(gu), pv = csrmf::mfp::ptrs(gv);
+    std::vector<csrmf::Ct> S = csrmf::mfp::dot_products(c, m, pu, pv, nullptr);
+    csrmf::mfp::release(c, gu);
+    csrmf::mfp::release(c, gv);
+    csrmf::mfp::free_handles(c, m.Pred);
+    m.Pred = csrmf::mfp::put_all(c, S);
     API_END(c)
 }
 
 int csrmf_decrypt_factors(csrmf_ctx* cx, double* U, double* V) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
-    MfState& m = csrmf::state(c);
+    MfState& m = csrmf::mfp::state(c);
     if (!m.factors) throw Error(CSRMF_E_STATE, "init_factors first");
     if (!U || !V) throw Error(CSRMF_E_INVAL, "outputs");
     std::vector<double> z;
     for (int a = 0; a < m.n_utab; ++a) {
-        csrmf::decrypt_slots(c, m.Utab[a], z);
+        csrmf::mfp::decrypt_slots(c, m.Utab[a], z);
         for (int b = 0; b < m.D && a * m.D + b < m.n_users; ++b)
             for (int f = 0; f < m.k; ++f) U[(size_t)(a * m.D + b) * m.k + f] = z[(size_t)b * m.B + f];
     }
     for (int a = 0; a < m.n_vtab; ++a) {
-        csrmf::decrypt_slots(c, m.Vtab[a], z);
+        csrmf::mfp::decrypt_slots(c, m.Vtab[a], z);
         for (int b = 0; b < m.D && a * m.D + b < m.n_items; ++b)
             for (int f = 0; f < m.k; ++f) V[(size_t)(a * m.D + b) * m.k + f] = z[(size_t)b * m.B + f];
     }
@@ -807,7 +832,7 @@ int csrmf_decrypt_factors(csrmf_ctx* cx, double* U, double* V) {
 int csrmf_decrypt_predictions(csrmf_ctx* cx, double* rhat, int32_t which) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
-    MfState& m = csrmf::state(c);
+    MfState& m = csrmf::mfp::state(c);
     if (!rhat) throw Error(CSRMF_E_INVAL, "output");
     const std::vector<uint64_t>& src = which == 0 ? m.Sdot : m.Pred;
     if (which != 0 && which != 1) throw Error(CSRMF_E_INVAL, "which must be 0 or 1");
@@ -817,7 +842,7 @@ int csrmf_decrypt_predictions(csrmf_ctx* cx, double* rhat, int32_t which) {
     for (int r = 0; r < m.nnz; ++r) {
         if (m.ct_of[r] != cur) {
             cur = m.ct_of[r];
-            csrmf::decrypt_slots(c, src[cur], z);
+            csrmf::mfp::decrypt_slots(c, src[cur], z);
         }
         rhat[r] = z[(size_t)m.blk_of[r] * m.B];
     }
@@ -827,7 +852,7 @@ int csrmf_decrypt_predictions(csrmf_ctx* cx, double* rhat, int32_t which) {
 int csrmf_mf_handles(const csrmf_ctx* cx, int32_t which, uint64_t* out, int32_t cap, int32_t* n) {
     Context* c = const_cast<Context*>(reinterpret_cast<const Context*>(cx));
     API_BEGIN(c)
-    MfState& m = csrmf::state(c);
+    MfState& m = csrmf::mfp::state(c);
     const std::vector<uint64_t>* v;
     switch (which) {
         case 0: v = &m.R; break;

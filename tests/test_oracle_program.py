@@ -73,7 +73,7 @@ def test_clear_program_multi_ciphertext_layout():
     assert np.max(np.abs(rhat - rf)) < 1e-12
 
 
-def run_encrypted_tiny(ctx, csr, U0, V0, mask0, epochs=1, alpha=0.01, lam=0.02, rule="R1"):
+def run_encrypted_tiny(ctx, csr, U0, V0, masks, epochs=1, alpha=0.01, lam=0.02, rule="R1"):
     """Encrypt the tiny workload with the oracle (serial order: R, Utab, Vtab, Ug, Vg)
     and run the program on CkksBackend; returns (layout, result, plaintexts)."""
     N = ctx.N
@@ -89,7 +89,7 @@ def run_encrypted_tiny(ctx, csr, U0, V0, mask0, epochs=1, alpha=0.01, lam=0.02, 
         "Vg": enc(program.slot_vectors(lay, items=V0, which="V")),
     }
     cts = {key: [ctx.encrypt_int(m, L, D40) for m in pt[key]] for key in ["R", "Utab", "Vtab", "Ug", "Vg"]}
-    be = program.CkksBackend(ctx, mask0)
+    be = program.CkksBackend(ctx, masks)
     res = program.run_epochs(be, lay, cts["R"], cts["Ug"], cts["Vg"], cts["Utab"], cts["Vtab"], epochs,
                              alpha, lam, rule=rule)
     return lay, res, pt
@@ -103,10 +103,7 @@ def test_encrypted_program_tiny_within_1e4_of_fp64():
     ctx = ckks.Context(prm, workloads.CRYPTO_SEED)
     lay0 = _layout_for(csr, prm.N, 4)
     ctx.keygen(rot_steps=program.rotation_steps(lay0))
-    ind = np.zeros(prm.N // 2)
-    ind[:4] = 1.0
-    mask0 = ctx.encode(ind, program.S_I)
-    lay, res, _ = run_encrypted_tiny(ctx, csr, U0, V0, mask0)
+    lay, res, _ = run_encrypted_tiny(ctx, csr, U0, V0, program.block_masks(ctx, 4))
     U = program.decode_tables([ctx.decrypt(c) for c in res.utab], lay, 32)
     V = program.decode_tables([ctx.decrypt(c) for c in res.vtab], lay, 64)
     rhat = program.decode_predictions([ctx.decrypt(c) for c in res.sdot], lay)
@@ -115,3 +112,77 @@ def test_encrypted_program_tiny_within_1e4_of_fp64():
     assert np.max(np.abs(V - Vf)) < 1e-4
     assert np.max(np.abs(rhat - rf)) < 1e-4
     assert res.utab[0].level == 0
+
+
+@pytest.mark.slow
+def test_encrypted_program_two_epochs_matches_golden():
+    """Two encrypted epochs (R2) on the two-epoch chain, through a gather:
+    within 1e-4 of FP64, and the output ciphertexts match the stored digests."""
+    from tests.golden import make_mf_tiny2 as g
+    from tests.test_gpu_mf import _golden_tiny2
+    prm = params.config_tiny_two_epochs()
+    csr = workloads.tiny_ratings()
+    U0, V0 = workloads.init_factors(csr.n_rows, csr.n_cols, g.K)
+    ctx = ckks.Context(prm, workloads.CRYPTO_SEED)
+    lay0 = _layout_for(csr, prm.N, g.K)
+    ctx.keygen(rot_steps=program.rotation_steps(lay0))
+    lay, res, _ = run_encrypted_tiny(ctx, csr, U0, V0, program.block_masks(ctx, g.K), epochs=g.EPOCHS,
+                                     alpha=g.LR, lam=g.LAM, rule=g.RULE)
+    U = program.decode_tables([ctx.decrypt(c) for c in res.utab], lay, csr.n_rows)
+    V = program.decode_tables([ctx.decrypt(c) for c in res.vtab], lay, csr.n_cols)
+    rhat = program.decode_predictions([ctx.decrypt(c) for c in res.sdot], lay)
+    Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, g.LR, g.LAM, g.EPOCHS, rule=g.RULE)
+    assert np.max(np.abs(U - Uf)) < 1e-4 and np.max(np.abs(V - Vf)) < 1e-4
+    assert np.max(np.abs(rhat - rf)) < 1e-4
+    golden = _golden_tiny2()
+    for kind, lst in (("utab", res.utab), ("vtab", res.vtab), ("sdot", res.sdot)):
+        for i, c in enumerate(lst):
+            assert (c.level, c.scale, g.digest(c.c0, c.c1)) == golden[(kind, i)], (kind, i)
+
+
+class _MaskNoise(program.ClearBackend):
+    """Cleartext program whose masks carry the real rounding error of the
+    encoded I_0 (decoded slot values of the integer mask) and whose weights are
+    the rounded integers W: the mask and weight error of the reading, without
+    ciphertext noise."""
+
+    def __init__(self, N, q, B, k, decoded):
+        super().__init__(N, q, B, k)
+        self.decoded = decoded           # {mask scale: S_I * (indicator + error)}
+
+    def mask_mul(self, a, terms, scale, mask_scale, const=0):
+        m = np.full(self.N // 2, float(const))
+        dec = self.decoded[mask_scale]
+        for p, W in terms:
+            m += W * np.roll(dec, p * self.B)
+        return self.V(a.z * m * a.scale / scale, a.level, scale)
+
+
+@pytest.mark.slow
+def test_mask_reading_within_1e4_at_mf100k_shape():
+    """The block-mask reading (gather masks at 2^30 with the exact term scale,
+    scatter masks at 2^20 with the self term's constant split off) keeps three
+    epochs at the MovieLens-100K shape (N = 2^15, k = 10, D = 512) within
+    1e-4 of FP64.  With every mask at 2^20 (the previous reading) the same
+    model drifts to ~3e-3, so this check fails if the split is undone."""
+    K, LR, LAM, EP = 10, 0.01, 0.02, 3
+    csr = workloads.movielens100k_shaped()
+    U0, V0 = workloads.init_factors(csr.n_rows, csr.n_cols, K)
+    prm = params.config_mf_n15()
+    lay = program.make_layout(prm.N, K, csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx)
+    ctx = ckks.Context(prm, workloads.CRYPTO_SEED)
+    dec = {s: ctx.decode(m, 1.0) for s, m in program.block_masks(ctx, K).items()}
+    be = _MaskNoise(prm.N, prm.q, lay.B, K, dec)
+    S = 2.0 ** 40
+    w = lambda Z: [be.wrap(z, prm.L, S) for z in Z]
+    res = program.run_epochs(be, lay, w(program.slot_vectors(lay, csr.values, which="R")),
+                             w(program.slot_vectors(lay, users=U0, which="U")),
+                             w(program.slot_vectors(lay, items=V0, which="V")),
+                             w(program.table_vectors(lay, U0, lay.n_utab)),
+                             w(program.table_vectors(lay, V0, lay.n_vtab)), EP, LR, LAM, rule="R2")
+    U = program.decode_tables([x.z for x in res.utab], lay, csr.n_rows)
+    V = program.decode_tables([x.z for x in res.vtab], lay, csr.n_cols)
+    rhat = program.decode_predictions([x.z for x in res.sdot], lay)
+    Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, LR, LAM, EP, rule="R2")
+    assert np.max(np.abs(U - Uf)) < 1e-4 and np.max(np.abs(V - Vf)) < 1e-4
+    assert np.max(np.abs(rhat - rf)) < 1e-4
