@@ -33,8 +33,10 @@
  *     The external form of a ciphertext (import/export) is coefficient form:
  *     uint64 residues in [0, q_i), laid out [2][level+1][N] (polynomial c0 then
  *     c1, limb q_0 first).
- *   - A context is not thread safe: use one per host thread or serialise.
- *     All device work of a context runs in order on its stream.
+ *   - Calls on one context are serialised by a lock (the serving worker
+ *     shares it).  All device work of a context runs in order on its stream;
+ *     evaluation calls return once their work is enqueued, calls that return
+ *     host data (decrypt, export) or touch caller device memory wait for it.
  *   - A ciphertext at level l has limbs q_0..q_l; q_0 is the base prime and
  *     q_1 > ... > q_L are the scale primes dropped by rescale, smallest first.
  */
@@ -79,7 +81,8 @@ typedef struct csrmf_params {
     double  lambda;         /* regularisation lambda (= mu)                     */
     double  damp;           /* dampening: alpha_t = alpha / (1 + damp * t)      */
     int32_t rule;           /* 1 = R1 (Alg. 1 summed), 2 = R2 (degree-normalised)*/
-    int32_t refresh_mode;   /* 0 = fail with CSRMF_E_LEVEL when levels run out   */
+    int32_t refresh_mode;   /* 0 = fail with CSRMF_E_LEVEL when levels run out;  */
+                            /* 1 = refresh the factor tables (csrmf_mf_epochs) */
 } csrmf_params;
 
 /* Create a context: derives the prime chain and roots, uploads the transform
@@ -219,7 +222,9 @@ int csrmf_conjugate_batch(csrmf_ctx* ctx, const uint64_t* a, int32_t n, uint64_t
  * reduced modulo chain limb limb_idx[r % n_idx] (0..L for q_i, L+1+k for
  * p_k).  Forward output position t holds a(psi^(2*brev(t)+1)), with brev the
  * log2N-bit reversal and psi the smallest primitive 2N-th root mod the limb's
- * prime.  Inputs must be reduced.  limb_idx is a host array. */
+ * prime.  Inputs must be reduced.  limb_idx is a host array.  The context's
+ * stream does not wait for other streams: writes to `data` must be complete
+ * when the call is made; the transform is complete when it returns. */
 int csrmf_ntt_rows(csrmf_ctx* ctx, uint64_t* data, int32_t n_rows, const int32_t* limb_idx,
                    int32_t n_idx, int32_t inverse);
 
@@ -331,7 +336,7 @@ int csrmf_init_factors(csrmf_ctx* ctx, const double* U0, const double* V0);
 /* Integer-plaintext form of csrmf_init_factors plus the block indicator masks:
  * utab[n_utab][N], vtab[n_vtab][N], ug[n_ct][N], vg[n_ct][N];
  * mask_scatter[N] and mask_gather[N] = encodings of the indicator of slots
- * 0..k-1 at scales 2^20 (scatters) and 2^30 (gathers, whose weights are all 1).
+ * 0..k-1 at scales 2^24 (scatters) and 2^30 (gathers, whose weights are all 1).
  * Counts are reported by csrmf_mf_layout.  Errors: INVAL (null pointer), STATE. */
 int csrmf_init_factors_int(csrmf_ctx* ctx, const int64_t* utab, const int64_t* vtab,
                            const int64_t* ug, const int64_t* vg, const int64_t* mask_scatter,
@@ -345,14 +350,21 @@ int csrmf_mf_layout(const csrmf_ctx* ctx, int32_t* n_ct, int32_t* n_utab, int32_
 /* Run n_epochs synchronous encrypted gradient-descent epochs.  Each epoch
  * computes for every rating ciphertext P = Ug*Vg, the block dot products by a
  * windowed rotate-and-sum, E = R - <u,v>, the gradient terms E*Vg and E*Ug,
- * scatters them into the factor tables with the learning-rate weights and the
- * (1 - alpha*lambda*...) self term, and gathers the new factors back into the
- * rating layout for the next epoch (not after the last one; a later call
- * gathers first).  The first epoch on gathered factors costs 3 levels, each
- * further one 4.  Rule 1: weights alpha_t and self term 1 - alpha_t*lambda*d;
- * rule 2: alpha_t/d and 1 - alpha_t*lambda (entities without ratings are
- * left unchanged).  alpha_t = lr / (1 + damp * t), t = epochs run so far.
- * Errors: LEVEL (not enough levels), STATE, DEVICE. */
+ * scatters them into the factor tables (held at scale 2^50) with the
+ * learning-rate weights and the (1 - alpha*lambda*...) self term; every
+ * further epoch first gathers the factors back into the rating layout.  The
+ * first epoch on gathered factors costs 3 levels, each further one 4.
+ * Rule 1: weights alpha_t and self term 1 - alpha_t*lambda*d; rule 2: alpha_t/d
+ * and 1 - alpha_t*lambda (entities without ratings are left unchanged).
+ * alpha_t = lr / (1 + damp * t), t = epochs run so far.
+ * With params.refresh_mode = 1, tables below level 4 are refreshed before a
+ * gather, following the masking step of the protocol (Sec. III-B): a mask
+ * polynomial (ChaCha20 purpose 9, object round*1024 + table, coefficients
+ * (w mod 2^51) - 2^50) is added, the key holder decrypts to integers mod q_0
+ * and encrypts them anew at the top level and the same scale (serial
+ * 0x20000000 + round*1024 + table), and the mask is subtracted.
+ * Errors: LEVEL (not enough levels, refresh off or chain shorter than 4),
+ * STATE, DEVICE. */
 int csrmf_mf_epochs(csrmf_ctx* ctx, int32_t n_epochs);
 
 /* Encrypted predictions r_hat = <u_i, v_j> on the observed ratings from the
@@ -366,6 +378,11 @@ int csrmf_decrypt_factors(csrmf_ctx* ctx, double* U, double* V);
  * which = 0: the forward predictions of the last epoch (epoch-start factors);
  * which = 1: the output of csrmf_predict. */
 int csrmf_decrypt_predictions(csrmf_ctx* ctx, double* rhat, int32_t which);
+
+/* Progress of the MF program since csrmf_init_factors: epochs run, table
+ * refreshes done, and the wall time spent in refreshes (seconds, device work
+ * included).  Any pointer may be NULL.  Errors: STATE. */
+int csrmf_mf_stats(const csrmf_ctx* ctx, int32_t* epochs_done, int32_t* refreshes, double* refresh_seconds);
 
 /* Handles of the program's ciphertexts (test hook; owned by the program, do
  * not free): which = 0 rating ciphertexts, 1 user tables, 2 item tables,

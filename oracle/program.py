@@ -36,21 +36,25 @@ after the inner sum, zero steps skipped, and the plaintext mask
     I_p = tau_{g_p}(I_0), g_p = 5^((-p B) mod N/2) mod 2N,
 I_0 the encoding of the indicator of slots 0..k-1 at the call's mask scale S_I
 and the integer weight W = rint((w * S_t * q_ell) / (S_src * S_I)) for the
-target scale S_t = Delta (q_ell the top prime of the accumulator).  One
-rescale per destination.
+target scale S_t (q_ell the top prime of the accumulator).  One rescale per
+destination.  Gathers target S_t = Delta = 2^40 (the factors that enter the
+products); scatters target S_t = 2^50, the scale the factor tables are held
+at, which leaves room for the small weights alpha/d (~1e-5): W ~ w * 2^26
+with S_I = 2^24 (at a 2^40 target and S_I = 2^20 it would be w * 2^20 ~ 10,
+a rounding of up to 5 percent, the same way every epoch).
 
 Mask precision.  Encoding I_0 rounds its N coefficients, so every slot of I_p
 is off by about sqrt(N/24)/S_I (5e-5 at N = 2^15, S_I = 2^20) and a sum of D
-masks with weight ~1 is off by sqrt(D) times that.  Two choices keep the
+masks with weight ~1 is off by sqrt(D) times that.  Three choices keep the
 result within the 1e-4 value contract at N = 2^15 and 2^16:
 * gather (every weight 1, one source scale): I_0 at S_I = 2^30; the
   accumulator's scale is declared as S_src * S_I * W_1 with
   W_1 = rint((S_t * q_ell) / (S_src * S_I)), the exact scale of every term,
   so no weight is rounded and the result's scale is within 2^-10 of S_t;
-* scatter: I_0 at S_I = 2^20.  The self term's weights w_b (one per table
+* scatter: I_0 at S_I = 2^24, target 2^50.  The self term's weights w_b (one per table
   entry) are split into a constant c, the lower median of the w_b of the
   present entries, applied as the constant polynomial
-  W_c = rint((c * S_t * q_ell) / S_T), plus masked corrections w_b - c for the
+  W_c = rint((c * S_t * q_ell) / S_T) (S_T the table's scale), plus masked corrections w_b - c for the
   entries whose weight differs (C_d).  Mask rounding then scales with the
   correction, not with the weight ~1.  Slots of absent entries and the
   padding slots of a table are multiplied by c (they hold no data).
@@ -64,11 +68,15 @@ from typing import List, Tuple
 
 import numpy as np
 
-from . import ckks, ring
+from . import chacha, ckks, ring
 
-S_I = 2.0 ** 20      # mask scale of a scatter
+S_I = 2.0 ** 24      # mask scale of a scatter
 S_IG = 2.0 ** 30     # mask scale of a gather
-S_T = 2.0 ** 40      # target scale of every permuted result
+S_T = 2.0 ** 40      # target scale of a gather (the gathered factors)
+S_TAB = 2.0 ** 50    # target scale of a scatter (the factor tables)
+REFRESH_LEVEL = 4    # tables below this level are refreshed before the next gather
+REFRESH_SERIAL = 0x20000000   # encryption serials of refreshed tables: + round * 1024 + table
+MASK_BITS = 50       # refresh masks: integer coefficients in [-2^50, 2^50)
 
 
 def block_masks(ctx, k):
@@ -243,6 +251,17 @@ class CkksBackend:
         self.B = B
         self._cache = {}
 
+    def refresh(self, ct, obj):
+        c = self.ctx
+        mask = refresh_mask(c.seed, self.N, obj)
+        masked = c.add_plain(ct, mask)                 # evaluating party
+        m = c.decrypt_int(masked)                      # key holder: integers mod q_0
+        saved = c.serial
+        c.serial = REFRESH_SERIAL + obj
+        fresh = c.encrypt_int(m, c.prm.L, ct.scale)
+        c.serial = saved
+        return c.add_plain(fresh, -mask)               # evaluating party
+
     def _mask(self, p, mask_scale):
         key = (float(mask_scale), p)
         if key not in self._cache:
@@ -265,11 +284,12 @@ class ClearBackend:
         level: int
         scale: float
 
-    def __init__(self, N, q_chain, B, k):
+    def __init__(self, N, q_chain, B, k, L=None):
         self.N = N
         self.q = q_chain
         self.B = B
         self.k = k
+        self.L = L        # top level (refresh target); default: the last prime of q_chain
 
     def wrap(self, z, level, scale):
         return ClearBackend.V(np.asarray(z, np.float64), level, scale)
@@ -317,6 +337,9 @@ class ClearBackend:
     def set_block(self, B):
         pass
 
+    def refresh(self, ct, obj):
+        return self.V(ct.z, len(self.q) - 1 if self.L is None else self.L, ct.scale)
+
 
 # ---------------------------------------------------------------- the program
 @dataclass
@@ -327,7 +350,7 @@ class Move:
     w: float      # real weight
 
 
-def block_permute(be, lay, srcs, dests_moves, self_terms, level, mask_scale, unit=False,
+def block_permute(be, lay, srcs, dests_moves, self_terms, level, mask_scale, target, unit=False,
                   exact_weights=False):
     """dests_moves[d] = list of Move; self_terms[d] = (table ciphertext, c,
     [(block, w_b - c)]) or None.  All sources share level and scale.  unit:
@@ -338,10 +361,10 @@ def block_permute(be, lay, srcs, dests_moves, self_terms, level, mask_scale, uni
     q_acc = float(be.top_prime(level))
     if unit:
         assert all(mv.w == 1.0 for moves in dests_moves for mv in moves)
-        W1 = weight(1.0, src_scale, q_acc, mask_scale, False)
+        W1 = weight(1.0, src_scale, q_acc, mask_scale, False, target)
         acc_scale = src_scale * mask_scale * float(W1)
     else:
-        acc_scale = S_T * q_acc
+        acc_scale = target * q_acc
     # hoisted baby rotations per source, only the betas that are used
     need = {}
     for d, moves in enumerate(dests_moves):
@@ -371,7 +394,7 @@ def block_permute(be, lay, srcs, dests_moves, self_terms, level, mask_scale, uni
                 terms = []
                 for mv in groups[gamma][(c, beta)]:
                     p = (mv.b + gamma * G) % D
-                    terms.append((p, weight(mv.w, src_scale, q_acc, mask_scale, exact_weights)))
+                    terms.append((p, weight(mv.w, src_scale, q_acc, mask_scale, exact_weights, target)))
                 t = be.mask_mul(baby[c][beta], terms, acc_scale, mask_scale)
                 inner = t if inner is None else be.add(inner, t)
             if gamma:
@@ -382,19 +405,19 @@ def block_permute(be, lay, srcs, dests_moves, self_terms, level, mask_scale, uni
             ct, cst, blocks = st
             ctd = be.drop(ct, level)
             s_self = be.scale(ctd)
-            Wc = weight(cst, s_self, q_acc, 1.0, exact_weights)
-            terms = [(b, weight(w, s_self, q_acc, mask_scale, exact_weights)) for b, w in blocks]
+            Wc = weight(cst, s_self, q_acc, 1.0, exact_weights, target)
+            terms = [(b, weight(w, s_self, q_acc, mask_scale, exact_weights, target)) for b, w in blocks]
             t = be.mask_mul(ctd, terms, acc_scale, mask_scale, const=Wc)
             acc = t if acc is None else be.add(acc, t)
         out.append(be.rescale(acc))
     return out
 
 
-def weight(w, s_src, q_acc, mask_scale, exact):
-    """The integer W that carries weight w from scale s_src to S_t * q_acc."""
+def weight(w, s_src, q_acc, mask_scale, exact, target):
+    """The integer W that carries weight w from scale s_src to target * q_acc."""
     if exact:
         return w
-    return int(np.rint((w * S_T * q_acc) / (s_src * mask_scale)))
+    return int(np.rint((w * target * q_acc) / (s_src * mask_scale)))
 
 
 @dataclass
@@ -404,18 +427,31 @@ class EpochResult:
     ug: list = None
     vg: list = None
     sdot: list = None
+    refresh_round: int = 0
 
 
 def run_epochs(be, lay, R, Ug, Vg, Utab, Vtab, n_epochs, alpha, lam, damp=0.0, rule="R1",
-               exact_weights=False):
-    """Run n_epochs; returns the final tables, the last forward dot products."""
+               exact_weights=False, refresh=False, refresh_round=0, epoch0=0):
+    """Run n_epochs from gathered factors Ug, Vg (None: gather first); every
+    later epoch first gathers from the tables, refreshing them when their
+    level is below REFRESH_LEVEL (only if refresh is allowed).  epoch0: epochs
+    run before (the dampening index).  Returns the final tables and the last
+    forward dot products."""
     be.set_block(lay.B)
     d_user = np.bincount(lay.rows, minlength=lay.n_users)
     c_item = np.bincount(lay.cols, minlength=lay.n_items)
     sdot = None
     for t in range(n_epochs):
-        a_t = alpha / (1.0 + damp * t)
-        lvl = be.level(Ug[0])
+        a_t = alpha / (1.0 + damp * (epoch0 + t))
+        if t > 0 or Ug is None:
+            # 6: gather for this epoch, after a refresh if the tables are too low
+            if be.level(Utab[0]) < REFRESH_LEVEL:
+                if not refresh:
+                    raise ValueError("level budget exhausted and refresh not allowed")
+                Utab, Vtab = refresh_tables(be, Utab, Vtab, refresh_round)
+                refresh_round += 1
+            Ug = _gather(be, lay, Utab, lay.rows, exact_weights)
+            Vg = _gather(be, lay, Vtab, lay.cols, exact_weights)
         # 1-3: block dot products and errors
         E, sdot = [], []
         for c in range(lay.n_ct):
@@ -439,11 +475,26 @@ def run_epochs(be, lay, R, Ug, Vg, Utab, Vtab, n_epochs, alpha, lam, damp=0.0, r
         # 5: scatter into the tables
         Utab = _scatter(be, lay, GU, Utab, lay.rows, d_user, lay.n_users, a_t, lam, rule, glevel, exact_weights)
         Vtab = _scatter(be, lay, GV, Vtab, lay.cols, c_item, lay.n_items, a_t, lam, rule, glevel, exact_weights)
-        # 6: gather for the next epoch
-        if t + 1 < n_epochs:
-            Ug = _gather(be, lay, Utab, lay.rows, exact_weights)
-            Vg = _gather(be, lay, Vtab, lay.cols, exact_weights)
-    return EpochResult(Utab, Vtab, Ug, Vg, sdot)
+    return EpochResult(Utab, Vtab, Ug, Vg, sdot, refresh_round)
+
+
+def refresh_tables(be, Utab, Vtab, rnd):
+    """Refresh of level-exhausted tables through the masking step of the
+    protocol (Sec. III-B): the evaluating party adds a mask polynomial, the key
+    holder decrypts to integers (mod q_0) and encrypts the same integers anew
+    at the top level and the same scale, the evaluating party removes the
+    mask.  Table j of round rnd (U tables first) uses mask stream id
+    rnd * 1024 + j and encryption serial REFRESH_SERIAL + rnd * 1024 + j."""
+    tabs = list(Utab) + list(Vtab)
+    out = [be.refresh(ct, rnd * 1024 + j) for j, ct in enumerate(tabs)]
+    return out[:len(Utab)], out[len(Utab):]
+
+
+def refresh_mask(seed, N, obj):
+    """Mask polynomial (ChaCha20 purpose 9, object obj, limb 0): coefficient
+    n = (w_n mod 2^51) - 2^50."""
+    w = chacha.words_u64(seed, chacha.P_REFRESH_MASK, obj, 0, N)
+    return (w % np.uint64(1 << (MASK_BITS + 1))).astype(np.int64) - (1 << MASK_BITS)
 
 
 def _scatter(be, lay, Gs, tabs, owner, deg, n_ent, a_t, lam, rule, level, exact):
@@ -455,7 +506,7 @@ def _scatter(be, lay, Gs, tabs, owner, deg, n_ent, a_t, lam, rule, level, exact)
         w = a_t if rule == "R1" else a_t / deg[e]
         moves[d].append(Move(int(lay.ct_of[r]), int(lay.blk_of[r]), b, w))
     return block_permute(be, lay, Gs, moves, self_terms(lay, tabs, deg, n_ent, a_t, lam, rule), level,
-                         S_I, False, exact)
+                         S_I, S_TAB, False, exact)
 
 
 def self_terms(lay, tabs, deg, n_ent, a_t, lam, rule):
@@ -489,7 +540,7 @@ def _gather(be, lay, tabs, owner, exact):
         a_ct, a = divmod(e, D)
         moves[int(lay.ct_of[r])].append(Move(a_ct, a, int(lay.blk_of[r]), 1.0))
     level = be.level(tabs[0])
-    return block_permute(be, lay, tabs, moves, None, level, S_IG, True, exact)
+    return block_permute(be, lay, tabs, moves, None, level, S_IG, S_T, True, exact)
 
 
 def decode_tables(vals, lay, n_ent):

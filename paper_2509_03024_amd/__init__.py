@@ -93,6 +93,7 @@ _SIGS = {
     "csrmf_decrypt_factors": [_p, _dp, _dp],
     "csrmf_decrypt_predictions": [_p, _dp, ctypes.c_int32],
     "csrmf_mf_handles": [_p, ctypes.c_int32, _u64p, ctypes.c_int32, _i32p],
+    "csrmf_mf_stats": [_p, _i32p, _i32p, ctypes.POINTER(ctypes.c_double)],
     "csrmf_autotune": [_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32],
     "csrmf_server_create": [_p, ctypes.c_int32, ctypes.c_int32, _dp, _dp, ctypes.c_double, ctypes.c_int32,
                             ctypes.POINTER(_p)],
@@ -363,6 +364,11 @@ class MF:
         self.ctx._chk(lib.csrmf_mf_layout(self.ctx.h, *[ctypes.byref(x) for x in v]))
         return dict(zip(["n_ct", "n_utab", "n_vtab", "D", "B"], [x.value for x in v]))
 
+    def stats(self):
+        e, r, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self.ctx._chk(lib.csrmf_mf_stats(self.ctx.h, ctypes.byref(e), ctypes.byref(r), ctypes.byref(s)))
+        return {"epochs_done": e.value, "refreshes": r.value, "refresh_seconds": s.value}
+
     def init_factors(self, U0, V0):
         U = np.ascontiguousarray(U0, np.float64)
         V = np.ascontiguousarray(V0, np.float64)
@@ -486,9 +492,11 @@ def kernel_batch_params():
     return params(16, 60, 24, 40, 3, 60, 3, 40)
 
 
-def mf_n15_params(k=10, lr=0.01, lam=0.02, rule=2):
-    return params(15, 60, 16, 40, 3, 60, 5, 40, k=k, lr=lr, lam=lam, rule=rule)
+def mf_n15_params(k=10, lr=0.01, lam=0.02, rule=2, refresh_mode=0):
+    """N = 2^15, q_0 60-bit + 16 x 40-bit, 3 x 60-bit special primes, dnum 5 (4-limb digits)."""
+    return params(15, 60, 16, 40, 3, 60, 5, 40, k=k, lr=lr, lam=lam, rule=rule, refresh_mode=refresh_mode)
 
 
-def mf_n16_params(k=16, lr=0.01, lam=0.02, rule=2):
-    return params(16, 60, 24, 40, 3, 60, 7, 40, k=k, lr=lr, lam=lam, rule=rule)
+def mf_n16_params(k=16, lr=0.01, lam=0.02, rule=2, refresh_mode=0):
+    """N = 2^16, q_0 60-bit + 24 x 40-bit, 3 x 60-bit special primes, dnum 7 (4-limb digits)."""
+    return params(16, 60, 24, 40, 3, 60, 7, 40, k=k, lr=lr, lam=lam, rule=rule, refresh_mode=refresh_mode)

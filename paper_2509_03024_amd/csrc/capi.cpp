@@ -62,15 +62,16 @@ const char* csrmf_last_error(const csrmf_ctx* ctx) {
 int csrmf_set_stream(csrmf_ctx* cx, void* s) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
-    CSRMF_HIP(hipStreamSynchronize(c->stream));
+    c->sync();
     c->stream = (hipStream_t)s;
+    c->staging.set_stream(c->stream);
     API_END(c)
 }
 
 int csrmf_sync(csrmf_ctx* cx) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
-    CSRMF_HIP(hipStreamSynchronize(c->stream));
+    c->sync();
     API_END(c)
 }
 

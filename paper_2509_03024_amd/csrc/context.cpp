@@ -14,8 +14,15 @@ typedef unsigned __int128 u128;
 // ------------------------------------------------------------------ pool
 Pool::~Pool() { release_all(); }
 
+size_t Pool::size_class(size_t bytes) {
+    if (bytes <= 4096) return 4096;
+    int e = 63 - __builtin_clzll((unsigned long long)(bytes - 1));   // 2^e < bytes <= 2^(e+1)
+    const size_t step = (size_t)1 << (e - 2);                          // eight classes per octave
+    return (bytes + step - 1) / step * step;
+}
+
 void* Pool::get(size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
+    bytes = size_class(bytes);
     auto it = free_.find(bytes);
     void* p = nullptr;
     if (it != free_.end()) {
@@ -24,7 +31,9 @@ void* Pool::get(size_t bytes) {
     } else {
         hipError_t e = hipMalloc(&p, bytes);
         if (e != hipSuccess) {
-            // give cached blocks back and retry once
+            // give cached blocks back (after the device is idle: queued work may
+            // still use them) and retry once
+            (void)hipDeviceSynchronize();
             for (auto& kv : free_) { (void)hipFree(kv.second); sizes_.erase(kv.second); }
             free_.clear();
             (void)hipGetLastError();
@@ -55,6 +64,55 @@ void Pool::release_all() {
     in_use_ = 0;
 }
 
+// ------------------------------------------------------------------ staging ring
+hipEvent_t HipMarkers::record() {
+    hipEvent_t e;
+    if (!spare.empty()) {
+        e = spare.back();
+        spare.pop_back();
+    } else {
+        CSRMF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    CSRMF_HIP(hipEventRecord(e, stream));
+    return e;
+}
+
+void HipMarkers::wait(hipEvent_t e) { CSRMF_HIP(hipEventSynchronize(e)); }
+
+HipMarkers::~HipMarkers() {
+    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+}
+
+void Staging::init(hipStream_t s) {
+    ops_.stream = s;
+    CSRMF_HIP(hipHostMalloc((void**)&host_, kBytes, hipHostMallocDefault));
+    CSRMF_HIP(hipMalloc((void**)&dev_, kBytes));
+}
+
+void Staging::release() {
+    if (ops_.stream) (void)hipStreamSynchronize(ops_.stream);
+    ring_.drained(ops_);
+    if (host_) (void)hipHostFree(host_);
+    if (dev_) (void)hipFree(dev_);
+    host_ = dev_ = nullptr;
+    ops_.stream = nullptr;
+}
+
+void* Staging::put(const void* src, size_t bytes) {
+    if (!host_) throw Error(CSRMF_E_STATE, "staging ring not initialised");
+    const size_t off = ring_.reserve(bytes, ops_);
+    if (bytes) {
+        std::memcpy(host_ + off, src, bytes);
+        CSRMF_HIP(hipMemcpyAsync(dev_ + off, host_ + off, bytes, hipMemcpyHostToDevice, ops_.stream));
+    }
+    return dev_ + off;
+}
+
+void Context::sync() {
+    CSRMF_HIP(hipStreamSynchronize(stream));
+    staging.drained();
+}
+
 // ------------------------------------------------------------------ helpers
 static uint64_t mm(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
 
@@ -75,8 +133,10 @@ Context::~Context() {
     else (void)hipDeviceSynchronize();
     destroy_mf(mf);
     mf = nullptr;
-    for (auto& kv : ptr_tables) (void)hipFree(kv.second);
+    staging.release();
     pool.release_all();
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+    stream = own_stream = nullptr;
 }
 
 // ------------------------------------------------------------------ init
@@ -113,6 +173,8 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
             if (moduli[i] == moduli[j]) throw Error(CSRMF_E_INVAL, "prime chain has a repeated prime");
 
     CSRMF_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    own_stream = stream;
+    staging.init(stream);
 
     const int nm = (int)moduli.size();
     mh.resize(nm);
@@ -275,18 +337,7 @@ void Context::free_ct(uint64_t h) {
 }
 
 uint64_t** Context::ptr_table(const std::vector<uint64_t*>& v) {
-    auto it = ptr_tables.find(v);
-    if (it != ptr_tables.end()) return it->second;
-    if (ptr_tables.size() >= 4096) {   // bound the cache; earlier launches may still read the tables
-        CSRMF_HIP(hipStreamSynchronize(stream));
-        for (auto& kv : ptr_tables) (void)hipFree(kv.second);
-        ptr_tables.clear();
-    }
-    uint64_t** d = nullptr;
-    CSRMF_HIP(hipMalloc(&d, std::max<size_t>(8, v.size() * sizeof(uint64_t*))));
-    upload(d, v.data(), v.size() * sizeof(uint64_t*), stream);
-    ptr_tables[v] = d;
-    return d;
+    return (uint64_t**)stage(v.data(), v.size() * sizeof(uint64_t*));
 }
 
 RowMap Context::map_ct(uint64_t* d, int nlimbs, int first) const {
@@ -386,7 +437,7 @@ void Context::keygen(const int32_t* steps, int n, bool conj) {
     }
     for (int i = 0; i < n; ++i) add_rotation_key(galois_for_step(steps[i]));
     if (conj) add_rotation_key((uint32_t)(2 * N - 1));
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    sync();
 }
 
 void Context::add_rotation_key(uint32_t g) {
@@ -453,7 +504,7 @@ void Context::make_switching_key(Key& key, const uint64_t* sprime, uint32_t key_
         mk.poly_stride = (int64_t)rows_words;
         launch_mul_const(tabs, mk, mk, rcd.p, true, stream);
     }
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    sync();
 }
 
 // ------------------------------------------------------------------ encrypt
@@ -516,7 +567,7 @@ void Context::encrypt_int_batch(const int64_t* m, int count, int level, double s
     launch_ew(tabs, EW_ADD, o0, o0, vmap(3), stream);
     launch_ew(tabs, EW_ADD, o0, o0, vmap(1), stream);
     launch_ew(tabs, EW_ADD, o1, o1, vmap(2), stream);
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    sync();
 }
 
 Ct Context::encrypt_int(const int64_t* m, int level, double scale) {
@@ -542,7 +593,7 @@ void Context::decrypt_int(const Ct& c, int64_t* m) {
     launch_ntt(tabs, mx, true, stream);
     std::vector<uint64_t> h(N);
     CSRMF_HIP(hipMemcpyAsync(h.data(), x.p, N * 8, hipMemcpyDeviceToHost, stream));
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    sync();
     const uint64_t q0 = moduli[0];
     for (uint64_t i = 0; i < N; ++i) m[i] = h[i] > q0 / 2 ? -(int64_t)(q0 - h[i]) : (int64_t)h[i];
 }
@@ -565,7 +616,7 @@ void Context::export_ct(const Ct& c, uint64_t* coeffs) {
     for (int i = 0; i < nl; ++i) both.push(nl + i, i);
     launch_ntt(tabs, both, true, stream);
     CSRMF_HIP(hipMemcpyAsync(coeffs, x.p, 2 * (size_t)nl * N * 8, hipMemcpyDeviceToHost, stream));
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    sync();
 }
 
 Ct Context::import_ct(const uint64_t* coeffs, int level, double scale) {
@@ -582,7 +633,7 @@ Ct Context::import_ct(const uint64_t* coeffs, int level, double scale) {
     RowMap m = map_ct(c.d, nl);
     for (int i = 0; i < nl; ++i) m.push(L + 1 + i, i);
     launch_ntt(tabs, m, false, stream);
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    sync();
     return c;
 }
 
@@ -599,7 +650,7 @@ void Context::export_key(int which, uint32_t g, uint64_t* out) {
         launch_ntt(tabs, m, true, stream);
         std::vector<uint64_t> v((size_t)rows * N);
         CSRMF_HIP(hipMemcpyAsync(v.data(), x.p, v.size() * 8, hipMemcpyDeviceToHost, stream));
-        CSRMF_HIP(hipStreamSynchronize(stream));
+        sync();
         if (mont) {
             for (int r = 0; r < rows; ++r) {
                 const uint64_t q = moduli[mods[r]];
@@ -665,16 +716,17 @@ void Context::add_batch(const std::vector<Ct*>& a, const std::vector<Ct*>& b, st
         mo.push(L + 1 + i, i);
     }
     launch_ew(tabs, sub ? EW_SUB : EW_ADD, mo, ma, mb, stream);
+    fence();
 }
 
 void Context::add_plain(const Ct& a, const int64_t* m, Ct& out) {
     const int nl = a.level + 1;
-    Scratch src(pool, N), ex(pool, (size_t)nl * N);
-    upload(src.p, m, N * 8, stream);
+    Scratch ex(pool, (size_t)nl * N);
+    const int64_t* src = (const int64_t*)stage(m, N * 8);
     RowMap me;
     me.base = ex.p;
     for (int i = 0; i < nl; ++i) me.push(i, i);
-    launch_expand_signed(tabs, me, (const int64_t*)src.p, 1, 0, stream);
+    launch_expand_signed(tabs, me, src, 1, 0, stream);
     launch_ntt(tabs, me, false, stream);
     out = new_ct(a.level, a.scale);
     RowMap ma = map_ct(a.d, nl), mo = map_ct(out.d, nl);
@@ -685,23 +737,22 @@ void Context::add_plain(const Ct& a, const int64_t* m, Ct& out) {
         mo1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
     }
     launch_ew(tabs, EW_COPY, mo1, ma1, ma1, stream);
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    fence();
 }
 
 void Context::mul_plain(const Ct& a, const int64_t* m, double pt_scale, Ct& out) {
     const int nl = a.level + 1;
-    Scratch src(pool, N), ex(pool, (size_t)nl * N);
-    upload(src.p, m, N * 8, stream);
+    Scratch ex(pool, (size_t)nl * N);
+    const int64_t* src = (const int64_t*)stage(m, N * 8);
     RowMap me;
     me.base = ex.p;
     for (int i = 0; i < nl; ++i) me.push(i, i);
-    launch_expand_signed(tabs, me, (const int64_t*)src.p, 1, 0, stream);
+    launch_expand_signed(tabs, me, src, 1, 0, stream);
     launch_ntt(tabs, me, false, stream);
     std::vector<uint64_t> rc;
     for (int i = 0; i < nl; ++i) { rc.push_back(mh[i].r_mod); rc.push_back(mh[i].r_mod_shoup); }
-    Scratch rcd(pool, rc.size());
-    upload(rcd.p, rc.data(), rc.size() * 8, stream);
-    launch_mul_const(tabs, me, me, rcd.p, false, stream);   // plaintext times 2^64
+    const uint64_t* rcd = (const uint64_t*)stage(rc.data(), rc.size() * 8);
+    launch_mul_const(tabs, me, me, rcd, false, stream);   // plaintext times 2^64
     out = new_ct(a.level, a.scale * pt_scale);
     RowMap ma = map_ct(a.d, nl), mo = map_ct(out.d, nl);
     launch_mul_mont(tabs, mo, ma, me, false, stream);
@@ -710,7 +761,7 @@ void Context::mul_plain(const Ct& a, const int64_t* m, double pt_scale, Ct& out)
         mo.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
     }
     launch_mul_mont(tabs, mo, ma, me, false, stream);
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    fence();
 }
 
 void Context::mul_int(const Ct& a, int64_t w, Ct& out, double declared) {
@@ -721,11 +772,10 @@ void Context::mul_int(const Ct& a, int64_t w, Ct& out, double declared) {
         c.push_back(r);
         c.push_back(shoup_pre(r, moduli[i]));
     }
-    Scratch cd(pool, c.size());
-    upload(cd.p, c.data(), c.size() * 8, stream);
+    const uint64_t* cd = (const uint64_t*)stage(c.data(), c.size() * 8);
     out = new_ct(a.level, declared != 0.0 ? declared : a.scale * (double)w);
-    launch_mul_const(tabs, map_ct(out.d, nl), map_ct(a.d, nl), cd.p, true, stream);
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    launch_mul_const(tabs, map_ct(out.d, nl), map_ct(a.d, nl), cd, true, stream);
+    fence();
 }
 
 void Context::mod_drop(Ct& c, int level) {
@@ -852,7 +902,7 @@ void Context::mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, st
     ks_inner(ext.p, lvl, B, relin, 1, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, a[i]->scale * b[i]->scale);
     ks_moddown(u.p, lvl, B, map_cts(out, nl), md, 1, true);
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    fence();
 }
 
 void Context::rescale(const std::vector<Ct*>& v) {
@@ -893,7 +943,7 @@ void Context::rescale(const std::vector<Ct*>& v) {
         c->level = l - 1;
         c->scale = c->scale / ql;
     }
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    fence();
 }
 
 void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out) {
@@ -919,7 +969,7 @@ void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& o
     ks_inner(ext.p, lvl, B, key, 1, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, in[i]->scale);
     ks_moddown(u.p, lvl, B, map_cts(out, nl), map_cts(in, nl), g, false);
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    fence();
 }
 
 void Context::rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std::vector<Ct*>& out) {
@@ -943,7 +993,7 @@ void Context::rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std:
         ks_inner(ext.p, lvl, 1, key_for(g), g, u.p);
         ks_moddown(u.p, lvl, 1, map_ct(out[k]->d, nl), map_ct(in.d, nl), g, false);
     }
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    fence();
 }
 
 std::string Context::autotune(int rows) {
@@ -1012,6 +1062,7 @@ void Context::hoist_begin(Hoist& h, const std::vector<Ct*>& in) {
     RowMap c1 = map_cts(in, nl);
     for (int i = 0; i < nl; ++i) c1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
     ks_modup(c1, lvl, B, h.ext, h.coef);
+    fence();
 }
 
 void Context::hoist_rotate(Hoist& h, uint32_t g, std::vector<Ct*>& out) {
@@ -1022,6 +1073,7 @@ void Context::hoist_rotate(Hoist& h, uint32_t g, std::vector<Ct*>& out) {
     ks_inner(h.ext, lvl, B, key, g, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, h.in[i]->scale);
     ks_moddown(u.p, lvl, B, map_cts(out, nl), map_cts(h.in, nl), g, false);
+    fence();
 }
 
 void Context::ntt_rows(uint64_t* data, int n_rows, const int32_t* idx, int n_idx, bool inverse) {
@@ -1035,7 +1087,7 @@ void Context::ntt_rows(uint64_t* data, int n_rows, const int32_t* idx, int n_idx
         m.push(i, idx[i]);
     }
     launch_ntt(tabs, m, inverse, stream);
-    CSRMF_HIP(hipStreamSynchronize(stream));
+    sync();   // the rows are caller memory: done on return
 }
 
 }  // namespace csrmf

@@ -14,6 +14,7 @@
 
 #include "../../include/csrmf.h"
 #include "kernels.h"
+#include "staging.h"
 
 namespace csrmf {
 
@@ -57,18 +58,57 @@ struct LevelConsts {
     uint64_t* rs = nullptr;         // [l][4]  h mod q_i, q_l^-1 mod q_i, shoup, 0
 };
 
-class Pool {  // caching device allocator
+// Caching device allocator.  Requests are rounded up to size classes (eight
+// per power of two), so buffers of similar size are reused instead of
+// allocated.  A block handed back with put() may be handed out again at once:
+// all users run on the context's single stream, so later work is ordered
+// after earlier work on the block.
+class Pool {
 public:
     ~Pool();
     void* get(size_t bytes);
     void put(void* p);
     void release_all();
     size_t bytes_in_use() const { return in_use_; }
+    static size_t size_class(size_t bytes);
 
 private:
     std::multimap<size_t, void*> free_;
     std::unordered_map<void*, size_t> sizes_;
     size_t in_use_ = 0;
+};
+
+// Markers of the staging ring: events on the context's stream.
+struct HipMarkers {
+    hipStream_t stream = nullptr;
+    std::vector<hipEvent_t> spare;
+    hipEvent_t record();
+    void wait(hipEvent_t e);
+    void release(hipEvent_t e) { spare.push_back(e); }
+    ~HipMarkers();
+};
+
+// Pinned host ring + device ring for per-launch arguments (see staging.h).
+class Staging {
+public:
+    static constexpr size_t kBytes = (size_t)64 << 20;
+    Staging() : ring_(kBytes) {}
+    ~Staging() { release(); }
+    void init(hipStream_t s);
+    void release();   // waits for the stream, frees both rings
+    void set_stream(hipStream_t s) { ops_.stream = s; }   // only after drained()
+    // copy `bytes` from host memory into the device ring (asynchronously, on
+    // the stream); the device pointer stays valid until work enqueued before
+    // the next fence() has completed
+    void* put(const void* src, size_t bytes);
+    void fence() { ring_.fence(ops_); }
+    void drained() { ring_.drained(ops_); }   // after a stream synchronisation
+
+private:
+    uint8_t* host_ = nullptr;
+    uint8_t* dev_ = nullptr;
+    HipMarkers ops_;
+    RingPositions<HipMarkers, hipEvent_t> ring_;
 };
 
 // Scratch buffer that returns itself to the pool.
@@ -98,7 +138,8 @@ struct Context {
     uint64_t* d_tw = nullptr;
     DevTables tabs{};
     std::vector<LevelConsts> lv;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;       // stream of all device work
+    hipStream_t own_stream = nullptr;   // the stream the context created (destroyed with it)
     Pool pool;
     std::string err;
     std::recursive_mutex mu;        // serialises API calls and the serving worker
@@ -113,7 +154,7 @@ struct Context {
 
     std::unordered_map<uint64_t, Ct> cts;
     uint64_t next_handle = 1;
-    std::map<std::vector<uint64_t*>, uint64_t**> ptr_tables;
+    Staging staging;
     MfState* mf = nullptr;
     std::vector<Server*> servers;   // stopped and freed before the context
 
@@ -132,7 +173,12 @@ struct Context {
     uint64_t put(const Ct& c);
     Ct& get(uint64_t h);
     void free_ct(uint64_t h);
+    // device copy of a pointer table (staging ring; valid for work enqueued before the next fence)
     uint64_t** ptr_table(const std::vector<uint64_t*>& v);
+    // per-launch arguments through the staging ring; fence() after enqueueing their users
+    void* stage(const void* src, size_t bytes) { return staging.put(src, bytes); }
+    void fence() { staging.fence(); }
+    void sync();   // wait for the stream (and recycle the staging ring)
 
     RowMap map_ct(uint64_t* d, int nlimbs, int first = 0) const;
     RowMap map_cts(const std::vector<Ct*>& v, int nlimbs, int first = 0);

@@ -127,7 +127,7 @@ void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap&
 // M_g = sum_m W_m tau_{gs[m]}(I0) over the group's terms
 // [term_begin[g], term_begin[g+1]) (a term with gs[m] = 0 adds the constant W_m),
 // formed on the fly from the evaluation-form plaintext I0 (limb k at i0 + k*N);
-// cw[2*(m*cw_stride + k)], +1 = W_m * 2^64 mod q_k and its shoup.
+// cw[2*(wi[m]*cw_stride + k)], +1 = W_m * 2^64 mod q_k and its shoup.
 // first[t] != 0: the accumulator starts at zero.  All pointers are device arrays.
 struct MaskTasks {
     uint64_t* const* acc;       // [n_tasks] ciphertext base pointers
@@ -136,7 +136,8 @@ struct MaskTasks {
     const uint64_t* const* src; // [n_groups]
     const int32_t* term_begin;  // [n_groups + 1]
     const uint32_t* gs;         // [n_terms] Galois element of I_p, or 0 for a constant term
-    const uint64_t* cw;         // [n_terms][cw_stride][2]
+    const int32_t* wi;          // [n_terms] row of the term's weight in cw
+    const uint64_t* cw;         // [n_weights][cw_stride][2]
     int32_t n_tasks, n_limbs, cw_stride;
     int64_t poly_stride;
 };

@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(kThreads) k_mask_mac_tasks(DevTables t, MaskTa
         for (int g = g0; g < g1; ++g) {
             uint64_t M = 0;
             for (int m = T.term_begin[g]; m < T.term_begin[g + 1]; ++m) {
-                const uint64_t* c = T.cw + 2 * ((size_t)m * T.cw_stride + k);
+                const uint64_t* c = T.cw + 2 * ((size_t)T.wi[m] * T.cw_stride + k);
                 const uint32_t g = T.gs[m];
                 // Galois element 0 marks a constant term (the plaintext W, no mask)
                 M = add_mod(M, g ? mul_shoup(row[galois_perm((uint32_t)i, g, logN)], c[0], c[1], md.q) : c[0], md.q);

@@ -20,6 +20,8 @@ struct MfState {
     uint64_t* mask0 = nullptr;      // I0 at the scatter mask scale, evaluation form [L+1][N]
     uint64_t* maskg = nullptr;      // I0 at the gather mask scale, evaluation form [L+1][N]
     int epochs_done = 0;
+    int refresh_round = 0;
+    double refresh_seconds = 0;     // wall time spent in refreshes (host + device)
     bool factors = false;
 };
 
@@ -29,11 +31,23 @@ namespace mfp {
 // of about sqrt(N/24)/S_I on every slot of every mask; a gather (all weights 1)
 // sums D masks, so it takes the larger scale and declares the exact scale of
 // its terms instead of rounding a weight; a scatter needs room for small
-// integer weights (learning rate over degree) and keeps 2^20, with the self
-// term's common weight applied as a constant so only corrections are masked.
-constexpr double kMaskScale = 1048576.0;           // 2^20, scatter
+// integer weights (learning rate over degree): 2^24 with the 2^50 table scale,
+// and the self term's common weight applied as a constant so only
+// corrections are masked.
+constexpr double kMaskScale = 16777216.0;          // 2^24, scatter
 constexpr double kGatherMaskScale = 1073741824.0;  // 2^30, gather
-constexpr double kTargetScale = 1099511627776.0;   // 2^40, scale of every permuted result
+constexpr double kTargetScale = 1099511627776.0;   // 2^40, scale of gathered factors
+// Scale the factor tables are held at (target of a scatter): the scatter
+// weights alpha/d are ~1e-5; their integers are W ~ w 2^26 here, where a 2^40
+// target with 2^20 masks gives W ~ w 2^20 ~ 10, rounded by up to 5 percent
+// the same way every epoch.
+constexpr double kTableScale = 1125899906842624.0; // 2^50
+// Refresh of level-exhausted tables: tables below this level are refreshed
+// before the next gather; masks have integer coefficients in [-2^50, 2^50);
+// refreshed table j of round r is encrypted with serial kRefreshSerial + r*1024 + j.
+constexpr int kRefreshLevel = 4;
+constexpr int kRefreshMaskBits = 50;
+constexpr uint32_t kRefreshSerial = 0x20000000u;
 
 // A block move: source ciphertext `src`, block a -> destination block b, weight w.
 struct Move {
@@ -58,14 +72,15 @@ std::vector<Ct> dropped(const std::vector<Ct*>& v, int level);
 std::vector<Ct> hmult_all(Context* c, const std::vector<Ct*>& a, const std::vector<Ct*>& b);
 std::vector<Ct> rotate_all(Context* c, const std::vector<Ct*>& a, int64_t r);
 std::vector<Ct> add_all(Context* c, const std::vector<Ct*>& a, const std::vector<Ct*>& b, bool sub);
-int64_t weight_int(double w, double s_src, double q_acc, double mask_scale);
+int64_t weight_int(double w, double s_src, double q_acc, double mask_scale, double target);
 std::vector<int64_t> encode_all(Context* c, const std::vector<std::vector<double>>& zs, double scale);
 std::vector<uint64_t> put_all(Context* c, std::vector<Ct>& v);
 void upload_masks(Context* c, MfState& m, const int64_t* mask_scatter, const int64_t* mask_gather);
 void encode_masks(Context* c, int k, std::vector<int64_t>& mask_scatter, std::vector<int64_t>& mask_gather);
 void free_masks(Context* c, MfState& m);
-// unit: every move has weight 1 (a gather): I0 at the gather scale and the
-// accumulator declared at the exact scale of its terms.
+// unit: every move has weight 1 (a gather): I0 at the gather scale, target
+// 2^40 and the accumulator declared at the exact scale of its terms;
+// otherwise (a scatter) I0 at the scatter scale and target kTableScale.
 std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& srcs,
                               const std::vector<std::vector<Move>>& dests, const std::vector<SelfTerm>* selfs,
                               int level, const BabyCache* cache, bool unit);

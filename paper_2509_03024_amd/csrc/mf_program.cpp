@@ -19,12 +19,17 @@
 // (a - b) mod D = gamma*G + beta, G = 2^ceil(log2(D)/2)):
 //   acc_d = sum_gamma Rot_{gamma G B}( sum_{c,beta} HRot_{beta B}(src_c) (.) M_{d,c,gamma,beta} )
 //   M = sum_moves W * tau_{g_p}(I0), p = (b + gamma G) mod D, g_p = 5^((-pB) mod N/2),
-//   W = rint((w * 2^40 * q_ell) / (S_src * 2^20)); one rescale per destination.
+//   W = rint((w * S_t * q_ell) / (S_src * S_I)); one rescale per destination.
+//   Scatter: S_I = 2^24, S_t = 2^50 (the tables' scale), self term as a constant
+//   plus masked corrections; gather: S_I = 2^30, S_t = 2^40, the accumulator
+//   declared at the exact scale of its terms (all weights are 1).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <tuple>
+#include <unordered_map>
 
 #include "mf_internal.h"
 #include "host_math.h"
@@ -161,7 +166,7 @@ static void upload_one(Context* c, uint64_t*& dst, const int64_t* mask) {
     for (int i = 0; i <= c->L; ++i) mm.push(i, i);
     launch_expand_signed(c->tabs, mm, (const int64_t*)src.p, 1, 0, c->stream);
     launch_ntt(c->tabs, mm, false, c->stream);
-    CSRMF_HIP(hipStreamSynchronize(c->stream));
+    c->sync();
 }
 
 void upload_masks(Context* c, MfState& m, const int64_t* mask_scatter, const int64_t* mask_gather) {
@@ -229,18 +234,88 @@ std::vector<Ct> add_all(Context* c, const std::vector<Ct*>& a, const std::vector
     return out;
 }
 
-int64_t weight_int(double w, double s_src, double q_acc, double mask_scale) {
-    return (int64_t)std::nearbyint((w * kTargetScale * q_acc) / (s_src * mask_scale));
+int64_t weight_int(double w, double s_src, double q_acc, double mask_scale, double target) {
+    return (int64_t)std::nearbyint((w * target * q_acc) / (s_src * mask_scale));
 }
 
-// Upload a host vector into a pool scratch block (synchronous).
-template <typename T>
-uint64_t* upload_vec(Context* c, const std::vector<T>& v, std::vector<uint64_t*>& owned) {
-    uint64_t* d = (uint64_t*)c->pool.get(std::max<size_t>(8, v.size() * sizeof(T)));
-    if (!v.empty()) CSRMF_HIP(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
-    owned.push_back(d);
-    return d;
-}
+// Per-limb constants W * 2^64 mod q_i and their Shoup factors, computed once
+// per distinct integer weight.
+class WeightRows {
+public:
+    WeightRows(Context* c, int nl) : c_(c), nl_(nl) {}
+    const std::vector<uint64_t>& row(int64_t W) {
+        auto it = rows_.find(W);
+        if (it != rows_.end()) return it->second;
+        std::vector<uint64_t> r;
+        r.reserve(2 * (size_t)nl_);
+        for (int i = 0; i < nl_; ++i) {
+            const uint64_t q = c_->moduli[i];
+            const uint64_t x = mul_mod_host(from_signed(W, q), c_->mh[i].r_mod, q);
+            r.push_back(x);
+            r.push_back(shoup_pre(x, q));
+        }
+        return rows_.emplace(W, std::move(r)).first->second;
+    }
+
+private:
+    Context* c_;
+    int nl_;
+    std::unordered_map<int64_t, std::vector<uint64_t>> rows_;
+};
+
+// One multi-task masked MAC launch being assembled on the host.
+struct MacLaunch {
+    std::vector<uint64_t*> acc, src;
+    std::vector<int32_t> grp_begin, first, term_begin, wi;
+    std::vector<uint32_t> gs;
+    std::vector<uint64_t> cw;
+    std::unordered_map<int64_t, int32_t> widx;
+
+    void task(uint64_t* a, bool is_first) {
+        acc.push_back(a);
+        first.push_back(is_first ? 1 : 0);
+        grp_begin.push_back((int32_t)src.size());
+    }
+    void group(const uint64_t* s) {
+        src.push_back(const_cast<uint64_t*>(s));
+        term_begin.push_back((int32_t)gs.size());
+    }
+    void term(uint32_t g, int64_t W, WeightRows& rows) {
+        auto it = widx.find(W);
+        int32_t w;
+        if (it == widx.end()) {
+            w = (int32_t)widx.size();
+            widx.emplace(W, w);
+            const std::vector<uint64_t>& r = rows.row(W);
+            cw.insert(cw.end(), r.begin(), r.end());
+        } else {
+            w = it->second;
+        }
+        gs.push_back(g);
+        wi.push_back(w);
+    }
+    // Stage the arguments, launch, and fence the staging ring behind the launch.
+    void run(Context* c, int nl, const uint64_t* mask, double bytes) {
+        if (acc.empty()) return;
+        grp_begin.push_back((int32_t)src.size());
+        term_begin.push_back((int32_t)gs.size());
+        MaskTasks T;
+        T.acc = (uint64_t* const*)c->stage(acc.data(), acc.size() * sizeof(uint64_t*));
+        T.grp_begin = (const int32_t*)c->stage(grp_begin.data(), grp_begin.size() * 4);
+        T.first = (const int32_t*)c->stage(first.data(), first.size() * 4);
+        T.src = (const uint64_t* const*)c->stage(src.data(), src.size() * sizeof(uint64_t*));
+        T.term_begin = (const int32_t*)c->stage(term_begin.data(), term_begin.size() * 4);
+        T.gs = (const uint32_t*)c->stage(gs.data(), gs.size() * 4);
+        T.wi = (const int32_t*)c->stage(wi.data(), wi.size() * 4);
+        T.cw = (const uint64_t*)c->stage(cw.data(), cw.size() * 8);
+        T.n_tasks = (int32_t)acc.size();
+        T.n_limbs = nl;
+        T.cw_stride = nl;
+        T.poly_stride = c->poly_stride();
+        launch_mask_mac_tasks(c->tabs, T, mask, bytes, c->stream);
+        c->fence();
+    }
+};
 
 constexpr int kHoistChunk = 128;   // sources whose digits are extended together
 
@@ -259,26 +334,20 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
     const double s_src = srcs.empty() ? 1.0 : srcs[0]->scale;
     const double q_acc = (double)c->moduli[level];
     const double mask_scale = unit ? kGatherMaskScale : kMaskScale;
+    const double target = unit ? kTargetScale : kTableScale;
     const uint64_t* mask = unit ? m.maskg : m.mask0;
     if (!mask) throw Error(CSRMF_E_STATE, "block masks not uploaded");
-    double acc_scale = kTargetScale * q_acc;
+    double acc_scale = target * q_acc;
     if (unit) {
         for (const auto& dv : dests)
             for (const Move& x : dv)
                 if (x.w != 1.0) throw Error(CSRMF_E_INVAL, "unit permutation with a weight other than 1");
         if (selfs) throw Error(CSRMF_E_INVAL, "unit permutation with self terms");
-        acc_scale = s_src * mask_scale * (double)weight_int(1.0, s_src, q_acc, mask_scale);
+        acc_scale = s_src * mask_scale * (double)weight_int(1.0, s_src, q_acc, mask_scale, target);
     }
     const int n_dest = (int)dests.size();
     const int n_gamma = D / G;
-    auto wconst = [&](int64_t W, std::vector<uint64_t>& out) {
-        for (int i = 0; i < nl; ++i) {
-            const uint64_t q = c->moduli[i];
-            const uint64_t r = mul_mod_host(from_signed(W, q), c->mh[i].r_mod, q);
-            out.push_back(r);
-            out.push_back(shoup_pre(r, q));
-        }
-    };
+    WeightRows wrows(c, nl);
     auto gal = [&](int p) { return c->galois_for_step(-(int64_t)p * B); };
 
     // groups keyed by (beta, source, destination, gamma) -> terms (p, W)
@@ -288,7 +357,7 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
         for (const Move& x : dests[d]) {
             const int delta = ((x.a - x.b) % D + D) % D;
             const int gamma = delta / G, beta = delta % G;
-            groups[{beta, x.src, d, gamma}].push_back({(x.b + gamma * G) % D, weight_int(x.w, s_src, q_acc, mask_scale)});
+            groups[{beta, x.src, d, gamma}].push_back({(x.b + gamma * G) % D, weight_int(x.w, s_src, q_acc, mask_scale, target)});
             auto& v = betas_of_src[x.src];
             if (std::find(v.begin(), v.end(), beta) == v.end()) v.push_back(beta);
         }
@@ -350,47 +419,21 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
                 tasks[{std::get<2>(it->first), std::get<3>(it->first)}].push_back({pit->second, &it->second});
             }
             if (tasks.empty()) continue;
-            std::vector<uint64_t*> acc_ptr, src_ptr;
-            std::vector<int32_t> grp_begin, first, term_begin;
-            std::vector<uint32_t> gs;
-            std::vector<uint64_t> cw;
+            MacLaunch ml;
             for (auto& tk : tasks) {
                 const int d = tk.first.first, gamma = tk.first.second;
                 Ct& tgt = gamma ? inner[d][gamma] : acc[d];
                 char& init = gamma ? inner_init[d][gamma] : acc_init[d];
-                acc_ptr.push_back(tgt.d);
-                first.push_back(init ? 0 : 1);
+                ml.task(tgt.d, !init);
                 init = 1;
-                grp_begin.push_back((int32_t)src_ptr.size());
                 for (auto& gr : tk.second) {
                     if (!baby_ptr[gr.first]) throw Error(CSRMF_E_STATE, "missing cached baby-step rotation");
-                    src_ptr.push_back(baby_ptr[gr.first]);
-                    term_begin.push_back((int32_t)gs.size());
-                    for (auto& t : *gr.second) {
-                        gs.push_back(gal(t.first));
-                        wconst(t.second, cw);
-                    }
+                    ml.group(baby_ptr[gr.first]);
+                    for (auto& tm : *gr.second) ml.term(gal(tm.first), tm.second, wrows);
                 }
             }
-            grp_begin.push_back((int32_t)src_ptr.size());
-            term_begin.push_back((int32_t)gs.size());
-            std::vector<uint64_t*> owned;
-            MaskTasks T;
-            T.acc = (uint64_t* const*)upload_vec(c, acc_ptr, owned);
-            T.grp_begin = (const int32_t*)upload_vec(c, grp_begin, owned);
-            T.first = (const int32_t*)upload_vec(c, first, owned);
-            T.src = (const uint64_t* const*)upload_vec(c, src_ptr, owned);
-            T.term_begin = (const int32_t*)upload_vec(c, term_begin, owned);
-            T.gs = (const uint32_t*)upload_vec(c, gs, owned);
-            T.cw = upload_vec(c, cw, owned);
-            T.n_tasks = (int32_t)acc_ptr.size();
-            T.n_limbs = nl;
-            T.cw_stride = nl;
-            T.poly_stride = c->poly_stride();
-            CSRMF_HIP(hipStreamSynchronize(c->stream));   // host vectors go out of scope
-            const double bytes = (double)c->N * 8.0 * nl * (2.0 * src_ptr.size() + 4.0 * acc_ptr.size() + gs.size());
-            launch_mask_mac_tasks(c->tabs, T, mask, bytes, c->stream);
-            for (uint64_t* p : owned) c->pool.put(p);
+            const double bytes = (double)c->N * 8.0 * nl * (2.0 * ml.src.size() + 4.0 * ml.acc.size() + ml.gs.size());
+            ml.run(c, nl, mask, bytes);
             release(c, babies);
         }
     }
@@ -437,48 +480,20 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
     // self terms: one task per destination; the constant c is a term with
     // Galois element 0 (no mask), the corrections are masked terms
     if (selfs) {
-        std::vector<uint64_t*> acc_ptr, src_ptr;
-        std::vector<int32_t> grp_begin, first, term_begin;
-        std::vector<uint32_t> gs;
-        std::vector<uint64_t> cw;
+        MacLaunch ml;
         for (int d = 0; d < n_dest; ++d) {
             const SelfTerm& st = (*selfs)[d];
             if (!st.t) continue;
             const double s_self = st.t->scale;
-            acc_ptr.push_back(acc[d].d);
-            first.push_back(acc_init[d] ? 0 : 1);
+            ml.task(acc[d].d, !acc_init[d]);
             acc_init[d] = 1;
-            grp_begin.push_back((int32_t)src_ptr.size());
-            src_ptr.push_back(st.t->d);
-            term_begin.push_back((int32_t)gs.size());
-            gs.push_back(0);
-            wconst(weight_int(st.c, s_self, q_acc, 1.0), cw);
-            for (auto& bw : st.corr) {
-                gs.push_back(gal(bw.first));
-                wconst(weight_int(bw.second, s_self, q_acc, mask_scale), cw);
-            }
+            ml.group(st.t->d);
+            ml.term(0, weight_int(st.c, s_self, q_acc, 1.0, target), wrows);
+            for (auto& bw : st.corr)
+                ml.term(gal(bw.first), weight_int(bw.second, s_self, q_acc, mask_scale, target), wrows);
         }
-        if (!acc_ptr.empty()) {
-            grp_begin.push_back((int32_t)src_ptr.size());
-            term_begin.push_back((int32_t)gs.size());
-            std::vector<uint64_t*> owned;
-            MaskTasks T;
-            T.acc = (uint64_t* const*)upload_vec(c, acc_ptr, owned);
-            T.grp_begin = (const int32_t*)upload_vec(c, grp_begin, owned);
-            T.first = (const int32_t*)upload_vec(c, first, owned);
-            T.src = (const uint64_t* const*)upload_vec(c, src_ptr, owned);
-            T.term_begin = (const int32_t*)upload_vec(c, term_begin, owned);
-            T.gs = (const uint32_t*)upload_vec(c, gs, owned);
-            T.cw = upload_vec(c, cw, owned);
-            T.n_tasks = (int32_t)acc_ptr.size();
-            T.n_limbs = nl;
-            T.cw_stride = nl;
-            T.poly_stride = c->poly_stride();
-            CSRMF_HIP(hipStreamSynchronize(c->stream));
-            const double bytes = (double)c->N * 8.0 * nl * (6.0 * acc_ptr.size() + (gs.size() - acc_ptr.size()));
-            launch_mask_mac_tasks(c->tabs, T, mask, bytes, c->stream);
-            for (uint64_t* p : owned) c->pool.put(p);
-        }
+        const double bytes = (double)c->N * 8.0 * nl * (6.0 * ml.acc.size() + (ml.gs.size() - ml.acc.size()));
+        ml.run(c, nl, mask, bytes);
     }
     for (int d = 0; d < n_dest; ++d)
         if (!acc_init[d]) throw Error(CSRMF_E_INVAL, "block permutation with an empty destination");
@@ -559,11 +574,69 @@ std::vector<Ct> dot_products(Context* c, MfState& m, const std::vector<Ct*>& ug,
     return S;
 }
 
-void run_epoch(Context* c, MfState& m, bool last) {
+// Refresh of the tables (see kRefreshLevel): mask, decrypt to integers mod q_0,
+// encrypt the same integers at the top level and scale, unmask.
+void refresh_tables(Context* c, MfState& m) {
+    c->sync();
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<uint64_t> all;
+    for (uint64_t h : m.Utab) all.push_back(h);
+    for (uint64_t h : m.Vtab) all.push_back(h);
+    std::vector<uint64_t> w(c->N);
+    std::vector<int64_t> mask(c->N), neg(c->N), plain(c->N);
+    std::vector<uint64_t> fresh;
+    for (size_t j = 0; j < all.size(); ++j) {
+        const uint32_t obj = (uint32_t)m.refresh_round * 1024u + (uint32_t)j;
+        chacha20_words(c->seed, kRefreshMask, obj, 0, c->N, w.data());
+        for (uint64_t n = 0; n < c->N; ++n) {
+            mask[n] = (int64_t)(w[n] % (1ull << (kRefreshMaskBits + 1))) - (int64_t)(1ull << kRefreshMaskBits);
+            neg[n] = -mask[n];
+        }
+        const Ct& t = c->get(all[j]);
+        Ct masked;
+        c->add_plain(t, mask.data(), masked);
+        c->decrypt_int(masked, plain.data());
+        c->pool.put(masked.d);
+        std::vector<Ct> out;
+        const uint32_t serial = kRefreshSerial + obj;
+        c->encrypt_int_batch(plain.data(), 1, c->L, t.scale, out, &serial);
+        Ct un;
+        c->add_plain(out[0], neg.data(), un);
+        c->pool.put(out[0].d);
+        fresh.push_back(c->put(un));
+    }
+    const size_t nu = m.Utab.size();
+    free_handles(c, m.Utab);
+    free_handles(c, m.Vtab);
+    m.Utab.assign(fresh.begin(), fresh.begin() + (long)nu);
+    m.Vtab.assign(fresh.begin() + (long)nu, fresh.end());
+    m.refresh_round++;
+    c->sync();
+    m.refresh_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Gather the factors for an epoch, refreshing the tables first if their level
+// is below kRefreshLevel (only when the parameters allow refresh).
+void prepare_epoch(Context* c, MfState& m) {
+    if (c->get(m.Utab[0]).level < kRefreshLevel) {
+        if (!c->prm.refresh_mode) throw Error(CSRMF_E_LEVEL, "level budget exhausted (refresh_mode = 0)");
+        refresh_tables(c, m);
+    }
+    std::vector<Ct> gu = gather(c, m, m.Utab, true);
+    std::vector<Ct> gv = gather(c, m, m.Vtab, false);
+    free_handles(c, m.Ug);
+    free_handles(c, m.Vg);
+    m.Ug = put_all(c, gu);
+    m.Vg = put_all(c, gv);
+}
+
+// One epoch from the gathered factors m.Ug, m.Vg: dot products, errors,
+// gradient terms, scatter into the tables.
+void run_epoch(Context* c, MfState& m) {
     const double a_t = c->prm.lr / (1.0 + c->prm.damp * (double)m.epochs_done);
     std::vector<Ct*> ug = cts_of(c, m.Ug), vg = cts_of(c, m.Vg), R = cts_of(c, m.R);
     const int lvl = ug[0]->level;
-    if (lvl < 3 + (last ? 0 : 1)) throw Error(CSRMF_E_LEVEL, "not enough levels left for an epoch");
+    if (lvl < 3) throw Error(CSRMF_E_LEVEL, "not enough levels left for an epoch");
     double sp = 0;
     std::vector<Ct> S = dot_products(c, m, ug, vg, &sp);
     const int slv = S[0].level;
@@ -597,14 +670,8 @@ void run_epoch(Context* c, MfState& m, bool last) {
     m.Vtab = put_all(c, nv);
     free_handles(c, m.Sdot);
     m.Sdot = put_all(c, S);
-    if (!last) {
-        std::vector<Ct> gu = gather(c, m, m.Utab, true);
-        std::vector<Ct> gv = gather(c, m, m.Vtab, false);
-        free_handles(c, m.Ug);
-        free_handles(c, m.Vg);
-        m.Ug = put_all(c, gu);
-        m.Vg = put_all(c, gv);
-    }
+    free_handles(c, m.Ug);
+    free_handles(c, m.Vg);
     m.epochs_done++;
 }
 
@@ -719,6 +786,16 @@ int csrmf_mf_layout(const csrmf_ctx* cx, int32_t* n_ct, int32_t* n_utab, int32_t
     API_END(c)
 }
 
+int csrmf_mf_stats(const csrmf_ctx* cx, int32_t* epochs_done, int32_t* refreshes, double* refresh_seconds) {
+    Context* c = const_cast<Context*>(reinterpret_cast<const Context*>(cx));
+    API_BEGIN(c)
+    MfState& m = csrmf::mfp::state(c);
+    if (epochs_done) *epochs_done = m.epochs_done;
+    if (refreshes) *refreshes = m.refresh_round;
+    if (refresh_seconds) *refresh_seconds = m.refresh_seconds;
+    API_END(c)
+}
+
 int csrmf_init_factors(csrmf_ctx* cx, const double* U0, const double* V0) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
@@ -743,6 +820,8 @@ int csrmf_init_factors(csrmf_ctx* cx, const double* U0, const double* V0) {
     csrmf::mfp::upload_masks(c, m, mask_s.data(), mask_g.data());
     m.factors = true;
     m.epochs_done = 0;
+    m.refresh_round = 0;
+    m.refresh_seconds = 0;
     API_END(c)
 }
 
@@ -761,6 +840,8 @@ int csrmf_init_factors_int(csrmf_ctx* cx, const int64_t* utab, const int64_t* vt
     csrmf::mfp::upload_masks(c, m, mask_scatter, mask_gather);
     m.factors = true;
     m.epochs_done = 0;
+    m.refresh_round = 0;
+    m.refresh_seconds = 0;
     API_END(c)
 }
 
@@ -771,24 +852,21 @@ int csrmf_mf_epochs(csrmf_ctx* cx, int32_t n_epochs) {
     if (!m.factors) throw Error(CSRMF_E_STATE, "init_factors first");
     if (n_epochs < 0) throw Error(CSRMF_E_INVAL, "n_epochs");
     if (n_epochs == 0) API_END_EARLY;
-    // Level budget of the whole request: an epoch on gathered factors uses 3
-    // levels, every further one 4 (its gather included).  After a previous
-    // call the factors are only in the tables, so they are gathered first.
-    const bool regather = m.Ug.empty();
-    const int lvl = regather ? c->get(m.Utab[0]).level - 1 : c->get(m.Ug[0]).level;
-    if (lvl < 3 + 4 * (n_epochs - 1)) throw Error(CSRMF_E_LEVEL, "not enough levels for the requested epochs");
-    if (regather) {
-        std::vector<csrmf::Ct> gu = csrmf::mfp::gather(c, m, m.Utab, true);
-        std::vector<csrmf::Ct> gv = csrmf::mfp::gather(c, m, m.Vtab, false);
-        m.Ug = csrmf::mfp::put_all(c, gu);
-        m.Vg = csrmf::mfp::put_all(c, gv);
+    // Level budget: an epoch on gathered factors uses 3 levels, every further
+    // one 4 (its gather included).  Without refresh the whole request must fit;
+    // with refresh, tables below kRefreshLevel are refreshed before a gather.
+    const bool have_g = !m.Ug.empty();
+    const int lvl = have_g ? c->get(m.Ug[0]).level : c->get(m.Utab[0]).level - 1;
+    if (!c->prm.refresh_mode) {
+        if (lvl < 3 + 4 * (n_epochs - 1)) throw Error(CSRMF_E_LEVEL, "not enough levels for the requested epochs");
+    } else if (c->L < csrmf::mfp::kRefreshLevel) {
+        if (lvl < 3 + 4 * (n_epochs - 1)) throw Error(CSRMF_E_LEVEL, "chain too short to refresh");
     }
-    for (int t = 0; t < n_epochs; ++t) csrmf::mfp::run_epoch(c, m, t + 1 == n_epochs);
-    if (n_epochs > 0) {
-        csrmf::mfp::free_handles(c, m.Ug);
-        csrmf::mfp::free_handles(c, m.Vg);
+    for (int t = 0; t < n_epochs; ++t) {
+        if (t > 0 || !have_g) csrmf::mfp::prepare_epoch(c, m);
+        csrmf::mfp::run_epoch(c, m);
     }
-    CSRMF_HIP(hipStreamSynchronize(c->stream));
+    c->sync();
     API_END(c)
 }
 

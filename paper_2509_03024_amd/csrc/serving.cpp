@@ -155,7 +155,7 @@ void Server::run() {
         try {
             std::lock_guard<std::recursive_mutex> lk(c->mu);
             process(batch);
-            CSRMF_HIP(hipStreamSynchronize(c->stream));
+            c->sync();
         } catch (const Error& e) {
             std::lock_guard<std::mutex> lk(mu);
             for (ServeRequest* r : batch) { r->status = e.code; r->error = e.what(); }
@@ -365,7 +365,7 @@ int csrmf_server_create(csrmf_ctx* cx, int32_t n_users, int32_t n_items, const d
         csrmf::encrypt_tables(c, m, n_items, V, s->Vtab);
         csrmf::cache_babies(c, m, s->Utab, s->ucache);
         csrmf::cache_babies(c, m, s->Vtab, s->vcache);
-        CSRMF_HIP(hipStreamSynchronize(c->stream));
+        c->sync();
         c->servers.push_back(s);
         s->worker = std::thread([s] { s->run(); });
     } catch (const Error& e) {

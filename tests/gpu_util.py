@@ -5,7 +5,9 @@ import numpy as np
 def to_device_u64(arr):
     import torch
     a = np.ascontiguousarray(arr, np.uint64)
-    return torch.from_numpy(a.view(np.int64).copy()).cuda()
+    t = torch.from_numpy(a.view(np.int64).copy()).cuda()
+    torch.cuda.synchronize()      # the library's stream does not wait for torch's
+    return t
 
 
 def from_device_u64(t):

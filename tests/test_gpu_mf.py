@@ -115,10 +115,10 @@ def test_invalid_csr_rejected():
     ctx.close()
 
 
-def _golden_tiny2():
+def _golden_tiny2(name="mf_tiny2_r2_2epochs.txt"):
     import os
     rows = {}
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mf_tiny2_r2_2epochs.txt")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
     with open(path) as f:
         for line in f:
             if line.startswith("#") or not line.strip():
@@ -128,11 +128,24 @@ def _golden_tiny2():
     return rows
 
 
-def test_two_epochs_bit_exact_through_a_gather():
-    """Two epochs (rule R2) on the two-epoch chain; the second starts from
-    gathered factors.  Every output ciphertext equals the oracle's (SHA-256
-    digests written by tests/golden/make_mf_tiny2.py from the oracle alone),
-    and the decrypted values are within 1e-4 of FP64 MF."""
+def _check_digests(ctx, m, g, golden):
+    n = 0
+    for kind, which in (("utab", 1), ("vtab", 2), ("sdot", 5)):
+        for i, h in enumerate(m.handles(which)):
+            got, lvl, sc = ctx.export_ct(h)
+            want = golden[(kind, i)]
+            assert (lvl, sc) == want[:2], (kind, i)
+            assert g.digest(got[0], got[1]) == want[2], (kind, i)
+            n += 1
+    assert n == len(golden)
+
+
+def test_two_epochs_bit_exact_through_a_gather_and_a_refresh():
+    """Two epochs (rule R2) on the two-epoch chain, the second from gathered
+    factors, then a third call of one epoch that first refreshes the tables
+    (level 0) and gathers.  Every output ciphertext equals the oracle's
+    (SHA-256 digests written by tests/golden/make_mf_tiny2.py from the oracle
+    alone), and the decrypted values are within 1e-4 of FP64 MF."""
     import paper_2509_03024_amd as pk
     from tests.golden import make_mf_tiny2 as g
     prm = params.config_tiny_two_epochs()
@@ -144,7 +157,7 @@ def test_two_epochs_bit_exact_through_a_gather():
     masks = program.block_masks(orc, g.K)
     golden = _golden_tiny2()
 
-    ctx = pk.Context(pk.params(12, 60, 7, 40, 2, 60, 4, 40, k=g.K, lr=g.LR, lam=g.LAM, rule=2),
+    ctx = pk.Context(pk.params(12, 60, 7, 40, 2, 60, 4, 40, k=g.K, lr=g.LR, lam=g.LAM, rule=2, refresh_mode=1),
                      workloads.CRYPTO_SEED)
     ctx.keygen([])
     m = pk.MF(ctx)
@@ -152,18 +165,18 @@ def test_two_epochs_bit_exact_through_a_gather():
     m.init_factors_int(np.stack(pt["Utab"]), np.stack(pt["Vtab"]), np.stack(pt["Ug"]), np.stack(pt["Vg"]),
                        masks[program.S_I], masks[program.S_IG], g.K)
     m.epochs(g.EPOCHS)
-    n = 0
-    for kind, which in (("utab", 1), ("vtab", 2), ("sdot", 5)):
-        for i, h in enumerate(m.handles(which)):
-            got, lvl, sc = ctx.export_ct(h)
-            want = golden[(kind, i)]
-            assert (lvl, sc) == want[:2], (kind, i)
-            assert g.digest(got[0], got[1]) == want[2], (kind, i)
-            n += 1
-    assert n == len(golden)
+    _check_digests(ctx, m, g, golden)
     U, V = m.decrypt_factors()
     rhat = m.decrypt_predictions(0)
     Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, g.LR, g.LAM, g.EPOCHS, rule=g.RULE)
+    assert np.max(np.abs(U - Uf)) < 1e-4 and np.max(np.abs(V - Vf)) < 1e-4
+    assert np.max(np.abs(rhat - rf)) < 1e-4
+    # third epoch: the tables are at level 0, so the call refreshes them first
+    m.epochs(1)
+    _check_digests(ctx, m, g, _golden_tiny2("mf_tiny2_r2_refresh.txt"))
+    U, V = m.decrypt_factors()
+    rhat = m.decrypt_predictions(0)
+    Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, g.LR, g.LAM, g.EPOCHS + 1, rule=g.RULE)
     assert np.max(np.abs(U - Uf)) < 1e-4 and np.max(np.abs(V - Vf)) < 1e-4
     assert np.max(np.abs(rhat - rf)) < 1e-4
     ctx.close()

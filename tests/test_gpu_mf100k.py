@@ -1,7 +1,8 @@
 """Encrypted MF at the MovieLens-100K-shaped workload (943 x 1682, 99,926
 ratings, k = 10, N = 2^15, 17 limbs, rule R2):
-* decrypted factors and forward predictions after 3 epochs within 1e-4 of
-  the FP64 synchronous epochs (oracle.mf);
+* decrypted factors and forward predictions after 3 epochs, and after 10
+  epochs with two table refreshes, within 1e-4 of the FP64 synchronous
+  epochs (oracle.mf);
 * the first epoch's forward dot-product ciphertext of a sampled rating
   ciphertexts bit-exact against the oracle (same seed, integer plaintexts and
   serial numbers; those ciphertexts depend only on their own rating block)."""
@@ -31,6 +32,31 @@ def test_mf100k_three_epochs_within_1e4_of_fp64():
     Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, LR, LAM, 3, rule="R2")
     print("max |U-Uf|", np.max(np.abs(U - Uf)), "max |V-Vf|", np.max(np.abs(V - Vf)),
           "max |rhat-rf|", np.max(np.abs(rhat - rf)))
+    assert np.max(np.abs(U - Uf)) < 1e-4
+    assert np.max(np.abs(V - Vf)) < 1e-4
+    assert np.max(np.abs(rhat - rf)) < 1e-4
+    ctx.close()
+
+
+def test_mf100k_ten_epochs_with_two_refreshes_within_1e4_of_fp64():
+    """The workload's full run: 10 epochs on the 16-prime chain, refreshing the
+    tables twice (after epochs 4 and 8), within 1e-4 of the FP64 epochs."""
+    import paper_2509_03024_amd as pk
+    csr = workloads.movielens100k_shaped()
+    U0, V0 = workloads.init_factors(csr.n_rows, csr.n_cols, K)
+    ctx = pk.Context(pk.mf_n15_params(k=K, lr=LR, lam=LAM, rule=2, refresh_mode=1), workloads.CRYPTO_SEED)
+    ctx.keygen([])
+    m = pk.MF(ctx)
+    m.encrypt_csr_rows(csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx, csr.values)
+    m.init_factors(U0, V0)
+    m.epochs(10)
+    st = m.stats()
+    assert st["epochs_done"] == 10 and st["refreshes"] == 2
+    U, V = m.decrypt_factors()
+    rhat = m.decrypt_predictions(0)
+    Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, LR, LAM, 10, rule="R2")
+    print("10 epochs: max |U-Uf|", np.max(np.abs(U - Uf)), "max |V-Vf|", np.max(np.abs(V - Vf)),
+          "max |rhat-rf|", np.max(np.abs(rhat - rf)), "refresh s", st["refresh_seconds"])
     assert np.max(np.abs(U - Uf)) < 1e-4
     assert np.max(np.abs(V - Vf)) < 1e-4
     assert np.max(np.abs(rhat - rf)) < 1e-4

@@ -161,10 +161,10 @@ class _MaskNoise(program.ClearBackend):
 @pytest.mark.slow
 def test_mask_reading_within_1e4_at_mf100k_shape():
     """The block-mask reading (gather masks at 2^30 with the exact term scale,
-    scatter masks at 2^20 with the self term's constant split off) keeps three
-    epochs at the MovieLens-100K shape (N = 2^15, k = 10, D = 512) within
-    1e-4 of FP64.  With every mask at 2^20 (the previous reading) the same
-    model drifts to ~3e-3, so this check fails if the split is undone."""
+    scatter masks at 2^24 into tables held at 2^50, the self term's constant
+    split off) keeps three epochs at the MovieLens-100K shape (N = 2^15,
+    k = 10, D = 512) within 1e-5 of FP64 (the model gives ~1e-6).  With every
+    mask at 2^20 and tables at 2^40 the same model drifts to ~3e-3."""
     K, LR, LAM, EP = 10, 0.01, 0.02, 3
     csr = workloads.movielens100k_shaped()
     U0, V0 = workloads.init_factors(csr.n_rows, csr.n_cols, K)
@@ -184,5 +184,5 @@ def test_mask_reading_within_1e4_at_mf100k_shape():
     V = program.decode_tables([x.z for x in res.vtab], lay, csr.n_cols)
     rhat = program.decode_predictions([x.z for x in res.sdot], lay)
     Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, LR, LAM, EP, rule="R2")
-    assert np.max(np.abs(U - Uf)) < 1e-4 and np.max(np.abs(V - Vf)) < 1e-4
-    assert np.max(np.abs(rhat - rf)) < 1e-4
+    assert np.max(np.abs(U - Uf)) < 1e-5 and np.max(np.abs(V - Vf)) < 1e-5
+    assert np.max(np.abs(rhat - rf)) < 1e-5
