@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--epochs", type=int, default=10, help="MF workloads: epochs (the 100K workload refreshes as needed)")
     ap.add_argument("--rates", default="10,25,50,100,200", help="serve: Poisson arrival rates (requests/s)")
     ap.add_argument("--requests", type=int, default=60, help="serve: requests per rate")
+    ap.add_argument("--ntt-chunk", type=int, default=None,
+                    help="fix the NTT schedule (rows per pair of passes) instead of autotuning (for profiles)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy a 512 MiB device buffer once before the timed steps (reference for HBM counters)")
     return ap.parse_args()
@@ -92,7 +94,10 @@ def bench_mf(args):
     t0 = time.perf_counter()
     ctx = pk.Context(prm, workloads.CRYPTO_SEED)
     ctx.keygen([], conj=False)
-    ctx.autotune()
+    if args.ntt_chunk is not None:
+        pk.set_ntt_schedule(args.ntt_chunk)
+    else:
+        ctx.autotune()
     m = pk.MF(ctx)
     n_ct = m.encrypt_csr_rows(csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx, csr.values)
     m.init_factors(U0, V0)
@@ -226,8 +231,12 @@ def main():
     ctx = pk.Context(pk.kernel_batch_params(), workloads.CRYPTO_SEED)
     ctx.keygen(CHAIN, conj=True)
     log(f"context + keys {time.perf_counter() - t0:.1f} s")
-    tune = ctx.autotune()
-    log(f"autotune {tune}")
+    if args.ntt_chunk is not None:
+        pk.set_ntt_schedule(args.ntt_chunk)
+        tune = {"fixed": args.ntt_chunk}
+    else:
+        tune = ctx.autotune()
+    log(f"NTT schedule {tune}")
     N = ctx.N
     L = ctx.L
     t0 = time.perf_counter()
@@ -284,21 +293,9 @@ def main():
     for w in range(args.warmup):
         step(False)
         log(f"warmup step {w} done")
-    torch.cuda.synchronize()
-    ctx.sync()
-    pk.profile_enable(True)
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        step(True)
-        log(f"timed step {s} done")
-    ctx.sync()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = pk.profile_report()
-    pk.profile_enable(False)
-
     # plain GPU path: the same rotate-and-sum chain, one ciphertext per call
-    # (every key switch its own sequence of launches), on PLAIN_CT ciphertexts
+    # (every key switch its own sequence of launches), on PLAIN_CT ciphertexts;
+    # before the timed steps, so that they end the run (profiles read its last launches)
     ctx.sync()
     t_pl = time.perf_counter()
     for i in range(PLAIN_CT):
@@ -316,6 +313,18 @@ def main():
     ctx.sync()
     plain_rate = PLAIN_CT * (len(CHAIN) + 1) / (time.perf_counter() - t_pl)
     log(f"plain path {plain_rate:.1f} rotations/s")
+    torch.cuda.synchronize()
+    ctx.sync()
+    pk.profile_enable(True)
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(True)
+        log(f"timed step {s} done")
+    ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = pk.profile_report()
+    pk.profile_enable(False)
 
     n_rot = N_CT * (len(CHAIN) + 1)
     value = n_rot * args.steps / elapsed

@@ -287,6 +287,11 @@ void csrmf_server_destroy(csrmf_server* s);
  * Errors: NOMEM, DEVICE. */
 int csrmf_autotune(csrmf_ctx* ctx, int32_t rows, char* report, int32_t cap);
 
+/* Fix the NTT schedule instead of tuning it (process-wide): transform
+ * chunk_rows rows per pair of passes (0: the whole batch at once).  For
+ * repeatable profiles.  Errors: INVAL (negative). */
+int csrmf_set_ntt_schedule(int32_t chunk_rows);
+
 /* ------------------------------------------------------------------------ */
 /* Per-kernel timing (benchmark hook; process-wide).                         */
 /* ------------------------------------------------------------------------ */

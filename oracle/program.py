@@ -177,17 +177,19 @@ def table_vectors(lay, F, n_tab):
 
 
 def rotation_steps(lay):
-    """Every rotation the program uses (left steps)."""
+    """Every rotation the program uses (left steps): the windowed sum
+    (1, 2, .., B/2 and -k') and the block steps 2^j B, j < log2 D, of the
+    baby and giant trees."""
     st = set()
     s = 1
     while s < lay.B:
         st.add(s)
         s *= 2
     st.add(-lay.kp)
-    for beta in range(1, lay.G):
-        st.add(beta * lay.B)
-    for gamma in range(1, lay.D // lay.G):
-        st.add(gamma * lay.G * lay.B)
+    s = 1
+    while s < lay.D:
+        st.add(s * lay.B)
+        s *= 2
     return sorted(st)
 
 
@@ -350,13 +352,75 @@ class Move:
     w: float      # real weight
 
 
+BABY_BLOCK = 64       # babies are built in blocks of this many consecutive steps
+MAX_ACCUMULATORS = 1024   # bound on destinations * D/G inner sums alive at once
+
+
+def _next_pow2(x):
+    p = 1
+    while p < x:
+        p *= 2
+    return p
+
+
+def baby_rotations(n):
+    """Rotations that build babies 1..n-1 of one source: every baby is made by
+    one rotation (inside a block of BABY_BLOCK from a smaller one by a doubling
+    step, or as the next block's base)."""
+    return max(0, n - 1)
+
+
+def giant_rotations(present, width):
+    """Rotations of the pairwise giant-step tree over positions 0..width-1 of
+    which `present` hold a nonempty inner sum."""
+    nodes = set(present)
+    count = 0
+    while width > 1:
+        nxt = set()
+        for t in range(width // 2):
+            if 2 * t + 1 in nodes:
+                count += 1
+            if 2 * t in nodes or 2 * t + 1 in nodes:
+                nxt.add(t)
+        nodes, width = nxt, width // 2
+    return count
+
+
+def choose_G(dests_moves, D):
+    """Baby-step size of one permutation: the power of two G <= D with the
+    fewest rotations (babies: blocks of doubling trees up to the largest baby
+    step a source needs; giants: pairwise trees over D/G positions per
+    destination), among those with len(dests) * D/G <= MAX_ACCUMULATORS;
+    ties go to the smaller G; G = D if no G meets the bound."""
+    best = None
+    G = 1
+    while G <= D:
+        if len(dests_moves) * (D // G) <= MAX_ACCUMULATORS:
+            top = {}
+            gam = {}
+            for d, moves in enumerate(dests_moves):
+                for mv in moves:
+                    gamma, beta = divmod((mv.a - mv.b) % D, G)
+                    top[mv.src] = max(top.get(mv.src, 0), beta)
+                    gam.setdefault(d, set()).add(gamma)
+            cost = sum(baby_rotations(m + 1) for m in top.values())
+            cost += sum(giant_rotations(s, D // G) for s in gam.values())
+            if best is None or cost < best[0]:
+                best = (cost, G)
+        G *= 2
+    return best[1] if best is not None else D
+
+
 def block_permute(be, lay, srcs, dests_moves, self_terms, level, mask_scale, target, unit=False,
-                  exact_weights=False):
+                  exact_weights=False, G=None):
     """dests_moves[d] = list of Move; self_terms[d] = (table ciphertext, c,
     [(block, w_b - c)]) or None.  All sources share level and scale.  unit:
     every move has weight 1 and the accumulator takes the exact scale of the
-    terms.  Returns the rescaled accumulators."""
-    D, G, B = lay.D, lay.G, lay.B
+    terms.  G: baby-step size (None: choose_G).  Returns the rescaled
+    accumulators."""
+    D, B = lay.D, lay.B
+    if G is None:
+        G = choose_G(dests_moves, D)
     src_scale = be.scale(srcs[0]) if srcs else None
     q_acc = float(be.top_prime(level))
     if unit:
@@ -365,21 +429,28 @@ def block_permute(be, lay, srcs, dests_moves, self_terms, level, mask_scale, tar
         acc_scale = src_scale * mask_scale * float(W1)
     else:
         acc_scale = target * q_acc
-    # hoisted baby rotations per source, only the betas that are used
-    need = {}
-    for d, moves in enumerate(dests_moves):
+    # babies Rot_{beta B}(src) for beta up to the largest one a source needs
+    top = {}
+    for moves in dests_moves:
         for mv in moves:
-            beta = ((mv.a - mv.b) % D) % G
-            need.setdefault(mv.src, set()).add(beta)
+            top[mv.src] = max(top.get(mv.src, 0), ((mv.a - mv.b) % D) % G)
     baby = {}
-    for c, betas in need.items():
-        src = be.drop(srcs[c], level)
-        steps = sorted(b * B for b in betas if b)
-        rots = be.hoisted(src, steps) if steps else {}
-        baby[c] = {0: src}
-        for b in betas:
-            if b:
-                baby[c][b] = rots[b * B]
+    for c, m in top.items():
+        n = m + 1
+        b = {}
+        base = be.drop(srcs[c], level)
+        for k in range(0, n, BABY_BLOCK):
+            b[k] = base
+            width = min(BABY_BLOCK, n - k)
+            s = 1
+            while s < width:
+                for j in range(s):
+                    if s + j < width:
+                        b[k + s + j] = be.rotate(b[k + j], s * B)
+                s *= 2
+            if k + BABY_BLOCK < n:
+                base = be.rotate(base, BABY_BLOCK * B)
+        baby[c] = b
     out = []
     for d, moves in enumerate(dests_moves):
         groups = {}
@@ -387,7 +458,7 @@ def block_permute(be, lay, srcs, dests_moves, self_terms, level, mask_scale, tar
             delta = (mv.a - mv.b) % D
             gamma, beta = divmod(delta, G)
             groups.setdefault(gamma, {}).setdefault((mv.src, beta), []).append(mv)
-        acc = None
+        nodes = {}
         for gamma in sorted(groups):
             inner = None
             for (c, beta) in sorted(groups[gamma]):
@@ -397,9 +468,21 @@ def block_permute(be, lay, srcs, dests_moves, self_terms, level, mask_scale, tar
                     terms.append((p, weight(mv.w, src_scale, q_acc, mask_scale, exact_weights, target)))
                 t = be.mask_mul(baby[c][beta], terms, acc_scale, mask_scale)
                 inner = t if inner is None else be.add(inner, t)
-            if gamma:
-                inner = be.rotate(inner, gamma * G * B)
-            acc = inner if acc is None else be.add(acc, inner)
+            nodes[gamma] = inner
+        # giant steps: sum_gamma Rot_{gamma G B}(inner_gamma) as a pairwise tree
+        width, step = D // G, G * B
+        while width > 1:
+            nxt = {}
+            for tt in range(width // 2):
+                left, right = nodes.get(2 * tt), nodes.get(2 * tt + 1)
+                if right is not None:
+                    right = be.rotate(right, step)
+                if left is not None and right is not None:
+                    nxt[tt] = be.add(left, right)
+                elif left is not None or right is not None:
+                    nxt[tt] = left if left is not None else right
+            nodes, width, step = nxt, width // 2, step * 2
+        acc = nodes.get(0)
         st = self_terms[d] if self_terms else None
         if st is not None:
             ct, cst, blocks = st

@@ -95,6 +95,7 @@ _SIGS = {
     "csrmf_mf_handles": [_p, ctypes.c_int32, _u64p, ctypes.c_int32, _i32p],
     "csrmf_mf_stats": [_p, _i32p, _i32p, ctypes.POINTER(ctypes.c_double)],
     "csrmf_autotune": [_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32],
+    "csrmf_set_ntt_schedule": [ctypes.c_int32],
     "csrmf_server_create": [_p, ctypes.c_int32, ctypes.c_int32, _dp, _dp, ctypes.c_double, ctypes.c_int32,
                             ctypes.POINTER(_p)],
     "csrmf_server_submit": [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _dp, ctypes.c_uint32, _u64p],
@@ -467,6 +468,13 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def set_ntt_schedule(chunk_rows):
+    """Fix the NTT schedule (rows per pair of passes; 0 = whole batch) instead of autotuning."""
+    rc = lib.csrmf_set_ntt_schedule(int(chunk_rows))
+    if rc != 0:
+        raise CsrmfError(rc, "bad schedule")
 
 
 def profile_enable(on=True):

@@ -398,6 +398,12 @@ int csrmf_autotune(csrmf_ctx* cx, int32_t rows, char* report, int32_t cap) {
     API_END(c)
 }
 
+int csrmf_set_ntt_schedule(int32_t chunk_rows) {
+    if (chunk_rows < 0) return CSRMF_E_INVAL;
+    csrmf::set_ntt_chunk_rows(chunk_rows);
+    return CSRMF_OK;
+}
+
 int csrmf_profile_enable(int32_t enable) {
     csrmf::prof_enable(enable != 0);
     return CSRMF_OK;

@@ -81,9 +81,17 @@ void free_masks(Context* c, MfState& m);
 // unit: every move has weight 1 (a gather): I0 at the gather scale, target
 // 2^40 and the accumulator declared at the exact scale of its terms;
 // otherwise (a scatter) I0 at the scatter scale and target kTableScale.
+// block_permute: the MF program's schedule (baby-step size per call, baby and
+// giant trees); block_permute_cached: serving's (layout G, cached or hoisted
+// babies, direct giant rotations).
 std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& srcs,
                               const std::vector<std::vector<Move>>& dests, const std::vector<SelfTerm>* selfs,
-                              int level, const BabyCache* cache, bool unit);
+                              int level, bool unit);
+std::vector<Ct> block_permute_cached(Context* c, MfState& m, const std::vector<Ct*>& srcs,
+                                     const std::vector<std::vector<Move>>& dests,
+                                     const std::vector<SelfTerm>* selfs, int level, const BabyCache* cache,
+                                     bool unit);
+int choose_G(const std::vector<std::vector<Move>>& dests, int D);
 std::vector<Ct> dot_products(Context* c, MfState& m, const std::vector<Ct*>& ug, const std::vector<Ct*>& vg,
                              double* sp_out);
 

@@ -319,6 +319,9 @@ struct MacLaunch {
 
 constexpr int kHoistChunk = 128;   // sources whose digits are extended together
 
+// Serving's permutation (tables are read-only, so their baby rotations are
+// cached): baby-step size m.G, babies HRot_{beta B} hoisted (or taken from
+// `cache`), one direct giant rotation per (destination, gamma).
 // srcs: source ciphertexts (viewed at `level`); dests[d]: moves into destination d;
 // selfs[d]: optional self term (constant plus masked corrections).  Schedule: the sources
 // are extended (ModUp) once per chunk; for every baby step beta one batched
@@ -326,9 +329,10 @@ constexpr int kHoistChunk = 128;   // sources whose digits are extended together
 // multi-task launch accumulates every (destination, gamma) inner sum that uses
 // them; then one batched giant rotation per gamma, the self terms, and one
 // batched rescale.  Sums are exact, so this order gives the defined result.
-std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& srcs,
-                              const std::vector<std::vector<Move>>& dests, const std::vector<SelfTerm>* selfs,
-                              int level, const BabyCache* cache, bool unit) {
+std::vector<Ct> block_permute_cached(Context* c, MfState& m, const std::vector<Ct*>& srcs,
+                                     const std::vector<std::vector<Move>>& dests,
+                                     const std::vector<SelfTerm>* selfs, int level, const BabyCache* cache,
+                                     bool unit) {
     const int D = m.D, G = m.G, B = m.B;
     const int nl = level + 1;
     const double s_src = srcs.empty() ? 1.0 : srcs[0]->scale;
@@ -503,6 +507,279 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
     return acc;
 }
 
+// ---------------------------------------------------------------- the MF program's permutation schedule
+constexpr int kBabyBlock = 64;          // babies are built in blocks of this many steps
+constexpr int kMaxAccumulators = 1024;  // bound on destinations * D/G inner sums alive at once
+constexpr int kMaxBabies = 1024;        // bound on baby ciphertexts alive at once (source chunks)
+constexpr int kRotateBatch = 128;       // ciphertexts per batched rotation call (ModUp scratch)
+
+int giant_rotations(std::vector<char> nodes, int width) {
+    int count = 0;
+    while (width > 1) {
+        std::vector<char> nxt(width / 2, 0);
+        for (int t = 0; t < width / 2; ++t) {
+            if (nodes[2 * t + 1]) ++count;
+            nxt[t] = nodes[2 * t] || nodes[2 * t + 1];
+        }
+        nodes.swap(nxt);
+        width /= 2;
+    }
+    return count;
+}
+
+// Baby-step size: the power of two G <= D with the fewest rotations (a source
+// needing baby steps up to beta costs beta rotations; a destination costs the
+// rotations of the pairwise giant tree over its D/G positions), among those
+// with n_dest * D/G <= kMaxAccumulators; ties go to the smaller G; D if none.
+int choose_G(const std::vector<std::vector<Move>>& dests, int D) {
+    long best = -1;
+    int best_G = D;
+    for (int G = 1; G <= D; G *= 2) {
+        const int ng = D / G;
+        if ((long)dests.size() * ng > kMaxAccumulators) continue;
+        std::map<int, int> top;
+        long cost = 0;
+        for (const auto& dv : dests) {
+            if (dv.empty()) continue;
+            std::vector<char> present(ng, 0);
+            for (const Move& x : dv) {
+                const int delta = ((x.a - x.b) % D + D) % D;
+                const int gamma = delta / G, beta = delta % G;
+                auto it = top.find(x.src);
+                if (it == top.end()) top[x.src] = beta;
+                else if (beta > it->second) it->second = beta;
+                present[gamma] = 1;
+            }
+            cost += giant_rotations(present, ng);
+        }
+        for (auto& kv : top) cost += kv.second;
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_G = G;
+        }
+    }
+    return best_G;
+}
+
+static void rotate_chunked(Context* c, std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out) {
+    for (size_t i = 0; i < in.size(); i += kRotateBatch) {
+        const size_t j = std::min(in.size(), i + kRotateBatch);
+        std::vector<Ct*> a(in.begin() + (long)i, in.begin() + (long)j), o(out.begin() + (long)i, out.begin() + (long)j);
+        c->rotate(a, g, o);
+    }
+}
+
+// The MF program's BlockPermute (same order of rotations as the definition):
+// baby-step size G = choose_G; per source, babies Rot_{beta B}(src) for beta
+// up to the largest one it needs, in blocks of kBabyBlock (block base
+// Rot_{k B}(src), inside a block baby k+s+j = Rot_{s B}(baby k+j) for s = 1, 2,
+// 4, ..; next base = Rot_{kBabyBlock B}(base)); inner sums per (destination,
+// gamma) by multi-task masked MAC launches, one per baby step; giant steps as
+// a pairwise tree (level j: node t = node 2t + Rot_{2^j G B}(node 2t+1));
+// then the self terms and one batched rescale.  Rotations of one level are
+// batched; modular sums are exact, so batching does not change the result.
+std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& srcs,
+                              const std::vector<std::vector<Move>>& dests, const std::vector<SelfTerm>* selfs,
+                              int level, bool unit) {
+    const int D = m.D, B = m.B;
+    const int G = choose_G(dests, D);
+    const int n_gamma = D / G;
+    const int nl = level + 1;
+    const double s_src = srcs.empty() ? 1.0 : srcs[0]->scale;
+    const double q_acc = (double)c->moduli[level];
+    const double mask_scale = unit ? kGatherMaskScale : kMaskScale;
+    const double target = unit ? kTargetScale : kTableScale;
+    const uint64_t* mask = unit ? m.maskg : m.mask0;
+    if (!mask) throw Error(CSRMF_E_STATE, "block masks not uploaded");
+    double acc_scale = target * q_acc;
+    if (unit) {
+        for (const auto& dv : dests)
+            for (const Move& x : dv)
+                if (x.w != 1.0) throw Error(CSRMF_E_INVAL, "unit permutation with a weight other than 1");
+        if (selfs) throw Error(CSRMF_E_INVAL, "unit permutation with self terms");
+        acc_scale = s_src * mask_scale * (double)weight_int(1.0, s_src, q_acc, mask_scale, target);
+    }
+    const int n_dest = (int)dests.size();
+    WeightRows wrows(c, nl);
+    auto gal = [&](int p) { return c->galois_for_step(-(int64_t)p * B); };
+
+    // groups keyed by (beta, source, destination, gamma) -> terms (p, W); top baby step per source
+    std::map<std::tuple<int, int, int, int>, std::vector<std::pair<int, int64_t>>> groups;
+    std::map<int, int> top;
+    for (int d = 0; d < n_dest; ++d)
+        for (const Move& x : dests[d]) {
+            const int delta = ((x.a - x.b) % D + D) % D;
+            const int gamma = delta / G, beta = delta % G;
+            groups[{beta, x.src, d, gamma}].push_back(
+                {(x.b + gamma * G) % D, weight_int(x.w, s_src, q_acc, mask_scale, target)});
+            auto it = top.find(x.src);
+            if (it == top.end()) top[x.src] = beta;
+            else if (beta > it->second) it->second = beta;
+        }
+    // leaves of the giant tree (d == nullptr: no moves with that gamma)
+    std::vector<std::vector<Ct>> nodes(n_dest, std::vector<Ct>(n_gamma));
+    std::vector<int> src_list;
+    int max_n = 1;
+    for (auto& kv : top) {
+        src_list.push_back(kv.first);
+        max_n = std::max(max_n, kv.second + 1);
+    }
+    const int chunk = std::max(1, std::min(kHoistChunk, kMaxBabies / std::min(kBabyBlock, max_n)));
+    for (size_t c0 = 0; c0 < src_list.size(); c0 += (size_t)chunk) {
+        const size_t c1 = std::min(src_list.size(), c0 + (size_t)chunk);
+        const int ns = (int)(c1 - c0);
+        std::vector<Ct> base(ns);
+        std::vector<char> base_owned(ns, 0);
+        std::vector<int> n_of(ns);
+        int kmax = 0;
+        for (int i = 0; i < ns; ++i) {
+            base[i] = *srcs[src_list[c0 + i]];
+            base[i].level = level;
+            n_of[i] = top[src_list[c0 + i]] + 1;
+            kmax = std::max(kmax, n_of[i]);
+        }
+        for (int k = 0; k < kmax; k += kBabyBlock) {
+            // babies of this block: bab[i][j] = Rot_{(k+j) B}(source i)
+            std::vector<std::vector<Ct>> bab(ns);
+            std::vector<int> width(ns, 0);
+            for (int i = 0; i < ns; ++i) {
+                width[i] = std::max(0, std::min(kBabyBlock, n_of[i] - k));
+                bab[i].resize(width[i]);
+                if (width[i] > 0) bab[i][0] = base[i];
+            }
+            for (int s = 1; s < kBabyBlock; s *= 2) {
+                std::vector<Ct*> in, out;
+                for (int i = 0; i < ns; ++i)
+                    for (int j = 0; j < s && s + j < width[i]; ++j) {
+                        in.push_back(&bab[i][j]);
+                        out.push_back(&bab[i][s + j]);
+                    }
+                if (in.empty()) break;
+                rotate_chunked(c, in, c->galois_for_step((int64_t)s * B), out);
+            }
+            // one multi-task MAC launch for every baby step of the block: each
+            // (destination, gamma) accumulator is read and written once per block
+            std::map<std::pair<int, int>, std::vector<std::pair<const Ct*, const std::vector<std::pair<int, int64_t>>*>>> tasks;
+            for (int j = 0; j < kBabyBlock && k + j < kmax; ++j) {
+                const int beta = k + j;
+                for (int i = 0; i < ns; ++i) {
+                    if (j >= width[i]) continue;
+                    auto lo = groups.lower_bound({beta, src_list[c0 + i], -1, -1});
+                    for (auto it = lo; it != groups.end() && std::get<0>(it->first) == beta &&
+                                       std::get<1>(it->first) == src_list[c0 + i]; ++it)
+                        tasks[{std::get<2>(it->first), std::get<3>(it->first)}].push_back({&bab[i][j], &it->second});
+                }
+            }
+            if (!tasks.empty()) {
+                MacLaunch ml;
+                for (auto& tk : tasks) {
+                    Ct& tgt = nodes[tk.first.first][tk.first.second];
+                    const bool first = tgt.d == nullptr;
+                    if (first) tgt = c->new_ct(level, acc_scale);
+                    ml.task(tgt.d, first);
+                    for (auto& gr : tk.second) {
+                        ml.group(gr.first->d);
+                        for (auto& tm : *gr.second) ml.term(gal(tm.first), tm.second, wrows);
+                    }
+                }
+                const double bytes = (double)c->N * 8.0 * nl * (2.0 * ml.src.size() + 4.0 * ml.acc.size() + ml.gs.size());
+                ml.run(c, nl, mask, bytes);
+            }
+            // next block's base; then drop this block's babies
+            std::vector<Ct> nb(ns);
+            std::vector<Ct*> bin, bout;
+            for (int i = 0; i < ns; ++i)
+                if (n_of[i] > k + kBabyBlock) {
+                    bin.push_back(&base[i]);
+                    bout.push_back(&nb[i]);
+                }
+            if (!bin.empty()) rotate_chunked(c, bin, c->galois_for_step((int64_t)kBabyBlock * B), bout);
+            for (int i = 0; i < ns; ++i) {
+                for (int jj = 1; jj < width[i]; ++jj) c->pool.put(bab[i][jj].d);
+                if (nb[i].d) {
+                    if (base_owned[i]) c->pool.put(base[i].d);
+                    base[i] = nb[i];
+                    base_owned[i] = 1;
+                }
+            }
+        }
+        for (int i = 0; i < ns; ++i)
+            if (base_owned[i]) c->pool.put(base[i].d);
+    }
+    // giant steps: pairwise tree, one batched rotation and one batched add per level
+    int width = n_gamma;
+    int64_t step = (int64_t)G * B;
+    while (width > 1) {
+        const int half = width / 2;
+        std::vector<std::vector<Ct>> rot(n_dest, std::vector<Ct>(half));
+        std::vector<Ct*> in, out;
+        for (int d = 0; d < n_dest; ++d)
+            for (int t2 = 0; t2 < half; ++t2)
+                if (nodes[d][2 * t2 + 1].d) {
+                    in.push_back(&nodes[d][2 * t2 + 1]);
+                    out.push_back(&rot[d][t2]);
+                }
+        if (!in.empty()) rotate_chunked(c, in, c->galois_for_step(step), out);
+        for (Ct* x : in) c->pool.put(x->d);
+        std::vector<std::vector<Ct>> nxt(n_dest, std::vector<Ct>(half));
+        std::vector<Ct*> a, b, o;
+        for (int d = 0; d < n_dest; ++d)
+            for (int t2 = 0; t2 < half; ++t2) {
+                Ct& left = nodes[d][2 * t2];
+                Ct& right = rot[d][t2];
+                if (left.d && right.d) {
+                    a.push_back(&left);
+                    b.push_back(&right);
+                    o.push_back(&nxt[d][t2]);
+                } else if (left.d) {
+                    nxt[d][t2] = left;
+                } else if (right.d) {
+                    nxt[d][t2] = right;
+                }
+            }
+        if (!a.empty()) {
+            c->add_batch(a, b, o, false);
+            for (Ct* x : a) c->pool.put(x->d);
+            for (Ct* x : b) c->pool.put(x->d);
+        }
+        nodes.swap(nxt);
+        width = half;
+        step *= 2;
+    }
+    std::vector<Ct> acc(n_dest);
+    std::vector<char> acc_init(n_dest, 0);
+    for (int d = 0; d < n_dest; ++d) {
+        if (nodes[d][0].d) {
+            acc[d] = nodes[d][0];
+            acc_init[d] = 1;
+        } else {
+            acc[d] = c->new_ct(level, acc_scale);
+        }
+    }
+    if (selfs) {
+        MacLaunch ml;
+        for (int d = 0; d < n_dest; ++d) {
+            const SelfTerm& st = (*selfs)[d];
+            if (!st.t) continue;
+            const double s_self = st.t->scale;
+            ml.task(acc[d].d, !acc_init[d]);
+            acc_init[d] = 1;
+            ml.group(st.t->d);
+            ml.term(0, weight_int(st.c, s_self, q_acc, 1.0, target), wrows);
+            for (auto& bw : st.corr)
+                ml.term(gal(bw.first), weight_int(bw.second, s_self, q_acc, mask_scale, target), wrows);
+        }
+        const double bytes = (double)c->N * 8.0 * nl * (6.0 * ml.acc.size() + (ml.gs.size() - ml.acc.size()));
+        ml.run(c, nl, mask, bytes);
+    }
+    for (int d = 0; d < n_dest; ++d)
+        if (!acc_init[d]) throw Error(CSRMF_E_INVAL, "block permutation with an empty destination");
+    for (auto& x : acc) x.scale = acc_scale;
+    std::vector<Ct*> pacc = ptrs(acc);
+    c->rescale(pacc);
+    return acc;
+}
+
 std::vector<Ct> scatter(Context* c, MfState& m, const std::vector<Ct*>& Gs, const std::vector<uint64_t>& tabs,
                         bool users, double a_t, int level) {
     const double lam = c->prm.lambda;
@@ -534,7 +811,7 @@ std::vector<Ct> scatter(Context* c, MfState& m, const std::vector<Ct*>& Gs, cons
         for (auto& bw : ws)
             if (bw.second != selfs[d].c) selfs[d].corr.push_back({bw.first, bw.second - selfs[d].c});
     }
-    return block_permute(c, m, Gs, moves, &selfs, level, nullptr, false);
+    return block_permute(c, m, Gs, moves, &selfs, level, false);
 }
 
 std::vector<Ct> gather(Context* c, MfState& m, const std::vector<uint64_t>& tabs, bool users) {
@@ -544,7 +821,7 @@ std::vector<Ct> gather(Context* c, MfState& m, const std::vector<uint64_t>& tabs
         moves[m.ct_of[r]].push_back({e / m.D, e % m.D, m.blk_of[r], 1.0});
     }
     std::vector<Ct*> srcs = cts_of(c, tabs);
-    return block_permute(c, m, srcs, moves, nullptr, srcs[0]->level, nullptr, true);
+    return block_permute(c, m, srcs, moves, nullptr, srcs[0]->level, true);
 }
 
 std::vector<uint64_t> put_all(Context* c, std::vector<Ct>& v) {
@@ -714,13 +991,12 @@ using csrmf::MfState;
 static void install_layout(Context* c, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr, const int32_t* col_idx) {
     if (!c->have_keys) throw Error(CSRMF_E_STATE, "keygen first");
     MfState* m = csrmf::mfp::make_layout(c, n_rows, n_cols, row_ptr, col_idx);
-    // rotation keys the program uses: windowed sum 1, 2, .., B/2 and -k'; baby
-    // steps beta*B (beta < G); giant steps gamma*G*B (gamma < D/G)
+    // rotation keys the program uses: windowed sum 1, 2, .., B/2 and -k'; the
+    // block steps 2^j B (j < log2 D) of the baby and giant trees
     std::vector<int32_t> steps;
     for (int s = 1; s < m->B; s *= 2) steps.push_back(s);
     steps.push_back(-m->kp);
-    for (int b = 1; b < m->G; ++b) steps.push_back(b * m->B);
-    for (int g = 1; g < m->D / m->G; ++g) steps.push_back(g * m->G * m->B);
+    for (int s = 1; s < m->D; s *= 2) steps.push_back(s * m->B);
     try {
         c->keygen(steps.data(), (int)steps.size(), false);
     } catch (...) {

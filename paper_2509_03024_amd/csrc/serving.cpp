@@ -202,8 +202,8 @@ void Server::process(std::vector<ServeRequest*>& batch) {
     std::vector<Ct*> us, vs;
     for (uint64_t h : Utab) us.push_back(&c->get(h));
     for (uint64_t h : Vtab) vs.push_back(&c->get(h));
-    std::vector<Ct> Ug = mfp::block_permute(c, lay, us, mu_, nullptr, L, &ucache, true);
-    std::vector<Ct> Vg = mfp::block_permute(c, lay, vs, mv_, nullptr, L, &vcache, true);
+    std::vector<Ct> Ug = mfp::block_permute_cached(c, lay, us, mu_, nullptr, L, &ucache, true);
+    std::vector<Ct> Vg = mfp::block_permute_cached(c, lay, vs, mv_, nullptr, L, &vcache, true);
     std::vector<Ct*> pu = mfp::ptrs(Ug), pv = mfp::ptrs(Vg);
     double sp = 0;
     std::vector<Ct> S = mfp::dot_products(c, lay, pu, pv, &sp);

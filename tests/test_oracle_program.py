@@ -186,3 +186,48 @@ def test_mask_reading_within_1e4_at_mf100k_shape():
     Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, LR, LAM, EP, rule="R2")
     assert np.max(np.abs(U - Uf)) < 1e-5 and np.max(np.abs(V - Vf)) < 1e-5
     assert np.max(np.abs(rhat - rf)) < 1e-5
+
+
+@pytest.mark.parametrize("G", [1, 2, 16, 128, 256, None])
+def test_block_permute_schedule_equals_direct_block_moves(G):
+    """BlockPermute's rotation schedule (baby blocks of doubling trees, the
+    pairwise giant tree, any baby-step size G including the chosen one) on
+    plain slot vectors equals the block moves applied directly: destination
+    block b gets the sum of w * (first k slots of source block a)."""
+    rng = np.random.default_rng(11)
+    N, k = 4096, 3
+    lay = program.make_layout(N, k, 1, 1, np.array([0, 0]), np.array([], np.int64))
+    D, B = lay.D, lay.B
+    assert D == 256 and B == 8
+    n_src, n_dst = 3, 4
+    be = program.ClearBackend(N, [2 ** 40 + 7] * 8, B, k)
+    srcs = [be.wrap(rng.normal(size=N // 2), 7, 2.0 ** 40) for _ in range(n_src)]
+    moves = [[] for _ in range(n_dst)]
+    want = np.zeros((n_dst, N // 2))
+    for _ in range(300):
+        c, a, b, d = int(rng.integers(n_src)), int(rng.integers(D)), int(rng.integers(D)), int(rng.integers(n_dst))
+        w = float(rng.normal())
+        moves[d].append(program.Move(c, a, b, w))
+        want[d, b * B: b * B + k] += w * srcs[c].z[a * B: a * B + k]
+    out = program.block_permute(be, lay, srcs, moves, None, 7, program.S_I, program.S_TAB,
+                                exact_weights=True, G=G)
+    for d in range(n_dst):
+        assert np.max(np.abs(out[d].z - want[d])) < 1e-12, (G, d)
+
+
+def test_choose_G_counts():
+    """The schedule cost model on hand-made move sets: a gather-like call (one
+    source, many destinations) prefers large G, a scatter-like call (many
+    sources, one destination) small G; rotation counts of the trees."""
+    assert program.baby_rotations(1) == 0 and program.baby_rotations(4) == 3
+    assert program.baby_rotations(64) == 63 and program.baby_rotations(65) == 64
+    assert program.baby_rotations(130) == 63 + 1 + 63 + 1 + 1
+    assert program.giant_rotations({0, 1, 2, 3}, 4) == 3
+    assert program.giant_rotations({0}, 8) == 0 and program.giant_rotations({7}, 8) == 3
+    D = 64
+    gather = [[program.Move(0, 0, b, 1.0) for b in range(D)] for _ in range(8)]
+    scatter = [[program.Move(c, b, 0, 1.0) for c in range(32) for b in range(D)]]
+    # gather: G=16 costs 15 + 8*3 = 39, G=32 costs 31 + 8*1 = 39 (tie -> smaller), G=64 63
+    assert program.choose_G(gather, D) == 16
+    # scatter: G=1 costs 0 + 63, G=2 costs 32 + 31 (tie -> smaller), G=4 costs 96 + 15
+    assert program.choose_G(scatter, D) == 1
