@@ -41,21 +41,28 @@ def crt(rows, moduli):
     return acc % Q
 
 
-def basis_convert(x, src, dst):
-    """Conv_{src -> dst}(x) for x of shape [len(src), N]; returns [len(dst), N]."""
+def basis_convert(x, src, dst, centered=False):
+    """Conv_{src -> dst}(x) = sum_i y_i * (B/b_i) mod c with
+    y_i = [x_i * (B/b_i)^-1]_{b_i}, for x of shape [len(src), N]; returns
+    [len(dst), N].  centered: y_i taken in (-b_i/2, b_i/2] (y_i - b_i when
+    2 y_i > b_i), so the result is x's centred representative mod B plus a
+    multiple e*B with |e| <= len(src)/2 instead of x + e*B, 0 <= e < len(src)."""
     B = prod(src)
     ys = []
     for i, b in enumerate(src):
         b = int(b)
         bhat = B // b
-        ys.append(mulmod(x[i], np.uint64(pow(bhat % b, -1, b)), b))
+        y = mulmod(x[i], np.uint64(pow(bhat % b, -1, b)), b).astype(object)
+        if centered:
+            y = np.array([int(v) - b if 2 * int(v) > b else int(v) for v in y], dtype=object)
+        ys.append(y)
     out = []
     for c in dst:
         c = int(c)
         acc = np.zeros(x.shape[-1], dtype=np.uint64)
         for i, b in enumerate(src):
             bhat_c = (B // int(b)) % c
-            y = ys[i] % np.uint64(c)
+            y = np.array([int(v) % c for v in ys[i]], dtype=np.uint64)
             acc = addmod(acc, mulmod(y, np.uint64(bhat_c), c), c)
         out.append(acc)
     return np.stack(out)
@@ -65,12 +72,15 @@ def mod_up(d, qmods, digit, pmods):
     """Extend the digit limbs `digit` (indices into qmods) of d to all of Q_l u P.
 
     d has shape [l+1, N] (limbs q_0..q_l); the result has shape [l+1+alpha, N]
-    in the order q_0..q_l, p_0..p_{alpha-1}.  Limbs inside the digit are copied.
+    in the order q_0..q_l, p_0..p_{alpha-1}.  Limbs inside the digit are copied;
+    the others come from the centred conversion: the digit is taken as its
+    centred representative mod Q_D (up to a small multiple of Q_D), so its
+    mean is 0 and key-switching adds no key-dependent bias.
     """
     all_mods = list(qmods) + list(pmods)
     src = [qmods[i] for i in digit]
     tgt_idx = [t for t in range(len(all_mods)) if t not in digit]
-    conv = basis_convert(d[digit], src, [all_mods[t] for t in tgt_idx])
+    conv = basis_convert(d[digit], src, [all_mods[t] for t in tgt_idx], centered=True)
     out = np.empty((len(all_mods), d.shape[-1]), dtype=np.uint64)
     for i in digit:
         out[i] = d[i]

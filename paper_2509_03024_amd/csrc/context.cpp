@@ -64,6 +64,23 @@ void Pool::release_all() {
     in_use_ = 0;
 }
 
+// Batched calls process at most this many ciphertexts per launch sequence, so
+// that their scratch (ModUp digits: n_digits * (l+1+alpha) limbs per
+// ciphertext, ~140 MB at N = 2^16 and 28 limbs) stays bounded; each
+// ciphertext's arithmetic is independent of the batch it is in.
+constexpr int kMaxBatch = 128;
+
+template <typename F>
+static bool split_batch(size_t n, F&& f) {
+    if (n <= (size_t)kMaxBatch) return false;
+    for (size_t i = 0; i < n; i += kMaxBatch) f(i, std::min(n, i + kMaxBatch));
+    return true;
+}
+
+static std::vector<Ct*> slice(const std::vector<Ct*>& v, size_t i, size_t j) {
+    return std::vector<Ct*>(v.begin() + (long)i, v.begin() + (long)j);
+}
+
 // ------------------------------------------------------------------ staging ring
 hipEvent_t HipMarkers::record() {
     hipEvent_t e;
@@ -510,6 +527,16 @@ void Context::make_switching_key(Key& key, const uint64_t* sprime, uint32_t key_
 // ------------------------------------------------------------------ encrypt
 void Context::encrypt_int_batch(const int64_t* m, int count, int level, double scale, std::vector<Ct>& out,
                                 const uint32_t* serials) {
+    if (count > kMaxBatch) {   // in order, so running serial numbers are unchanged
+        out.clear();
+        for (int i = 0; i < count; i += kMaxBatch) {
+            std::vector<Ct> part;
+            encrypt_int_batch(m + (size_t)i * N, std::min(kMaxBatch, count - i), level, scale, part,
+                              serials ? serials + i : nullptr);
+            out.insert(out.end(), part.begin(), part.end());
+        }
+        return;
+    }
     if (!have_keys) throw Error(CSRMF_E_STATE, "keygen first");
     if (level < 0 || level > L) throw Error(CSRMF_E_INVAL, "level out of range");
     // signed inputs: [count][4][N] = v, e0, e1, m
@@ -808,7 +835,7 @@ void Context::ks_modup(const RowMap& d_in, int level, int B, uint64_t* ext, uint
         dst.batch_stride = (int64_t)nd * nr * N;
         for (int t = 0; t < nr; ++t)
             if (!(t >= dc.lo && t < dc.hi)) dst.push(jj * nr + t, gmod_ext(level, t));
-        launch_basis_convert(tabs, dst, src, dc.yc, dc.cc, stream);
+        launch_basis_convert(tabs, dst, src, dc.yc, dc.cc, true, stream);   // centred digits
         launch_ntt(tabs, dst, false, stream);
         cpy_src = d_in;
         cpy_src.n = 0;
@@ -861,7 +888,7 @@ void Context::ks_moddown(uint64_t* u, int level, int B, const RowMap& out, const
     mcv.batch = 2 * B;
     mcv.batch_stride = (int64_t)nl * N;
     for (int i = 0; i < nl; ++i) mcv.push(i, i);
-    launch_basis_convert(tabs, mcv, mp, c.md_y, c.md_c, stream);
+    launch_basis_convert(tabs, mcv, mp, c.md_y, c.md_c, false, stream);
     launch_ntt(tabs, mcv, false, stream);
     RowMap mu;
     mu.base = u;
@@ -879,6 +906,11 @@ void Context::ks_moddown(uint64_t* u, int level, int B, const RowMap& out, const
 }
 
 void Context::mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, std::vector<Ct*>& out) {
+    if (split_batch(a.size(), [&](size_t i, size_t j) {
+            std::vector<Ct*> sa = slice(a, i, j), sb = slice(b, i, j), so = slice(out, i, j);
+            mul_relin(sa, sb, so);
+        }))
+        return;
     const int B = (int)a.size();
     if (B == 0) return;
     if (!have_keys) throw Error(CSRMF_E_STATE, "keygen first");
@@ -906,6 +938,7 @@ void Context::mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, st
 }
 
 void Context::rescale(const std::vector<Ct*>& v) {
+    if (split_batch(v.size(), [&](size_t i, size_t j) { rescale(slice(v, i, j)); })) return;
     const int B = (int)v.size();
     if (B == 0) return;
     const int l = v[0]->level;
@@ -947,6 +980,11 @@ void Context::rescale(const std::vector<Ct*>& v) {
 }
 
 void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out) {
+    if (split_batch(in.size(), [&](size_t i, size_t j) {
+            std::vector<Ct*> so = slice(out, i, j);
+            rotate(slice(in, i, j), g, so);
+        }))
+        return;
     const int B = (int)in.size();
     if (B == 0) return;
     const Key& key = key_for(g);

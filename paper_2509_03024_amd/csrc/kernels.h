@@ -89,8 +89,10 @@ void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, cons
 // src map: n_src (1..16) rows; dst map: n_tgt rows.  Device constants:
 //   yc[2i], yc[2i+1]            = Qhat_i^-1 mod src_i and its shoup
 //   cc[i*n_tgt+t]               = Qhat_i * 2^64 mod tgt_t (Montgomery form)
+// centered: y_i taken in (-q_i/2, q_i/2] (ModUp of key-switching digits), so
+// the result is the centred representative mod Q plus a small multiple of Q.
 void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src,
-                          const uint64_t* yc, const uint64_t* cc, hipStream_t s);
+                          const uint64_t* yc, const uint64_t* cc, bool centered, hipStream_t s);
 
 // Key-switching inner product over the extended basis Q_l u P (n_rows = l+1+alpha
 // rows): u0[t] = sum_j mont(ext_j[t][perm(k)], kb_j[row(t)]), u1 likewise with

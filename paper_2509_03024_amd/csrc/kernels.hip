@@ -433,7 +433,10 @@ __global__ void __launch_bounds__(kThreads) k_automorphism(DevTables t, uint32_t
 // (Shoup, canonical), then for every target t the products y_i * (Qhat_i 2^64
 // mod t) are summed exactly in 128 bits and reduced once by Montgomery REDC:
 // sum < NS * 2^60 * t <= t * 2^64, so REDC returns sum * 2^-64 mod t in [0, 2t).
-template <int NS>
+// kCentered (ModUp): y_s is taken in (-q_s/2, q_s/2]: a term with 2 y_s > q_s
+// contributes (q_s - y_s) * (t - c) = -(q_s - y_s) * c (mod t), and every
+// term stays below 2^59 * t.
+template <int NS, bool kCentered>
 __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap dst, RowMap src, const uint64_t* yc,
                                                             const uint64_t* cc) {
     const int logN = t.logN;
@@ -444,11 +447,15 @@ __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap 
     const int i = chunk * kThreads + threadIdx.x;
     const int nt = dst.n;
     uint64_t y[NS];
+    bool neg[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         int mod;
         const uint64_t* p = map_row(src, b, s, logN, mod);
-        y[s] = mul_shoup(p[i], yc[2 * s], yc[2 * s + 1], t.mods[mod].q);
+        const uint64_t qs = t.mods[mod].q;
+        const uint64_t v = mul_shoup(p[i], yc[2 * s], yc[2 * s + 1], qs);
+        neg[s] = kCentered && 2 * v > qs;
+        y[s] = neg[s] ? qs - v : v;
     }
     for (int tt = 0; tt < nt; ++tt) {
         int mod;
@@ -457,7 +464,8 @@ __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap 
         uint64_t lo = 0, hi = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const uint64_t c = cc[s * nt + tt];
+            const uint64_t c0 = cc[s * nt + tt];
+            const uint64_t c = (neg[s] && c0) ? md.q - c0 : c0;
             const uint64_t pl = y[s] * c;
             const uint64_t ph = mulhi64(y[s], c);
             lo += pl;
@@ -668,32 +676,34 @@ void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, cons
 
 template <int NS>
 static void launch_bc(const DevTables& t, const RowMap& dst, const RowMap& src, const uint64_t* yc,
-                      const uint64_t* cc, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_basis_convert<NS>, dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc);
+                      const uint64_t* cc, bool centered, int blocks, hipStream_t s) {
+    if (centered) hipLaunchKernelGGL((k_basis_convert<NS, true>), dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc);
+    else hipLaunchKernelGGL((k_basis_convert<NS, false>), dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc);
 }
 
 void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src, const uint64_t* yc,
-                          const uint64_t* cc, hipStream_t s) {
+                          const uint64_t* cc, bool centered, hipStream_t s) {
     if (!dst.n || !src.n) return;
     const int blocks = dst.batch * ((1 << t.logN) / kThreads);
     ProfScope ps_("k_basis_convert", s, NB(dst.batch) * (src.n + dst.n));
+    const bool ce = centered;
     switch (src.n) {
-        case 1: launch_bc<1>(t, dst, src, yc, cc, blocks, s); break;
-        case 2: launch_bc<2>(t, dst, src, yc, cc, blocks, s); break;
-        case 3: launch_bc<3>(t, dst, src, yc, cc, blocks, s); break;
-        case 4: launch_bc<4>(t, dst, src, yc, cc, blocks, s); break;
-        case 5: launch_bc<5>(t, dst, src, yc, cc, blocks, s); break;
-        case 6: launch_bc<6>(t, dst, src, yc, cc, blocks, s); break;
-        case 7: launch_bc<7>(t, dst, src, yc, cc, blocks, s); break;
-        case 8: launch_bc<8>(t, dst, src, yc, cc, blocks, s); break;
-        case 9: launch_bc<9>(t, dst, src, yc, cc, blocks, s); break;
-        case 10: launch_bc<10>(t, dst, src, yc, cc, blocks, s); break;
-        case 11: launch_bc<11>(t, dst, src, yc, cc, blocks, s); break;
-        case 12: launch_bc<12>(t, dst, src, yc, cc, blocks, s); break;
-        case 13: launch_bc<13>(t, dst, src, yc, cc, blocks, s); break;
-        case 14: launch_bc<14>(t, dst, src, yc, cc, blocks, s); break;
-        case 15: launch_bc<15>(t, dst, src, yc, cc, blocks, s); break;
-        case 16: launch_bc<16>(t, dst, src, yc, cc, blocks, s); break;
+        case 1: launch_bc<1>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 2: launch_bc<2>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 3: launch_bc<3>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 4: launch_bc<4>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 5: launch_bc<5>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 6: launch_bc<6>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 7: launch_bc<7>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 8: launch_bc<8>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 9: launch_bc<9>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 10: launch_bc<10>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 11: launch_bc<11>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 12: launch_bc<12>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 13: launch_bc<13>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 14: launch_bc<14>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 15: launch_bc<15>(t, dst, src, yc, cc, ce, blocks, s); break;
+        case 16: launch_bc<16>(t, dst, src, yc, cc, ce, blocks, s); break;
         default: break;   // digit sizes are validated at context creation
     }
 }

@@ -250,5 +250,32 @@ def test_mod_up_digit():
     mods = qm + prm.p
     for n, x in enumerate(xs):
         xd = x % QD
-        cands = [[(xd + e * QD) % m for m in mods] for e in range(len(D))]
+        xc = xd - QD if 2 * xd > QD else xd          # centred representative
+        cands = [[(xc + e * QD) % m for m in mods] for e in range(-(len(D) // 2) - 1, len(D) // 2 + 2)]
         assert [int(ext[i][n]) for i in range(len(mods))] in cands
+
+
+def test_mod_up_extension_is_centred():
+    """The extended digit, read as an integer through the CRT over all limbs,
+    is x_c + e*Q_D with x_c the centred representative of the digit and
+    |e| <= |D|/2 + 1; over many coefficients its mean is ~0 relative to Q_D
+    (the uncentred conversion averages Q_D/2 or more)."""
+    prm = params.config_tiny()
+    qm = prm.q
+    xs, rows = _rand_rns(qm, 400, 9)
+    D = [0, 1]
+    ext = rns.mod_up(rows, qm, D, prm.p)
+    mods = qm + prm.p
+    M = rns.prod(mods)
+    QD = qm[0] * qm[1]
+    rec = rns.crt(ext, mods)
+    vals = []
+    for n, x in enumerate(xs):
+        v = int(rec[n])
+        v = v - M if v > M // 2 else v
+        xd = x % QD
+        xc = xd - QD if 2 * xd > QD else xd
+        e, r = divmod(v - xc, QD)
+        assert r == 0 and abs(e) <= len(D) // 2 + 1
+        vals.append(v / QD)
+    assert abs(sum(vals) / len(vals)) < 0.15
