@@ -26,10 +26,12 @@ PLAIN_CT = 8
 LOGN = 16
 CHAIN = [1 << a for a in range(15)]
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of a kernel in the timed step, from rocprofv3 FETCH_SIZE +
-# WRITE_SIZE counters scaled by a plain copy of known size (see profiles/); only
-# valid for the kernel code the counters were taken on.
-TRAFFIC = {}
+# HBM bytes per launch of a kernel in the timed step (average over the step's
+# launches), from rocprofv3 FETCH_SIZE (x2.0) + WRITE_SIZE (x1.0) counters, the
+# factors read off a 512 MiB copy, at the 512-row NTT schedule the autotuner
+# picks here (profiles/ks_kernel_batch_n16_hbm_counters.md); only valid for the
+# kernel code the counters were taken on.
+TRAFFIC = {"k_ntt_pass<rows,fwd>": 482.1e6}
 
 
 def parse():
@@ -360,6 +362,8 @@ def main():
                            "batched_rotation_phase_speedup": round(n_rot * args.steps / phase["rotations"] / plain_rate, 2)},
         "roofline": {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(name),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 counters)",
+                     "alg_bytes_per_launch": round(total_bytes / launches),
                      "avg_launch_us": round(1e3 * avg_ms, 2), "launches_in_timed_steps": launches},
         "kernels": kernel_table,
     }
