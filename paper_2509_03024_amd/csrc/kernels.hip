@@ -17,6 +17,7 @@ namespace csrmf {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (separate L2 each)
 constexpr int kEwPerThread = 2;
 
 __device__ __forceinline__ uint64_t* map_row(const RowMap& m, int b, int k, int logN, int& mod) {
@@ -569,14 +570,23 @@ __global__ void __launch_bounds__(kThreads) k_rescale_combine(DevTables t, RowMa
 // [term_begin[g], term_begin[g+1]).  If first[t] != 0 the accumulator starts at 0.
 
 
+// Grid order (XCD-aware): work-groups are dispatched to the 8 XCDs round
+// robin, so block b runs on XCD b % 8.  A tile (limb k, chunk of elements)
+// is given to one XCD and all tasks of that tile run there back to back:
+//   xcd = b % 8,  task = (b / 8) % n_tasks,  tile = ((b / 8) / n_tasks) * 8 + xcd,
+// so the tile of every source (babies read by many tasks) stays in that XCD's
+// L2 while its tasks run, instead of being fetched once per task.
 __global__ void __launch_bounds__(kThreads) k_mask_mac_tasks(DevTables t, MaskTasks T, const uint64_t* i0) {
     const int logN = t.logN;
     const int N = 1 << logN;
     const int chunks = N / (kThreads * kEwPerThread);
-    const int chunk = blockIdx.x % chunks;
-    const int r = blockIdx.x / chunks;
-    const int k = r % T.n_limbs;             // limb
-    const int task = r / T.n_limbs;
+    const int xcd = blockIdx.x & (kXcds - 1);
+    const int j = blockIdx.x / kXcds;
+    const int task = j % T.n_tasks;
+    const int tile = (j / T.n_tasks) * kXcds + xcd;
+    if (tile >= T.n_limbs * chunks) return;
+    const int k = tile / chunks;             // limb
+    const int chunk = tile % chunks;
     const int base_i = chunk * kThreads * kEwPerThread + threadIdx.x;
     const Modulus md = t.mods[k];
     const uint64_t* row = i0 + ((size_t)k << logN);
@@ -724,7 +734,8 @@ void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap&
 void launch_mask_mac_tasks(const DevTables& t, const MaskTasks& T, const uint64_t* i0, double bytes, hipStream_t s) {
     if (T.n_tasks <= 0) return;
     ProfScope ps_("k_mask_mac_tasks", s, bytes);
-    const int blocks = T.n_tasks * T.n_limbs * ((1 << t.logN) / (kThreads * kEwPerThread));
+    const int tiles = T.n_limbs * ((1 << t.logN) / (kThreads * kEwPerThread));
+    const int blocks = kXcds * T.n_tasks * ((tiles + kXcds - 1) / kXcds);
     hipLaunchKernelGGL(k_mask_mac_tasks, dim3(blocks), dim3(kThreads), 0, s, t, T, i0);
 }
 

@@ -935,6 +935,9 @@ void run_epoch(Context* c, MfState& m) {
     std::vector<Ct> GU = hmult_all(c, pe, pvgd);
     std::vector<Ct> GV = hmult_all(c, pe, pugd);
     release(c, E);
+    // the gathered factors are not needed any more (the next epoch gathers anew)
+    free_handles(c, m.Ug);
+    free_handles(c, m.Vg);
     const int glv = GU[0].level;
     std::vector<Ct*> pgu = ptrs(GU), pgv = ptrs(GV);
     std::vector<Ct> nu = scatter(c, m, pgu, m.Utab, true, a_t, glv);
@@ -947,8 +950,6 @@ void run_epoch(Context* c, MfState& m) {
     m.Vtab = put_all(c, nv);
     free_handles(c, m.Sdot);
     m.Sdot = put_all(c, S);
-    free_handles(c, m.Ug);
-    free_handles(c, m.Vg);
     m.epochs_done++;
 }
 
