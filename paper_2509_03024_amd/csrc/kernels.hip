@@ -18,6 +18,12 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (separate L2 each)
+// Elements per thread of the masked MAC.  A tile is kThreads * kMacPerThread
+// elements of one limb; all tasks of a tile run on one XCD, and the tiles of
+// the launch's sources (babies: up to ~500 ciphertexts x 16 B per element)
+// must stay within that XCD's 4 MB L2, which 2 allows (8 was measured 16 %
+// slower, 4x larger tiles).
+constexpr int kMacPerThread = 2;
 constexpr int kEwPerThread = 2;
 
 __device__ __forceinline__ uint64_t* map_row(const RowMap& m, int b, int k, int logN, int& mod) {
@@ -447,6 +453,11 @@ __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap 
     const int b = blockIdx.x / chunks;
     const int i = chunk * kThreads + threadIdx.x;
     const int nt = dst.n;
+    // the constants are the same for every thread: stage them in LDS once, so
+    // the NS * nt multiply-accumulates below do not wait on global loads
+    __shared__ uint64_t s_cc[16 * kMaxMapRows];
+    for (int idx = threadIdx.x; idx < NS * nt; idx += kThreads) s_cc[idx] = cc[idx];
+    __syncthreads();
     uint64_t y[NS];
     bool neg[NS];
 #pragma unroll
@@ -465,7 +476,7 @@ __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap 
         uint64_t lo = 0, hi = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const uint64_t c0 = cc[s * nt + tt];
+            const uint64_t c0 = s_cc[s * nt + tt];
             const uint64_t c = (neg[s] && c0) ? md.q - c0 : c0;
             const uint64_t pl = y[s] * c;
             const uint64_t ph = mulhi64(y[s], c);
@@ -579,7 +590,7 @@ __global__ void __launch_bounds__(kThreads) k_rescale_combine(DevTables t, RowMa
 __global__ void __launch_bounds__(kThreads) k_mask_mac_tasks(DevTables t, MaskTasks T, const uint64_t* i0) {
     const int logN = t.logN;
     const int N = 1 << logN;
-    const int chunks = N / (kThreads * kEwPerThread);
+    const int chunks = N / (kThreads * kMacPerThread);
     const int xcd = blockIdx.x & (kXcds - 1);
     const int j = blockIdx.x / kXcds;
     const int task = j % T.n_tasks;
@@ -587,32 +598,56 @@ __global__ void __launch_bounds__(kThreads) k_mask_mac_tasks(DevTables t, MaskTa
     if (tile >= T.n_limbs * chunks) return;
     const int k = tile / chunks;             // limb
     const int chunk = tile % chunks;
-    const int base_i = chunk * kThreads * kEwPerThread + threadIdx.x;
+    // each thread owns kMacPerThread elements (stride kThreads, coalesced per
+    // step), so a group's and a term's metadata is loaded once for all of them
+    const int base_i = chunk * kThreads * kMacPerThread + threadIdx.x;
     const Modulus md = t.mods[k];
     const uint64_t* row = i0 + ((size_t)k << logN);
     uint64_t* pa = T.acc[task] + ((size_t)k << logN);
     const int g0 = T.grp_begin[task], g1 = T.grp_begin[task + 1];
-    for (int uu = 0; uu < kEwPerThread; ++uu) {
-        const int i = base_i + uu * kThreads;
-        uint64_t a0 = 0, a1 = 0;
-        if (!T.first[task]) {
-            a0 = pa[i];
-            a1 = pa[i + T.poly_stride];
+    uint64_t a0[kMacPerThread], a1[kMacPerThread];
+    if (T.first[task]) {
+#pragma unroll
+        for (int u = 0; u < kMacPerThread; ++u) a0[u] = a1[u] = 0;
+    } else {
+#pragma unroll
+        for (int u = 0; u < kMacPerThread; ++u) {
+            a0[u] = pa[base_i + u * kThreads];
+            a1[u] = pa[base_i + u * kThreads + T.poly_stride];
         }
-        for (int g = g0; g < g1; ++g) {
-            uint64_t M = 0;
-            for (int m = T.term_begin[g]; m < T.term_begin[g + 1]; ++m) {
-                const uint64_t* c = T.cw + 2 * ((size_t)T.wi[m] * T.cw_stride + k);
-                const uint32_t g = T.gs[m];
-                // Galois element 0 marks a constant term (the plaintext W, no mask)
-                M = add_mod(M, g ? mul_shoup(row[galois_perm((uint32_t)i, g, logN)], c[0], c[1], md.q) : c[0], md.q);
+    }
+    for (int g = g0; g < g1; ++g) {
+        uint64_t M[kMacPerThread];
+#pragma unroll
+        for (int u = 0; u < kMacPerThread; ++u) M[u] = 0;
+        const int m1 = T.term_begin[g + 1];
+        for (int m = T.term_begin[g]; m < m1; ++m) {
+            const uint64_t* c = T.cw + 2 * ((size_t)T.wi[m] * T.cw_stride + k);
+            const uint64_t w = c[0], ws = c[1];
+            const uint32_t gm = T.gs[m];
+            // Galois element 0 marks a constant term (the plaintext W, no mask)
+            if (gm) {
+#pragma unroll
+                for (int u = 0; u < kMacPerThread; ++u)
+                    M[u] = add_mod(M[u], mul_shoup(row[galois_perm((uint32_t)(base_i + u * kThreads), gm, logN)], w, ws,
+                                                   md.q), md.q);
+            } else {
+#pragma unroll
+                for (int u = 0; u < kMacPerThread; ++u) M[u] = add_mod(M[u], w, md.q);
             }
-            const uint64_t* ps = T.src[g] + ((size_t)k << logN);
-            a0 = add_mod(a0, mul_mont(ps[i], M, md.q, md.qneg_inv), md.q);
-            a1 = add_mod(a1, mul_mont(ps[i + T.poly_stride], M, md.q, md.qneg_inv), md.q);
         }
-        pa[i] = a0;
-        pa[i + T.poly_stride] = a1;
+        const uint64_t* ps = T.src[g] + ((size_t)k << logN);
+#pragma unroll
+        for (int u = 0; u < kMacPerThread; ++u) {
+            const int i = base_i + u * kThreads;
+            a0[u] = add_mod(a0[u], mul_mont(ps[i], M[u], md.q, md.qneg_inv), md.q);
+            a1[u] = add_mod(a1[u], mul_mont(ps[i + T.poly_stride], M[u], md.q, md.qneg_inv), md.q);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kMacPerThread; ++u) {
+        pa[base_i + u * kThreads] = a0[u];
+        pa[base_i + u * kThreads + T.poly_stride] = a1[u];
     }
 }
 
@@ -734,7 +769,7 @@ void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap&
 void launch_mask_mac_tasks(const DevTables& t, const MaskTasks& T, const uint64_t* i0, double bytes, hipStream_t s) {
     if (T.n_tasks <= 0) return;
     ProfScope ps_("k_mask_mac_tasks", s, bytes);
-    const int tiles = T.n_limbs * ((1 << t.logN) / (kThreads * kEwPerThread));
+    const int tiles = T.n_limbs * ((1 << t.logN) / (kThreads * kMacPerThread));
     const int blocks = kXcds * T.n_tasks * ((tiles + kXcds - 1) / kXcds);
     hipLaunchKernelGGL(k_mask_mac_tasks, dim3(blocks), dim3(kThreads), 0, s, t, T, i0);
 }
