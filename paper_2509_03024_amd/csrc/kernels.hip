@@ -70,7 +70,7 @@ __device__ __forceinline__ uint32_t galois_perm(uint32_t k, uint32_t g, int logN
 constexpr int kNttThreads = 512;
 constexpr int kNttPerThread = 8;
 constexpr int kNttBlockLog = 12;
-constexpr int kNttBlockElems = kNttThreads * kNttPerThread;   // 4096 residues, 32 KiB of LDS
+constexpr int kNttBlockElems = kNttThreads * kNttPerThread;   // 4096 residues, 32 KiB (+2 KiB padding) of LDS
 static_assert(kNttBlockElems == 1 << kNttBlockLog, "block size");
 
 __device__ __forceinline__ void bfly_fwd(uint64_t& x, uint64_t& y, uint64_t w, uint64_t wp, uint64_t q, uint64_t q2) {
@@ -223,7 +223,16 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data,
     const size_t col0 = kCols ? ((size_t)chunk << SPB_L) + sub : 0;
     const size_t run0 = kCols ? 0 : ((size_t)chunk << kNttBlockLog) + ((size_t)sub << SL);
     auto gaddr = [&](int p) -> size_t { return kCols ? col0 + ((size_t)p << L2) : run0 + p; };
-    auto laddr = [&](int p) -> int { return kCols ? (p << SPB_L) + sub : (sub << SL) + p; };
+    // LDS word of position p.  The rows passes pad one word after every 16:
+    // their exchanges move 8 residues per thread at lane strides of 8 and 64
+    // positions, which would otherwise put 4 to 8 lanes of a wave on the same
+    // banks.  The columns passes interleave 2^SPB_L sub-transforms and need no
+    // padding.
+    auto laddr = [&](int p) -> int {
+        if (kCols) return (p << SPB_L) + sub;
+        const int w = (sub << SL) + p;
+        return w + (w >> 4);
+    };
     const int c0 = kCols ? 1 : (1 << L1) + (chunk << SPB_L) + sub;
     typedef NttIo<T, M> Io;
 
@@ -247,14 +256,36 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data,
             __syncthreads();
             ntt_round<3, false>(x, W, Wp, c0, a, tt >> ld, md);
         }
+        if (kCols) {
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk)
-            data[gaddr(j0 + (kk << ld))] = kCols ? Io::out_mid(x[kk], md) : Io::out_fwd_end(x[kk], md);
+            for (int kk = 0; kk < 8; ++kk) data[gaddr(j0 + (kk << ld))] = Io::out_mid(x[kk], md);
+        } else {
+            // the last round leaves each thread 8 adjacent residues; one more
+            // exchange lets consecutive lanes store consecutive residues
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) lds[laddr(j0 + (kk << ld))] = x[kk];
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+                data[gaddr(tt + (kk << (SL - 3)))] = Io::out_fwd_end(lds[laddr(tt + (kk << (SL - 3)))], md);
+        }
     } else {
         ld = 0;
         j0 = tt << 3;
+        if (kCols) {
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(data[gaddr(j0 + kk)], kFirstPass, md);
+            for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(data[gaddr(j0 + kk)], kFirstPass, md);
+        } else {
+            // consecutive lanes load consecutive residues; an exchange hands
+            // each thread the 8 adjacent residues of the first round
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+                lds[laddr(tt + (kk << (SL - 3)))] = Io::in(data[gaddr(tt + (kk << (SL - 3)))], kFirstPass, md);
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) x[kk] = lds[laddr(j0 + kk)];
+            __syncthreads();
+        }
         ntt_round<3, true>(x, W, Wp, c0, SL - 3, tt, md);
 #pragma unroll
         for (int a = SL - 6; a >= R0; a -= 3) {
@@ -294,7 +325,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data,
 
 template <int SL, bool kCols, bool kInverse>
 __global__ void __launch_bounds__(kNttThreads) k_ntt_pass(DevTables t, RowMap m) {
-    __shared__ uint64_t lds[kNttBlockElems];
+    __shared__ uint64_t lds[kNttBlockElems + kNttBlockElems / 16];   // rows passes pad 1 word in 16
     constexpr int SPB_L = kNttBlockLog - SL;
     const int logN = t.logN, L1 = t.L1, L2 = logN - L1;
     const size_t N = (size_t)1 << logN;
@@ -436,13 +467,31 @@ __global__ void __launch_bounds__(kThreads) k_automorphism(DevTables t, uint32_t
     }
 }
 
-// Basis conversion: one thread per coefficient.  y_i = x_i * [Qhat_i^-1]_{q_i}
-// (Shoup, canonical), then for every target t the products y_i * (Qhat_i 2^64
-// mod t) are summed exactly in 128 bits and reduced once by Montgomery REDC:
-// sum < NS * 2^60 * t <= t * 2^64, so REDC returns sum * 2^-64 mod t in [0, 2t).
-// kCentered (ModUp): y_s is taken in (-q_s/2, q_s/2]: a term with 2 y_s > q_s
-// contributes (q_s - y_s) * (t - c) = -(q_s - y_s) * c (mod t), and every
-// term stays below 2^59 * t.
+// Basis conversion: one thread per coefficient.  y_s = x_s * [Qhat_s^-1]_{q_s}
+// (Shoup, canonical); every target t receives sum_s y_s * [Qhat_s]_t mod t.
+// kCentered (ModUp): y_s is taken in (-q_s/2, q_s/2].
+//
+// Targets below 2^44 are summed in FP64, exactly: each term y * c (c the
+// centred constant, |y|, |c| <= 2^43) is split as h + l by an FMA two-product,
+// reduced as (h - k t) + l with k = rint(h / t) (|h - k t| < 2^44, so both
+// steps are exact), and the reduced terms (each below 2^45) are summed exactly
+// in the double accumulator before one final reduction.  A source wider than
+// 2^44 enters as y_hi * [2^32 c]_t + y_lo * c with y = y_hi 2^32 + y_lo.
+//
+// Wider targets sum the products y_s * (Qhat_s 2^64 mod t) exactly in 128
+// bits and reduce once by Montgomery REDC: sum < NS * 2^60 * t <= t * 2^64, so
+// REDC returns sum * 2^-64 mod t in [0, 2t).  There a centred term with
+// 2 y_s > q_s contributes (q_s - y_s) * (t - c) = -(q_s - y_s) * c (mod t),
+// and every term stays below 2^59 * t.
+//
+// cc holds three [NS][nt] tables: the REDC-form constants, then for the FP64
+// targets the centred constants and the centred [2^32 c]_t as doubles.
+__device__ __forceinline__ double fma_mulmod(double y, double c, double t, double tinv) {
+    const double h = y * c;
+    const double l = fma(y, c, -h);
+    return fma(-rint(h * tinv), t, h) + l;
+}
+
 template <int NS, bool kCentered>
 __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap dst, RowMap src, const uint64_t* yc,
                                                             const uint64_t* cc) {
@@ -455,31 +504,58 @@ __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap 
     const int nt = dst.n;
     // the constants are the same for every thread: stage them in LDS once, so
     // the NS * nt multiply-accumulates below do not wait on global loads
-    __shared__ uint64_t s_cc[16 * kMaxMapRows];
-    for (int idx = threadIdx.x; idx < NS * nt; idx += kThreads) s_cc[idx] = cc[idx];
+    extern __shared__ uint64_t s_cc[];   // [3][NS * nt]
+    const double* s_cd = reinterpret_cast<const double*>(s_cc + NS * nt);
+    for (int idx = threadIdx.x; idx < 3 * NS * nt; idx += kThreads) s_cc[idx] = cc[idx];
     __syncthreads();
-    uint64_t y[NS];
-    bool neg[NS];
+    // each source as a signed value held in doubles: a narrow one whole, a wide
+    // one as y_hi 2^32 + y_lo with 0 <= y_lo < 2^32
+    double ylo[NS], yhi[NS];
+    bool wide[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         int mod;
         const uint64_t* p = map_row(src, b, s, logN, mod);
         const uint64_t qs = t.mods[mod].q;
         const uint64_t v = mul_shoup(p[i], yc[2 * s], yc[2 * s + 1], qs);
-        neg[s] = kCentered && 2 * v > qs;
-        y[s] = neg[s] ? qs - v : v;
+        const int64_t sv = (kCentered && 2 * v > qs) ? (int64_t)v - (int64_t)qs : (int64_t)v;
+        wide[s] = qs >= kFp64PrimeBound;
+        const int64_t h = sv >> 32;
+        yhi[s] = wide[s] ? (double)h : 0.0;
+        ylo[s] = wide[s] ? (double)(uint32_t)sv : (double)sv;
+    }
+    for (int tt = 0; tt < nt; ++tt) {
+        int mod;
+        uint64_t* o = map_row(dst, b, tt, logN, mod);
+        const uint64_t qt = t.mods[mod].q;
+        if (qt >= kFp64PrimeBound) continue;
+        const double tq = (double)qt, tinv = 1.0 / tq;
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            acc += fma_mulmod(ylo[s], s_cd[s * nt + tt], tq, tinv);
+            if (wide[s]) acc += fma_mulmod(yhi[s], s_cd[(NS + s) * nt + tt], tq, tinv);
+        }
+        double r = fma(-rint(acc * tinv), tq, acc);
+        r = r < 0.0 ? r + tq : r;
+        o[i] = (uint64_t)r;
     }
     for (int tt = 0; tt < nt; ++tt) {
         int mod;
         uint64_t* o = map_row(dst, b, tt, logN, mod);
         const Modulus md = t.mods[mod];
+        if (md.q < kFp64PrimeBound) continue;
         uint64_t lo = 0, hi = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
+            const int64_t sv = wide[s] ? (int64_t)(((uint64_t)(int64_t)yhi[s] << 32) | (uint32_t)ylo[s])
+                                       : (int64_t)ylo[s];
+            const bool neg = sv < 0;
+            const uint64_t y = neg ? (uint64_t)(-sv) : (uint64_t)sv;
             const uint64_t c0 = s_cc[s * nt + tt];
-            const uint64_t c = (neg[s] && c0) ? md.q - c0 : c0;
-            const uint64_t pl = y[s] * c;
-            const uint64_t ph = mulhi64(y[s], c);
+            const uint64_t c = (neg && c0) ? md.q - c0 : c0;
+            const uint64_t pl = y * c;
+            const uint64_t ph = mulhi64(y, c);
             lo += pl;
             hi += ph + (lo < pl ? 1u : 0u);
         }
@@ -722,8 +798,9 @@ void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, cons
 template <int NS>
 static void launch_bc(const DevTables& t, const RowMap& dst, const RowMap& src, const uint64_t* yc,
                       const uint64_t* cc, bool centered, int blocks, hipStream_t s) {
-    if (centered) hipLaunchKernelGGL((k_basis_convert<NS, true>), dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc);
-    else hipLaunchKernelGGL((k_basis_convert<NS, false>), dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc);
+    const size_t lds = 3 * sizeof(uint64_t) * NS * dst.n;   // at most 3 * 8 * 16 * 64 = 24 KiB
+    if (centered) hipLaunchKernelGGL((k_basis_convert<NS, true>), dim3(blocks), dim3(kThreads), lds, s, t, dst, src, yc, cc);
+    else hipLaunchKernelGGL((k_basis_convert<NS, false>), dim3(blocks), dim3(kThreads), lds, s, t, dst, src, yc, cc);
 }
 
 void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src, const uint64_t* yc,
