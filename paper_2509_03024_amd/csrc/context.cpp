@@ -858,11 +858,10 @@ void Context::ks_modup(const RowMap& d_in, int level, int B, uint64_t* ext, uint
     mc.batch = B;
     mc.batch_stride = (int64_t)nl * N;
     for (int i = 0; i < nl; ++i) mc.push(i, i);
-    launch_ew(tabs, EW_COPY, mc, d_in, d_in, stream);
-    launch_ntt(tabs, mc, true, stream);
+    launch_ntt_from(tabs, mc, d_in, true, stream);   // coefficient form of d_in, which stays as it is
     for (int jj = 0; jj < nd; ++jj) {
         const DigitConsts& dc = c.digits[jj];
-        RowMap src, dst, cpy_src, cpy_dst;
+        RowMap src, dst;
         src.base = coef;
         src.batch = B;
         src.batch_stride = (int64_t)nl * N;
@@ -874,19 +873,12 @@ void Context::ks_modup(const RowMap& d_in, int level, int B, uint64_t* ext, uint
             if (!(t >= dc.lo && t < dc.hi)) dst.push(jj * nr + t, gmod_ext(level, t));
         launch_basis_convert(tabs, dst, src, dc.yc, dc.cc, true, stream);   // centred digits
         launch_ntt(tabs, dst, false, stream);
-        cpy_src = d_in;
-        cpy_src.n = 0;
-        cpy_dst = dst;
-        cpy_dst.n = 0;
-        for (int i = dc.lo; i < dc.hi; ++i) {
-            cpy_src.push(d_in.e[i] >> 8, i);
-            cpy_dst.push(jj * nr + i, i);
-        }
-        launch_ew(tabs, EW_COPY, cpy_dst, cpy_src, cpy_src, stream);
+        // the digit's own limbs are d_in's: ks_inner reads them there
     }
 }
 
-void Context::ks_inner(const uint64_t* ext, int level, int B, const Key& key, uint32_t g, uint64_t* u) {
+void Context::ks_inner(const uint64_t* ext, const RowMap& d_in, int level, int B, const Key& key, uint32_t g,
+                       uint64_t* u) {
     const int nr = n_ext(level);
     const int nd = (int)lv[level].digits.size();
     const int nall = L + 1 + alpha;
@@ -906,6 +898,10 @@ void Context::ks_inner(const uint64_t* ext, int level, int B, const Key& key, ui
     a.n_q = level + 1;
     a.key_shift = L - level;
     a.n_digits = nd;
+    if (d_in.n != level + 1 || d_in.batch != B) throw Error(CSRMF_E_INVAL, "key-switch input map does not match the level or batch");
+    for (int j = 0; j < nd; ++j)
+        for (int i = lv[level].digits[j].lo; i < lv[level].digits[j].hi; ++i) a.digit_of[i] = j;
+    a.own = d_in;
     launch_ks_inner(tabs, mu, a, g, stream);
 }
 
@@ -968,7 +964,7 @@ void Context::mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, st
     for (int i = 0; i < nl; ++i) d2.e[i] = ((uint32_t)(2 * nl + i) << 8) | (uint32_t)i;
     Scratch ext(pool, (size_t)B * nd * nr * N), coef(pool, (size_t)B * nl * N), u(pool, (size_t)B * 2 * nr * N);
     ks_modup(d2, lvl, B, ext.p, coef.p);
-    ks_inner(ext.p, lvl, B, relin, 1, u.p);
+    ks_inner(ext.p, d2, lvl, B, relin, 1, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, a[i]->scale * b[i]->scale);
     ks_moddown(u.p, lvl, B, map_cts(out, nl), md, 1, true);
     fence();
@@ -992,8 +988,7 @@ void Context::rescale(const std::vector<Ct*>& v) {
     mt.poly_stride = (int64_t)N;
     mt.push(0, l);
     mt.push(1, l);
-    launch_ew(tabs, EW_COPY, mt, src, src, stream);
-    launch_ntt(tabs, mt, true, stream);
+    launch_ntt_from(tabs, mt, src, true, stream);
     RowMap mt1 = mt;
     mt1.n = 1;
     RowMap mT;
@@ -1041,7 +1036,7 @@ void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& o
     launch_automorphism(tabs, g, md, c1, false, stream);
     Scratch ext(pool, (size_t)B * nd * nr * N), coef(pool, (size_t)B * nl * N), u(pool, (size_t)B * 2 * nr * N);
     ks_modup(md, lvl, B, ext.p, coef.p);
-    ks_inner(ext.p, lvl, B, key, 1, u.p);
+    ks_inner(ext.p, md, lvl, B, key, 1, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, in[i]->scale);
     ks_moddown(u.p, lvl, B, map_cts(out, nl), map_cts(in, nl), g, false);
     fence();
@@ -1065,7 +1060,7 @@ void Context::rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std:
             launch_ew(tabs, EW_COPY, o, a, a, stream);
             continue;
         }
-        ks_inner(ext.p, lvl, 1, key_for(g), g, u.p);
+        ks_inner(ext.p, c1, lvl, 1, key_for(g), g, u.p);
         ks_moddown(u.p, lvl, 1, map_ct(out[k]->d, nl), map_ct(in.d, nl), g, false);
     }
     fence();
@@ -1145,7 +1140,9 @@ void Context::hoist_rotate(Hoist& h, uint32_t g, std::vector<Ct*>& out) {
     const int lvl = h.level, nl = lvl + 1, nr = n_ext(lvl);
     const Key& key = key_for(g);
     Scratch u(pool, (size_t)B * 2 * nr * N);
-    ks_inner(h.ext, lvl, B, key, g, u.p);
+    RowMap c1 = map_cts(h.in, nl);
+    for (int i = 0; i < nl; ++i) c1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+    ks_inner(h.ext, c1, lvl, B, key, g, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, h.in[i]->scale);
     ks_moddown(u.p, lvl, B, map_cts(out, nl), map_cts(h.in, nl), g, false);
     fence();

@@ -228,7 +228,8 @@ struct Context {
 
     // --- key-switching pieces
     void ks_modup(const RowMap& d_in, int level, int B, uint64_t* ext, uint64_t* coef);
-    void ks_inner(const uint64_t* ext, int level, int B, const Key& key, uint32_t g, uint64_t* u);
+    // d_in: the ModUp input (evaluation form), which supplies each digit's own limbs
+    void ks_inner(const uint64_t* ext, const RowMap& d_in, int level, int B, const Key& key, uint32_t g, uint64_t* u);
     void ks_moddown(uint64_t* u, int level, int B, const RowMap& out, const RowMap& addend,
                     uint32_t g_add, bool addend_both);
 

@@ -47,6 +47,9 @@ struct DevTables {
 };
 
 void launch_ntt(const DevTables& t, const RowMap& rows, bool inverse, hipStream_t s);
+// The same transform of rows that are read from `src` (same shape; its first
+// pass reads src, writes rows) and left in `rows`; src is not modified.
+void launch_ntt_from(const DevTables& t, const RowMap& rows, const RowMap& src, bool inverse, hipStream_t s);
 
 // NTT schedule tunable: rows per pair of passes (0 = whole batch), process-wide.
 void set_ntt_chunk_rows(int rows);
@@ -103,7 +106,7 @@ void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& s
 // u: map with n = n_rows (u0 rows), u1 rows at +poly_stride.  g != 1 applies
 // tau_g to the ext rows on the fly (hoisted rotation).
 struct KsArgs {
-    const uint64_t* ext;
+    const uint64_t* ext;       // ModUp output [batch][digit][limb][N]; a digit's own Q limbs are not stored there
     int64_t ext_batch_stride;
     int64_t ext_digit_stride;
     const uint64_t* key;
@@ -112,6 +115,8 @@ struct KsArgs {
     int32_t n_q;
     int32_t key_shift;
     int32_t n_digits;
+    int32_t digit_of[kMaxMapRows];   // Q limb -> the digit that holds it
+    RowMap own;                      // the key-switched polynomial itself (evaluation form), rows = Q limbs
 };
 void launch_ks_inner(const DevTables& t, const RowMap& u, const KsArgs& a, uint32_t g, hipStream_t s);
 

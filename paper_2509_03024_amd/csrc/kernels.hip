@@ -209,9 +209,12 @@ template <> struct NttIo<double, ModF> {
     }
 };
 
+// `in` is read once, at the start of the pass, and `data` written at its end
+// (the same tile of the same limb): in == data transforms in place.
 template <int SL, bool kCols, bool kInverse, typename T, typename M>
-__device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data, const uint64_t* W, const uint64_t* Wp,
-                                              const M& md, const Modulus& mi, int L1, int L2, int chunk, int tid) {
+__device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t* in, uint64_t* data, const uint64_t* W,
+                                              const uint64_t* Wp, const M& md, const Modulus& mi, int L1, int L2,
+                                              int chunk, int tid) {
     T* lds = reinterpret_cast<T*>(lds_raw);
     constexpr int TPS_L = SL - 3;
     constexpr int SPB_L = kNttBlockLog - SL;        // log2(sub-transforms per block)
@@ -228,11 +231,12 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data,
     // positions, which would otherwise put 4 to 8 lanes of a wave on the same
     // banks.  The columns passes interleave 2^SPB_L sub-transforms and need no
     // padding.
-    auto laddr = [&](int p) -> int {
-        if (kCols) return (p << SPB_L) + sub;
-        const int w = (sub << SL) + p;
-        return w + (w >> 4);
-    };
+    // A thread's positions are a base j0 plus the bit field kk << ld, disjoint
+    // from j0's bits, so the padded word splits into pad(base) + pad(offset):
+    // one address register per exchange and an immediate offset per residue.
+    auto pad = [](int w) -> int { return kCols ? w : w + (w >> 4); };
+    auto lbase = [&](int j) -> int { return pad(kCols ? (j << SPB_L) + sub : (sub << SL) + j); };
+    auto loff = [&](int kk, int l) -> int { return pad(kCols ? (kk << l) << SPB_L : kk << l); };
     const int c0 = kCols ? 1 : (1 << L1) + (chunk << SPB_L) + sub;
     typedef NttIo<T, M> Io;
 
@@ -242,17 +246,17 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data,
         ld = SL - 3;
         j0 = tt;
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(data[gaddr(tt + (kk << ld))], kFirstPass, md);
+        for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(in[gaddr(tt + (kk << ld))], kFirstPass, md);
         ntt_round<R0, false>(x, W, Wp, c0, 0, 0, md);
 #pragma unroll
         for (int a = R0; a < SL; a += 3) {
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) lds[laddr(j0 + (kk << ld))] = x[kk];
+            for (int kk = 0; kk < 8; ++kk) lds[lbase(j0) + loff(kk, ld)] = x[kk];
             __syncthreads();
             ld = SL - a - 3;
             j0 = ((tt >> ld) << (ld + 3)) | (tt & ((1 << ld) - 1));
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) x[kk] = lds[laddr(j0 + (kk << ld))];
+            for (int kk = 0; kk < 8; ++kk) x[kk] = lds[lbase(j0) + loff(kk, ld)];
             __syncthreads();
             ntt_round<3, false>(x, W, Wp, c0, a, tt >> ld, md);
         }
@@ -263,49 +267,49 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data,
             // the last round leaves each thread 8 adjacent residues; one more
             // exchange lets consecutive lanes store consecutive residues
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) lds[laddr(j0 + (kk << ld))] = x[kk];
+            for (int kk = 0; kk < 8; ++kk) lds[lbase(j0) + loff(kk, ld)] = x[kk];
             __syncthreads();
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk)
-                data[gaddr(tt + (kk << (SL - 3)))] = Io::out_fwd_end(lds[laddr(tt + (kk << (SL - 3)))], md);
+                data[gaddr(tt + (kk << (SL - 3)))] = Io::out_fwd_end(lds[lbase(tt) + loff(kk, SL - 3)], md);
         }
     } else {
         ld = 0;
         j0 = tt << 3;
         if (kCols) {
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(data[gaddr(j0 + kk)], kFirstPass, md);
+            for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(in[gaddr(j0 + kk)], kFirstPass, md);
         } else {
             // consecutive lanes load consecutive residues; an exchange hands
             // each thread the 8 adjacent residues of the first round
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk)
-                lds[laddr(tt + (kk << (SL - 3)))] = Io::in(data[gaddr(tt + (kk << (SL - 3)))], kFirstPass, md);
+                lds[lbase(tt) + loff(kk, SL - 3)] = Io::in(in[gaddr(tt + (kk << (SL - 3)))], kFirstPass, md);
             __syncthreads();
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) x[kk] = lds[laddr(j0 + kk)];
+            for (int kk = 0; kk < 8; ++kk) x[kk] = lds[lbase(j0) + loff(kk, 0)];
             __syncthreads();
         }
         ntt_round<3, true>(x, W, Wp, c0, SL - 3, tt, md);
 #pragma unroll
         for (int a = SL - 6; a >= R0; a -= 3) {
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) lds[laddr(j0 + (kk << ld))] = x[kk];
+            for (int kk = 0; kk < 8; ++kk) lds[lbase(j0) + loff(kk, ld)] = x[kk];
             __syncthreads();
             ld = SL - a - 3;
             j0 = ((tt >> ld) << (ld + 3)) | (tt & ((1 << ld) - 1));
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) x[kk] = lds[laddr(j0 + (kk << ld))];
+            for (int kk = 0; kk < 8; ++kk) x[kk] = lds[lbase(j0) + loff(kk, ld)];
             __syncthreads();
             ntt_round<3, true>(x, W, Wp, c0, a, tt >> ld, md);
         }
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) lds[laddr(j0 + (kk << ld))] = x[kk];
+        for (int kk = 0; kk < 8; ++kk) lds[lbase(j0) + loff(kk, ld)] = x[kk];
         __syncthreads();
         ld = SL - 3;
         j0 = tt;
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) x[kk] = lds[laddr(j0 + (kk << ld))];
+        for (int kk = 0; kk < 8; ++kk) x[kk] = lds[lbase(j0) + loff(kk, ld)];
         ntt_round<R0, true>(x, W, Wp, c0, 0, 0, md);
         if (kCols) {
             if constexpr (std::is_same<T, double>::value) {
@@ -324,7 +328,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* data,
 }
 
 template <int SL, bool kCols, bool kInverse>
-__global__ void __launch_bounds__(kNttThreads) k_ntt_pass(DevTables t, RowMap m) {
+__global__ void __launch_bounds__(kNttThreads) k_ntt_pass(DevTables t, RowMap m, RowMap src) {
     __shared__ uint64_t lds[kNttBlockElems + kNttBlockElems / 16];   // rows passes pad 1 word in 16
     constexpr int SPB_L = kNttBlockLog - SL;
     const int logN = t.logN, L1 = t.L1, L2 = logN - L1;
@@ -333,34 +337,38 @@ __global__ void __launch_bounds__(kNttThreads) k_ntt_pass(DevTables t, RowMap m)
     int b, k, chunk, mod;
     block_coords(blockIdx.x, chunks, m.batch, b, k, chunk);
     uint64_t* data = map_row(m, b, k, logN, mod);
+    int smod;
+    const uint64_t* in = src.n ? map_row(src, b, k, logN, smod) : data;
     const Modulus md = t.mods[mod];
     const uint64_t* W = t.tw + (size_t)mod * 4 * N + (kInverse ? 2 * N : 0);
     const uint64_t* Wp = W + N;
     if (md.q < kFp64PrimeBound) {
         const ModF mf{(double)md.q, 1.0 / (double)md.q};
-        ntt_pass_body<SL, kCols, kInverse, double, ModF>(lds, data, W, Wp, mf, md, L1, L2, chunk, threadIdx.x);
+        ntt_pass_body<SL, kCols, kInverse, double, ModF>(lds, in, data, W, Wp, mf, md, L1, L2, chunk, threadIdx.x);
     } else {
-        ntt_pass_body<SL, kCols, kInverse, uint64_t, Modulus>(lds, data, W, Wp, md, md, L1, L2, chunk, threadIdx.x);
+        ntt_pass_body<SL, kCols, kInverse, uint64_t, Modulus>(lds, in, data, W, Wp, md, md, L1, L2, chunk, threadIdx.x);
     }
 }
 
 template <int SL>
-void launch_ntt_pass(const DevTables& t, const RowMap& m, bool cols, bool inverse, int blocks, hipStream_t s) {
+void launch_ntt_pass(const DevTables& t, const RowMap& m, const RowMap& src, bool cols, bool inverse, int blocks,
+                     hipStream_t s) {
     if (cols) {
-        if (inverse) hipLaunchKernelGGL((k_ntt_pass<SL, true, true>), dim3(blocks), dim3(kNttThreads), 0, s, t, m);
-        else hipLaunchKernelGGL((k_ntt_pass<SL, true, false>), dim3(blocks), dim3(kNttThreads), 0, s, t, m);
+        if (inverse) hipLaunchKernelGGL((k_ntt_pass<SL, true, true>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
+        else hipLaunchKernelGGL((k_ntt_pass<SL, true, false>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
     } else {
-        if (inverse) hipLaunchKernelGGL((k_ntt_pass<SL, false, true>), dim3(blocks), dim3(kNttThreads), 0, s, t, m);
-        else hipLaunchKernelGGL((k_ntt_pass<SL, false, false>), dim3(blocks), dim3(kNttThreads), 0, s, t, m);
+        if (inverse) hipLaunchKernelGGL((k_ntt_pass<SL, false, true>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
+        else hipLaunchKernelGGL((k_ntt_pass<SL, false, false>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
     }
 }
 
-void dispatch_ntt_pass(const DevTables& t, const RowMap& m, bool cols, bool inverse, int blocks, hipStream_t s) {
+void dispatch_ntt_pass(const DevTables& t, const RowMap& m, const RowMap& src, bool cols, bool inverse, int blocks,
+                       hipStream_t s) {
     const int SL = cols ? t.L1 : t.logN - t.L1;
     switch (SL) {
-        case 6: launch_ntt_pass<6>(t, m, cols, inverse, blocks, s); break;
-        case 7: launch_ntt_pass<7>(t, m, cols, inverse, blocks, s); break;
-        case 8: launch_ntt_pass<8>(t, m, cols, inverse, blocks, s); break;
+        case 6: launch_ntt_pass<6>(t, m, src, cols, inverse, blocks, s); break;
+        case 7: launch_ntt_pass<7>(t, m, src, cols, inverse, blocks, s); break;
+        case 8: launch_ntt_pass<8>(t, m, src, cols, inverse, blocks, s); break;
         default: break;   // log2N is validated to [12, 16] at context creation
     }
 }
@@ -572,12 +580,16 @@ __global__ void __launch_bounds__(kThreads) k_ks_inner(DevTables t, RowMap u, Ks
     const Modulus md = t.mods[mod];
     const int64_t krow = (int64_t)(k < a.n_q ? k : k + a.key_shift) << logN;
     const uint64_t* pe0 = a.ext + (int64_t)b * a.ext_batch_stride + ((int64_t)k << logN);
+    // a Q limb's own digit is the input polynomial's limb itself
+    const int jown = k < a.n_q ? a.digit_of[k] : -1;
+    int omod;
+    const uint64_t* pown = k < a.n_q ? map_row(a.own, b, k, logN, omod) : nullptr;
     for (int uu = 0; uu < kEwPerThread; ++uu) {
         const int i = base_i + uu * kThreads;
         const uint32_t src = (g == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g, logN);
         uint64_t acc0 = 0, acc1 = 0;
         for (int j = 0; j < a.n_digits; ++j) {
-            const uint64_t x = pe0[(int64_t)j * a.ext_digit_stride + src];
+            const uint64_t x = j == jown ? pown[src] : pe0[(int64_t)j * a.ext_digit_stride + src];
             const uint64_t* pk = a.key + (int64_t)j * a.key_digit_stride + krow;
             acc0 = add_mod(acc0, mul_mont(x, pk[i], md.q, md.qneg_inv), md.q);
             acc1 = add_mod(acc1, mul_mont(x, pk[i + a.key_poly_stride], md.q, md.qneg_inv), md.q);
@@ -742,24 +754,32 @@ void set_ntt_chunk_rows(int rows) { g_ntt_chunk_rows = rows < 0 ? 0 : rows; }
 int ntt_chunk_rows() { return g_ntt_chunk_rows; }
 
 void launch_ntt(const DevTables& t, const RowMap& m, bool inverse, hipStream_t s) {
+    launch_ntt_from(t, m, RowMap(), inverse, s);
+}
+
+void launch_ntt_from(const DevTables& t, const RowMap& m, const RowMap& src, bool inverse, hipStream_t s) {
     if (m.rows() == 0) return;
+    if (src.n && (src.n != m.n || src.batch != m.batch)) throw std::length_error("transform source map differs in shape");
     const int per_b = m.n;
     int bchunk = m.batch;
     if (g_ntt_chunk_rows > 0) bchunk = per_b >= g_ntt_chunk_rows ? 1 : g_ntt_chunk_rows / per_b;
     if (bchunk > m.batch) bchunk = m.batch;
+    const RowMap none{};
     for (int b0 = 0; b0 < m.batch; b0 += bchunk) {
-        RowMap sub = m;
-        sub.batch = (m.batch - b0) < bchunk ? (m.batch - b0) : bchunk;
+        RowMap sub = m, ssub = src;
+        sub.batch = ssub.batch = (m.batch - b0) < bchunk ? (m.batch - b0) : bchunk;
         if (m.ptrs) sub.ptrs = m.ptrs + b0;
         else sub.base = m.base + (int64_t)b0 * m.batch_stride;
+        if (src.ptrs) ssub.ptrs = src.ptrs + b0;
+        else if (src.n) ssub.base = src.base + (int64_t)b0 * src.batch_stride;
         const int blocks = sub.rows() * (int)(((size_t)1 << t.logN) / kNttBlockElems);
         const double bytes = NB(sub.rows()) * 2;
         if (!inverse) {
-            { ProfScope ps_("k_ntt_pass<cols,fwd>", s, bytes); dispatch_ntt_pass(t, sub, true, false, blocks, s); }
-            { ProfScope ps_("k_ntt_pass<rows,fwd>", s, bytes); dispatch_ntt_pass(t, sub, false, false, blocks, s); }
+            { ProfScope ps_("k_ntt_pass<cols,fwd>", s, bytes); dispatch_ntt_pass(t, sub, ssub, true, false, blocks, s); }
+            { ProfScope ps_("k_ntt_pass<rows,fwd>", s, bytes); dispatch_ntt_pass(t, sub, none, false, false, blocks, s); }
         } else {
-            { ProfScope ps_("k_ntt_pass<rows,inv>", s, bytes); dispatch_ntt_pass(t, sub, false, true, blocks, s); }
-            { ProfScope ps_("k_ntt_pass<cols,inv>", s, bytes); dispatch_ntt_pass(t, sub, true, true, blocks, s); }
+            { ProfScope ps_("k_ntt_pass<rows,inv>", s, bytes); dispatch_ntt_pass(t, sub, ssub, false, true, blocks, s); }
+            { ProfScope ps_("k_ntt_pass<cols,inv>", s, bytes); dispatch_ntt_pass(t, sub, none, true, true, blocks, s); }
         }
     }
 }
