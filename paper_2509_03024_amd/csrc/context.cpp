@@ -138,34 +138,6 @@ static void upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
     CSRMF_HIP(hipStreamSynchronize(s));   // the host buffer may be reused on return
 }
 
-// Constant table of a basis conversion from NS sources to nt targets, given the
-// canonical constants c[s][t] (s-major): the REDC form c 2^64 mod t for every
-// target, then, for the targets below 2^44 that the kernel sums in FP64, the
-// centred c and the centred [2^32 c]_t as raw doubles (zero for wider targets).
-static std::vector<uint64_t> bc_table(const std::vector<uint64_t>& c, const std::vector<uint64_t>& tq,
-                                      const std::vector<uint64_t>& r_mod) {
-    const size_t nt = tq.size(), ns = nt ? c.size() / nt : 0;
-    std::vector<uint64_t> out(3 * ns * nt, 0);
-    auto centred = [](uint64_t v, uint64_t q) {
-        const double d = v > q / 2 ? -(double)(q - v) : (double)v;
-        uint64_t bits;
-        std::memcpy(&bits, &d, 8);
-        return bits;
-    };
-    for (size_t s = 0; s < ns; ++s) {
-        for (size_t t = 0; t < nt; ++t) {
-            const size_t k = s * nt + t;
-            const uint64_t q = tq[t];
-            out[k] = mm(c[k], r_mod[t], q);
-            if (q < kFp64PrimeBound) {
-                out[ns * nt + k] = centred(c[k], q);
-                out[2 * ns * nt + k] = centred(mm(c[k], (1ull << 32) % q, q), q);
-            }
-        }
-    }
-    return out;
-}
-
 static uint64_t* upload_consts(Pool& pool, const std::vector<uint64_t>& v, hipStream_t s) {
     uint64_t* d = (uint64_t*)pool.get(std::max<size_t>(8, v.size() * 8));
     if (!v.empty()) upload(d, v.data(), v.size() * 8, s);
@@ -286,7 +258,7 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
             DigitConsts dc;
             dc.lo = lo;
             dc.hi = hi;
-            std::vector<uint64_t> yc, cc, tq, trm;
+            std::vector<uint64_t> yc, cc;
             std::vector<int> tg;
             for (int t = 0; t < nr; ++t)
                 if (!(t >= lo && t < hi)) tg.push_back(gmod_ext(l, t));
@@ -298,20 +270,16 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
                 yc.push_back(w);
                 yc.push_back(shoup_pre(w, qi));
             }
-            for (int tm : tg) {
-                tq.push_back(moduli[tm]);
-                trm.push_back(mh[tm].r_mod);
-            }
             for (int i = lo; i < hi; ++i) {
                 for (int tm : tg) {
                     const uint64_t qt = moduli[tm];
                     uint64_t hat = 1;
                     for (int k = lo; k < hi; ++k) if (k != i) hat = mm(hat, moduli[k] % qt, qt);
-                    cc.push_back(hat);
+                    cc.push_back(mm(hat, mh[tm].r_mod, qt));
                 }
             }
             dc.yc = upload_consts(pool, yc, stream);
-            dc.cc = upload_consts(pool, bc_table(cc, tq, trm), stream);
+            dc.cc = upload_consts(pool, cc, stream);
             c.digits.push_back(dc);
         }
         std::vector<uint64_t> y, cv, pinv, rs;
@@ -323,17 +291,12 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
             y.push_back(w);
             y.push_back(shoup_pre(w, pk_));
         }
-        std::vector<uint64_t> mdq, mdr;
-        for (int i = 0; i <= l; ++i) {
-            mdq.push_back(moduli[i]);
-            mdr.push_back(mh[i].r_mod);
-        }
         for (int k = 0; k < alpha; ++k) {
             for (int i = 0; i <= l; ++i) {
                 const uint64_t qi = moduli[i];
                 uint64_t hat = 1;
                 for (int kk = 0; kk < alpha; ++kk) if (kk != k) hat = mm(hat, moduli[L + 1 + kk] % qi, qi);
-                cv.push_back(hat);
+                cv.push_back(mm(hat, mh[i].r_mod, qi));
             }
         }
         for (int i = 0; i <= l; ++i) {
@@ -356,7 +319,7 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
             }
         }
         c.md_y = upload_consts(pool, y, stream);
-        c.md_c = upload_consts(pool, bc_table(cv, mdq, mdr), stream);
+        c.md_c = upload_consts(pool, cv, stream);
         c.md_pinv = upload_consts(pool, pinv, stream);
         c.rs = upload_consts(pool, rs, stream);
     }

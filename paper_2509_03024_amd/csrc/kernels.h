@@ -60,8 +60,10 @@ int ntt_chunk_rows();
 void launch_expand_signed(const DevTables& t, const RowMap& out, const int64_t* src, int n_src,
                           int64_t src_batch_stride, hipStream_t s);
 
-enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_NEG = 2, EW_COPY = 3 };
-// out = a (op) b (EW_NEG: out = -a; EW_COPY: out = a); maps share (n, batch).
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_NEG = 2, EW_COPY = 3, EW_F64C = 4 };
+// out = a (op) b (EW_NEG: out = -a; EW_COPY: out = a; EW_F64C: rows of primes
+// below 2^44 become their centred values as raw doubles, the others are
+// copied); maps share (n, batch).
 void launch_ew(const DevTables& t, EwOp op, const RowMap& out, const RowMap& a, const RowMap& b,
                hipStream_t s);
 
@@ -134,7 +136,9 @@ void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap&
 // M_g = sum_m W_m tau_{gs[m]}(I0) over the group's terms
 // [term_begin[g], term_begin[g+1]) (a term with gs[m] = 0 adds the constant W_m),
 // formed on the fly from the evaluation-form plaintext I0 (limb k at i0 + k*N);
-// cw[2*(wi[m]*cw_stride + k)], +1 = W_m * 2^64 mod q_k and its shoup.
+// cw[2*(wi[m]*cw_stride + k)], +1 = W_m * 2^64 mod q_k and its shoup, or, for
+// a prime below 2^44, the centred W_m mod q_k and fl(W_m / q_k) as raw doubles
+// (the I0 rows of those limbs hold centred doubles too).
 // first[t] != 0: the accumulator starts at zero.  All pointers are device arrays.
 struct MaskTasks {
     uint64_t* const* acc;       // [n_tasks] ciphertext base pointers

@@ -408,6 +408,7 @@ __global__ void __launch_bounds__(kThreads) k_ew(DevTables t, int op, RowMap out
         if (op == EW_ADD) r = add_mod(x, pb[i], q);
         else if (op == EW_SUB) r = sub_mod(x, pb[i], q);
         else if (op == EW_NEG) r = neg_mod(x, q);
+        else if (op == EW_F64C && q < kFp64PrimeBound) r = f64_bits(x > q / 2 ? -(double)(q - x) : (double)x);
         else r = x;
         o[i] = r;
     }
@@ -475,31 +476,13 @@ __global__ void __launch_bounds__(kThreads) k_automorphism(DevTables t, uint32_t
     }
 }
 
-// Basis conversion: one thread per coefficient.  y_s = x_s * [Qhat_s^-1]_{q_s}
-// (Shoup, canonical); every target t receives sum_s y_s * [Qhat_s]_t mod t.
-// kCentered (ModUp): y_s is taken in (-q_s/2, q_s/2].
-//
-// Targets below 2^44 are summed in FP64, exactly: each term y * c (c the
-// centred constant, |y|, |c| <= 2^43) is split as h + l by an FMA two-product,
-// reduced as (h - k t) + l with k = rint(h / t) (|h - k t| < 2^44, so both
-// steps are exact), and the reduced terms (each below 2^45) are summed exactly
-// in the double accumulator before one final reduction.  A source wider than
-// 2^44 enters as y_hi * [2^32 c]_t + y_lo * c with y = y_hi 2^32 + y_lo.
-//
-// Wider targets sum the products y_s * (Qhat_s 2^64 mod t) exactly in 128
-// bits and reduce once by Montgomery REDC: sum < NS * 2^60 * t <= t * 2^64, so
-// REDC returns sum * 2^-64 mod t in [0, 2t).  There a centred term with
-// 2 y_s > q_s contributes (q_s - y_s) * (t - c) = -(q_s - y_s) * c (mod t),
-// and every term stays below 2^59 * t.
-//
-// cc holds three [NS][nt] tables: the REDC-form constants, then for the FP64
-// targets the centred constants and the centred [2^32 c]_t as doubles.
-__device__ __forceinline__ double fma_mulmod(double y, double c, double t, double tinv) {
-    const double h = y * c;
-    const double l = fma(y, c, -h);
-    return fma(-rint(h * tinv), t, h) + l;
-}
-
+// Basis conversion: one thread per coefficient.  y_i = x_i * [Qhat_i^-1]_{q_i}
+// (Shoup, canonical), then for every target t the products y_i * (Qhat_i 2^64
+// mod t) are summed exactly in 128 bits and reduced once by Montgomery REDC:
+// sum < NS * 2^60 * t <= t * 2^64, so REDC returns sum * 2^-64 mod t in [0, 2t).
+// kCentered (ModUp): y_s is taken in (-q_s/2, q_s/2]: a term with 2 y_s > q_s
+// contributes (q_s - y_s) * (t - c) = -(q_s - y_s) * c (mod t), and every
+// term stays below 2^59 * t.
 template <int NS, bool kCentered>
 __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap dst, RowMap src, const uint64_t* yc,
                                                             const uint64_t* cc) {
@@ -512,58 +495,31 @@ __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap 
     const int nt = dst.n;
     // the constants are the same for every thread: stage them in LDS once, so
     // the NS * nt multiply-accumulates below do not wait on global loads
-    extern __shared__ uint64_t s_cc[];   // [3][NS * nt]
-    const double* s_cd = reinterpret_cast<const double*>(s_cc + NS * nt);
-    for (int idx = threadIdx.x; idx < 3 * NS * nt; idx += kThreads) s_cc[idx] = cc[idx];
+    __shared__ uint64_t s_cc[16 * kMaxMapRows];
+    for (int idx = threadIdx.x; idx < NS * nt; idx += kThreads) s_cc[idx] = cc[idx];
     __syncthreads();
-    // each source as a signed value held in doubles: a narrow one whole, a wide
-    // one as y_hi 2^32 + y_lo with 0 <= y_lo < 2^32
-    double ylo[NS], yhi[NS];
-    bool wide[NS];
+    uint64_t y[NS];
+    bool neg[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         int mod;
         const uint64_t* p = map_row(src, b, s, logN, mod);
         const uint64_t qs = t.mods[mod].q;
         const uint64_t v = mul_shoup(p[i], yc[2 * s], yc[2 * s + 1], qs);
-        const int64_t sv = (kCentered && 2 * v > qs) ? (int64_t)v - (int64_t)qs : (int64_t)v;
-        wide[s] = qs >= kFp64PrimeBound;
-        const int64_t h = sv >> 32;
-        yhi[s] = wide[s] ? (double)h : 0.0;
-        ylo[s] = wide[s] ? (double)(uint32_t)sv : (double)sv;
-    }
-    for (int tt = 0; tt < nt; ++tt) {
-        int mod;
-        uint64_t* o = map_row(dst, b, tt, logN, mod);
-        const uint64_t qt = t.mods[mod].q;
-        if (qt >= kFp64PrimeBound) continue;
-        const double tq = (double)qt, tinv = 1.0 / tq;
-        double acc = 0.0;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            acc += fma_mulmod(ylo[s], s_cd[s * nt + tt], tq, tinv);
-            if (wide[s]) acc += fma_mulmod(yhi[s], s_cd[(NS + s) * nt + tt], tq, tinv);
-        }
-        double r = fma(-rint(acc * tinv), tq, acc);
-        r = r < 0.0 ? r + tq : r;
-        o[i] = (uint64_t)r;
+        neg[s] = kCentered && 2 * v > qs;
+        y[s] = neg[s] ? qs - v : v;
     }
     for (int tt = 0; tt < nt; ++tt) {
         int mod;
         uint64_t* o = map_row(dst, b, tt, logN, mod);
         const Modulus md = t.mods[mod];
-        if (md.q < kFp64PrimeBound) continue;
         uint64_t lo = 0, hi = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const int64_t sv = wide[s] ? (int64_t)(((uint64_t)(int64_t)yhi[s] << 32) | (uint32_t)ylo[s])
-                                       : (int64_t)ylo[s];
-            const bool neg = sv < 0;
-            const uint64_t y = neg ? (uint64_t)(-sv) : (uint64_t)sv;
             const uint64_t c0 = s_cc[s * nt + tt];
-            const uint64_t c = (neg && c0) ? md.q - c0 : c0;
-            const uint64_t pl = y * c;
-            const uint64_t ph = mulhi64(y, c);
+            const uint64_t c = (neg[s] && c0) ? md.q - c0 : c0;
+            const uint64_t pl = y[s] * c;
+            const uint64_t ph = mulhi64(y[s], c);
             lo += pl;
             hi += ph + (lo < pl ? 1u : 0u);
         }
@@ -669,6 +625,85 @@ __global__ void __launch_bounds__(kThreads) k_rescale_combine(DevTables t, RowMa
 // [term_begin[g], term_begin[g+1]).  If first[t] != 0 the accumulator starts at 0.
 
 
+// FP64 form of the masked MAC for a limb whose prime is below 2^44 (the mask
+// row and the weight rows of such a limb hold centred doubles: the mask value,
+// and w with fl(w/q)).  Every product is exact (FMA two-product, reduced by
+// rint(h/q)), reduced terms stay below q in magnitude, and the double sums are
+// re-centred every kF64Batch additions, so they never exceed 2^53.  The
+// canonical residues that come out equal those of the integer path.
+constexpr int kF64Batch = 256;
+
+__device__ __forceinline__ double f64_centre(double v, double q, double qinv) { return fma(-rint(v * qinv), q, v); }
+
+__device__ __forceinline__ double f64_mulmod(double a, double b, double q, double qinv) {
+    const double h = a * b;
+    const double l = fma(a, b, -h);
+    return fma(-rint(h * qinv), q, h) + l;
+}
+
+__device__ __forceinline__ void mask_mac_f64(const MaskTasks& T, int task, int k, int base_i, int g0, int g1,
+                                             const uint64_t* row, uint64_t* pa, uint64_t q64, int logN) {
+    const double q = (double)q64, qinv = 1.0 / q;
+    const ModF mf{q, qinv};
+    double a0[kMacPerThread], a1[kMacPerThread];
+    if (T.first[task]) {
+#pragma unroll
+        for (int u = 0; u < kMacPerThread; ++u) a0[u] = a1[u] = 0.0;
+    } else {
+#pragma unroll
+        for (int u = 0; u < kMacPerThread; ++u) {
+            a0[u] = (double)pa[base_i + u * kThreads];
+            a1[u] = (double)pa[base_i + u * kThreads + T.poly_stride];
+        }
+    }
+    int n_acc = 0;
+    for (int g = g0; g < g1; ++g) {
+        double M[kMacPerThread];
+#pragma unroll
+        for (int u = 0; u < kMacPerThread; ++u) M[u] = 0.0;
+        const int m0 = T.term_begin[g], m1 = T.term_begin[g + 1];
+        for (int m = m0; m < m1; ++m) {
+            const uint64_t* c = T.cw + 2 * ((size_t)T.wi[m] * T.cw_stride + k);
+            const double w = as_f64(c[0]), wq = as_f64(c[1]);
+            const uint32_t gm = T.gs[m];
+            // Galois element 0 marks a constant term (the plaintext W, no mask)
+            if (gm) {
+#pragma unroll
+                for (int u = 0; u < kMacPerThread; ++u)
+                    M[u] += fmul_centred(as_f64(row[galois_perm((uint32_t)(base_i + u * kThreads), gm, logN)]), w, wq, q);
+            } else {
+#pragma unroll
+                for (int u = 0; u < kMacPerThread; ++u) M[u] += w;
+            }
+            if ((m - m0) % kF64Batch == kF64Batch - 1) {
+#pragma unroll
+                for (int u = 0; u < kMacPerThread; ++u) M[u] = f64_centre(M[u], q, qinv);
+            }
+        }
+        const uint64_t* ps = T.src[g] + ((size_t)k << logN);
+#pragma unroll
+        for (int u = 0; u < kMacPerThread; ++u) {
+            const int i = base_i + u * kThreads;
+            const double Mc = f64_centre(M[u], q, qinv);
+            a0[u] += f64_mulmod((double)ps[i], Mc, q, qinv);
+            a1[u] += f64_mulmod((double)ps[i + T.poly_stride], Mc, q, qinv);
+        }
+        if (++n_acc == kF64Batch) {
+            n_acc = 0;
+#pragma unroll
+            for (int u = 0; u < kMacPerThread; ++u) {
+                a0[u] = f64_centre(a0[u], q, qinv);
+                a1[u] = f64_centre(a1[u], q, qinv);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kMacPerThread; ++u) {
+        pa[base_i + u * kThreads] = f64_canon(a0[u], mf);
+        pa[base_i + u * kThreads + T.poly_stride] = f64_canon(a1[u], mf);
+    }
+}
+
 // Grid order (XCD-aware): work-groups are dispatched to the 8 XCDs round
 // robin, so block b runs on XCD b % 8.  A tile (limb k, chunk of elements)
 // is given to one XCD and all tasks of that tile run there back to back:
@@ -693,6 +728,10 @@ __global__ void __launch_bounds__(kThreads) k_mask_mac_tasks(DevTables t, MaskTa
     const uint64_t* row = i0 + ((size_t)k << logN);
     uint64_t* pa = T.acc[task] + ((size_t)k << logN);
     const int g0 = T.grp_begin[task], g1 = T.grp_begin[task + 1];
+    if (md.q < kFp64PrimeBound) {
+        mask_mac_f64(T, task, k, base_i, g0, g1, row, pa, md.q, logN);
+        return;
+    }
     uint64_t a0[kMacPerThread], a1[kMacPerThread];
     if (T.first[task]) {
 #pragma unroll
@@ -818,9 +857,8 @@ void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, cons
 template <int NS>
 static void launch_bc(const DevTables& t, const RowMap& dst, const RowMap& src, const uint64_t* yc,
                       const uint64_t* cc, bool centered, int blocks, hipStream_t s) {
-    const size_t lds = 3 * sizeof(uint64_t) * NS * dst.n;   // at most 3 * 8 * 16 * 64 = 24 KiB
-    if (centered) hipLaunchKernelGGL((k_basis_convert<NS, true>), dim3(blocks), dim3(kThreads), lds, s, t, dst, src, yc, cc);
-    else hipLaunchKernelGGL((k_basis_convert<NS, false>), dim3(blocks), dim3(kThreads), lds, s, t, dst, src, yc, cc);
+    if (centered) hipLaunchKernelGGL((k_basis_convert<NS, true>), dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc);
+    else hipLaunchKernelGGL((k_basis_convert<NS, false>), dim3(blocks), dim3(kThreads), 0, s, t, dst, src, yc, cc);
 }
 
 void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src, const uint64_t* yc,

@@ -17,8 +17,10 @@ struct MfState {
     std::vector<int32_t> rows, ct_of, blk_of;
     std::vector<double> deg_u, deg_v;
     std::vector<uint64_t> R, Utab, Vtab, Ug, Vg, Sdot, Pred;   // handles
-    uint64_t* mask0 = nullptr;      // I0 at the scatter mask scale, evaluation form [L+1][N]
-    uint64_t* maskg = nullptr;      // I0 at the gather mask scale, evaluation form [L+1][N]
+    // I0 in evaluation form [L+1][N]: canonical residues, or centred raw
+    // doubles in the rows of primes below 2^44 (the masked MAC's FP64 form)
+    uint64_t* mask0 = nullptr;      // at the scatter mask scale
+    uint64_t* maskg = nullptr;      // at the gather mask scale
     int epochs_done = 0;
     int refresh_round = 0;
     double refresh_seconds = 0;     // wall time spent in refreshes (host + device)

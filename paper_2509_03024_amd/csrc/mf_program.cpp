@@ -166,6 +166,7 @@ static void upload_one(Context* c, uint64_t*& dst, const int64_t* mask) {
     for (int i = 0; i <= c->L; ++i) mm.push(i, i);
     launch_expand_signed(c->tabs, mm, (const int64_t*)src.p, 1, 0, c->stream);
     launch_ntt(c->tabs, mm, false, c->stream);
+    launch_ew(c->tabs, EW_F64C, mm, mm, mm, c->stream);   // the MAC's FP64 limbs read centred doubles
     c->sync();
 }
 
@@ -238,8 +239,9 @@ int64_t weight_int(double w, double s_src, double q_acc, double mask_scale, doub
     return (int64_t)std::nearbyint((w * target * q_acc) / (s_src * mask_scale));
 }
 
-// Per-limb constants W * 2^64 mod q_i and their Shoup factors, computed once
-// per distinct integer weight.
+// Per-limb constants of an integer weight W, computed once per distinct W:
+// for a prime below 2^44 (the MAC's FP64 form) the centred W mod q_i and
+// fl(W/q_i) as raw doubles, otherwise W * 2^64 mod q_i and its Shoup factor.
 class WeightRows {
 public:
     WeightRows(Context* c, int nl) : c_(c), nl_(nl) {}
@@ -250,9 +252,19 @@ public:
         r.reserve(2 * (size_t)nl_);
         for (int i = 0; i < nl_; ++i) {
             const uint64_t q = c_->moduli[i];
-            const uint64_t x = mul_mod_host(from_signed(W, q), c_->mh[i].r_mod, q);
-            r.push_back(x);
-            r.push_back(shoup_pre(x, q));
+            const uint64_t w = from_signed(W, q);
+            if (q < kFp64PrimeBound) {
+                const double wd = w > q / 2 ? -(double)(q - w) : (double)w, wq = wd / (double)q;
+                uint64_t b0, b1;
+                std::memcpy(&b0, &wd, 8);
+                std::memcpy(&b1, &wq, 8);
+                r.push_back(b0);
+                r.push_back(b1);
+            } else {
+                const uint64_t x = mul_mod_host(w, c_->mh[i].r_mod, q);
+                r.push_back(x);
+                r.push_back(shoup_pre(x, q));
+            }
         }
         return rows_.emplace(W, std::move(r)).first->second;
     }
