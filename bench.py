@@ -114,6 +114,7 @@ def bench_mf(args):
     prof = pk.profile_report()
     pk.profile_enable(False)
     st = m.stats()
+    mac = m.mac_counts()
     U, V = m.decrypt_factors()
     rhat = m.decrypt_predictions(0)
     rmse = float(np.sqrt(np.mean((rhat - csr.values) ** 2)))
@@ -133,6 +134,7 @@ def bench_mf(args):
         "rmse_last_forward": round(rmse, 5),
         "kernels": {k2: {"launches": v[0], "total_ms": round(v[1], 3)}
                     for k2, v in sorted(prof.items(), key=lambda kv: -kv[1][1])},
+        "masked_mac": mac_summary(mac, prof, 1 << prm.log2N),
     }
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -211,6 +213,22 @@ def bench_serve(args):
         "config": {"workload": "serving: Poisson PREDICT/UPDATE requests over 6040 x 3706 tables, k=16, "
                                "N=2^15 (rows <= 512) / 2^16"},
         "sweep": results, "servers": stats}), flush=True)
+
+
+def mac_summary(mac, prof, N):
+    """The masked MAC's work in the timed epochs and the rates it ran at.  Source
+    rows are read (2 polynomials), accumulator rows read and written (2 x 2),
+    and each mask term forms one limb row of mask values from the resident I0
+    row (a permuted read, from cache)."""
+    _, ms, _ = prof.get("k_mask_mac_tasks", (0, 0.0, 0.0))
+    hbm = 8.0 * N * (2 * mac["group_rows"] + 4 * mac["task_rows"])
+    out = dict(mac)
+    out["terms_per_group"] = round(mac["terms"] / max(1, mac["groups"]), 2)
+    if ms > 0:
+        s = ms * 1e-3
+        out["source_and_accumulator_GBps"] = round(hbm / s / 1e9, 1)
+        out["mask_elements_per_s"] = float(f"{mac['term_rows'] * N / s:.4g}")
+    return out
 
 
 def main():

@@ -389,6 +389,13 @@ int csrmf_decrypt_predictions(csrmf_ctx* ctx, double* rhat, int32_t which);
  * included).  Any pointer may be NULL.  Errors: STATE. */
 int csrmf_mf_stats(const csrmf_ctx* ctx, int32_t* epochs_done, int32_t* refreshes, double* refresh_seconds);
 
+/* Work of the masked multiply-accumulate (the BlockPermute MAC of the MF
+ * program) since csrmf_init_factors, into counts[7]: accumulators (tasks),
+ * source ciphertexts (groups), mask terms, constant terms, and tasks, groups
+ * and mask terms each multiplied by the limbs of their launch (one limb row
+ * is N residues).  Errors: INVAL (counts NULL), STATE. */
+int csrmf_mf_mac_counts(const csrmf_ctx* ctx, int64_t* counts);
+
 /* Handles of the program's ciphertexts (test hook; owned by the program, do
  * not free): which = 0 rating ciphertexts, 1 user tables, 2 item tables,
  * 3 gathered users, 4 gathered items, 5 forward dot products of the last

@@ -94,6 +94,7 @@ _SIGS = {
     "csrmf_decrypt_predictions": [_p, _dp, ctypes.c_int32],
     "csrmf_mf_handles": [_p, ctypes.c_int32, _u64p, ctypes.c_int32, _i32p],
     "csrmf_mf_stats": [_p, _i32p, _i32p, ctypes.POINTER(ctypes.c_double)],
+    "csrmf_mf_mac_counts": [_p, ctypes.POINTER(ctypes.c_int64)],
     "csrmf_autotune": [_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32],
     "csrmf_set_ntt_schedule": [ctypes.c_int32],
     "csrmf_server_create": [_p, ctypes.c_int32, ctypes.c_int32, _dp, _dp, ctypes.c_double, ctypes.c_int32,
@@ -369,6 +370,13 @@ class MF:
         e, r, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         self.ctx._chk(lib.csrmf_mf_stats(self.ctx.h, ctypes.byref(e), ctypes.byref(r), ctypes.byref(s)))
         return {"epochs_done": e.value, "refreshes": r.value, "refresh_seconds": s.value}
+
+    def mac_counts(self):
+        """Masked-MAC work since init_factors (see csrmf_mf_mac_counts)."""
+        v = (ctypes.c_int64 * 7)()
+        self.ctx._chk(lib.csrmf_mf_mac_counts(self.ctx.h, v))
+        keys = ["tasks", "groups", "terms", "const_terms", "task_rows", "group_rows", "term_rows"]
+        return dict(zip(keys, list(v)))
 
     def init_factors(self, U0, V0):
         U = np.ascontiguousarray(U0, np.float64)

@@ -24,6 +24,11 @@ struct MfState {
     int epochs_done = 0;
     int refresh_round = 0;
     double refresh_seconds = 0;     // wall time spent in refreshes (host + device)
+    // masked-MAC work since initialisation: tasks (accumulators), groups
+    // (source ciphertexts), mask terms (constant terms apart), and the same
+    // counts weighted by the limbs each launch covers
+    int64_t mac_tasks = 0, mac_groups = 0, mac_terms = 0, mac_const_terms = 0;
+    int64_t mac_task_rows = 0, mac_group_rows = 0, mac_term_rows = 0;
     bool factors = false;
 };
 

@@ -322,6 +322,15 @@ struct MacLaunch {
         T.cw = (const uint64_t*)c->stage(cw.data(), cw.size() * 8);
         T.n_tasks = (int32_t)acc.size();
         T.n_limbs = nl;
+        MfState& st = state(c);
+        const int64_t n_const = std::count(gs.begin(), gs.end(), 0u);
+        st.mac_tasks += (int64_t)acc.size();
+        st.mac_groups += (int64_t)src.size();
+        st.mac_terms += (int64_t)gs.size() - n_const;
+        st.mac_const_terms += n_const;
+        st.mac_task_rows += (int64_t)acc.size() * nl;
+        st.mac_group_rows += (int64_t)src.size() * nl;
+        st.mac_term_rows += ((int64_t)gs.size() - n_const) * nl;
         T.cw_stride = nl;
         T.poly_stride = c->poly_stride();
         launch_mask_mac_tasks(c->tabs, T, mask, bytes, c->stream);
@@ -1082,6 +1091,17 @@ int csrmf_mf_stats(const csrmf_ctx* cx, int32_t* epochs_done, int32_t* refreshes
     if (epochs_done) *epochs_done = m.epochs_done;
     if (refreshes) *refreshes = m.refresh_round;
     if (refresh_seconds) *refresh_seconds = m.refresh_seconds;
+    API_END(c)
+}
+
+int csrmf_mf_mac_counts(const csrmf_ctx* cx, int64_t* counts) {
+    Context* c = const_cast<Context*>(reinterpret_cast<const Context*>(cx));
+    API_BEGIN(c)
+    if (!counts) throw Error(CSRMF_E_INVAL, "counts");
+    const MfState& m = csrmf::mfp::state(c);
+    const int64_t v[7] = {m.mac_tasks, m.mac_groups, m.mac_terms, m.mac_const_terms,
+                          m.mac_task_rows, m.mac_group_rows, m.mac_term_rows};
+    std::memcpy(counts, v, sizeof(v));
     API_END(c)
 }
 
