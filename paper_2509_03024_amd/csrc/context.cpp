@@ -840,17 +840,10 @@ void Context::ks_modup(const RowMap& d_in, int level, int B, uint64_t* ext, uint
     }
 }
 
-void Context::ks_inner(const uint64_t* ext, const RowMap& d_in, int level, int B, const Key& key, uint32_t g,
-                       uint64_t* u) {
+KsArgs Context::ks_args(const uint64_t* ext, const RowMap& d_in, int level, int B, const Key& key) const {
     const int nr = n_ext(level);
     const int nd = (int)lv[level].digits.size();
     const int nall = L + 1 + alpha;
-    RowMap mu;
-    mu.base = u;
-    mu.batch = B;
-    mu.batch_stride = 2 * (int64_t)nr * N;
-    mu.poly_stride = (int64_t)nr * N;
-    for (int t = 0; t < nr; ++t) mu.push(t, gmod_ext(level, t));
     KsArgs a;
     a.ext = ext;
     a.ext_batch_stride = (int64_t)nd * nr * N;
@@ -865,11 +858,27 @@ void Context::ks_inner(const uint64_t* ext, const RowMap& d_in, int level, int B
     for (int j = 0; j < nd; ++j)
         for (int i = lv[level].digits[j].lo; i < lv[level].digits[j].hi; ++i) a.digit_of[i] = j;
     a.own = d_in;
-    launch_ks_inner(tabs, mu, a, g, stream);
+    a.row0 = 0;
+    return a;
 }
 
-void Context::ks_moddown(uint64_t* u, int level, int B, const RowMap& out, const RowMap& addend,
-                         uint32_t g_add, bool addend_both) {
+// The inner product of the special limbs (the P part of u, which ModDown
+// converts); the Q limbs' inner product is formed inside the ModDown combine.
+void Context::ks_inner(const KsArgs& a, int level, int B, uint32_t g, uint64_t* u) {
+    const int nl = level + 1, nr = n_ext(level);
+    RowMap mu;
+    mu.base = u;
+    mu.batch = B;
+    mu.batch_stride = 2 * (int64_t)nr * N;
+    mu.poly_stride = (int64_t)nr * N;
+    for (int t = nl; t < nr; ++t) mu.push(t, gmod_ext(level, t));
+    KsArgs ap = a;
+    ap.row0 = nl;
+    launch_ks_inner(tabs, mu, ap, g, stream);
+}
+
+void Context::ks_moddown(const KsArgs& a, uint32_t g, uint64_t* u, int level, int B, const RowMap& out,
+                         const RowMap& addend, uint32_t g_add, bool addend_both) {
     const int nl = level + 1, nr = n_ext(level);
     const LevelConsts& c = lv[level];
     RowMap mp;   // P rows of u0 and u1: 2B groups of alpha rows
@@ -886,19 +895,13 @@ void Context::ks_moddown(uint64_t* u, int level, int B, const RowMap& out, const
     for (int i = 0; i < nl; ++i) mcv.push(i, i);
     launch_basis_convert(tabs, mcv, mp, c.md_y, c.md_c, false, stream);
     launch_ntt(tabs, mcv, false, stream);
-    RowMap mu;
-    mu.base = u;
-    mu.batch = B;
-    mu.batch_stride = 2 * (int64_t)nr * N;
-    mu.poly_stride = (int64_t)nr * N;
-    for (int i = 0; i < nl; ++i) mu.push(i, i);
     RowMap mc2;
     mc2.base = conv.p;
     mc2.batch = B;
     mc2.batch_stride = 2 * (int64_t)nl * N;
     mc2.poly_stride = (int64_t)nl * N;
     for (int i = 0; i < nl; ++i) mc2.push(i, i);
-    launch_moddown_combine(tabs, out, mu, mc2, addend, g_add, addend_both, c.md_pinv, stream);
+    launch_ks_combine(tabs, out, a, g, mc2, addend, g_add, addend_both, c.md_pinv, stream);
 }
 
 void Context::mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, std::vector<Ct*>& out) {
@@ -927,9 +930,10 @@ void Context::mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, st
     for (int i = 0; i < nl; ++i) d2.e[i] = ((uint32_t)(2 * nl + i) << 8) | (uint32_t)i;
     Scratch ext(pool, (size_t)B * nd * nr * N), coef(pool, (size_t)B * nl * N), u(pool, (size_t)B * 2 * nr * N);
     ks_modup(d2, lvl, B, ext.p, coef.p);
-    ks_inner(ext.p, d2, lvl, B, relin, 1, u.p);
+    const KsArgs ka = ks_args(ext.p, d2, lvl, B, relin);
+    ks_inner(ka, lvl, B, 1, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, a[i]->scale * b[i]->scale);
-    ks_moddown(u.p, lvl, B, map_cts(out, nl), md, 1, true);
+    ks_moddown(ka, 1, u.p, lvl, B, map_cts(out, nl), md, 1, true);
     fence();
 }
 
@@ -999,9 +1003,10 @@ void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& o
     launch_automorphism(tabs, g, md, c1, false, stream);
     Scratch ext(pool, (size_t)B * nd * nr * N), coef(pool, (size_t)B * nl * N), u(pool, (size_t)B * 2 * nr * N);
     ks_modup(md, lvl, B, ext.p, coef.p);
-    ks_inner(ext.p, md, lvl, B, key, 1, u.p);
+    const KsArgs ka = ks_args(ext.p, md, lvl, B, key);
+    ks_inner(ka, lvl, B, 1, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, in[i]->scale);
-    ks_moddown(u.p, lvl, B, map_cts(out, nl), map_cts(in, nl), g, false);
+    ks_moddown(ka, 1, u.p, lvl, B, map_cts(out, nl), map_cts(in, nl), g, false);
     fence();
 }
 
@@ -1023,8 +1028,9 @@ void Context::rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std:
             launch_ew(tabs, EW_COPY, o, a, a, stream);
             continue;
         }
-        ks_inner(ext.p, c1, lvl, 1, key_for(g), g, u.p);
-        ks_moddown(u.p, lvl, 1, map_ct(out[k]->d, nl), map_ct(in.d, nl), g, false);
+        const KsArgs ka = ks_args(ext.p, c1, lvl, 1, key_for(g));
+        ks_inner(ka, lvl, 1, g, u.p);
+        ks_moddown(ka, g, u.p, lvl, 1, map_ct(out[k]->d, nl), map_ct(in.d, nl), g, false);
     }
     fence();
 }
@@ -1105,9 +1111,10 @@ void Context::hoist_rotate(Hoist& h, uint32_t g, std::vector<Ct*>& out) {
     Scratch u(pool, (size_t)B * 2 * nr * N);
     RowMap c1 = map_cts(h.in, nl);
     for (int i = 0; i < nl; ++i) c1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
-    ks_inner(h.ext, c1, lvl, B, key, g, u.p);
+    const KsArgs ka = ks_args(h.ext, c1, lvl, B, key);
+    ks_inner(ka, lvl, B, g, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, h.in[i]->scale);
-    ks_moddown(u.p, lvl, B, map_cts(out, nl), map_cts(h.in, nl), g, false);
+    ks_moddown(ka, g, u.p, lvl, B, map_cts(out, nl), map_cts(h.in, nl), g, false);
     fence();
 }
 

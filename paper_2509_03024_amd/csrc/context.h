@@ -228,10 +228,14 @@ struct Context {
 
     // --- key-switching pieces
     void ks_modup(const RowMap& d_in, int level, int B, uint64_t* ext, uint64_t* coef);
-    // d_in: the ModUp input (evaluation form), which supplies each digit's own limbs
-    void ks_inner(const uint64_t* ext, const RowMap& d_in, int level, int B, const Key& key, uint32_t g, uint64_t* u);
-    void ks_moddown(uint64_t* u, int level, int B, const RowMap& out, const RowMap& addend,
-                    uint32_t g_add, bool addend_both);
+    // Arguments of the inner product with `key`; d_in: the ModUp input
+    // (evaluation form), which supplies each digit's own limbs
+    KsArgs ks_args(const uint64_t* ext, const RowMap& d_in, int level, int B, const Key& key) const;
+    // u's special limbs (tau_g applied to the ext reads)
+    void ks_inner(const KsArgs& a, int level, int B, uint32_t g, uint64_t* u);
+    // ModDown of u's special limbs, fused with the Q limbs' inner product (a, g)
+    void ks_moddown(const KsArgs& a, uint32_t g, uint64_t* u, int level, int B, const RowMap& out,
+                    const RowMap& addend, uint32_t g_add, bool addend_both);
 
     // --- schedule autotuning (returns a JSON report)
     std::string autotune(int rows);

@@ -119,16 +119,19 @@ struct KsArgs {
     int32_t n_digits;
     int32_t digit_of[kMaxMapRows];   // Q limb -> the digit that holds it
     RowMap own;                      // the key-switched polynomial itself (evaluation form), rows = Q limbs
+    int32_t row0;                    // limb of the first output row (the map's rows are limbs row0, row0+1, ...)
 };
 void launch_ks_inner(const DevTables& t, const RowMap& u, const KsArgs& a, uint32_t g, hipStream_t s);
 
-// ModDown combine over q_0..q_l:  out_i = (u_i - conv_i) * P^-1 (mod q_i)
-// [+ tau_g(addend_i) if addend.n > 0].  consts[2i], +1 = P^-1 mod q_i, shoup.
-// All maps have n = number of Q limbs; both polys (+poly_stride) are processed
-// when both_polys; the addend is applied to poly 0 only when add_poly0_only.
-void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap& u,
-                            const RowMap& conv, const RowMap& addend, uint32_t g_add,
-                            bool addend_both_polys, const uint64_t* consts, hipStream_t s);
+// Key-switch tail over the Q limbs q_0..q_l, fused: u = sum_j ext_j * key_j
+// (the inner product of launch_ks_inner, Galois element g applied to the ext
+// reads), then the ModDown combine out_i = (u_i - conv_i) * P^-1 (mod q_i)
+// [+ tau_g_add(addend_i) if addend.n > 0, on both polynomials when
+// addend_both, else on poly 0]; consts[2i], +1 = P^-1 mod q_i and its shoup.
+// The Q limbs' inner product is never stored.  a.row0 must be 0; out, conv and
+// addend have n = l + 1 rows (the Q limbs in order).
+void launch_ks_combine(const DevTables& t, const RowMap& out, const KsArgs& a, uint32_t g, const RowMap& conv,
+                       const RowMap& addend, uint32_t g_add, bool addend_both, const uint64_t* consts, hipStream_t s);
 
 // Multi-task masked MAC (the inner sums of block permutations): task t
 // accumulates into acc[t] (both polynomials, limbs 0..n_limbs-1) its groups

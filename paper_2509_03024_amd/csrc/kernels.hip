@@ -529,49 +529,63 @@ __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap 
     }
 }
 
+// Inner product of the extended digits with a switching key for limb kl at
+// element i: (sum_j x_j key_j0, sum_j x_j key_j1), x_j = ext_j (or, for the
+// limb's own digit, the input limb itself) at the tau_g source of i.
+__device__ __forceinline__ void ks_dot(const KsArgs& a, int b, int kl, int i, uint32_t src, int logN,
+                                       const Modulus& md, uint64_t& acc0, uint64_t& acc1) {
+    const int64_t krow = (int64_t)(kl < a.n_q ? kl : kl + a.key_shift) << logN;
+    const uint64_t* pe0 = a.ext + (int64_t)b * a.ext_batch_stride + ((int64_t)kl << logN);
+    // a Q limb's own digit is the input polynomial's limb itself
+    const int jown = kl < a.n_q ? a.digit_of[kl] : -1;
+    int omod;
+    const uint64_t* pown = kl < a.n_q ? map_row(a.own, b, kl, logN, omod) : nullptr;
+    acc0 = acc1 = 0;
+    for (int j = 0; j < a.n_digits; ++j) {
+        const uint64_t x = j == jown ? pown[src] : pe0[(int64_t)j * a.ext_digit_stride + src];
+        const uint64_t* pk = a.key + (int64_t)j * a.key_digit_stride + krow;
+        acc0 = add_mod(acc0, mul_mont(x, pk[i], md.q, md.qneg_inv), md.q);
+        acc1 = add_mod(acc1, mul_mont(x, pk[i + a.key_poly_stride], md.q, md.qneg_inv), md.q);
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) k_ks_inner(DevTables t, RowMap u, KsArgs a, uint32_t g) {
     EW_PROLOGUE(u)
     int mod;
     uint64_t* pu = map_row(u, b, k, logN, mod);
     const Modulus md = t.mods[mod];
-    const int64_t krow = (int64_t)(k < a.n_q ? k : k + a.key_shift) << logN;
-    const uint64_t* pe0 = a.ext + (int64_t)b * a.ext_batch_stride + ((int64_t)k << logN);
-    // a Q limb's own digit is the input polynomial's limb itself
-    const int jown = k < a.n_q ? a.digit_of[k] : -1;
-    int omod;
-    const uint64_t* pown = k < a.n_q ? map_row(a.own, b, k, logN, omod) : nullptr;
     for (int uu = 0; uu < kEwPerThread; ++uu) {
         const int i = base_i + uu * kThreads;
         const uint32_t src = (g == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g, logN);
-        uint64_t acc0 = 0, acc1 = 0;
-        for (int j = 0; j < a.n_digits; ++j) {
-            const uint64_t x = j == jown ? pown[src] : pe0[(int64_t)j * a.ext_digit_stride + src];
-            const uint64_t* pk = a.key + (int64_t)j * a.key_digit_stride + krow;
-            acc0 = add_mod(acc0, mul_mont(x, pk[i], md.q, md.qneg_inv), md.q);
-            acc1 = add_mod(acc1, mul_mont(x, pk[i + a.key_poly_stride], md.q, md.qneg_inv), md.q);
-        }
+        uint64_t acc0, acc1;
+        ks_dot(a, b, k + a.row0, i, src, logN, md, acc0, acc1);
         pu[i] = acc0;
         pu[i + u.poly_stride] = acc1;
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_moddown_combine(DevTables t, RowMap out, RowMap u, RowMap conv, RowMap add, uint32_t g_add, int add_both, const uint64_t* consts) {
+__global__ void __launch_bounds__(kThreads) k_ks_combine(DevTables t, RowMap out, KsArgs a, uint32_t g, RowMap conv,
+                                                         RowMap add, uint32_t g_add, int add_both,
+                                                         const uint64_t* consts) {
     EW_PROLOGUE(out)
-    int mod, m1, m2, m3;
+    int mod, m2, m3;
     uint64_t* o = map_row(out, b, k, logN, mod);
-    const uint64_t* pu = map_row(u, b, k, logN, m1);
     const uint64_t* pc = map_row(conv, b, k, logN, m2);
     const uint64_t* pa = add.n ? map_row(add, b, k, logN, m3) : nullptr;
-    const uint64_t q = t.mods[mod].q;
+    const Modulus md = t.mods[mod];
+    const uint64_t q = md.q;
     const uint64_t c = consts[2 * k], cp = consts[2 * k + 1];
     for (int uu = 0; uu < kEwPerThread; ++uu) {
         const int i = base_i + uu * kThreads;
-        const uint32_t src = (g_add == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g_add, logN);
-        uint64_t r0 = mul_shoup(sub_mod(pu[i], pc[i], q), c, cp, q);
-        uint64_t r1 = mul_shoup(sub_mod(pu[i + u.poly_stride], pc[i + conv.poly_stride], q), c, cp, q);
+        const uint32_t src = (g == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g, logN);
+        uint64_t u0, u1;
+        ks_dot(a, b, k, i, src, logN, md, u0, u1);
+        const uint32_t sa = (g_add == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g_add, logN);
+        uint64_t r0 = mul_shoup(sub_mod(u0, pc[i], q), c, cp, q);
+        uint64_t r1 = mul_shoup(sub_mod(u1, pc[i + conv.poly_stride], q), c, cp, q);
         if (pa) {
-            r0 = add_mod(r0, pa[src], q);
-            if (add_both) r1 = add_mod(r1, pa[src + add.poly_stride], q);
+            r0 = add_mod(r0, pa[sa], q);
+            if (add_both) r1 = add_mod(r1, pa[sa + add.poly_stride], q);
         }
         o[i] = r0;
         o[i + out.poly_stride] = r1;
@@ -893,11 +907,13 @@ void launch_ks_inner(const DevTables& t, const RowMap& u, const KsArgs& a, uint3
     { ProfScope ps_("k_ks_inner", s, NB(u.rows()) * (a.n_digits + 2) + NB(u.n) * 2 * a.n_digits); hipLaunchKernelGGL(k_ks_inner, dim3(ew_blocks(t, u)), dim3(kThreads), 0, s, t, u, a, g); }
 }
 
-void launch_moddown_combine(const DevTables& t, const RowMap& out, const RowMap& u, const RowMap& conv,
-                            const RowMap& addend, uint32_t g_add, bool addend_both, const uint64_t* consts,
-                            hipStream_t s) {
+void launch_ks_combine(const DevTables& t, const RowMap& out, const KsArgs& a, uint32_t g, const RowMap& conv,
+                       const RowMap& addend, uint32_t g_add, bool addend_both, const uint64_t* consts, hipStream_t s) {
     if (!out.rows()) return;
-    { ProfScope ps_("k_moddown_combine", s, NB(out.rows()) * (6 + (addend.n ? (addend_both ? 2 : 1) : 0))); hipLaunchKernelGGL(k_moddown_combine, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, u, conv,
+    if (a.row0 != 0) throw std::length_error("fused key-switch tail covers the Q limbs from limb 0");
+    const double bytes = NB(out.rows()) * (a.n_digits + 4 + (addend.n ? (addend_both ? 2 : 1) : 0)) +
+                         NB(out.n) * 2 * a.n_digits;
+    { ProfScope ps_("k_ks_combine", s, bytes); hipLaunchKernelGGL(k_ks_combine, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, a, g, conv,
                        addend, g_add, addend_both ? 1 : 0, consts); }
 }
 

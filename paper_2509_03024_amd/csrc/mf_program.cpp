@@ -322,15 +322,17 @@ struct MacLaunch {
         T.cw = (const uint64_t*)c->stage(cw.data(), cw.size() * 8);
         T.n_tasks = (int32_t)acc.size();
         T.n_limbs = nl;
-        MfState& st = state(c);
-        const int64_t n_const = std::count(gs.begin(), gs.end(), 0u);
-        st.mac_tasks += (int64_t)acc.size();
-        st.mac_groups += (int64_t)src.size();
-        st.mac_terms += (int64_t)gs.size() - n_const;
-        st.mac_const_terms += n_const;
-        st.mac_task_rows += (int64_t)acc.size() * nl;
-        st.mac_group_rows += (int64_t)src.size() * nl;
-        st.mac_term_rows += ((int64_t)gs.size() - n_const) * nl;
+        if (c->mf) {   // the MF program's counters (a server's launches are not counted)
+            MfState& st = *c->mf;
+            const int64_t n_const = std::count(gs.begin(), gs.end(), 0u);
+            st.mac_tasks += (int64_t)acc.size();
+            st.mac_groups += (int64_t)src.size();
+            st.mac_terms += (int64_t)gs.size() - n_const;
+            st.mac_const_terms += n_const;
+            st.mac_task_rows += (int64_t)acc.size() * nl;
+            st.mac_group_rows += (int64_t)src.size() * nl;
+            st.mac_term_rows += ((int64_t)gs.size() - n_const) * nl;
+        }
         T.cw_stride = nl;
         T.poly_stride = c->poly_stride();
         launch_mask_mac_tasks(c->tabs, T, mask, bytes, c->stream);
