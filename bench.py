@@ -288,9 +288,8 @@ def main():
         cur = list(cts)
         owned = []
         for r in CHAIN:
-            rot = ctx.rotate_batch(cur, r)
-            nxt = ctx.add_batch(cur, rot)
-            for h in rot + owned:
+            nxt = ctx.rotate_add_batch(cur, cur, r)   # cur + Rot(cur, r), the add fused into the key switch
+            for h in owned:
                 ctx.free(h)
             cur = owned = nxt
         conj = ctx.conjugate_batch(cur)

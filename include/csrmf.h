@@ -211,6 +211,12 @@ int csrmf_rotate_hoisted(csrmf_ctx* ctx, uint64_t a, const int32_t* r, int32_t n
 int csrmf_hmult_batch(csrmf_ctx* ctx, const uint64_t* a, const uint64_t* b, int32_t n,
                       uint64_t* out);
 int csrmf_rotate_batch(csrmf_ctx* ctx, const uint64_t* a, int32_t n, int32_t r, uint64_t* out);
+/* out[i] = acc[i] + Rot(a[i], r), the step of a rotate-and-sum (Sec. III-C:
+ * the dot products over a block are summed by rotations), with the addition
+ * fused into the key switch's last kernel.  acc[i] must have a[i]'s scale and
+ * at least its level; the result has a[i]'s level.  acc may equal a. */
+int csrmf_rotate_add_batch(csrmf_ctx* ctx, const uint64_t* a, const uint64_t* acc, int32_t n, int32_t r,
+                           uint64_t* out);
 int csrmf_conjugate_batch(csrmf_ctx* ctx, const uint64_t* a, int32_t n, uint64_t* out);
 
 /* ------------------------------------------------------------------------ */

@@ -81,6 +81,7 @@ _SIGS = {
     "csrmf_rotate_hoisted": [_p, ctypes.c_uint64, _i32p, ctypes.c_int32, _u64p],
     "csrmf_hmult_batch": [_p, _u64p, _u64p, ctypes.c_int32, _u64p],
     "csrmf_rotate_batch": [_p, _u64p, ctypes.c_int32, ctypes.c_int32, _u64p],
+    "csrmf_rotate_add_batch": [_p, _u64p, _u64p, ctypes.c_int32, ctypes.c_int32, _u64p],
     "csrmf_conjugate_batch": [_p, _u64p, ctypes.c_int32, _u64p],
     "csrmf_ntt_rows": [_p, _p, ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_int32],
     "csrmf_encrypt_csr_rows": [_p, ctypes.c_int32, ctypes.c_int32, _i64p, _i32p, _dp, _i32p],
@@ -313,6 +314,17 @@ class Context:
         a = np.asarray(a, np.uint64)
         out = np.zeros(len(a), np.uint64)
         self._chk(lib.csrmf_rotate_batch(self.h, _ptr(a, ctypes.c_uint64), len(a), r, _ptr(out, ctypes.c_uint64)))
+        return [int(x) for x in out]
+
+    def rotate_add_batch(self, a, acc, r):
+        """[acc[i] + Rot(a[i], r)], the addition fused into the key switch."""
+        a = np.asarray(a, np.uint64)
+        acc = np.asarray(acc, np.uint64)
+        if len(acc) != len(a):
+            raise ValueError("one accumulator per rotated ciphertext")
+        out = np.zeros(len(a), np.uint64)
+        self._chk(lib.csrmf_rotate_add_batch(self.h, _ptr(a, ctypes.c_uint64), _ptr(acc, ctypes.c_uint64), len(a), r,
+                                             _ptr(out, ctypes.c_uint64)))
         return [int(x) for x in out]
 
     def conjugate_batch(self, a):

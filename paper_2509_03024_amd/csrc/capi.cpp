@@ -349,6 +349,26 @@ int csrmf_rotate_batch(csrmf_ctx* cx, const uint64_t* a, int32_t n, int32_t r, u
     API_END(c)
 }
 
+int csrmf_rotate_add_batch(csrmf_ctx* cx, const uint64_t* a, const uint64_t* acc, int32_t n, int32_t r,
+                           uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(a && acc && out && n > 0, "arguments");
+    const uint32_t g = c->galois_for_step(r);
+    std::vector<Ct*> va, vacc;
+    for (int i = 0; i < n; ++i) {
+        va.push_back(&c->get(a[i]));
+        vacc.push_back(&c->get(acc[i]));
+    }
+    std::vector<Ct> res(n);
+    std::vector<Ct*> vo;
+    for (auto& x : res) vo.push_back(&x);
+    if (g == 1) c->add_batch(vacc, va, vo, false);
+    else c->rotate(va, g, vo, &vacc);
+    for (int i = 0; i < n; ++i) out[i] = c->put(res[i]);
+    API_END(c)
+}
+
 int csrmf_conjugate(csrmf_ctx* cx, uint64_t a, uint64_t* out) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)

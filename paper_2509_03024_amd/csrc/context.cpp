@@ -878,7 +878,7 @@ void Context::ks_inner(const KsArgs& a, int level, int B, uint32_t g, uint64_t* 
 }
 
 void Context::ks_moddown(const KsArgs& a, uint32_t g, uint64_t* u, int level, int B, const RowMap& out,
-                         const RowMap& addend, uint32_t g_add, bool addend_both) {
+                         const RowMap& addend, uint32_t g_add, bool addend_both, const RowMap& acc) {
     const int nl = level + 1, nr = n_ext(level);
     const LevelConsts& c = lv[level];
     RowMap mp;   // P rows of u0 and u1: 2B groups of alpha rows
@@ -901,7 +901,7 @@ void Context::ks_moddown(const KsArgs& a, uint32_t g, uint64_t* u, int level, in
     mc2.batch_stride = 2 * (int64_t)nl * N;
     mc2.poly_stride = (int64_t)nl * N;
     for (int i = 0; i < nl; ++i) mc2.push(i, i);
-    launch_ks_combine(tabs, out, a, g, mc2, addend, g_add, addend_both, c.md_pinv, stream);
+    launch_ks_combine(tabs, out, a, g, mc2, addend, g_add, addend_both, c.md_pinv, acc, stream);
 }
 
 void Context::mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, std::vector<Ct*>& out) {
@@ -978,10 +978,15 @@ void Context::rescale(const std::vector<Ct*>& v) {
     fence();
 }
 
-void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out) {
+void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out, const std::vector<Ct*>* acc) {
     if (split_batch(in.size(), [&](size_t i, size_t j) {
             std::vector<Ct*> so = slice(out, i, j);
-            rotate(slice(in, i, j), g, so);
+            if (acc) {
+                std::vector<Ct*> sa = slice(*acc, i, j);
+                rotate(slice(in, i, j), g, so, &sa);
+            } else {
+                rotate(slice(in, i, j), g, so);
+            }
         }))
         return;
     const int B = (int)in.size();
@@ -990,6 +995,13 @@ void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& o
     const int lvl = in[0]->level;
     for (Ct* c : in)
         if (c->level != lvl) throw Error(CSRMF_E_INVAL, "batch operands must share a level");
+    if (acc) {
+        if ((int)acc->size() != B) throw Error(CSRMF_E_INVAL, "one accumulator per rotated ciphertext");
+        for (int i = 0; i < B; ++i) {
+            if ((*acc)[i]->level < lvl) throw Error(CSRMF_E_INVAL, "accumulator below the rotated ciphertext's level");
+            check_scales(in[i]->scale, (*acc)[i]->scale);
+        }
+    }
     const int nl = lvl + 1, nr = n_ext(lvl);
     const int nd = (int)lv[lvl].digits.size();
     Scratch d(pool, (size_t)B * nl * N);
@@ -1006,7 +1018,8 @@ void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& o
     const KsArgs ka = ks_args(ext.p, md, lvl, B, key);
     ks_inner(ka, lvl, B, 1, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, in[i]->scale);
-    ks_moddown(ka, 1, u.p, lvl, B, map_cts(out, nl), map_cts(in, nl), g, false);
+    ks_moddown(ka, 1, u.p, lvl, B, map_cts(out, nl), map_cts(in, nl), g, false,
+               acc ? map_cts(*acc, nl) : RowMap());
     fence();
 }
 

@@ -210,7 +210,8 @@ struct Context {
     void mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, std::vector<Ct*>& out);
     void rescale(const std::vector<Ct*>& v);          // in place
     void mod_drop(Ct& c, int level);                   // in place
-    void rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out);
+    // out[i] = tau_g(in[i]) key-switched; with acc, out[i] = acc[i] + that (fused)
+    void rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out, const std::vector<Ct*>* acc = nullptr);
     void rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std::vector<Ct*>& out);
     void check_scales(double a, double b) const;
 
@@ -235,7 +236,7 @@ struct Context {
     void ks_inner(const KsArgs& a, int level, int B, uint32_t g, uint64_t* u);
     // ModDown of u's special limbs, fused with the Q limbs' inner product (a, g)
     void ks_moddown(const KsArgs& a, uint32_t g, uint64_t* u, int level, int B, const RowMap& out,
-                    const RowMap& addend, uint32_t g_add, bool addend_both);
+                    const RowMap& addend, uint32_t g_add, bool addend_both, const RowMap& acc = RowMap());
 
     // --- schedule autotuning (returns a JSON report)
     std::string autotune(int rows);

@@ -128,10 +128,12 @@ void launch_ks_inner(const DevTables& t, const RowMap& u, const KsArgs& a, uint3
 // reads), then the ModDown combine out_i = (u_i - conv_i) * P^-1 (mod q_i)
 // [+ tau_g_add(addend_i) if addend.n > 0, on both polynomials when
 // addend_both, else on poly 0]; consts[2i], +1 = P^-1 mod q_i and its shoup.
-// The Q limbs' inner product is never stored.  a.row0 must be 0; out, conv and
-// addend have n = l + 1 rows (the Q limbs in order).
+// With acc.n > 0 the accumulator acc (both polynomials) is added as well.
+// The Q limbs' inner product is never stored.  a.row0 must be 0; out, conv,
+// addend and acc have n = l + 1 rows (the Q limbs in order).
 void launch_ks_combine(const DevTables& t, const RowMap& out, const KsArgs& a, uint32_t g, const RowMap& conv,
-                       const RowMap& addend, uint32_t g_add, bool addend_both, const uint64_t* consts, hipStream_t s);
+                       const RowMap& addend, uint32_t g_add, bool addend_both, const uint64_t* consts,
+                       const RowMap& acc, hipStream_t s);
 
 // Multi-task masked MAC (the inner sums of block permutations): task t
 // accumulates into acc[t] (both polynomials, limbs 0..n_limbs-1) its groups

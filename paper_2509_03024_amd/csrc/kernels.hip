@@ -566,12 +566,13 @@ __global__ void __launch_bounds__(kThreads) k_ks_inner(DevTables t, RowMap u, Ks
 
 __global__ void __launch_bounds__(kThreads) k_ks_combine(DevTables t, RowMap out, KsArgs a, uint32_t g, RowMap conv,
                                                          RowMap add, uint32_t g_add, int add_both,
-                                                         const uint64_t* consts) {
+                                                         const uint64_t* consts, RowMap acc) {
     EW_PROLOGUE(out)
-    int mod, m2, m3;
+    int mod, m2, m3, m4;
     uint64_t* o = map_row(out, b, k, logN, mod);
     const uint64_t* pc = map_row(conv, b, k, logN, m2);
     const uint64_t* pa = add.n ? map_row(add, b, k, logN, m3) : nullptr;
+    const uint64_t* pacc = acc.n ? map_row(acc, b, k, logN, m4) : nullptr;
     const Modulus md = t.mods[mod];
     const uint64_t q = md.q;
     const uint64_t c = consts[2 * k], cp = consts[2 * k + 1];
@@ -586,6 +587,10 @@ __global__ void __launch_bounds__(kThreads) k_ks_combine(DevTables t, RowMap out
         if (pa) {
             r0 = add_mod(r0, pa[sa], q);
             if (add_both) r1 = add_mod(r1, pa[sa + add.poly_stride], q);
+        }
+        if (pacc) {
+            r0 = add_mod(r0, pacc[i], q);
+            r1 = add_mod(r1, pacc[i + acc.poly_stride], q);
         }
         o[i] = r0;
         o[i + out.poly_stride] = r1;
@@ -908,13 +913,15 @@ void launch_ks_inner(const DevTables& t, const RowMap& u, const KsArgs& a, uint3
 }
 
 void launch_ks_combine(const DevTables& t, const RowMap& out, const KsArgs& a, uint32_t g, const RowMap& conv,
-                       const RowMap& addend, uint32_t g_add, bool addend_both, const uint64_t* consts, hipStream_t s) {
+                       const RowMap& addend, uint32_t g_add, bool addend_both, const uint64_t* consts,
+                       const RowMap& acc, hipStream_t s) {
     if (!out.rows()) return;
     if (a.row0 != 0) throw std::length_error("fused key-switch tail covers the Q limbs from limb 0");
-    const double bytes = NB(out.rows()) * (a.n_digits + 4 + (addend.n ? (addend_both ? 2 : 1) : 0)) +
+    if (acc.n && (acc.n != out.n || acc.batch != out.batch)) throw std::length_error("accumulator map differs in shape");
+    const double bytes = NB(out.rows()) * (a.n_digits + 4 + (addend.n ? (addend_both ? 2 : 1) : 0) + (acc.n ? 2 : 0)) +
                          NB(out.n) * 2 * a.n_digits;
     { ProfScope ps_("k_ks_combine", s, bytes); hipLaunchKernelGGL(k_ks_combine, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, a, g, conv,
-                       addend, g_add, addend_both ? 1 : 0, consts); }
+                       addend, g_add, addend_both ? 1 : 0, consts, acc); }
 }
 
 void launch_mask_mac_tasks(const DevTables& t, const MaskTasks& T, const uint64_t* i0, double bytes, hipStream_t s) {

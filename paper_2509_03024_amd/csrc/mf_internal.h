@@ -78,6 +78,7 @@ std::vector<Ct*> ptrs(std::vector<Ct>& v);
 std::vector<Ct> dropped(const std::vector<Ct*>& v, int level);
 std::vector<Ct> hmult_all(Context* c, const std::vector<Ct*>& a, const std::vector<Ct*>& b);
 std::vector<Ct> rotate_all(Context* c, const std::vector<Ct*>& a, int64_t r);
+std::vector<Ct> rotate_add_all(Context* c, const std::vector<Ct*>& a, int64_t r);   // a + Rot(a, r), fused
 std::vector<Ct> add_all(Context* c, const std::vector<Ct*>& a, const std::vector<Ct*>& b, bool sub);
 int64_t weight_int(double w, double s_src, double q_acc, double mask_scale, double target);
 std::vector<int64_t> encode_all(Context* c, const std::vector<std::vector<double>>& zs, double scale);

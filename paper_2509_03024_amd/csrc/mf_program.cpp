@@ -228,6 +228,14 @@ std::vector<Ct> rotate_all(Context* c, const std::vector<Ct*>& a, int64_t r) {
     return out;
 }
 
+// a[i] + Rot(a[i], r), the addition fused into the key switch
+std::vector<Ct> rotate_add_all(Context* c, const std::vector<Ct*>& a, int64_t r) {
+    std::vector<Ct> out(a.size());
+    std::vector<Ct*> po = ptrs(out);
+    c->rotate(a, c->galois_for_step(r), po, &a);
+    return out;
+}
+
 std::vector<Ct> add_all(Context* c, const std::vector<Ct*>& a, const std::vector<Ct*>& b, bool sub) {
     std::vector<Ct> out(a.size());
     std::vector<Ct*> po = ptrs(out);
@@ -470,39 +478,31 @@ std::vector<Ct> block_permute_cached(Context* c, MfState& m, const std::vector<C
         for (int d = 0; d < n_dest; ++d)
             if (inner[d][gamma].d) ds.push_back(d);
         if (ds.empty()) continue;
-        std::vector<Ct*> in;
-        for (int d : ds) in.push_back(&inner[d][gamma]);
-        std::vector<Ct> rot(ds.size());
-        std::vector<Ct*> prot = ptrs(rot);
-        c->rotate(in, c->galois_for_step((int64_t)gamma * G * B), prot);
-        std::vector<Ct*> a, b;
-        std::vector<int> add_d;
-        for (size_t i = 0; i < ds.size(); ++i) {
-            const int d = ds[i];
-            c->pool.put(inner[d][gamma].d);
-            inner[d][gamma].d = nullptr;
-            if (acc_init[d]) {
-                a.push_back(&acc[d]);
-                b.push_back(&rot[i]);
-                add_d.push_back(d);
-            } else {
-                c->pool.put(acc[d].d);
+        // destinations with a running sum take acc + Rot(inner) in one fused
+        // key switch; the others start their sum with the rotation
+        const uint32_t gg = c->galois_for_step((int64_t)gamma * G * B);
+        std::vector<int> part[2];   // [0]: no running sum yet, [1]: acc + rotation
+        for (int d : ds) part[acc_init[d] ? 1 : 0].push_back(d);
+        for (int with_acc = 0; with_acc < 2; ++with_acc) {
+            const std::vector<int>& dd = part[with_acc];
+            if (dd.empty()) continue;
+            std::vector<Ct*> in, accs;
+            for (int d : dd) {
+                in.push_back(&inner[d][gamma]);
+                accs.push_back(&acc[d]);
+            }
+            std::vector<Ct> rot(dd.size());
+            std::vector<Ct*> prot = ptrs(rot);
+            c->rotate(in, gg, prot, with_acc ? &accs : nullptr);
+            for (size_t i = 0; i < dd.size(); ++i) {
+                const int d = dd[i];
+                c->pool.put(inner[d][gamma].d);
+                inner[d][gamma].d = nullptr;
+                if (acc[d].d) c->pool.put(acc[d].d);
                 acc[d] = rot[i];
-                rot[i].d = nullptr;
                 acc_init[d] = 1;
             }
         }
-        if (!a.empty()) {
-            std::vector<Ct> sum(a.size());
-            std::vector<Ct*> ps = ptrs(sum);
-            c->add_batch(a, b, ps, false);
-            for (size_t i = 0; i < add_d.size(); ++i) {
-                c->pool.put(acc[add_d[i]].d);
-                acc[add_d[i]] = sum[i];
-            }
-        }
-        for (auto& r : rot)
-            if (r.d) c->pool.put(r.d);
     }
     // self terms: one task per destination; the constant c is a term with
     // Galois element 0 (no mask), the corrections are masked terms
@@ -584,11 +584,18 @@ int choose_G(const std::vector<std::vector<Move>>& dests, int D) {
     return best_G;
 }
 
-static void rotate_chunked(Context* c, std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out) {
+// out[i] = Rot_g(in[i]) (+ acc[i], fused, when acc is given)
+static void rotate_chunked(Context* c, std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out,
+                           const std::vector<Ct*>* acc = nullptr) {
     for (size_t i = 0; i < in.size(); i += kRotateBatch) {
         const size_t j = std::min(in.size(), i + kRotateBatch);
         std::vector<Ct*> a(in.begin() + (long)i, in.begin() + (long)j), o(out.begin() + (long)i, out.begin() + (long)j);
-        c->rotate(a, g, o);
+        if (acc) {
+            std::vector<Ct*> s(acc->begin() + (long)i, acc->begin() + (long)j);
+            c->rotate(a, g, o, &s);
+        } else {
+            c->rotate(a, g, o);
+        }
     }
 }
 
@@ -729,42 +736,35 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
         for (int i = 0; i < ns; ++i)
             if (base_owned[i]) c->pool.put(base[i].d);
     }
-    // giant steps: pairwise tree, one batched rotation and one batched add per level
+    // giant steps: pairwise tree, one batched rotation per level (the addition
+    // of the left node fused into the key switch where both nodes exist)
     int width = n_gamma;
     int64_t step = (int64_t)G * B;
     while (width > 1) {
         const int half = width / 2;
-        std::vector<std::vector<Ct>> rot(n_dest, std::vector<Ct>(half));
-        std::vector<Ct*> in, out;
-        for (int d = 0; d < n_dest; ++d)
-            for (int t2 = 0; t2 < half; ++t2)
-                if (nodes[d][2 * t2 + 1].d) {
-                    in.push_back(&nodes[d][2 * t2 + 1]);
-                    out.push_back(&rot[d][t2]);
-                }
-        if (!in.empty()) rotate_chunked(c, in, c->galois_for_step(step), out);
-        for (Ct* x : in) c->pool.put(x->d);
         std::vector<std::vector<Ct>> nxt(n_dest, std::vector<Ct>(half));
-        std::vector<Ct*> a, b, o;
+        std::vector<Ct*> in_f, acc_f, out_f, in_p, out_p;
         for (int d = 0; d < n_dest; ++d)
             for (int t2 = 0; t2 < half; ++t2) {
                 Ct& left = nodes[d][2 * t2];
-                Ct& right = rot[d][t2];
+                Ct& right = nodes[d][2 * t2 + 1];
                 if (left.d && right.d) {
-                    a.push_back(&left);
-                    b.push_back(&right);
-                    o.push_back(&nxt[d][t2]);
+                    in_f.push_back(&right);
+                    acc_f.push_back(&left);
+                    out_f.push_back(&nxt[d][t2]);
+                } else if (right.d) {
+                    in_p.push_back(&right);
+                    out_p.push_back(&nxt[d][t2]);
                 } else if (left.d) {
                     nxt[d][t2] = left;
-                } else if (right.d) {
-                    nxt[d][t2] = right;
                 }
             }
-        if (!a.empty()) {
-            c->add_batch(a, b, o, false);
-            for (Ct* x : a) c->pool.put(x->d);
-            for (Ct* x : b) c->pool.put(x->d);
-        }
+        const uint32_t gs = c->galois_for_step(step);
+        if (!in_f.empty()) rotate_chunked(c, in_f, gs, out_f, &acc_f);
+        if (!in_p.empty()) rotate_chunked(c, in_p, gs, out_p);
+        for (Ct* x : in_f) c->pool.put(x->d);
+        for (Ct* x : acc_f) c->pool.put(x->d);
+        for (Ct* x : in_p) c->pool.put(x->d);
         nodes.swap(nxt);
         width = half;
         step *= 2;
@@ -860,12 +860,8 @@ std::vector<Ct> dot_products(Context* c, MfState& m, const std::vector<Ct*>& ug,
     std::vector<Ct> T = hmult_all(c, ug, vg);
     if (sp_out) *sp_out = T[0].scale;
     for (int s = 1; s < m.B; s *= 2) {
-        std::vector<Ct*> pt = ptrs(T);
-        std::vector<Ct> rot = rotate_all(c, pt, s);
-        std::vector<Ct*> pr = ptrs(rot);
-        std::vector<Ct> sum = add_all(c, pt, pr, false);
+        std::vector<Ct> sum = rotate_add_all(c, ptrs(T), s);
         release(c, T);
-        release(c, rot);
         T = std::move(sum);
     }
     std::vector<Ct*> pt = ptrs(T);

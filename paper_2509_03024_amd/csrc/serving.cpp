@@ -258,12 +258,8 @@ void Server::process(std::vector<ServeRequest*>& batch) {
         std::vector<Ct> T = mfp::hmult_all(c, pe, pvd);
         // sum over all blocks
         for (int s = B; s < B * D; s *= 2) {
-            std::vector<Ct*> pt_ = mfp::ptrs(T);
-            std::vector<Ct> rot = mfp::rotate_all(c, pt_, s);
-            std::vector<Ct*> pr = mfp::ptrs(rot);
-            std::vector<Ct> sum = mfp::add_all(c, pt_, pr, false);
+            std::vector<Ct> sum = mfp::rotate_add_all(c, mfp::ptrs(T), s);
             mfp::release(c, T);
-            mfp::release(c, rot);
             T = std::move(sum);
         }
         // per request: add chunk sums, then combine with the self term

@@ -127,6 +127,27 @@ def test_rotation(pair, r):
     _same(lib, lib.rotate(h, r), orc.rotate(o, r))
 
 
+def test_rotate_add_batch(pair):
+    """acc + Rot(a, r) with the addition fused into the key switch equals the
+    oracle's rotation followed by its addition; also with acc = a, with an
+    accumulator above a's level, and for r = 0 (a plain addition)."""
+    lib, orc = pair
+    hs = [_enc_pair(lib, orc, 60 + i) for i in range(3)]
+    acc = [_enc_pair(lib, orc, 70 + i) for i in range(3)]
+    a = [h for h, _, _ in hs]
+    out = lib.rotate_add_batch(a, [h for h, _, _ in acc], 3)
+    for (h, o, _), (ha, oa, _), ho in zip(hs, acc, out):
+        _same(lib, ho, orc.add(oa, orc.rotate(o, 3)))
+    out = lib.rotate_add_batch(a, a, 5)
+    for (h, o, _), ho in zip(hs, out):
+        _same(lib, ho, orc.add(o, orc.rotate(o, 5)))
+    hl, ol, _ = _enc_pair(lib, orc, 80, level=1)
+    (ho,) = lib.rotate_add_batch([hl], [hs[0][0]], 1)
+    _same(lib, ho, orc.add(hs[0][1], orc.rotate(ol, 1)))
+    (ho,) = lib.rotate_add_batch([a[1]], [a[2]], 0)
+    _same(lib, ho, orc.add(hs[2][1], hs[1][1]))
+
+
 def test_rotation_lower_level_and_conjugate(pair):
     lib, orc = pair
     h, o, z = _enc_pair(lib, orc, 30, level=1)
