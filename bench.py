@@ -28,10 +28,23 @@ CHAIN = [1 << a for a in range(15)]
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of a kernel in the timed step (average over the step's
 # launches), from rocprofv3 FETCH_SIZE (x2.0) + WRITE_SIZE (x1.0) counters, the
-# factors read off a 512 MiB copy, at the 512-row NTT schedule the autotuner
-# picks here (profiles/ks_kernel_batch_n16_hbm_counters.md); only valid for the
-# kernel code the counters were taken on.
-TRAFFIC = {"k_ntt_pass<rows,fwd>": 482.1e6}
+# factors read off a 512 MiB copy (profiles/ks_kernel_batch_n16_hbm_counters.md),
+# with the NTT schedule (rows per pair of passes) of that run and the
+# algorithmic bytes of its launches; only valid for the kernel code the counters
+# were taken on.  Under another schedule the launches differ in size and the
+# measured bytes are scaled by the algorithmic bytes (traffic_basis says which).
+TRAFFIC = {"k_ntt_pass<rows,fwd>": {"schedule": 2048, "bytes": 1494.8e6, "alg_bytes": 1471.1e6}}
+
+
+def traffic_of(name, schedule, alg_bytes):
+    t = TRAFFIC.get(name)
+    if t is None:
+        return None, None
+    if t["schedule"] == schedule:
+        return t["bytes"], f"rocprofv3 counters at NTT schedule {schedule}"
+    return round(t["bytes"] / t["alg_bytes"] * alg_bytes), \
+        f"rocprofv3 counters at NTT schedule {t['schedule']}, scaled by algorithmic bytes to schedule {schedule}"
+
 
 
 def parse():
@@ -254,8 +267,10 @@ def main():
     if args.ntt_chunk is not None:
         pk.set_ntt_schedule(args.ntt_chunk)
         tune = {"fixed": args.ntt_chunk}
+        schedule = args.ntt_chunk
     else:
         tune = ctx.autotune()
+        schedule = tune["chosen"]
     log(f"NTT schedule {tune}")
     N = ctx.N
     L = ctx.L
@@ -351,6 +366,7 @@ def main():
     name, (launches, total_ms, total_bytes) = dom
     avg_ms = total_ms / launches
     achieved = (total_bytes / launches) / (avg_ms * 1e-3) / 1e9
+    traffic, traffic_basis = traffic_of(name, schedule, total_bytes / launches)
     kernel_table = {k: {"launches": v[0], "total_ms": round(v[1], 3), "avg_us": round(1e3 * v[1] / v[0], 2),
                         "alg_GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                     for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
@@ -378,8 +394,8 @@ def main():
                            "what": "same rotate-and-sum chain, one ciphertext per call",
                            "batched_rotation_phase_speedup": round(n_rot * args.steps / phase["rotations"] / plain_rate, 2)},
         "roofline": {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(name),
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 counters)",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch", "traffic_basis": traffic_basis,
                      "alg_bytes_per_launch": round(total_bytes / launches),
                      "avg_launch_us": round(1e3 * avg_ms, 2), "launches_in_timed_steps": launches},
         "kernels": kernel_table,
