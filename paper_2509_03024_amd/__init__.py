@@ -504,9 +504,13 @@ def profile_enable(on=True):
 def profile_report():
     """{kernel: (launches, total_ms, algorithmic_bytes)} recorded since profile_enable()."""
     import json
-    n = lib.csrmf_profile_report(None, 0)
-    buf = ctypes.create_string_buffer(n + 1)
-    lib.csrmf_profile_report(buf, n + 1)
+    cap = 1 << 20
+    while True:   # one call that fits: two calls could see reports of different lengths
+        buf = ctypes.create_string_buffer(cap)
+        n = lib.csrmf_profile_report(buf, cap)
+        if n < cap:
+            break
+        cap = 2 * n
     return {k: (int(v[0]), float(v[1]), float(v[2])) for k, v in json.loads(buf.value.decode()).items()}
 
 

@@ -1,5 +1,6 @@
 #include "prof.h"
 
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -62,21 +63,24 @@ std::string prof_report_json() {
     struct Agg { long n = 0; double ms = 0, bytes = 0; };
     std::map<std::string, Agg> agg;
     for (auto& r : g_recs) {
+        (void)hipEventSynchronize(r.a);
         (void)hipEventSynchronize(r.b);
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = 0.f;
         auto& e = agg[r.name];
         e.n += 1;
         e.ms += ms;
         e.bytes += r.bytes;
     }
     std::ostringstream o;
+    o.precision(12);
     o << "{";
     bool first = true;
     for (auto& kv : agg) {
         if (!first) o << ", ";
         first = false;
-        o << "\"" << kv.first << "\": [" << kv.second.n << ", " << kv.second.ms << ", " << kv.second.bytes << "]";
+        const double ms = std::isfinite(kv.second.ms) ? kv.second.ms : 0.0;
+        o << "\"" << kv.first << "\": [" << kv.second.n << ", " << ms << ", " << kv.second.bytes << "]";
     }
     o << "}";
     return o.str();
