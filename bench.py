@@ -33,13 +33,17 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of its launches; only valid for the kernel code the counters
 # were taken on.  Under another schedule the launches differ in size and the
 # measured bytes are scaled by the algorithmic bytes (traffic_basis says which).
-TRAFFIC = {"k_ntt_pass<rows,fwd>": {"schedule": 2048, "bytes": 1494.8e6, "alg_bytes": 1471.1e6}}
+# (schedule None: the kernel's launches do not depend on the NTT schedule.)
+TRAFFIC = {"k_ntt_pass<rows,fwd>": {"schedule": 2048, "bytes": 1494.4e6, "alg_bytes": 1471.1e6},
+           "k_basis_convert": {"schedule": None, "bytes": 1174.5e6, "alg_bytes": 1174.4e6}}
 
 
 def traffic_of(name, schedule, alg_bytes):
     t = TRAFFIC.get(name)
     if t is None:
         return None, None
+    if t["schedule"] is None:
+        return t["bytes"], "rocprofv3 counters"
     if t["schedule"] == schedule:
         return t["bytes"], f"rocprofv3 counters at NTT schedule {schedule}"
     return round(t["bytes"] / t["alg_bytes"] * alg_bytes), \
