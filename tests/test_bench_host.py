@@ -1,0 +1,66 @@
+"""Host logic of bench.py (no GPU): the measured-traffic lookup that feeds the
+roofline object, the masked-MAC summary of the MF lines, and the one-GPU rule."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_traffic_at_the_measured_schedule_is_the_measurement():
+    b = _bench()
+    for name, t in b.TRAFFIC.items():
+        if t["schedule"] is None:
+            val, basis = b.traffic_of(name, 512, t["alg_bytes"])
+            assert val == t["bytes"] and basis == "rocprofv3 counters"
+        else:
+            val, basis = b.traffic_of(name, t["schedule"], t["alg_bytes"])
+            assert val == t["bytes"] and str(t["schedule"]) in basis
+
+
+def test_traffic_under_another_schedule_scales_with_the_launch():
+    b = _bench()
+    name, t = next((n, t) for n, t in b.TRAFFIC.items() if t["schedule"] is not None)
+    other = 64 if t["schedule"] != 64 else 128
+    half = t["alg_bytes"] / 2
+    val, basis = b.traffic_of(name, other, half)
+    assert abs(val - t["bytes"] / 2) <= 1.0
+    assert "scaled" in basis and str(other) in basis
+    # the measured bytes are within a few percent of the algorithmic ones
+    assert 0.99 <= t["bytes"] / t["alg_bytes"] <= 1.10
+
+
+def test_traffic_of_an_unmeasured_kernel_is_null():
+    b = _bench()
+    assert b.traffic_of("k_not_measured", 2048, 1e9) == (None, None)
+
+
+def test_mac_summary_rates():
+    b = _bench()
+    N = 1 << 15
+    mac = {"tasks": 10, "groups": 40, "terms": 44, "const_terms": 2,
+           "task_rows": 100, "group_rows": 400, "term_rows": 440}
+    prof = {"k_mask_mac_tasks": (3, 2.0, 0.0)}   # 3 launches, 2 ms
+    out = b.mac_summary(mac, prof, N)
+    assert out["terms_per_group"] == 1.1
+    hbm = 8.0 * N * (2 * 400 + 4 * 100)
+    assert abs(out["source_and_accumulator_GBps"] - round(hbm / 2e-3 / 1e9, 1)) < 1e-9
+    assert out["mask_elements_per_s"] == float(f"{440 * N / 2e-3:.4g}")
+    # without a timed MAC launch only the counts are reported
+    out = b.mac_summary(mac, {}, N)
+    assert "source_and_accumulator_GBps" not in out and out["groups"] == 40
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
