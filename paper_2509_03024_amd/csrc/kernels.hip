@@ -22,7 +22,7 @@ constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (sepa
 // elements of one limb; all tasks of a tile run on one XCD, and the tiles of
 // the launch's sources (babies: up to ~500 ciphertexts x 16 B per element)
 // must stay within that XCD's 4 MB L2, which 2 allows (8 was measured 16 %
-// slower, 4x larger tiles).
+// slower, 4x larger tiles; 4 only 2 % faster at half the occupancy).
 constexpr int kMacPerThread = 2;
 constexpr int kEwPerThread = 2;
 
