@@ -1,19 +1,30 @@
-"""Benchmark: batched CKKS key switching at N = 2^16 on one MI355X.
+"""Benchmark: batched CKKS key switching at N = 2^16 on one MI355X, with the
+encrypted MF workloads beside it.
 
-Workload (the kernel-batch configuration): 64 ciphertexts of uniform random
-residues at N = 2^16 with q_0 (60-bit) + 24 x 40-bit scale primes, 3 x 60-bit
-special primes, dnum = 3.  One step is one pass of the whole batched path:
-  (i)   forward + inverse NTT of all 64 x 2 x 25 limbs,
-  (ii)  64 HMult (tensor, relinearise, rescale) ct_i x ct_{i+1 mod 64},
-  (iii) per ciphertext a rotate-and-sum chain over steps 2^0 .. 2^14 plus a
-        conjugation: 16 key switches per ciphertext, 1024 per step.
-value = key-switch rotations per second over whole steps (1024 * K / time of
-the K timed steps, phases (i) and (ii) included).
+Default run (one JSON line):
+* the kernel-batch workload (the headline metric): 64 ciphertexts of uniform
+  random residues at N = 2^16 with q_0 (60-bit) + 24 x 40-bit scale primes,
+  3 x 60-bit special primes, dnum = 3.  One step is one pass of the whole
+  batched path:
+    (i)   forward + inverse NTT of all 64 x 2 x 25 limbs,
+    (ii)  64 HMult (tensor, relinearise, rescale) ct_i x ct_{i+1 mod 64},
+    (iii) per ciphertext a rotate-and-sum chain over steps 2^0 .. 2^14 plus a
+          conjugation: 16 key switches per ciphertext, 1024 per step.
+  value = key-switch rotations per second over whole steps (1024 * K / time
+  of the K timed steps, phases (i) and (ii) included);
+* "mf100k": 10 encrypted MF epochs on the MovieLens-100K-shaped matrix
+  (943 x 1682, 99,926 ratings, k = 10, N = 2^15, two table refreshes);
+* "tiny": the latency of one encrypted MF epoch at the tiny configuration
+  (32 x 64, 205 ratings, k = 4, N = 2^12);
+* "cpu_baseline" legs: the oracle on bounded samples of each workload, run
+  in parallel processes after the GPU work.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       [--no-mf] [--workload ks|mf100k|mf1m|serve]
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -26,16 +37,23 @@ PLAIN_CT = 8
 LOGN = 16
 CHAIN = [1 << a for a in range(15)]
 HBM_PEAK_GBS = 8000.0
+# MI355X: 256 CUs at 2.4 GHz; fp64 vector 78.6 TFLOP/s (FMA = 2), fp32 157.3.
+FP64_FMA_PER_S = 78.6e12 / 2
+# Modular-multiply rates measured on an MI355X by a register-resident
+# microbenchmark (4 independent dependent chains per thread, 8192 x 256
+# threads, every result stored; method and figures in the design doc), in
+# operations per second.
+MODMUL_RATE = {"shoup_u64": None, "montgomery_u64": None, "fp64_exact": None, "mac_64x64_128": None}
 # HBM bytes per launch of a kernel in the timed step (average over the step's
-# launches), from rocprofv3 FETCH_SIZE (x2.0) + WRITE_SIZE (x1.0) counters, the
-# factors read off a 512 MiB copy (profiles/ks_kernel_batch_n16_hbm_counters.md),
-# with the NTT schedule (rows per pair of passes) of that run and the
-# algorithmic bytes of its launches; only valid for the kernel code the counters
-# were taken on.  Under another schedule the launches differ in size and the
-# measured bytes are scaled by the algorithmic bytes (traffic_basis says which).
-# (schedule None: the kernel's launches do not depend on the NTT schedule.)
-TRAFFIC = {"k_ntt_pass<rows,fwd>": {"schedule": 2048, "bytes": 1494.4e6, "alg_bytes": 1471.1e6},
-           "k_basis_convert": {"schedule": None, "bytes": 1174.6e6, "alg_bytes": 1174.4e6}}
+# launches), from rocprofv3 FETCH_SIZE + WRITE_SIZE counters scaled by a 512 MiB
+# copy (profiles/), with the NTT schedule (rows per pair of passes) of that run
+# and the algorithmic bytes of its launches; only valid for the kernel code the
+# counters were taken on.  Under another schedule the launches differ in size
+# and the measured bytes are scaled by the algorithmic bytes (traffic_basis).
+TRAFFIC = {}
+# Counter bytes of the whole rotation phase (all kernels) per rotation, from
+# the same counter runs; None until measured on the current kernels.
+KS_COUNTER_BYTES_PER_ROTATION = None
 
 
 def traffic_of(name, schedule, alg_bytes):
@@ -50,19 +68,19 @@ def traffic_of(name, schedule, alg_bytes):
         f"rocprofv3 counters at NTT schedule {t['schedule']}, scaled by algorithmic bytes to schedule {schedule}"
 
 
-
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mf", action="store_true", help="default run: skip the MF-100K and tiny sub-objects")
     ap.add_argument("--workload", default="ks", choices=["ks", "mf100k", "mf1m", "serve"],
-                    help="ks: batched key switching (default); mf100k / mf1m: encrypted MF epochs on the "
-                         "MovieLens-100K / -1M shaped synthetic matrices")
-    ap.add_argument("--epochs", type=int, default=10, help="MF workloads: epochs (the 100K workload refreshes as needed)")
-    ap.add_argument("--rates", default="10,25,50,100,200", help="serve: Poisson arrival rates (requests/s)")
-    ap.add_argument("--requests", type=int, default=60, help="serve: requests per rate")
+                    help="ks: batched key switching with the MF sub-objects (default); mf100k / mf1m: "
+                         "encrypted MF epochs alone; serve: the request stream")
+    ap.add_argument("--epochs", type=int, default=None, help="MF workloads: epochs (100K: 10, 1M: 5)")
+    ap.add_argument("--rates", default="10,20,50,100,200,500", help="serve: Poisson arrival rates (requests/s)")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--ntt-chunk", type=int, default=None,
                     help="fix the NTT schedule (rows per pair of passes) instead of autotuning (for profiles)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -74,10 +92,55 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline():
-    """The oracle (numpy, one host thread) on a bounded sample: one non-hoisted
-    rotation of one 25-limb ciphertext at N = 2^16 (key generation untimed)."""
-    import numpy as np
+# ---------------------------------------------------------------- models of one rotation
+def ks_model(N, nl, alpha, dnum_digits, key_share):
+    """Algorithmic HBM bytes and modular multiplies of one rotate-and-add
+    acc + Rot(a, r) at nl limbs (acc = a, as in the chain): read a (c0, c1) and
+    write the result once, plus the key's share (key bytes / ciphertexts that
+    use it); multiplies of the hybrid key switch: the transforms (N/2 log2 N
+    butterflies per limb), the ModUp and ModDown conversions (one
+    multiply-accumulate per source limb and target limb), the inner product
+    (digits x extended limbs x 2) and the ModDown scaling."""
+    logN = N.bit_length() - 1
+    limb = 8 * N
+    nr = nl + alpha
+    key_bytes = len(dnum_digits) * 2 * nr * limb
+    alg_bytes = 4 * nl * limb + key_bytes / key_share
+    ntt_limbs = nl + sum(nr - d for d in dnum_digits) + 2 * alpha + 2 * nl
+    bfly = ntt_limbs * (N // 2) * logN
+    conv = N * (sum(d * (nr - d) for d in dnum_digits) + 2 * alpha * nl)
+    inner = N * len(dnum_digits) * nr * 2
+    scal = N * 2 * nl
+    return {"alg_bytes": alg_bytes, "limb_ntts": ntt_limbs, "butterflies": bfly, "conv_macs": conv,
+            "inner_mults": inner, "scale_mults": scal, "modmuls": bfly + conv + inner + scal}
+
+
+def valu_bound(model, q_is_fp64):
+    """Seconds per rotation if only the measured modular-multiply rates
+    limited it: butterflies of the 40-bit limbs in the exact FP64 form, the
+    60-bit ones with Shoup multiplies, conversion terms as 64x64->128-bit
+    multiply-accumulates, inner products and scalings as Montgomery multiplies."""
+    r = MODMUL_RATE
+    if any(v is None for v in r.values()):
+        return None
+    f = q_is_fp64
+    return (model["butterflies"] * f / r["fp64_exact"] + model["butterflies"] * (1 - f) / r["shoup_u64"]
+            + model["conv_macs"] / r["mac_64x64_128"]
+            + (model["inner_mults"] + model["scale_mults"]) / r["montgomery_u64"])
+
+
+# ---------------------------------------------------------------- CPU oracle legs
+def _single_thread_env():
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+
+
+def cpu_leg_ks(n_workers):
+    """Oracle key switching at the kernel-batch shape: keys once, then one
+    non-hoisted rotation of one 25-limb ciphertext in this process, and one
+    rotation per worker of a process pool over other ciphertexts."""
+    _single_thread_env()
+    import multiprocessing as mp
     from oracle import ckks, params
     import workloads
     prm = params.config_kernel_batch()
@@ -85,23 +148,151 @@ def cpu_baseline():
     t0 = time.perf_counter()
     orc.keygen(rot_steps=[1])
     t_key = time.perf_counter() - t0
-    x = workloads.random_residues(prm.q, prm.N, 2, seed=99)
-    ct = ckks.Ciphertext(x[0], x[1], 2.0 ** 40)
+    global _POOL_ORC
+    _POOL_ORC = orc
     t0 = time.perf_counter()
-    orc.rotate(ct, 1)
+    _pool_rotation(0)
     t_rot = time.perf_counter() - t0
+    pool_rate = None
+    if n_workers > 1:
+        ctxf = mp.get_context("fork")      # the keys are shared with the workers by fork
+        with ctxf.Pool(n_workers) as p:
+            t0 = time.perf_counter()
+            p.map(_pool_rotation, range(1, n_workers + 1))
+            pool_rate = n_workers / (time.perf_counter() - t0)
     return {"value": 1.0 / t_rot, "unit": "key-switch rotations/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 non-hoisted rotation of one ciphertext, N=2^16, 25 limbs, dnum=3 "
-                      f"({t_rot:.1f} s; key generation {t_key:.1f} s untimed)"}
+            "sample": f"1 non-hoisted rotation of one ciphertext, N=2^16, 25 limbs, dnum=3 ({t_rot:.1f} s; "
+                      f"key generation {t_key:.1f} s untimed)",
+            "pool": None if pool_rate is None else
+            {"value": pool_rate, "cores": n_workers,
+             "sample": f"{n_workers} rotations of different ciphertexts in a pool of {n_workers} processes"},
+            "host_cpu_count": os.cpu_count()}
 
 
-def bench_mf(args):
-    """Encrypted CSR-MF epochs: value = ratings processed per second of epoch time."""
+_POOL_ORC = None
+
+
+def _pool_rotation(i):
+    from oracle import ckks
+    import workloads
+    prm = _POOL_ORC.prm
+    x = workloads.random_residues(prm.q, prm.N, 2, seed=2000 + i)
+    _POOL_ORC.rotate(ckks.Ciphertext(x[0], x[1], 2.0 ** 40), 1)
+    return i
+
+
+def cpu_leg_mf100k(n_ks_per_epoch, epochs):
+    """MovieLens-100K shape: the FP64 MF (numpy, all epochs, timed) and the
+    oracle on one rotation of one rating-sized ciphertext at N = 2^15 (17
+    limbs, dnum 5), extrapolated to the epochs' key switches (the count the
+    library performed; the key switches dominate the oracle's time)."""
+    _single_thread_env()
+    import numpy as np
+    from oracle import ckks, mf, params
+    import workloads
+    csr = workloads.movielens100k_shaped()
+    U0, V0 = workloads.init_factors(csr.n_rows, csr.n_cols, 10)
+    t0 = time.perf_counter()
+    mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, 0.01, 0.02, epochs, rule="R2")
+    t_fp64 = time.perf_counter() - t0
+    prm = params.config_mf_n15()
+    orc = ckks.Context(prm, workloads.CRYPTO_SEED)
+    orc.keygen(rot_steps=[1])
+    x = workloads.random_residues(prm.q, prm.N, 2, seed=7)
+    t0 = time.perf_counter()
+    orc.rotate(ckks.Ciphertext(x[0], x[1], 2.0 ** 40), 1)
+    t_rot = time.perf_counter() - t0
+    t_total = t_rot * n_ks_per_epoch * epochs
+    return {"value": csr.nnz * epochs / t_total, "unit": "ratings/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 oracle rotation at N=2^15, 17 limbs ({t_rot:.1f} s), extrapolated to the "
+                      f"{n_ks_per_epoch} key switches per epoch the library ran, x {epochs} epochs (extrapolated)",
+            "fp64_mf": {"ratings_per_s": csr.nnz * epochs / t_fp64, "seconds": t_fp64,
+                        "what": f"plaintext FP64 MF (oracle.mf, rule R2), {epochs} epochs"},
+            "host_cpu_count": os.cpu_count()}
+
+
+def cpu_leg_tiny():
+    """Config 1: the whole encrypted oracle for one epoch (keys excluded)."""
+    _single_thread_env()
+    from oracle import ckks, params, program
+    import workloads
+    from tests.test_oracle_program import run_encrypted_tiny
+    csr = workloads.tiny_ratings()
+    U0, V0 = workloads.init_factors(32, 64, 4)
+    prm = params.config_tiny()
+    lay = program.make_layout(prm.N, 4, 32, 64, csr.row_ptr, csr.col_idx)
+    orc = ckks.Context(prm, workloads.CRYPTO_SEED)
+    orc.keygen(rot_steps=program.rotation_steps(lay))
+    t0 = time.perf_counter()
+    run_encrypted_tiny(orc, csr, U0, V0, program.block_masks(orc, 4))
+    t = time.perf_counter() - t0
+    return {"value": t, "unit": "s per epoch", "cores": 1, "kind": "oracle",
+            "sample": "the full encrypted oracle, 1 epoch of the tiny workload (encryption included, keys excluded)",
+            "host_cpu_count": os.cpu_count()}
+
+
+def run_cpu_legs(legs):
+    """Run the legs {name: (fn, args)} in parallel spawned processes (they
+    never touch the GPU); returns {name: result or error}."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    out = {}
+    with cf.ProcessPoolExecutor(max_workers=len(legs), mp_context=mp.get_context("spawn")) as ex:
+        futs = {name: ex.submit(fn, *a) for name, (fn, a) in legs.items()}
+        for name, f in futs.items():
+            try:
+                out[name] = f.result()
+            except Exception as e:   # reported, not fatal: the GPU figures stand on their own
+                out[name] = {"error": repr(e)}
+            log(f"cpu leg {name} done")
+    return out
+
+
+# ---------------------------------------------------------------- helpers
+def kernel_table(prof):
+    return {k: {"launches": v[0], "total_ms": round(v[1], 3), "avg_us": round(1e3 * v[1] / v[0], 2),
+                "alg_GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+            for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+
+
+def dominant_roofline(prof, schedule=None):
+    """Roofline entry of the kernel with the largest total time: algorithmic
+    bytes per launch over its average launch duration (HIP events on the
+    library's stream), against the HBM peak."""
+    name, (launches, total_ms, total_bytes) = max(prof.items(), key=lambda kv: kv[1][1])
+    avg_ms = total_ms / launches
+    achieved = (total_bytes / launches) / (avg_ms * 1e-3) / 1e9
+    traffic, basis = traffic_of(name, schedule, total_bytes / launches)
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "HBM bytes per launch",
+            "traffic_basis": basis, "alg_bytes_per_launch": round(total_bytes / launches),
+            "avg_launch_us": round(1e3 * avg_ms, 2), "launches_in_timed_steps": launches}
+
+
+def mac_summary(mac, prof, N):
+    """The masked MAC's work in the timed epochs and the rates it ran at.  Source
+    rows are read (2 polynomials), accumulator rows read and written (2 x 2),
+    and each mask term forms one limb row of mask values from the resident I0
+    row (a permuted read, from cache)."""
+    _, ms, _ = prof.get("k_mask_mac_tasks", (0, 0.0, 0.0))
+    hbm = 8.0 * N * (2 * mac["group_rows"] + 4 * mac["task_rows"])
+    out = dict(mac)
+    out["terms_per_group"] = round(mac["terms"] / max(1, mac["groups"]), 2)
+    if ms > 0:
+        s = ms * 1e-3
+        out["source_and_accumulator_GBps"] = round(hbm / s / 1e9, 1)
+        out["mask_elements_per_s"] = float(f"{mac['term_rows'] * N / s:.4g}")
+    return out
+
+
+# ---------------------------------------------------------------- MF workloads
+def run_mf(which, epochs, ntt_chunk=None):
+    """Encrypted CSR-MF epochs: ratings processed per second of epoch time."""
     import numpy as np
     import torch
     import paper_2509_03024_amd as pk
     import workloads
-    if args.workload == "mf100k":
+    if which == "mf100k":
         csr = workloads.movielens100k_shaped()
         prm, k, name = pk.mf_n15_params(k=10, lr=0.01, lam=0.02, rule=2, refresh_mode=1), 10, \
             "MovieLens-100K-shaped 943 x 1682"
@@ -113,23 +304,25 @@ def bench_mf(args):
     t0 = time.perf_counter()
     ctx = pk.Context(prm, workloads.CRYPTO_SEED)
     ctx.keygen([], conj=False)
-    if args.ntt_chunk is not None:
-        pk.set_ntt_schedule(args.ntt_chunk)
+    if ntt_chunk is not None:
+        ctx.set_ntt_schedule(ntt_chunk)
     else:
         ctx.autotune()
     m = pk.MF(ctx)
     n_ct = m.encrypt_csr_rows(csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx, csr.values)
     m.init_factors(U0, V0)
     ctx.sync()
-    log(f"MF set-up (keys, encryption of {n_ct} rating ciphertexts) {time.perf_counter() - t0:.1f} s")
+    log(f"{which}: set-up (keys, encryption of {n_ct} rating ciphertexts) {time.perf_counter() - t0:.1f} s")
+    ks0 = ctx.counters()["key_switches"]
     pk.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    m.epochs(args.epochs)
+    m.epochs(epochs)
     ctx.sync()
     elapsed = time.perf_counter() - t0
     prof = pk.profile_report()
     pk.profile_enable(False)
+    n_ks = ctx.counters()["key_switches"] - ks0
     st = m.stats()
     mac = m.mac_counts()
     U, V = m.decrypt_factors()
@@ -137,45 +330,79 @@ def bench_mf(args):
     rmse = float(np.sqrt(np.mean((rhat - csr.values) ** 2)))
     out = {
         "metric": "encrypted CSR-MF ratings/s",
-        "value": round(csr.nnz * args.epochs / elapsed, 2),
+        "value": round(csr.nnz * epochs / elapsed, 2),
+        "unit": "ratings/s",
+        "epochs": epochs,
+        "ms_per_epoch": round(1e3 * elapsed / epochs, 3),
         "refreshes": st["refreshes"],
         "refresh_s": round(st["refresh_seconds"], 3),
-        "ratings_per_s_excluding_refresh": round(csr.nnz * args.epochs / (elapsed - st["refresh_seconds"]), 2),
-        "unit": "ratings/s",
-        "n_gpus": 1, "steps": args.epochs, "warmup": 0,
-        "ms_per_step": round(1e3 * elapsed / args.epochs, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "ratings_per_s_excluding_refresh": round(csr.nnz * epochs / (elapsed - st["refresh_seconds"]), 2),
+        "key_switches_per_epoch": round(n_ks / epochs),
         "config": {"workload": f"encrypted MF, {name}, {csr.nnz} ratings, k={k}, N=2^{prm.log2N}, "
-                               f"{n_ct} rating ciphertexts, rule R2, {args.epochs} epochs "
+                               f"{n_ct} rating ciphertexts, rule R2, {epochs} epochs "
                                f"({st['refreshes']} table refreshes)"},
         "rmse_last_forward": round(rmse, 5),
-        "kernels": {k2: {"launches": v[0], "total_ms": round(v[1], 3)}
-                    for k2, v in sorted(prof.items(), key=lambda kv: -kv[1][1])},
+        "roofline": dominant_roofline(prof),
+        "kernels": kernel_table(prof),
         "masked_mac": mac_summary(mac, prof, 1 << prm.log2N),
     }
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
+def run_tiny(reps=3):
+    """Latency of one encrypted MF epoch at the tiny configuration (N = 2^12,
+    32 x 64, 205 ratings, k = 4, rule R1); the factors are re-encrypted before
+    each epoch (the chain holds one epoch)."""
+    import numpy as np
+    import paper_2509_03024_amd as pk
+    from oracle import mf
+    import workloads
+    csr = workloads.tiny_ratings()
+    U0, V0 = workloads.init_factors(32, 64, 4)
+    ctx = pk.Context(pk.tiny_params(k=4, lr=0.01, lam=0.02, rule=1), workloads.CRYPTO_SEED)
+    ctx.keygen([])
+    m = pk.MF(ctx)
+    m.encrypt_csr_rows(32, 64, csr.row_ptr, csr.col_idx, csr.values)
+    lat = []
+    for _ in range(reps + 1):
+        m.init_factors(U0, V0)
+        ctx.sync()
+        t0 = time.perf_counter()
+        m.epochs(1)
+        ctx.sync()
+        lat.append(time.perf_counter() - t0)
+    U, V = m.decrypt_factors()
+    Uf, Vf, rf = mf.train(U0, V0, csr.row_ptr, csr.col_idx, csr.values, 0.01, 0.02, 1, rule="R1")
+    err = float(max(np.max(np.abs(U - Uf)), np.max(np.abs(V - Vf))))
+    ctx.close()
+    return {"metric": "encrypted MF epoch latency", "value": round(1e3 * float(np.median(lat[1:])), 3),
+            "unit": "ms", "first_epoch_ms": round(1e3 * lat[0], 3), "max_abs_error_vs_fp64": err,
+            "config": {"workload": "tiny: 32 x 64, 205 ratings, k=4, N=2^12, rule R1, 1 epoch"}}
+
+
+# ---------------------------------------------------------------- serving
 def bench_serve(args):
     """Poisson stream of encrypted per-user PREDICT / UPDATE requests (50/50) over the
     MovieLens-1M-shaped tables (6040 x 3706, k = 16): rows of lognormal(4.5, 1) length
     clipped to [5, 2000], items Zipf(1.1); rows of <= 512 items go to the N = 2^15
     server, longer ones to the N = 2^16 server.  Reports p50/p99 latency per rate."""
-    import threading
     import numpy as np
+    import torch
     import paper_2509_03024_amd as pk
     import workloads
     k = 16
     U0, V0 = workloads.init_factors(6040, 3706, k)
     t0 = time.perf_counter()
     servers = {}
+    free, total = torch.cuda.mem_get_info()
+    budget = 0.8 * free / 2            # 0.8 x free HBM at start, split over the two servers
     for name, prm in (("n15", pk.mf_n15_params(k=k, lr=0.01, lam=0.02, rule=2)),
                       ("n16", pk.mf_n16_params(k=k, lr=0.01, lam=0.02, rule=2))):
         ctx = pk.Context(prm, workloads.CRYPTO_SEED)
         ctx.keygen([])
         ctx.autotune()
-        servers[name] = (ctx, pk.Server(ctx, U0, V0, hbm_budget_bytes=40e9, max_batch=64))
+        servers[name] = (ctx, pk.Server(ctx, U0, V0, hbm_budget_bytes=budget, max_batch=64))
         log(f"server {name} ready ({time.perf_counter() - t0:.1f} s)")
     rng = np.random.default_rng(7)
     weights = np.arange(1, 3707, dtype=np.float64) ** -1.1
@@ -228,39 +455,14 @@ def bench_serve(args):
         "n_gpus": 1, "steps": len(results), "warmup": 0, "ms_per_step": None, "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "serving: Poisson PREDICT/UPDATE requests over 6040 x 3706 tables, k=16, "
-                               "N=2^15 (rows <= 512) / 2^16"},
+                               "N=2^15 (rows <= 512) / 2^16", "hbm_budget_bytes_per_server": budget},
         "sweep": results, "servers": stats}), flush=True)
 
 
-def mac_summary(mac, prof, N):
-    """The masked MAC's work in the timed epochs and the rates it ran at.  Source
-    rows are read (2 polynomials), accumulator rows read and written (2 x 2),
-    and each mask term forms one limb row of mask values from the resident I0
-    row (a permuted read, from cache)."""
-    _, ms, _ = prof.get("k_mask_mac_tasks", (0, 0.0, 0.0))
-    hbm = 8.0 * N * (2 * mac["group_rows"] + 4 * mac["task_rows"])
-    out = dict(mac)
-    out["terms_per_group"] = round(mac["terms"] / max(1, mac["groups"]), 2)
-    if ms > 0:
-        s = ms * 1e-3
-        out["source_and_accumulator_GBps"] = round(hbm / s / 1e9, 1)
-        out["mask_elements_per_s"] = float(f"{mac['term_rows'] * N / s:.4g}")
-    return out
-
-
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-    if args.workload == "serve":
-        return bench_serve(args)
-    if args.workload != "ks":
-        return bench_mf(args)
+# ---------------------------------------------------------------- key switching (the headline)
+def bench_ks(args):
     import numpy as np
     import torch
-    assert torch.cuda.is_available(), "bench.py needs the GPU"
-    torch.cuda.set_device(0)
     import paper_2509_03024_amd as pk
     import workloads
 
@@ -269,7 +471,7 @@ def main():
     ctx.keygen(CHAIN, conj=True)
     log(f"context + keys {time.perf_counter() - t0:.1f} s")
     if args.ntt_chunk is not None:
-        pk.set_ntt_schedule(args.ntt_chunk)
+        ctx.set_ntt_schedule(args.ntt_chunk)
         tune = {"fixed": args.ntt_chunk}
         schedule = args.ntt_chunk
     else:
@@ -366,14 +568,30 @@ def main():
 
     n_rot = N_CT * (len(CHAIN) + 1)
     value = n_rot * args.steps / elapsed
-    dom = max(prof.items(), key=lambda kv: kv[1][1])
-    name, (launches, total_ms, total_bytes) = dom
-    avg_ms = total_ms / launches
-    achieved = (total_bytes / launches) / (avg_ms * 1e-3) / 1e9
-    traffic, traffic_basis = traffic_of(name, schedule, total_bytes / launches)
-    kernel_table = {k: {"launches": v[0], "total_ms": round(v[1], 3), "avg_us": round(1e3 * v[1] / v[0], 2),
-                        "alg_GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
-                    for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    rot_rate = n_rot * args.steps / phase["rotations"]
+    # metric-level rooflines of the rotation phase (25 limbs, digits 9, 9, 7)
+    g = -(-(L + 1) // 3)
+    digits = [min(g, L + 1 - j * g) for j in range(3) if j * g < L + 1]
+    model = ks_model(N, L + 1, ctx.alpha, digits, N_CT)
+    # the 40-bit limbs (FP64 butterflies) among all transformed limbs
+    t_valu = valu_bound(model, (L + 1 - 1) / (L + 1 + ctx.alpha))
+    ks_roof = {
+        "what": "rotation phase: rotate-and-add at 25 limbs (read c0, c1; write the result; "
+                "the key's share over the 64 ciphertexts that use it)",
+        "alg_bytes_per_rotation": round(model["alg_bytes"]),
+        "rotations_per_s": round(rot_rate, 2),
+        "achieved_GBps": round(rot_rate * model["alg_bytes"] / 1e9, 1),
+        "hbm_roofline_rotations_per_s": round(HBM_PEAK_GBS * 1e9 / model["alg_bytes"], 1),
+        "ks_hbm_frac": round(rot_rate * model["alg_bytes"] / (HBM_PEAK_GBS * 1e9), 4),
+        "counter_bytes_per_rotation": KS_COUNTER_BYTES_PER_ROTATION,
+        "modmuls_per_rotation": model["modmuls"],
+        "limb_ntts_per_rotation": model["limb_ntts"],
+        "valu": None if t_valu is None else {
+            "bound_rotations_per_s": round(1.0 / t_valu, 1),
+            "frac": round(rot_rate * t_valu, 4),
+            "modmul_rates_per_s": MODMUL_RATE,
+            "basis": "measured modular-multiply rates x this rotation's multiplies by kind"},
+    }
     out = {
         "metric": "key-switch rotations/s at N=2^16",
         "value": round(value, 2),
@@ -393,21 +611,57 @@ def main():
                    "ciphertexts": N_CT, "log2N": LOGN, "limbs": L + 1, "special": ctx.alpha, "dnum": 3},
         "phase_ms_per_step": {k: round(1e3 * v / args.steps, 3) for k, v in phase.items()},
         "autotune_ms": tune,
-        "rotation_phase_rotations_per_s": round(n_rot * args.steps / phase["rotations"], 2),
+        "rotation_phase_rotations_per_s": round(rot_rate, 2),
         "plain_gpu_path": {"rotations_per_s": round(plain_rate, 2), "ciphertexts": PLAIN_CT,
                            "what": "same rotate-and-sum chain, one ciphertext per call",
-                           "batched_rotation_phase_speedup": round(n_rot * args.steps / phase["rotations"] / plain_rate, 2)},
-        "roofline": {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_unit": "HBM bytes per launch", "traffic_basis": traffic_basis,
-                     "alg_bytes_per_launch": round(total_bytes / launches),
-                     "avg_launch_us": round(1e3 * avg_ms, 2), "launches_in_timed_steps": launches},
-        "kernels": kernel_table,
+                           "batched_rotation_phase_speedup": round(rot_rate / plain_rate, 2)},
+        "roofline": dominant_roofline(prof, schedule),
+        "ks_roofline": ks_roof,
+        "kernels": kernel_table(prof),
     }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline()
     ctx.close()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only (one MI355X); --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    if args.workload == "serve":
+        return bench_serve(args)
+    if args.workload in ("mf100k", "mf1m"):
+        epochs = args.epochs or (10 if args.workload == "mf100k" else 5)
+        out = run_mf(args.workload, epochs, args.ntt_chunk)
+        out.update({"n_gpus": 1, "steps": epochs, "warmup": 0, "ms_per_step": out["ms_per_epoch"],
+                    "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+                    "data": "synthetic"})
+        if not args.no_cpu_baseline and args.workload == "mf100k":
+            legs = run_cpu_legs({"mf100k": (cpu_leg_mf100k, (out["key_switches_per_epoch"], epochs))})
+            out["cpu_baseline"] = legs["mf100k"]
+        print(json.dumps(out), flush=True)
+        return
+    out = bench_ks(args)
+    if not args.no_mf:
+        log("MF-100K: 10 epochs ...")
+        out["mf100k"] = run_mf("mf100k", args.epochs or 10)
+        log(f"MF-100K {out['mf100k']['value']} ratings/s")
+        out["tiny"] = run_tiny()
+        log(f"tiny epoch {out['tiny']['value']} ms")
+    if not args.no_cpu_baseline:
+        log("cpu baselines (oracle, parallel processes) ...")
+        legs = {"ks": (cpu_leg_ks, (max(1, min(8, (os.cpu_count() or 2) - 3)),))}
+        if not args.no_mf:
+            legs["mf100k"] = (cpu_leg_mf100k, (out["mf100k"]["key_switches_per_epoch"], out["mf100k"]["epochs"]))
+            legs["tiny"] = (cpu_leg_tiny, ())
+        res = run_cpu_legs(legs)
+        out["cpu_baseline"] = res["ks"]
+        if not args.no_mf:
+            out["mf100k"]["cpu_baseline"] = res["mf100k"]
+            out["tiny"]["cpu_baseline"] = res["tiny"]
     print(json.dumps(out), flush=True)
 
 

@@ -23,7 +23,7 @@
  *
  * Conventions
  *   - Every call returns 0 on success or a negative CSRMF_E_* code; the
- *     message of the last failure on this context is csrmf_last_error().
+ *     message of the calling thread's last failure is csrmf_last_error().
  *   - The caller owns every host array passed in or out.  Inputs are copied;
  *     outputs are written into caller buffers of the documented size.
  *   - The library owns all device memory and every ciphertext.  A ciphertext is
@@ -95,7 +95,10 @@ int csrmf_create(const csrmf_params* p, const uint8_t seed[32], csrmf_ctx** out)
 /* Free every device and host resource of the context.  NULL is ignored. */
 void csrmf_destroy(csrmf_ctx* ctx);
 
-/* Message of the last failure on ctx (empty string if none; never NULL). */
+/* Message of the calling thread's last failed call, csrmf_create included
+ * (empty if that thread's last call succeeded; never NULL).  The pointer
+ * stays valid until the thread's next call into the library.  ctx is not
+ * used and may be NULL. */
 const char* csrmf_last_error(const csrmf_ctx* ctx);
 
 /* Run all further device work of ctx on this hipStream_t (NULL = the null
@@ -108,6 +111,11 @@ int csrmf_sync(csrmf_ctx* ctx);
 /* Query the modulus chain: q[0..L] then p[0..alpha-1] into moduli (caller
  * array of L+1+alpha entries); any pointer may be NULL. */
 int csrmf_get_chain(const csrmf_ctx* ctx, int32_t* L, int32_t* alpha, uint64_t* moduli);
+
+/* Work counters of the context since its creation: key switches enqueued
+ * (relinearisations and rotations, each ciphertext of a batch counted once).
+ * Errors: INVAL (null pointer). */
+int csrmf_counters(const csrmf_ctx* ctx, int64_t* key_switches);
 
 /* Key generation (Sec. III-B: the crypto service provider creates the keys).
  * Creates the secret key s, the public key, the relinearisation key (s^2 -> s)
@@ -288,15 +296,15 @@ void csrmf_server_destroy(csrmf_server* s);
 /* Time the candidate NTT schedules (rows transformed per pair of passes) on
  * `rows` limbs of this context's ring (0: 64 ciphertexts x 2 x (L+1) limbs,
  * the batched key-switching shape) with HIP events, and keep the fastest for
- * all later work in the process.  Writes a JSON report of the timings into
+ * all later work of this context.  Writes a JSON report of the timings into
  * report (NUL-terminated, truncated to cap bytes; may be NULL).
  * Errors: NOMEM, DEVICE. */
 int csrmf_autotune(csrmf_ctx* ctx, int32_t rows, char* report, int32_t cap);
 
-/* Fix the NTT schedule instead of tuning it (process-wide): transform
- * chunk_rows rows per pair of passes (0: the whole batch at once).  For
- * repeatable profiles.  Errors: INVAL (negative). */
-int csrmf_set_ntt_schedule(int32_t chunk_rows);
+/* Fix this context's NTT schedule instead of tuning it: transform chunk_rows
+ * rows per pair of passes (0: the whole batch at once).  For repeatable
+ * profiles.  Results do not depend on the schedule.  Errors: INVAL (negative). */
+int csrmf_set_ntt_schedule(csrmf_ctx* ctx, int32_t chunk_rows);
 
 /* ------------------------------------------------------------------------ */
 /* Per-kernel timing (benchmark hook; process-wide).                         */
@@ -377,6 +385,13 @@ int csrmf_mf_layout(const csrmf_ctx* ctx, int32_t* n_ct, int32_t* n_utab, int32_
  * Errors: LEVEL (not enough levels, refresh off or chain shorter than 4),
  * STATE, DEVICE. */
 int csrmf_mf_epochs(csrmf_ctx* ctx, int32_t n_epochs);
+
+/* Memory bound of the block permutations (scatters and gathers): at most
+ * max_babies baby-step rotations of the sources (ciphertexts of the source's
+ * size) are alive at once; sources are processed in chunks that respect it
+ * (default 1024).  Every baby is built the same way in any chunk and the
+ * sums are exact, so results do not depend on it.  Errors: INVAL (< 1). */
+int csrmf_set_baby_budget(csrmf_ctx* ctx, int32_t max_babies);
 
 /* Encrypted predictions r_hat = <u_i, v_j> on the observed ratings from the
  * current factor tables (gather + product + windowed sum).  Errors: LEVEL. */

@@ -26,12 +26,13 @@ One epoch, Ug and Vg at level l:
     rating layout, weight 1), one rescale.
 
 BlockPermute: a move (source ciphertext c, source block a -> destination
-block b, weight w) has delta = (a - b) mod D = gamma*G + beta with
-G = 2^ceil(log2(D)/2).  For destination d:
-    acc_d = sum_gamma Rot_{gamma G B}( sum_{c, beta} HRot_{beta B}(src_c) (.) M_{d,c,gamma,beta} )
+block b, weight w) has delta = (a - b) mod D = gamma*G + beta, with the
+baby-step size G of the call fixed by the schedule (see "the permutation
+schedule" below).  For destination d:
+    acc_d = sum_gamma Rot_{gamma G B}( sum_{c, beta} Rot_{beta B}(src_c) (.) M_{d,c,gamma,beta} )
             + T_d (.) (W_c + sum_{b in C_d} W_b I_b)                  (scatter only)
-with HRot hoisted per source, the giant rotation applied once per (d, gamma)
-after the inner sum, zero steps skipped, and the plaintext mask
+with the baby rotations built once per source, the giant rotation applied
+once per (d, gamma) after the inner sum, zero steps skipped, and the plaintext mask
     M_{d,c,gamma,beta} = sum_{moves in the group} W * I_{(b + gamma G) mod D},
     I_p = tau_{g_p}(I_0), g_p = 5^((-p B) mod N/2) mod 2N,
 I_0 the encoding of the indicator of slots 0..k-1 at the call's mask scale S_I
@@ -224,9 +225,6 @@ class CkksBackend:
     def rotate(self, a, r):
         return self.ctx.rotate(a, r)
 
-    def hoisted(self, a, steps):
-        return self.ctx.hoisted_rotations(a, steps)
-
     def mul_int(self, a, w):
         return self.ctx.mul_int(a, w)
 
@@ -318,9 +316,6 @@ class ClearBackend:
     def rotate(self, a, r):
         return self.V(np.roll(a.z, -r), a.level, a.scale)
 
-    def hoisted(self, a, steps):
-        return {r: self.rotate(a, r) for r in steps}
-
     def mul_int(self, a, w):
         return self.V(a.z, a.level, a.scale * float(w))   # value unchanged; scale absorbs w
 
@@ -352,7 +347,25 @@ class Move:
     w: float      # real weight
 
 
-BABY_BLOCK = 64       # babies are built in blocks of this many consecutive steps
+# ---------------------------------------------------------------- the permutation schedule
+# Every arrangement of BlockPermute's rotations gives the same slot values, but
+# not the same bits: each key switch rounds in its own way.  The paper leaves
+# this data movement to the implementation, so the schedule is part of the
+# definition here (a reading), and an implementation that is to match bit for
+# bit follows it:
+#   * baby-step size G: choose_G, the power of two with the fewest rotations
+#     among those that keep at most MAX_ACCUMULATORS inner sums
+#     (destinations x D/G) alive, ties to the smaller G;
+#   * babies Rot_{beta B}(src) for beta up to the largest one the source needs,
+#     in blocks of BABY_BLOCK steps: block base Rot_{k B}(src) (k a multiple of
+#     BABY_BLOCK, the next base Rot_{BABY_BLOCK B} of the previous one), inside
+#     a block baby k+s+j = Rot_{s B}(baby k+j) for s = 1, 2, 4, ..;
+#   * per destination, inner sums over (source, beta) in that order, then the
+#     giant steps as a pairwise tree (level j: node t = node 2t +
+#     Rot_{2^j G B}(node 2t+1)), the self term, one rescale.
+# What does not change a ciphertext is left free: batching of rotations, the
+# order of exact modular sums, and how many sources are processed at once.
+BABY_BLOCK = 64           # babies are built in blocks of this many consecutive steps
 MAX_ACCUMULATORS = 1024   # bound on destinations * D/G inner sums alive at once
 
 

@@ -97,7 +97,9 @@ _SIGS = {
     "csrmf_mf_stats": [_p, _i32p, _i32p, ctypes.POINTER(ctypes.c_double)],
     "csrmf_mf_mac_counts": [_p, ctypes.POINTER(ctypes.c_int64)],
     "csrmf_autotune": [_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32],
-    "csrmf_set_ntt_schedule": [ctypes.c_int32],
+    "csrmf_set_ntt_schedule": [_p, ctypes.c_int32],
+    "csrmf_set_baby_budget": [_p, ctypes.c_int32],
+    "csrmf_counters": [_p, ctypes.POINTER(ctypes.c_int64)],
     "csrmf_server_create": [_p, ctypes.c_int32, ctypes.c_int32, _dp, _dp, ctypes.c_double, ctypes.c_int32,
                             ctypes.POINTER(_p)],
     "csrmf_server_submit": [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _dp, ctypes.c_uint32, _u64p],
@@ -133,7 +135,7 @@ class Context:
         h = _p()
         rc = lib.csrmf_create(ctypes.byref(prm), seed, ctypes.byref(h))
         if rc != CSRMF_OK:
-            raise CsrmfError(rc, "csrmf_create failed")
+            raise CsrmfError(rc, lib.csrmf_last_error(None).decode())
         self.h = h
         self.prm = prm
         self.N = 1 << prm.log2N
@@ -296,6 +298,16 @@ class Context:
     def conjugate(self, a):
         return self._unary(lib.csrmf_conjugate, a)
 
+    def counters(self):
+        """{"key_switches": relinearisations and rotations enqueued so far}."""
+        v = ctypes.c_int64()
+        self._chk(lib.csrmf_counters(self.h, ctypes.byref(v)))
+        return {"key_switches": v.value}
+
+    def set_ntt_schedule(self, chunk_rows):
+        """Fix this context's NTT schedule (rows per pair of passes; 0 = whole batch)."""
+        self._chk(lib.csrmf_set_ntt_schedule(self.h, int(chunk_rows)))
+
     def rotate_hoisted(self, a, steps):
         st = np.asarray(list(steps), np.int32)
         out = np.zeros(len(st), np.uint64)
@@ -404,6 +416,10 @@ class MF:
     def epochs(self, n):
         self.ctx._chk(lib.csrmf_mf_epochs(self.ctx.h, n))
 
+    def set_baby_budget(self, max_babies):
+        """Block permutations keep at most max_babies baby rotations alive (memory bound)."""
+        self.ctx._chk(lib.csrmf_set_baby_budget(self.ctx.h, int(max_babies)))
+
     def predict(self):
         self.ctx._chk(lib.csrmf_predict(self.ctx.h))
 
@@ -488,13 +504,6 @@ class Server:
             self.close()
         except Exception:
             pass
-
-
-def set_ntt_schedule(chunk_rows):
-    """Fix the NTT schedule (rows per pair of passes; 0 = whole batch) instead of autotuning."""
-    rc = lib.csrmf_set_ntt_schedule(int(chunk_rows))
-    if rc != 0:
-        raise CsrmfError(rc, "bad schedule")
 
 
 def profile_enable(on=True):

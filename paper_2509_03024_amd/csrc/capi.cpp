@@ -11,21 +11,23 @@ using csrmf::Context;
 using csrmf::Ct;
 using csrmf::Error;
 
+#define tl_err csrmf::last_error()
+
 #define API_BEGIN(ctx)                                   \
-    if (!(ctx)) return CSRMF_E_INVAL;                    \
+    if (!(ctx)) { tl_err = "null context"; return CSRMF_E_INVAL; } \
     std::lock_guard<std::recursive_mutex> lk_((ctx)->mu); \
     try {
 #define API_END(ctx)                                     \
-        (ctx)->err.clear();                              \
+        tl_err.clear();                                  \
         return CSRMF_OK;                                 \
     } catch (const Error& e) {                           \
-        (ctx)->err = e.what();                           \
+        tl_err = e.what();                               \
         return e.code;                                   \
     } catch (const std::bad_alloc&) {                    \
-        (ctx)->err = "host allocation failed";           \
+        tl_err = "host allocation failed";               \
         return CSRMF_E_NOMEM;                            \
     } catch (const std::exception& e) {                  \
-        (ctx)->err = e.what();                           \
+        tl_err = e.what();                               \
         return CSRMF_E_DEVICE;                           \
     }
 
@@ -35,29 +37,32 @@ using csrmf::Error;
 extern "C" {
 
 int csrmf_create(const csrmf_params* p, const uint8_t seed[32], csrmf_ctx** out) {
-    if (!p || !seed || !out) return CSRMF_E_INVAL;
+    if (!p || !seed || !out) {
+        tl_err = "csrmf_create: null argument";
+        return CSRMF_E_INVAL;
+    }
     *out = nullptr;
     Context* c = nullptr;
     try {
         c = new Context();
         c->init(*p, seed);
     } catch (const Error& e) {
+        tl_err = std::string("csrmf_create: ") + e.what();
         delete c;
         return e.code;
-    } catch (...) {
+    } catch (const std::exception& e) {
+        tl_err = std::string("csrmf_create: ") + e.what();
         delete c;
         return CSRMF_E_NOMEM;
     }
+    tl_err.clear();
     *out = reinterpret_cast<csrmf_ctx*>(c);
     return CSRMF_OK;
 }
 
 void csrmf_destroy(csrmf_ctx* ctx) { delete reinterpret_cast<Context*>(ctx); }
 
-const char* csrmf_last_error(const csrmf_ctx* ctx) {
-    if (!ctx) return "null context";
-    return reinterpret_cast<const Context*>(ctx)->err.c_str();
-}
+const char* csrmf_last_error(const csrmf_ctx*) { return tl_err.c_str(); }
 
 int csrmf_set_stream(csrmf_ctx* cx, void* s) {
     Context* c = reinterpret_cast<Context*>(cx);
@@ -73,6 +78,16 @@ int csrmf_sync(csrmf_ctx* cx) {
     API_BEGIN(c)
     c->sync();
     API_END(c)
+}
+
+int csrmf_counters(const csrmf_ctx* cx, int64_t* key_switches) {
+    const Context* c = reinterpret_cast<const Context*>(cx);
+    if (!c || !key_switches) {
+        tl_err = "csrmf_counters: null argument";
+        return CSRMF_E_INVAL;
+    }
+    *key_switches = c->n_key_switches;
+    return CSRMF_OK;
 }
 
 int csrmf_get_chain(const csrmf_ctx* cx, int32_t* L, int32_t* alpha, uint64_t* moduli) {
@@ -418,10 +433,12 @@ int csrmf_autotune(csrmf_ctx* cx, int32_t rows, char* report, int32_t cap) {
     API_END(c)
 }
 
-int csrmf_set_ntt_schedule(int32_t chunk_rows) {
-    if (chunk_rows < 0) return CSRMF_E_INVAL;
-    csrmf::set_ntt_chunk_rows(chunk_rows);
-    return CSRMF_OK;
+int csrmf_set_ntt_schedule(csrmf_ctx* cx, int32_t chunk_rows) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(chunk_rows >= 0, "NTT schedule: rows per pair of passes must be >= 0");
+    c->tabs.ntt_chunk_rows = chunk_rows;
+    API_END(c)
 }
 
 int csrmf_profile_enable(int32_t enable) {

@@ -81,6 +81,11 @@ static std::vector<Ct*> slice(const std::vector<Ct*>& v, size_t i, size_t j) {
     return std::vector<Ct*>(v.begin() + (long)i, v.begin() + (long)j);
 }
 
+std::string& last_error() {
+    static thread_local std::string msg;
+    return msg;
+}
+
 // ------------------------------------------------------------------ staging ring
 hipEvent_t HipMarkers::record() {
     hipEvent_t e;
@@ -878,7 +883,8 @@ void Context::ks_inner(const KsArgs& a, int level, int B, uint32_t g, uint64_t* 
 }
 
 void Context::ks_moddown(const KsArgs& a, uint32_t g, uint64_t* u, int level, int B, const RowMap& out,
-                         const RowMap& addend, uint32_t g_add, bool addend_both, const RowMap& acc) {
+                         const RowMap& addend, uint32_t g_add, bool addend_both, const RowMap& acc,
+                         uint64_t* conv_buf) {
     const int nl = level + 1, nr = n_ext(level);
     const LevelConsts& c = lv[level];
     RowMap mp;   // P rows of u0 and u1: 2B groups of alpha rows
@@ -887,16 +893,20 @@ void Context::ks_moddown(const KsArgs& a, uint32_t g, uint64_t* u, int level, in
     mp.batch_stride = (int64_t)nr * N;
     for (int k = 0; k < alpha; ++k) mp.push(nl + k, L + 1 + k);
     launch_ntt(tabs, mp, true, stream);
-    Scratch conv(pool, 2 * (size_t)B * nl * N);
+    std::unique_ptr<Scratch> own;
+    if (!conv_buf) {
+        own.reset(new Scratch(pool, 2 * (size_t)B * nl * N));
+        conv_buf = own->p;
+    }
     RowMap mcv;
-    mcv.base = conv.p;
+    mcv.base = conv_buf;
     mcv.batch = 2 * B;
     mcv.batch_stride = (int64_t)nl * N;
     for (int i = 0; i < nl; ++i) mcv.push(i, i);
     launch_basis_convert(tabs, mcv, mp, c.md_y, c.md_c, false, stream);
     launch_ntt(tabs, mcv, false, stream);
     RowMap mc2;
-    mc2.base = conv.p;
+    mc2.base = conv_buf;
     mc2.batch = B;
     mc2.batch_stride = 2 * (int64_t)nl * N;
     mc2.poly_stride = (int64_t)nl * N;
@@ -930,6 +940,7 @@ void Context::mul_relin(const std::vector<Ct*>& a, const std::vector<Ct*>& b, st
     for (int i = 0; i < nl; ++i) d2.e[i] = ((uint32_t)(2 * nl + i) << 8) | (uint32_t)i;
     Scratch ext(pool, (size_t)B * nd * nr * N), coef(pool, (size_t)B * nl * N), u(pool, (size_t)B * 2 * nr * N);
     ks_modup(d2, lvl, B, ext.p, coef.p);
+    n_key_switches += B;
     const KsArgs ka = ks_args(ext.p, d2, lvl, B, relin);
     ks_inner(ka, lvl, B, 1, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, a[i]->scale * b[i]->scale);
@@ -1004,21 +1015,20 @@ void Context::rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& o
     }
     const int nl = lvl + 1, nr = n_ext(lvl);
     const int nd = (int)lv[lvl].digits.size();
-    Scratch d(pool, (size_t)B * nl * N);
-    RowMap md;
-    md.base = d.p;
-    md.batch = B;
-    md.batch_stride = (int64_t)nl * N;
-    for (int i = 0; i < nl; ++i) md.push(i, i);
+    // KS(tau_g(c1)) in the hoisted form: ModUp of c1 itself, tau_g applied to
+    // the extended digits as the inner product reads them.  The centred
+    // extension commutes with tau_g (a negated coefficient has negated centred
+    // digits), so this is bit for bit the plain rotation, without a pass that
+    // writes tau_g(c1).
     RowMap c1 = map_cts(in, nl);
     for (int i = 0; i < nl; ++i) c1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
-    launch_automorphism(tabs, g, md, c1, false, stream);
     Scratch ext(pool, (size_t)B * nd * nr * N), coef(pool, (size_t)B * nl * N), u(pool, (size_t)B * 2 * nr * N);
-    ks_modup(md, lvl, B, ext.p, coef.p);
-    const KsArgs ka = ks_args(ext.p, md, lvl, B, key);
-    ks_inner(ka, lvl, B, 1, u.p);
+    ks_modup(c1, lvl, B, ext.p, coef.p);
+    n_key_switches += B;
+    const KsArgs ka = ks_args(ext.p, c1, lvl, B, key);
+    ks_inner(ka, lvl, B, g, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, in[i]->scale);
-    ks_moddown(ka, 1, u.p, lvl, B, map_cts(out, nl), map_cts(in, nl), g, false,
+    ks_moddown(ka, g, u.p, lvl, B, map_cts(out, nl), map_cts(in, nl), g, false,
                acc ? map_cts(*acc, nl) : RowMap());
     fence();
 }
@@ -1042,6 +1052,7 @@ void Context::rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std:
             continue;
         }
         const KsArgs ka = ks_args(ext.p, c1, lvl, 1, key_for(g));
+        ++n_key_switches;
         ks_inner(ka, lvl, 1, g, u.p);
         ks_moddown(ka, g, u.p, lvl, 1, map_ct(out[k]->d, nl), map_ct(in.d, nl), g, false);
     }
@@ -1069,7 +1080,7 @@ std::string Context::autotune(int rows) {
     float best_ms = 1e30f;
     std::string rep = "{";
     for (int cnd : cands) {
-        set_ntt_chunk_rows(cnd);
+        tabs.ntt_chunk_rows = cnd;
         launch_ntt(tabs, m, false, stream);     // warm
         launch_ntt(tabs, m, true, stream);
         CSRMF_HIP(hipEventRecord(a, stream));
@@ -1087,7 +1098,7 @@ std::string Context::autotune(int rows) {
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    set_ntt_chunk_rows(best);
+    tabs.ntt_chunk_rows = best;
     rep += ", \"chosen\": " + std::to_string(best) + "}";
     return rep;
 }
@@ -1125,6 +1136,7 @@ void Context::hoist_rotate(Hoist& h, uint32_t g, std::vector<Ct*>& out) {
     RowMap c1 = map_cts(h.in, nl);
     for (int i = 0; i < nl; ++i) c1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
     const KsArgs ka = ks_args(h.ext, c1, lvl, B, key);
+    n_key_switches += B;
     ks_inner(ka, lvl, B, g, u.p);
     for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, h.in[i]->scale);
     ks_moddown(ka, g, u.p, lvl, B, map_cts(out, nl), map_cts(h.in, nl), g, false);

@@ -121,6 +121,9 @@ struct Scratch {
     Scratch& operator=(const Scratch&) = delete;
 };
 
+// Message of the calling thread's last failed API call (csrmf_last_error).
+std::string& last_error();
+
 struct MfState;  // encrypted matrix-factorisation program (mf_program.cpp)
 void destroy_mf(MfState* m);
 struct Server;   // request server (serving.cpp)
@@ -141,7 +144,6 @@ struct Context {
     hipStream_t stream = nullptr;       // stream of all device work
     hipStream_t own_stream = nullptr;   // the stream the context created (destroyed with it)
     Pool pool;
-    std::string err;
     std::recursive_mutex mu;        // serialises API calls and the serving worker
 
     uint64_t serial = 0;
@@ -156,6 +158,8 @@ struct Context {
     uint64_t next_handle = 1;
     Staging staging;
     MfState* mf = nullptr;
+    int max_babies = 1024;          // block permutations: baby ciphertexts alive at once
+    int64_t n_key_switches = 0;     // key switches enqueued (relinearisations and rotations)
     std::vector<Server*> servers;   // stopped and freed before the context
 
     Context() = default;
@@ -235,8 +239,11 @@ struct Context {
     // u's special limbs (tau_g applied to the ext reads)
     void ks_inner(const KsArgs& a, int level, int B, uint32_t g, uint64_t* u);
     // ModDown of u's special limbs, fused with the Q limbs' inner product (a, g)
+    // (conv_buf: scratch of 2 B (level+1) N words for the converted P part, or
+    // null to take it from the pool)
     void ks_moddown(const KsArgs& a, uint32_t g, uint64_t* u, int level, int B, const RowMap& out,
-                    const RowMap& addend, uint32_t g_add, bool addend_both, const RowMap& acc = RowMap());
+                    const RowMap& addend, uint32_t g_add, bool addend_both, const RowMap& acc = RowMap(),
+                    uint64_t* conv_buf = nullptr);
 
     // --- schedule autotuning (returns a JSON report)
     std::string autotune(int rows);

@@ -1,6 +1,7 @@
 // Launch wrappers of the gfx950 kernels (implemented in kernels.hip).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <stdexcept>
@@ -44,6 +45,7 @@ struct DevTables {
     const Modulus* mods;         // [n_mod]
     const uint64_t* tw;          // [n_mod][4][N]: psi^brev, shoup, psi^-brev, shoup
                                  // (FP64 primes: as doubles, w then fl(w/q))
+    int ntt_chunk_rows = 0;      // NTT schedule (host side): rows per pair of passes, 0 = the whole batch
 };
 
 void launch_ntt(const DevTables& t, const RowMap& rows, bool inverse, hipStream_t s);
@@ -51,9 +53,6 @@ void launch_ntt(const DevTables& t, const RowMap& rows, bool inverse, hipStream_
 // pass reads src, writes rows) and left in `rows`; src is not modified.
 void launch_ntt_from(const DevTables& t, const RowMap& rows, const RowMap& src, bool inverse, hipStream_t s);
 
-// NTT schedule tunable: rows per pair of passes (0 = whole batch), process-wide.
-void set_ntt_chunk_rows(int rows);
-int ntt_chunk_rows();
 
 // out row (b, k) = from_signed(src + b*src_batch_stride + (k % n_src)*N), int64
 // coefficients (n_src = 1 broadcasts one signed polynomial to every limb).
@@ -85,7 +84,6 @@ void launch_tensor(const DevTables& t, const RowMap& d, const RowMap& a, const R
 
 // Automorphism tau_g in evaluation form: out[k] = in[perm_g(k)] with
 // perm_g(k) = brev(((2 brev(k) + 1) g mod 2N - 1) / 2).  both_polys: also rows at +poly_stride.
-// If add_to != 0 the permuted row is added into out instead of stored.
 void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, const RowMap& in,
                          bool both_polys, hipStream_t s);
 
@@ -158,6 +156,16 @@ struct MaskTasks {
     int64_t poly_stride;
 };
 void launch_mask_mac_tasks(const DevTables& t, const MaskTasks& T, const uint64_t* i0, double bytes, hipStream_t s);
+
+// Kernel arguments are these structs by value: the host and device passes
+// must agree on their layout, and the largest argument list (k_ks_combine:
+// DevTables, KsArgs, four RowMaps and scalars, about 2 KiB) must stay under
+// the 4 KiB kernel-argument limit.
+static_assert(sizeof(RowMap) == 296 && alignof(RowMap) == 8, "RowMap layout");
+static_assert(sizeof(KsArgs) == 624 && offsetof(KsArgs, own) == 320, "KsArgs layout");
+static_assert(sizeof(DevTables) == 32, "DevTables layout");
+static_assert(sizeof(MaskTasks) == 88, "MaskTasks layout");
+static_assert(sizeof(DevTables) + sizeof(KsArgs) + 4 * sizeof(RowMap) + 32 < 4096, "kernel arguments");
 
 // Rescale step 1 (coefficient form top limb, one row per batch element and
 // poly): t = (c_l + h) mod q_l with h = floor(q_l/2), then dst row k =

@@ -822,12 +822,10 @@ inline int ew_blocks(const DevTables& t, const RowMap& m) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-// Rows per pair of passes (0: the whole batch at once).  With a chunk, both
-// passes of a sub-batch run back to back so the second pass can find the
-// first pass's output in the last-level cache.  Chosen by the autotuner.
-static int g_ntt_chunk_rows = 0;
-void set_ntt_chunk_rows(int rows) { g_ntt_chunk_rows = rows < 0 ? 0 : rows; }
-int ntt_chunk_rows() { return g_ntt_chunk_rows; }
+// t.ntt_chunk_rows: rows per pair of passes (0: the whole batch at once).
+// With a chunk, both passes of a sub-batch run back to back so the second
+// pass can find the first pass's output in the last-level cache.  Chosen per
+// context by the autotuner.
 
 void launch_ntt(const DevTables& t, const RowMap& m, bool inverse, hipStream_t s) {
     launch_ntt_from(t, m, RowMap(), inverse, s);
@@ -838,7 +836,8 @@ void launch_ntt_from(const DevTables& t, const RowMap& m, const RowMap& src, boo
     if (src.n && (src.n != m.n || src.batch != m.batch)) throw std::length_error("transform source map differs in shape");
     const int per_b = m.n;
     int bchunk = m.batch;
-    if (g_ntt_chunk_rows > 0) bchunk = per_b >= g_ntt_chunk_rows ? 1 : g_ntt_chunk_rows / per_b;
+    const int cr = t.ntt_chunk_rows;
+    if (cr > 0) bchunk = per_b >= cr ? 1 : cr / per_b;
     if (bchunk > m.batch) bchunk = m.batch;
     const RowMap none{};
     for (int b0 = 0; b0 < m.batch; b0 += bchunk) {
@@ -849,7 +848,9 @@ void launch_ntt_from(const DevTables& t, const RowMap& m, const RowMap& src, boo
         if (src.ptrs) ssub.ptrs = src.ptrs + b0;
         else if (src.n) ssub.base = src.base + (int64_t)b0 * src.batch_stride;
         const int blocks = sub.rows() * (int)(((size_t)1 << t.logN) / kNttBlockElems);
-        const double bytes = NB(sub.rows()) * 2;
+        // algorithmic bytes: a transform reads and writes each row once, half
+        // of that is charged to each of its two passes
+        const double bytes = NB(sub.rows());
         if (!inverse) {
             { ProfScope ps_("k_ntt_pass<cols,fwd>", s, bytes); dispatch_ntt_pass(t, sub, ssub, true, false, blocks, s); }
             { ProfScope ps_("k_ntt_pass<rows,fwd>", s, bytes); dispatch_ntt_pass(t, sub, none, false, false, blocks, s); }

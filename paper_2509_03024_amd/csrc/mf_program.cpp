@@ -291,6 +291,18 @@ struct MacLaunch {
     std::vector<uint64_t> cw;
     std::unordered_map<int64_t, int32_t> widx;
 
+    // Algorithmic HBM bytes of the launch: every distinct source read once
+    // (both polynomials), every accumulator written (and read unless it
+    // starts at zero); the mask values come from the resident I_0 rows.
+    double hbm_bytes(int nl, uint64_t N) const {
+        std::vector<uint64_t*> u(src);
+        std::sort(u.begin(), u.end());
+        const size_t n_src = (size_t)(std::unique(u.begin(), u.end()) - u.begin());
+        size_t acc_rows = 0;
+        for (int32_t f : first) acc_rows += f ? 2 : 4;
+        return (double)N * 8.0 * nl * (2.0 * (double)n_src + (double)acc_rows);
+    }
+
     void task(uint64_t* a, bool is_first) {
         acc.push_back(a);
         first.push_back(is_first ? 1 : 0);
@@ -467,7 +479,7 @@ std::vector<Ct> block_permute_cached(Context* c, MfState& m, const std::vector<C
                     for (auto& tm : *gr.second) ml.term(gal(tm.first), tm.second, wrows);
                 }
             }
-            const double bytes = (double)c->N * 8.0 * nl * (2.0 * ml.src.size() + 4.0 * ml.acc.size() + ml.gs.size());
+            const double bytes = ml.hbm_bytes(nl, c->N);
             ml.run(c, nl, mask, bytes);
             release(c, babies);
         }
@@ -519,7 +531,7 @@ std::vector<Ct> block_permute_cached(Context* c, MfState& m, const std::vector<C
             for (auto& bw : st.corr)
                 ml.term(gal(bw.first), weight_int(bw.second, s_self, q_acc, mask_scale, target), wrows);
         }
-        const double bytes = (double)c->N * 8.0 * nl * (6.0 * ml.acc.size() + (ml.gs.size() - ml.acc.size()));
+        const double bytes = ml.hbm_bytes(nl, c->N);
         ml.run(c, nl, mask, bytes);
     }
     for (int d = 0; d < n_dest; ++d)
@@ -533,7 +545,6 @@ std::vector<Ct> block_permute_cached(Context* c, MfState& m, const std::vector<C
 // ---------------------------------------------------------------- the MF program's permutation schedule
 constexpr int kBabyBlock = 64;          // babies are built in blocks of this many steps
 constexpr int kMaxAccumulators = 1024;  // bound on destinations * D/G inner sums alive at once
-constexpr int kMaxBabies = 1024;        // bound on baby ciphertexts alive at once (source chunks)
 constexpr int kRotateBatch = 128;       // ciphertexts per batched rotation call (ModUp scratch)
 
 int giant_rotations(std::vector<char> nodes, int width) {
@@ -654,7 +665,9 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
         src_list.push_back(kv.first);
         max_n = std::max(max_n, kv.second + 1);
     }
-    const int chunk = std::max(1, std::min(kHoistChunk, kMaxBabies / std::min(kBabyBlock, max_n)));
+    // sources whose babies are built together: at most c->max_babies babies alive
+    // (a memory bound only: every baby is built the same way in any chunk)
+    const int chunk = std::max(1, std::min(kHoistChunk, c->max_babies / std::min(kBabyBlock, max_n)));
     for (size_t c0 = 0; c0 < src_list.size(); c0 += (size_t)chunk) {
         const size_t c1 = std::min(src_list.size(), c0 + (size_t)chunk);
         const int ns = (int)(c1 - c0);
@@ -712,7 +725,7 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
                         for (auto& tm : *gr.second) ml.term(gal(tm.first), tm.second, wrows);
                     }
                 }
-                const double bytes = (double)c->N * 8.0 * nl * (2.0 * ml.src.size() + 4.0 * ml.acc.size() + ml.gs.size());
+                const double bytes = ml.hbm_bytes(nl, c->N);
                 ml.run(c, nl, mask, bytes);
             }
             // next block's base; then drop this block's babies
@@ -792,7 +805,7 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
             for (auto& bw : st.corr)
                 ml.term(gal(bw.first), weight_int(bw.second, s_self, q_acc, mask_scale, target), wrows);
         }
-        const double bytes = (double)c->N * 8.0 * nl * (6.0 * ml.acc.size() + (ml.gs.size() - ml.acc.size()));
+        const double bytes = ml.hbm_bytes(nl, c->N);
         ml.run(c, nl, mask, bytes);
     }
     for (int d = 0; d < n_dest; ++d)
@@ -989,22 +1002,22 @@ using csrmf::Error;
 using csrmf::MfState;
 
 #define API_BEGIN(ctx)                 \
-    if (!(ctx)) return CSRMF_E_INVAL;  \
+    if (!(ctx)) { csrmf::last_error() = "null context"; return CSRMF_E_INVAL; } \
     std::lock_guard<std::recursive_mutex> lk_((ctx)->mu); \
     try {
 #define API_END_EARLY                  \
-    { c->err.clear(); return CSRMF_OK; }
+    { csrmf::last_error().clear(); return CSRMF_OK; }
 #define API_END(ctx)                   \
-        (ctx)->err.clear();            \
+        csrmf::last_error().clear();            \
         return CSRMF_OK;               \
     } catch (const Error& e) {         \
-        (ctx)->err = e.what();         \
+        csrmf::last_error() = e.what();         \
         return e.code;                 \
     } catch (const std::bad_alloc&) {  \
-        (ctx)->err = "host allocation failed"; \
+        csrmf::last_error() = "host allocation failed"; \
         return CSRMF_E_NOMEM;          \
     } catch (const std::exception& e) { \
-        (ctx)->err = e.what();         \
+        csrmf::last_error() = e.what();         \
         return CSRMF_E_DEVICE;         \
     }
 
@@ -1174,6 +1187,14 @@ int csrmf_mf_epochs(csrmf_ctx* cx, int32_t n_epochs) {
         csrmf::mfp::run_epoch(c, m);
     }
     c->sync();
+    API_END(c)
+}
+
+int csrmf_set_baby_budget(csrmf_ctx* cx, int32_t max_babies) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    if (max_babies < 1) throw Error(CSRMF_E_INVAL, "baby budget must be at least 1");
+    c->max_babies = max_babies;
     API_END(c)
 }
 

@@ -365,11 +365,11 @@ int csrmf_server_create(csrmf_ctx* cx, int32_t n_users, int32_t n_items, const d
         c->servers.push_back(s);
         s->worker = std::thread([s] { s->run(); });
     } catch (const Error& e) {
-        c->err = e.what();
+        csrmf::last_error() = e.what();
         delete s;
         return e.code;
     } catch (const std::exception& e) {
-        c->err = e.what();
+        csrmf::last_error() = e.what();
         delete s;
         return CSRMF_E_DEVICE;
     }

@@ -40,5 +40,9 @@ def test_create_rejects_bad_params_without_gpu_work():
     assert pk.lib.csrmf_create(ctypes.byref(bad), bytes(32), ctypes.byref(h)) == -1
     bad = pk.params(12, 61, 3, 40, 1, 61, 4)         # primes must be below 2^60
     assert pk.lib.csrmf_create(ctypes.byref(bad), bytes(32), ctypes.byref(h)) == -1
+    assert b"log2N" not in pk.lib.csrmf_last_error(None)
+    bad = pk.params(9, 60, 3, 40, 1, 60, 4)
+    assert pk.lib.csrmf_create(ctypes.byref(bad), bytes(32), ctypes.byref(h)) == -1
+    assert b"log2N must be in [12, 16]" in pk.lib.csrmf_last_error(None)    # the failed create's message
     assert pk.lib.csrmf_create(None, bytes(32), ctypes.byref(h)) == -1
-    assert pk.lib.csrmf_last_error(None) == b"null context"
+    assert b"null argument" in pk.lib.csrmf_last_error(None)

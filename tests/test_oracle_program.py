@@ -95,8 +95,10 @@ def run_encrypted_tiny(ctx, csr, U0, V0, masks, epochs=1, alpha=0.01, lam=0.02, 
     return lay, res, pt
 
 
-@pytest.mark.slow
 def test_encrypted_program_tiny_within_1e4_of_fp64():
+    """The whole program on oracle ciphertexts (every CkksBackend operation but
+    refresh, which test_oracle_backend pins): decrypted factors and forward
+    predictions within 1e-4 of the FP64 epoch (about 45 s)."""
     prm = params.config_tiny()
     csr = workloads.tiny_ratings()
     U0, V0 = workloads.init_factors(32, 64, 4)
