@@ -206,6 +206,25 @@ int csrmf_mod_drop(csrmf_ctx* ctx, uint64_t a, int32_t level, uint64_t* out);
  * Errors: KEY (no key for this step). */
 int csrmf_rotate(csrmf_ctx* ctx, uint64_t a, int32_t r, uint64_t* out);
 
+/* Allocation-free variant of csrmf_rotate, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the rotation by r of ciphertext a is written into
+ * the existing ciphertext `out` (any handle of this context other than a; its
+ * level and scale become a's), and every temporary lives in one static
+ * 128 MiB device buffer of the library (one per device, held until the
+ * process ends).  The call allocates nothing: no hipMalloc, no pool block, no
+ * staging.  Same bits as csrmf_rotate.
+ * Limit: the rotation's scratch, 8 N ((l+1) * 3 + dnum_l * (l+1+alpha) +
+ * 2 (l+1+alpha)) bytes at level l (dnum_l = digits present at that level),
+ * must fit in 128 MiB: every level of the N <= 2^15 chains and of the
+ * N = 2^16 chain with 3 digits does; with 4-limb digits at N = 2^16, levels
+ * up to 20 do.
+ * Calls on one device share the buffer; they are ordered on one context's
+ * stream, but calls on two contexts (or streams) of one device that overlap
+ * in time race.  Errors: INVAL (a == out, unknown handle, scratch too
+ * large), KEY. */
+int csrmf_rotate_noalloc(csrmf_ctx* ctx, uint64_t a, int32_t r, uint64_t out);
+
 /* Complex conjugation of the slots (Galois element 2N-1). */
 int csrmf_conjugate(csrmf_ctx* ctx, uint64_t a, uint64_t* out);
 

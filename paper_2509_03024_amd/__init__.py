@@ -100,6 +100,7 @@ _SIGS = {
     "csrmf_set_ntt_schedule": [_p, ctypes.c_int32],
     "csrmf_set_baby_budget": [_p, ctypes.c_int32],
     "csrmf_counters": [_p, ctypes.POINTER(ctypes.c_int64)],
+    "csrmf_rotate_noalloc": [_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint64],
     "csrmf_server_create": [_p, ctypes.c_int32, ctypes.c_int32, _dp, _dp, ctypes.c_double, ctypes.c_int32,
                             ctypes.POINTER(_p)],
     "csrmf_server_submit": [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _dp, ctypes.c_uint32, _u64p],
@@ -297,6 +298,11 @@ class Context:
 
     def conjugate(self, a):
         return self._unary(lib.csrmf_conjugate, a)
+
+    def rotate_noalloc(self, a, r, out):
+        """Rotation of a by r written into the existing ciphertext `out`; no
+        device allocation (the library's static scratch buffer)."""
+        self._chk(lib.csrmf_rotate_noalloc(self.h, a, r, out))
 
     def counters(self):
         """{"key_switches": relinearisations and rotations enqueued so far}."""

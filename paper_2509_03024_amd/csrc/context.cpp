@@ -197,6 +197,7 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
     CSRMF_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     own_stream = stream;
     staging.init(stream);
+    noalloc_scratch = noalloc_scratch_for_current_device();
 
     const int nm = (int)moduli.size();
     mh.resize(nm);

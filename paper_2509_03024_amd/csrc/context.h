@@ -124,6 +124,13 @@ struct Scratch {
 // Message of the calling thread's last failed API call (csrmf_last_error).
 std::string& last_error();
 
+// Static device scratch of csrmf_rotate_noalloc (bytes; each device the
+// library runs on holds one until the process ends).
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+// Device address of that buffer on the current device (looked up once per
+// device with hipGetSymbolAddress, then cached).
+uint64_t* noalloc_scratch_for_current_device();
+
 struct MfState;  // encrypted matrix-factorisation program (mf_program.cpp)
 void destroy_mf(MfState* m);
 struct Server;   // request server (serving.cpp)
@@ -217,6 +224,10 @@ struct Context {
     // out[i] = tau_g(in[i]) key-switched; with acc, out[i] = acc[i] + that (fused)
     void rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out, const std::vector<Ct*>* acc = nullptr);
     void rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std::vector<Ct*>& out);
+    // out = tau_g(in) key-switched into the existing ciphertext `out` (not
+    // `in`), all scratch in the library's static device buffer: no allocation
+    void rotate_noalloc(const Ct& in, uint32_t g, Ct& out);
+    uint64_t* noalloc_scratch = nullptr;   // this context's device address of that buffer
     void check_scales(double a, double b) const;
 
     // --- hoisted rotations of a batch: ModUp once, then any number of Galois elements
