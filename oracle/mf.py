@@ -112,3 +112,54 @@ def sequential_alg1(U, V, row_ptr, col_idx, vals, alpha, lam, epochs):
             U[i] = U[i] + alpha * gu
             V[j] = V[j] + alpha * gv
     return U, V
+
+
+# ---------------------------------------------------------------- Alg. 2: user-item batch pairs
+def batch_pairs(row_ptr, col_idx, u_batch, v_batch):
+    """Group the ratings by user-item batch pair (Sec. III-D): user i is in
+    user batch i // u_batch at local index i % u_batch, item j likewise with
+    v_batch.  Returns [((ub, vb), [rating indices in CSR order])] with the
+    pairs in order of their first rating in CSR order (the order in which the
+    grouping of Alg. 2 meets them)."""
+    rows = csr_rows(row_ptr)
+    groups = {}
+    for r, (i, j) in enumerate(zip(rows, np.asarray(col_idx))):
+        groups.setdefault((int(i) // u_batch, int(j) // v_batch), []).append(r)
+    return list(groups.items())
+
+
+def batch_pair_epoch(U, V, row_ptr, col_idx, vals, alpha, lam, u_batch, v_batch, t=0, damp=0.1):
+    """One epoch of Alg. 2: for each batch pair in turn, every rating of the
+    pair uses the factors as they are when the pair starts; the per-rating
+    terms grad_u = a'(e v - lambda u), grad_v = a'(e u - lambda v) are summed
+    per local index (the accumulators) and added to the batch once the pair's
+    ratings are done, before the next pair; a' = alpha / (1 + damp * t).
+    Returns (U', V', predictions of each rating at the start of its pair)."""
+    U = np.array(U, np.float64, copy=True)
+    V = np.array(V, np.float64, copy=True)
+    rows = csr_rows(row_ptr)
+    cols = np.asarray(col_idx)
+    vals = np.asarray(vals, np.float64)
+    a_t = alpha / (1.0 + damp * t)
+    rhat = np.zeros(len(vals))
+    for _, idx in batch_pairs(row_ptr, col_idx, u_batch, v_batch):
+        idx = np.asarray(idx)
+        i, j = rows[idx], cols[idx]
+        p = np.einsum("ij,ij->i", U[i], V[j])
+        rhat[idx] = p
+        e = vals[idx] - p
+        dU = np.zeros_like(U)
+        dV = np.zeros_like(V)
+        np.add.at(dU, i, a_t * (e[:, None] * V[j] - lam * U[i]))
+        np.add.at(dV, j, a_t * (e[:, None] * U[i] - lam * V[j]))
+        U += dU
+        V += dV
+    return U, V, rhat
+
+
+def train_batch_pairs(U, V, row_ptr, col_idx, vals, alpha, lam, epochs, u_batch, v_batch, damp=0.1):
+    """`epochs` epochs of Alg. 2; returns (U, V, predictions of the last epoch)."""
+    rhat = None
+    for t in range(epochs):
+        U, V, rhat = batch_pair_epoch(U, V, row_ptr, col_idx, vals, alpha, lam, u_batch, v_batch, t, damp)
+    return U, V, rhat

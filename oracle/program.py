@@ -651,3 +651,119 @@ def decode_tables(vals, lay, n_ent):
 def decode_predictions(vals, lay):
     """Slot vectors of the forward dot products -> r_hat per rating (CSR order)."""
     return np.array([vals[int(c)][int(t) * lay.B] for c, t in zip(lay.ct_of, lay.blk_of)])
+
+
+# ---------------------------------------------------------------- Alg. 2 on ciphertexts
+# The user-item batch pairs of Sec. III-D with a batch = one factor-table
+# ciphertext (the D profiles it holds): user i is local index i mod D of batch
+# i div D, items likewise.  The ratings of each pair, in CSR order, are packed
+# into rating ciphertexts of their own (D blocks each); pairs come in the order
+# of their first rating.  An epoch runs the pairs one after the other, each
+# from the tables as they are when it starts (Alg. 2):
+#   Ug, Vg <- gather of the pair's user table and item table into the pair's
+#             rating layout (BlockPermute, weight 1);
+#   Sdot, E, G_U = HMult(E, Vg), G_V = HMult(E, Ug) as in the epoch above;
+#   user table <- BlockPermute(G_U -> table, weight a') + self term
+#                 (1 - a' lambda c_i) u_i, c_i = ratings of user i in the pair
+#                 (1 for users of the table without one);  items likewise;
+# with a' = alpha / (1 + damp t) and the per-rating lambda of Alg. 2.  Before a
+# pair whose tables are below REFRESH_LEVEL, all tables are refreshed.
+@dataclass
+class Pair:
+    ub: int               # user table (batch) index
+    vb: int               # item table index
+    cts: list             # its rating ciphertexts
+    ratings: np.ndarray   # its ratings (CSR indices)
+
+
+def make_pair_layout(N, k, n_users, n_items, row_ptr, col_idx):
+    from .mf import batch_pairs
+    lay = make_layout(N, k, n_users, n_items, row_ptr, col_idx)   # shape of the blocks and tables
+    D = lay.D
+    ct_of = np.zeros(len(lay.rows), np.int64)
+    blk_of = np.zeros(len(lay.rows), np.int64)
+    pairs, c = [], 0
+    for (ub, vb), idx in batch_pairs(row_ptr, col_idx, D, D):
+        idx = np.asarray(idx, np.int64)
+        n = -(-len(idx) // D)
+        ct_of[idx] = c + np.arange(len(idx)) // D
+        blk_of[idx] = np.arange(len(idx)) % D
+        pairs.append(Pair(ub, vb, list(range(c, c + n)), idx))
+        c += n
+    lay.ct_of, lay.blk_of, lay.n_ct = ct_of, blk_of, c
+    lay.pairs = pairs
+    return lay
+
+
+def _pair_moves(lay, pair, owner, to_table):
+    """Moves of one pair: gather (table block -> the pair's rating blocks) or
+    scatter (rating blocks -> table block, weight set by the caller)."""
+    D, c0 = lay.D, pair.cts[0]
+    if to_table:
+        return [Move(int(lay.ct_of[r]) - c0, int(lay.blk_of[r]), int(owner[r]) % D, 1.0) for r in pair.ratings]
+    moves = [[] for _ in pair.cts]
+    for r in pair.ratings:
+        moves[int(lay.ct_of[r]) - c0].append(Move(0, int(owner[r]) % D, int(lay.blk_of[r]), 1.0))
+    return moves
+
+
+def run_pair_epochs(be, lay, R, Utab, Vtab, n_epochs, alpha, lam, damp=0.1, exact_weights=False, refresh=True,
+                    refresh_round=0, epoch0=0):
+    """Alg. 2 epochs on a pair layout; returns the tables and the dot products
+    of every rating ciphertext from the last epoch (at the start of its pair)."""
+    be.set_block(lay.B)
+    Utab, Vtab = list(Utab), list(Vtab)
+    sdot = [None] * lay.n_ct
+    for t in range(n_epochs):
+        a_t = alpha / (1.0 + damp * (epoch0 + t))
+        for pr in lay.pairs:
+            if min(be.level(Utab[pr.ub]), be.level(Vtab[pr.vb])) < REFRESH_LEVEL:
+                if not refresh:
+                    raise ValueError("level budget exhausted and refresh not allowed")
+                Utab, Vtab = refresh_tables(be, Utab, Vtab, refresh_round)
+                refresh_round += 1
+            ut, vt = Utab[pr.ub], Vtab[pr.vb]
+            Ug = block_permute(be, lay, [ut], _pair_moves(lay, pr, lay.rows, False), None, be.level(ut),
+                               S_IG, S_T, True, exact_weights)
+            Vg = block_permute(be, lay, [vt], _pair_moves(lay, pr, lay.cols, False), None, be.level(vt),
+                               S_IG, S_T, True, exact_weights)
+            E = []
+            for i, c in enumerate(pr.cts):
+                P = be.hmult(Ug[i], Vg[i])
+                T = P
+                s = 1
+                while s < lay.B:
+                    T = be.add(T, be.rotate(T, s))
+                    s *= 2
+                S = be.rotate(T, -lay.kp)
+                sdot[c] = S
+                WR = int(np.rint((be.scale(P) * float(be.top_prime(be.level(R[c])))) / be.scale(R[c])))
+                Re = be.drop(be.rescale(be.mul_int(R[c], WR)), be.level(S))
+                E.append(be.sub(Re, S))
+            GU = [be.hmult(E[i], be.drop(Vg[i], be.level(E[i]))) for i in range(len(pr.cts))]
+            GV = [be.hmult(E[i], be.drop(Ug[i], be.level(E[i]))) for i in range(len(pr.cts))]
+            glevel = be.level(GU[0])
+            for tabs, G, owner, b in ((Utab, GU, lay.rows, pr.ub), (Vtab, GV, lay.cols, pr.vb)):
+                n_ent = lay.n_users if owner is lay.rows else lay.n_items
+                cnt = np.zeros(n_ent)
+                np.add.at(cnt, np.asarray(owner)[pr.ratings], 1.0)
+                moves = _pair_moves(lay, pr, owner, True)
+                for mv in moves:
+                    mv.w = a_t
+                st = _pair_self_term(lay, tabs[b], b, cnt, n_ent, a_t, lam)
+                tabs[b] = block_permute(be, lay, G, [moves], [st], glevel, S_I, S_TAB, False, exact_weights)[0]
+    return EpochResult(Utab, Vtab, None, None, sdot, refresh_round)
+
+
+def _pair_self_term(lay, tab, d, cnt, n_ent, a_t, lam):
+    """Self term of table d for one pair: w_b = 1 - a' lambda c_e (c_e the
+    entity's ratings in the pair), as a constant (lower median) plus corrections."""
+    ws = []
+    for b in range(lay.D):
+        e = d * lay.D + b
+        if e >= n_ent:
+            break
+        ws.append((b, 1.0 - a_t * lam * cnt[e]))
+    srt = sorted(w for _, w in ws)
+    c = srt[(len(srt) - 1) // 2]
+    return (tab, c, [(b, w - c) for b, w in ws if w != c])
