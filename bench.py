@@ -43,17 +43,26 @@ FP64_FMA_PER_S = 78.6e12 / 2
 # microbenchmark (4 independent dependent chains per thread, 8192 x 256
 # threads, every result stored; method and figures in the design doc), in
 # operations per second.
-MODMUL_RATE = {"shoup_u64": None, "montgomery_u64": None, "fp64_exact": None, "mac_64x64_128": None}
+MODMUL_RATE = {"shoup_u64": 1.912e12, "montgomery_u64": 1.319e12, "fp64_exact": 6.346e12, "mac_64x64_128": 2.303e12}
 # HBM bytes per launch of a kernel in the timed step (average over the step's
 # launches), from rocprofv3 FETCH_SIZE + WRITE_SIZE counters scaled by a 512 MiB
 # copy (profiles/), with the NTT schedule (rows per pair of passes) of that run
 # and the algorithmic bytes of its launches; only valid for the kernel code the
 # counters were taken on.  Under another schedule the launches differ in size
 # and the measured bytes are scaled by the algorithmic bytes (traffic_basis).
-TRAFFIC = {}
-# Counter bytes of the whole rotation phase (all kernels) per rotation, from
-# the same counter runs; None until measured on the current kernels.
-KS_COUNTER_BYTES_PER_ROTATION = None
+TRAFFIC = {
+    "k_ntt_pass<rows,fwd>": {"bytes": 1.494e+09, "alg_bytes": 7.356e+08, "schedule": 2048},
+    "k_ntt_pass<cols,fwd>": {"bytes": 1.472e+09, "alg_bytes": 7.356e+08, "schedule": 2048},
+    "k_ntt_pass<rows,inv>": {"bytes": 1.065e+09, "alg_bytes": 5.251e+08, "schedule": 2048},
+    "k_ntt_pass<cols,inv>": {"bytes": 1.051e+09, "alg_bytes": 5.251e+08, "schedule": 2048},
+    "k_basis_convert": {"bytes": 1.175e+09, "alg_bytes": 1.174e+09, "schedule": None},
+    "k_ks_combine": {"bytes": 7.802e+09, "alg_bytes": 8.319e+09, "schedule": None},
+    "k_ks_inner": {"bytes": 5.128e+08, "alg_bytes": 5.128e+08, "schedule": None},
+}
+# Counter bytes (FETCH_SIZE + WRITE_SIZE, scaled as above) of a whole step of
+# the kernel-batch workload (transform phase, HMult phase and rotation phase),
+# from the same counter runs; None once the kernels have changed.
+KS_COUNTER_BYTES_PER_STEP = 575.8e9
 
 
 def traffic_of(name, schedule, alg_bytes):
@@ -75,7 +84,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mf", action="store_true", help="default run: skip the MF-100K and tiny sub-objects")
-    ap.add_argument("--workload", default="ks", choices=["ks", "mf100k", "mf1m", "serve"],
+    ap.add_argument("--workload", default="ks", choices=["ks", "mf100k", "mf1m", "serve", "accuracy"],
                     help="ks: batched key switching with the MF sub-objects (default); mf100k / mf1m: "
                          "encrypted MF epochs alone; serve: the request stream")
     ap.add_argument("--epochs", type=int, default=None, help="MF workloads: epochs (100K: 10, 1M: 5)")
@@ -83,6 +92,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--ntt-chunk", type=int, default=None,
                     help="fix the NTT schedule (rows per pair of passes) instead of autotuning (for profiles)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the HIP-graph replay, so that the timed steps end the run (profiles)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy a 512 MiB device buffer once before the timed steps (reference for HBM counters)")
     return ap.parse_args()
@@ -107,12 +118,17 @@ def ks_model(N, nl, alpha, dnum_digits, key_share):
     key_bytes = len(dnum_digits) * 2 * nr * limb
     alg_bytes = 4 * nl * limb + key_bytes / key_share
     ntt_limbs = nl + sum(nr - d for d in dnum_digits) + 2 * alpha + 2 * nl
+    # limbs of 60-bit primes among them (q_0 and the special primes; the
+    # others take the FP64 butterflies): q_0 of c1, the special primes and q_0
+    # of every digit that does not hold it, the special primes of ModDown, q_0
+    # of both ModDown outputs
+    int_limbs = 1 + len(dnum_digits) * alpha + (len(dnum_digits) - 1) + 2 * alpha + 2
     bfly = ntt_limbs * (N // 2) * logN
     conv = N * (sum(d * (nr - d) for d in dnum_digits) + 2 * alpha * nl)
     inner = N * len(dnum_digits) * nr * 2
     scal = N * 2 * nl
-    return {"alg_bytes": alg_bytes, "limb_ntts": ntt_limbs, "butterflies": bfly, "conv_macs": conv,
-            "inner_mults": inner, "scale_mults": scal, "modmuls": bfly + conv + inner + scal}
+    return {"alg_bytes": alg_bytes, "limb_ntts": ntt_limbs, "int_limb_ntts": int_limbs, "butterflies": bfly,
+            "conv_macs": conv, "inner_mults": inner, "scale_mults": scal, "modmuls": bfly + conv + inner + scal}
 
 
 def valu_bound(model, q_is_fp64):
@@ -246,6 +262,88 @@ def run_cpu_legs(legs):
                 out[name] = {"error": repr(e)}
             log(f"cpu leg {name} done")
     return out
+
+
+# ---------------------------------------------------------------- accuracy (RMSE per iteration)
+ACC_ITERS, ACC_LR, ACC_LAM, ACC_DAMP = 20, 0.001, 0.02, 0.1
+
+
+def run_accuracy(iters=ACC_ITERS):
+    """RMSE (Eq. 10) of the decrypted predictions after every iteration of
+    the encrypted MF at the MovieLens-100K shape, without batching (CSR
+    rows, synchronous epochs, rule R1, the summed form of Alg. 1) and with
+    the user-item batch pairs of Alg. 2 (dampened rate), both at alpha =
+    0.001, lambda = 0.02, k = 10, N = 2^15, tables refreshed as the levels
+    run out.  The prediction after iteration t is <u_i, v_j> from the
+    decrypted factors (decrypted on the host, the last step of Alg. 1)."""
+    import numpy as np
+    import paper_2509_03024_amd as pk
+    import workloads
+    csr = workloads.movielens100k_shaped()
+    K = 10
+    U0, V0 = workloads.init_factors(csr.n_rows, csr.n_cols, K)
+    rows = np.repeat(np.arange(csr.n_rows), np.diff(csr.row_ptr))
+    cols = np.asarray(csr.col_idx)
+
+    def rmse(U, V):
+        return float(np.sqrt(np.mean((np.einsum("ij,ij->i", U[rows], V[cols]) - csr.values) ** 2)))
+
+    out = {"initial_rmse": round(rmse(U0, V0), 5)}
+    for name, pairs, rule, damp in (("without_batching", 0, 1, 0.0), ("with_batching_alg2", 1, 1, ACC_DAMP)):
+        ctx = pk.Context(pk.params(15, 60, 16, 40, 3, 60, 5, 40, k=K, lr=ACC_LR, lam=ACC_LAM, damp=damp, rule=rule,
+                                   refresh_mode=1, batch_pairs=pairs), workloads.CRYPTO_SEED)
+        ctx.keygen([])
+        m = pk.MF(ctx)
+        m.encrypt_csr_rows(csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx, csr.values)
+        m.init_factors(U0, V0)
+        curve, t_ep = [], 0.0
+        for it in range(iters):
+            t0 = time.perf_counter()
+            m.epochs(1)
+            t_ep += time.perf_counter() - t0
+            U, V = m.decrypt_factors()
+            curve.append(round(rmse(U, V), 5))
+        log(f"accuracy {name}: RMSE {curve[0]} -> {curve[-1]} over {iters} iterations")
+        out[name] = {"rmse": curve, "reduction": round(1 - curve[-1] / out["initial_rmse"], 4),
+                     "refreshes": m.stats()["refreshes"], "epoch_s": round(t_ep / iters, 3)}
+        ctx.close()
+    # iterations each variant needs to reach the RMSE the slower one ends at
+    target = max(out["without_batching"]["rmse"][-1], out["with_batching_alg2"]["rmse"][-1])
+    for name in ("without_batching", "with_batching_alg2"):
+        out[name]["iterations_to_slower_final_rmse"] = next(
+            i + 1 for i, x in enumerate(out[name]["rmse"]) if x <= target)
+    out.update({"metric": "RMSE (Eq. 10) per iteration, encrypted MF", "value": out["without_batching"]["rmse"][-1],
+                "unit": "rmse", "higher_is_better": False,
+                "config": {"workload": f"encrypted MF, MovieLens-100K-shaped 943 x 1682, {csr.nnz} ratings, k={K}, "
+                                       f"N=2^15, alpha={ACC_LR}, lambda={ACC_LAM}, {iters} iterations, without "
+                                       f"batching (rule R1) and with Alg. 2 batch pairs (damp {ACC_DAMP})"}})
+    return out
+
+
+def cpu_leg_accuracy(iters=ACC_ITERS):
+    """The FP64 MF (oracle.mf) on the same iterations: the reference curves."""
+    _single_thread_env()
+    import numpy as np
+    from oracle import mf
+    import workloads
+    csr = workloads.movielens100k_shaped()
+    U0, V0 = workloads.init_factors(csr.n_rows, csr.n_cols, 10)
+    res = {}
+    t0 = time.perf_counter()
+    for name in ("without_batching", "with_batching_alg2"):
+        U, V, curve = U0, V0, []
+        for t in range(iters):
+            if name == "without_batching":
+                U, V, _ = mf.epoch(U, V, csr.row_ptr, csr.col_idx, csr.values, ACC_LR, ACC_LAM, t, 0.0, "R1")
+            else:
+                U, V, _ = mf.batch_pair_epoch(U, V, csr.row_ptr, csr.col_idx, csr.values, ACC_LR, ACC_LAM,
+                                              512, 512, t, ACC_DAMP)
+            curve.append(round(mf.rmse(mf.predict(U, V, csr.row_ptr, csr.col_idx), csr.values), 5))
+        res[name] = curve
+    dt = time.perf_counter() - t0
+    return {"value": 2 * iters * csr.nnz / dt, "unit": "ratings/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 MF (oracle.mf), both variants, {iters} iterations each", "fp64_rmse": res}
+
 
 
 # ---------------------------------------------------------------- helpers
@@ -459,6 +557,41 @@ def bench_serve(args):
         "sweep": results, "servers": stats}), flush=True)
 
 
+def graph_replay(ctx, cts, steps, eager_ms):
+    """The HMult and rotation phases of a step captured once in a HIP graph and
+    replayed `steps` times (the transform phase works on caller memory and
+    waits for it, so it stays eager).  Reported, not fatal."""
+    try:
+        ctx.sync()
+        ctx.graph_begin()
+        prods = ctx.hmult_batch(cts, cts[1:] + cts[:1])
+        for p in prods:
+            ctx.free(p)
+        cur, owned = list(cts), []
+        for r in CHAIN:
+            nxt = ctx.rotate_add_batch(cur, cur, r)
+            for h in owned:
+                ctx.free(h)
+            cur = owned = nxt
+        for h in ctx.conjugate_batch(cur) + owned:
+            ctx.free(h)
+        gid = ctx.graph_end()
+        ctx.graph_launch(gid)
+        ctx.sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.graph_launch(gid)
+        ctx.sync()
+        t_graph = (time.perf_counter() - t0) / steps
+        ctx.graph_destroy(gid)
+        log(f"graph replay {1e3 * t_graph:.2f} ms vs eager {1e3 * eager_ms:.2f} ms")
+        return {"what": "HMult + rotation phases of a step captured in one HIP graph, replayed",
+                "ms_per_replay": round(1e3 * t_graph, 3), "eager_ms": round(1e3 * eager_ms, 3),
+                "rotations_per_s_incl_hmult": round(N_CT * (len(CHAIN) + 1) / t_graph, 2)}
+    except Exception as e:
+        return {"error": repr(e)}
+
+
 # ---------------------------------------------------------------- key switching (the headline)
 def bench_ks(args):
     import numpy as np
@@ -477,7 +610,7 @@ def bench_ks(args):
     else:
         tune = ctx.autotune()
         schedule = tune["chosen"]
-    log(f"NTT schedule {tune}")
+    log(f"schedule {tune}")
     N = ctx.N
     L = ctx.L
     t0 = time.perf_counter()
@@ -566,6 +699,9 @@ def bench_ks(args):
     prof = pk.profile_report()
     pk.profile_enable(False)
 
+    eager_ms = (phase["hmult"] + phase["rotations"]) / args.steps
+    graph = {"skipped": "--no-graph"} if args.no_graph else graph_replay(ctx, cts, args.steps, eager_ms)
+
     n_rot = N_CT * (len(CHAIN) + 1)
     value = n_rot * args.steps / elapsed
     rot_rate = n_rot * args.steps / phase["rotations"]
@@ -574,7 +710,7 @@ def bench_ks(args):
     digits = [min(g, L + 1 - j * g) for j in range(3) if j * g < L + 1]
     model = ks_model(N, L + 1, ctx.alpha, digits, N_CT)
     # the 40-bit limbs (FP64 butterflies) among all transformed limbs
-    t_valu = valu_bound(model, (L + 1 - 1) / (L + 1 + ctx.alpha))
+    t_valu = valu_bound(model, 1.0 - model["int_limb_ntts"] / model["limb_ntts"])
     ks_roof = {
         "what": "rotation phase: rotate-and-add at 25 limbs (read c0, c1; write the result; "
                 "the key's share over the 64 ciphertexts that use it)",
@@ -583,7 +719,9 @@ def bench_ks(args):
         "achieved_GBps": round(rot_rate * model["alg_bytes"] / 1e9, 1),
         "hbm_roofline_rotations_per_s": round(HBM_PEAK_GBS * 1e9 / model["alg_bytes"], 1),
         "ks_hbm_frac": round(rot_rate * model["alg_bytes"] / (HBM_PEAK_GBS * 1e9), 4),
-        "counter_bytes_per_rotation": KS_COUNTER_BYTES_PER_ROTATION,
+        "counter_bytes_per_step": KS_COUNTER_BYTES_PER_STEP,
+        "counter_bytes_per_rotation_whole_step": None if KS_COUNTER_BYTES_PER_STEP is None
+        else round(KS_COUNTER_BYTES_PER_STEP / n_rot),
         "modmuls_per_rotation": model["modmuls"],
         "limb_ntts_per_rotation": model["limb_ntts"],
         "valu": None if t_valu is None else {
@@ -615,6 +753,7 @@ def bench_ks(args):
         "plain_gpu_path": {"rotations_per_s": round(plain_rate, 2), "ciphertexts": PLAIN_CT,
                            "what": "same rotate-and-sum chain, one ciphertext per call",
                            "batched_rotation_phase_speedup": round(rot_rate / plain_rate, 2)},
+        "graph_path": graph,
         "roofline": dominant_roofline(prof, schedule),
         "ks_roofline": ks_roof,
         "kernels": kernel_table(prof),
@@ -633,6 +772,18 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "accuracy":
+        out = run_accuracy(args.epochs or ACC_ITERS)
+        out.update({"n_gpus": 1, "steps": args.epochs or ACC_ITERS, "warmup": 0, "scaling": "weak",
+                    "vs_baseline": None, "dtype": "u64", "data": "synthetic"})
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = run_cpu_legs({"acc": (cpu_leg_accuracy, (args.epochs or ACC_ITERS,))})["acc"]
+            ref = out["cpu_baseline"].get("fp64_rmse", {})
+            for name, curve in ref.items():
+                enc = out[name]["rmse"]
+                out[name]["max_abs_diff_vs_fp64"] = round(max(abs(a - b) for a, b in zip(enc, curve)), 6)
+        print(json.dumps(out), flush=True)
+        return
     if args.workload in ("mf100k", "mf1m"):
         epochs = args.epochs or (10 if args.workload == "mf100k" else 5)
         out = run_mf(args.workload, epochs, args.ntt_chunk)

@@ -83,6 +83,9 @@ typedef struct csrmf_params {
     int32_t rule;           /* 1 = R1 (Alg. 1 summed), 2 = R2 (degree-normalised)*/
     int32_t refresh_mode;   /* 0 = fail with CSRMF_E_LEVEL when levels run out;  */
                             /* 1 = refresh the factor tables (csrmf_mf_epochs) */
+    int32_t batch_pairs;    /* 0 = CSR rows packed greedily, synchronous epochs  */
+                            /* (Alg. 1 with the accumulator of Alg. 2);          */
+                            /* 1 = user-item batch pairs (Alg. 2, Sec. III-D)   */
 } csrmf_params;
 
 /* Create a context: derives the prime chain and roots, uploads the transform
@@ -272,24 +275,46 @@ typedef struct csrmf_server csrmf_server;
  * the baby-step rotations of the gathers; the rotation keys the requests need
  * are generated if missing.  A worker thread admits queued requests while
  * their ciphertext footprint (about 16 ciphertexts per row chunk) fits in
- * hbm_budget_bytes and runs everything admitted as one batch (at most
- * max_batch requests); requests arriving meanwhile join the next batch.
+ * what hbm_budget_bytes leaves beside the batches still on the device,
+ * enqueues each batch (at most max_batch requests) without waiting for it,
+ * and pipelines up to four batches on the context's stream (continuous
+ * batching); a request is done, and its footprint returned, when its batch's
+ * completion event has fired.
  * Errors: INVAL, STATE, NOMEM, DEVICE, LEVEL (a chain of fewer than 2 levels). */
 int csrmf_server_create(csrmf_ctx* ctx, int32_t n_users, int32_t n_items, const double* U, const double* V,
                         double hbm_budget_bytes, int32_t max_batch, csrmf_server** out);
+
+/* csrmf_server_create with the tables given as integer plaintexts (the
+ * caller's encodings, so that an independent implementation can check the
+ * results bit for bit): utab[ceil(n_users/D)][N], vtab[ceil(n_items/D)][N]
+ * (entity a*D + b at block b, k factors in slots bB..bB+k-1, scale
+ * 2^log2_scale) and mask_gather[N], the indicator of slots 0..k-1 encoded at
+ * 2^30.  The tables are encrypted at the top level with the context's running
+ * serial numbers, the U tables first.  Errors as csrmf_server_create. */
+int csrmf_server_create_int(csrmf_ctx* ctx, int32_t n_users, int32_t n_items, const int64_t* utab,
+                            const int64_t* vtab, const int64_t* mask_gather, double hbm_budget_bytes,
+                            int32_t max_batch, csrmf_server** out);
 
 /* Queue a request: op 0 = PREDICT (r_hat = <u_user, v_j> for the row's items),
  * op 1 = UPDATE (one R2 gradient step of u_user on the row:
  * u' = (1 - lr*lambda) u + (lr/d) sum_j (r_j - <u, v_j>) v_j; items stay fixed).
  * items[n]: the row's item ids, increasing; ratings[n]: the row's ratings
- * (UPDATE only; encrypted on admission with randomness derived from
- * client_serial < 2^27, so equal requests give equal ciphertexts).  Rows longer
- * than D blocks are cut into up to 8 chunks.  id receives the request id.
- * A PREDICT uses 2 levels of the chain, an UPDATE 4.
- * Errors: INVAL, NOMEM (the request alone exceeds the budget), LEVEL (an
- * UPDATE on a chain of fewer than 4 levels). */
+ * (UPDATE only; chunk c of the row is encoded in slots tB..tB+k-1 of block t
+ * and encrypted on admission at the top level with encryption serial
+ * 0x40000000 + 8 * client_serial + c, so equal requests give equal
+ * ciphertexts).  client_serial < 2^27; an UPDATE may not reuse the serial of
+ * an earlier UPDATE on the same server (the randomness would repeat).  Rows
+ * longer than D blocks are cut into up to 8 chunks.  id receives the request
+ * id.  A PREDICT uses 2 levels of the chain, an UPDATE 4.
+ * Errors: INVAL (also a reused UPDATE serial), NOMEM (the request alone
+ * exceeds the budget), LEVEL (an UPDATE on a chain of fewer than 4 levels). */
 int csrmf_server_submit(csrmf_server* s, int32_t op, int32_t user, int32_t n, const int32_t* items,
                         const double* ratings, uint32_t client_serial, uint64_t* id);
+
+/* csrmf_server_submit with an UPDATE's rating chunks already encoded by the
+ * client: plain[ceil(n/D)][N] (int64), NULL for a PREDICT. */
+int csrmf_server_submit_int(csrmf_server* s, int32_t op, int32_t user, int32_t n, const int32_t* items,
+                            const int64_t* plain, uint32_t client_serial, uint64_t* id);
 
 /* Status of a request (wait != 0: block until it finishes): 0 queued,
  * 1 running, 2 done, or a negative error code (also returned).  When done,
@@ -312,10 +337,12 @@ void csrmf_server_destroy(csrmf_server* s);
 /* Schedule autotuning.                                                      */
 /* ------------------------------------------------------------------------ */
 
-/* Time the candidate NTT schedules (rows transformed per pair of passes) on
- * `rows` limbs of this context's ring (0: 64 ciphertexts x 2 x (L+1) limbs,
- * the batched key-switching shape) with HIP events, and keep the fastest for
- * all later work of this context.  Writes a JSON report of the timings into
+/* Time the candidate NTT schedules (rows transformed per pair of passes, the
+ * intermediate cached or streamed) on `rows` limbs of this context's ring
+ * (0: 64 ciphertexts x 2 x (L+1) limbs, the batched key-switching shape) and,
+ * if the context has a rotation key, the ModUp sub-batch sizes on one batched
+ * rotation of up to 64 zero ciphertexts, with HIP events, and keep the
+ * fastest for all later work of this context.  Writes a JSON report of the timings into
  * report (NUL-terminated, truncated to cap bytes; may be NULL).
  * Errors: NOMEM, DEVICE. */
 int csrmf_autotune(csrmf_ctx* ctx, int32_t rows, char* report, int32_t cap);
@@ -324,6 +351,41 @@ int csrmf_autotune(csrmf_ctx* ctx, int32_t rows, char* report, int32_t cap);
  * rows per pair of passes (0: the whole batch at once).  For repeatable
  * profiles.  Results do not depend on the schedule.  Errors: INVAL (negative). */
 int csrmf_set_ntt_schedule(csrmf_ctx* ctx, int32_t chunk_rows);
+
+/* The whole schedule of this context: NTT rows per pair of passes (0: the
+ * whole batch), whether the intermediate between the two passes goes through
+ * the caches (1) or is streamed past them (0), and ciphertexts per ModUp
+ * sub-batch of a key switch (0: the whole batch; a sub-batch runs its inverse
+ * transform, conversions and forward transforms before the next, so a small
+ * one keeps each stage's output in the last-level cache).  Results do not
+ * depend on the schedule.  csrmf_autotune chooses all three (the ModUp
+ * sub-batch only when the context has a rotation key).  Errors: INVAL. */
+int csrmf_set_schedule(csrmf_ctx* ctx, int32_t ntt_chunk_rows, int32_t ntt_cached_mid, int32_t modup_chunk);
+int csrmf_get_schedule(const csrmf_ctx* ctx, int32_t* ntt_chunk_rows, int32_t* ntt_cached_mid, int32_t* modup_chunk);
+
+/* ------------------------------------------------------------------------ */
+/* HIP graphs of evaluation sequences.                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Record instead of run: after csrmf_graph_begin the context's evaluation
+ * calls (add, mul_int, hmult, relinearise, rescale, rotations, their batched
+ * forms, free_ct) are captured from the context's stream into a HIP graph
+ * until csrmf_graph_end, which instantiates it and returns its id; nothing
+ * runs until csrmf_graph_launch, which replays the whole sequence on the
+ * stream.  Calls that wait for the device (encryption, decryption, export,
+ * keys, csrmf_ntt_rows, csrmf_sync) fail with STATE while capturing.  The
+ * ciphertexts the captured calls create are the graph's buffers: every launch
+ * writes them again, from the inputs as they are at launch time; handles
+ * freed during the capture may be reused only within it; all of the graph's
+ * memory (its buffers and a 32 MiB pinned argument arena) is freed by
+ * csrmf_graph_destroy, after which handles created during the capture must
+ * not be used.  Per-kernel profiling must be off while capturing.
+ * Errors: STATE (capture open or not open, profiling on), NOMEM, DEVICE,
+ * INVAL (unknown graph). */
+int csrmf_graph_begin(csrmf_ctx* ctx);
+int csrmf_graph_end(csrmf_ctx* ctx, uint64_t* graph);
+int csrmf_graph_launch(csrmf_ctx* ctx, uint64_t graph);
+int csrmf_graph_destroy(csrmf_ctx* ctx, uint64_t graph);
 
 /* ------------------------------------------------------------------------ */
 /* Per-kernel timing (benchmark hook; process-wide).                         */
@@ -342,7 +404,13 @@ int csrmf_profile_report(char* buf, int32_t cap);
 /* Encrypted CSR matrix factorisation (Alg. 1 / Alg. 2).                     */
 /* ------------------------------------------------------------------------ */
 
-/* Pack the CSR rating matrix (n_rows users x n_cols items; row_ptr[n_rows+1],
+/* With params.batch_pairs = 1 the ratings are grouped by user-item batch
+ * pair instead (Sec. III-D, Alg. 2): a batch is one factor-table ciphertext
+ * (D profiles: user i is local index i mod D of batch i div D, items
+ * likewise), the pairs come in the order of their first rating in CSR order,
+ * and each pair's ratings (CSR order) fill rating ciphertexts of their own.
+ *
+ * Pack the CSR rating matrix (n_rows users x n_cols items; row_ptr[n_rows+1],
  * col_idx[nnz] sorted within a row, values[nnz]) into block layout and encrypt
  * it (Alg. 1 EncryptCsrMatrix).  With k' = 2^ceil(log2 k), block width B = 2k'
  * and D = N/(2B) blocks per ciphertext, rows are packed greedily in CSR order;
@@ -385,7 +453,17 @@ int csrmf_init_factors_int(csrmf_ctx* ctx, const int64_t* utab, const int64_t* v
 int csrmf_mf_layout(const csrmf_ctx* ctx, int32_t* n_ct, int32_t* n_utab, int32_t* n_vtab,
                     int32_t* D, int32_t* B);
 
-/* Run n_epochs synchronous encrypted gradient-descent epochs.  Each epoch
+/* With params.batch_pairs = 1 an epoch is Alg. 2: the batch pairs in turn,
+ * each from the tables as they are when it starts: gather of its user table
+ * and item table into its rating ciphertexts, dot products, errors, gradient
+ * terms, and the scatter into those two tables with weight a_t per rating
+ * and self term (1 - a_t*lambda*c) (c = the entity's ratings in the pair; 1
+ * for entities without one); a pair costs 4 levels of its tables, and all
+ * tables are refreshed (refresh_mode = 1) before a pair whose tables are
+ * below level 4.  Forward predictions are those at the start of each
+ * rating's pair.
+ *
+ * Run n_epochs synchronous encrypted gradient-descent epochs.  Each epoch
  * computes for every rating ciphertext P = Ug*Vg, the block dot products by a
  * windowed rotate-and-sum, E = R - <u,v>, the gradient terms E*Vg and E*Ug,
  * scatters them into the factor tables (held at scale 2^50) with the
@@ -442,6 +520,42 @@ int csrmf_mf_mac_counts(const csrmf_ctx* ctx, int64_t* counts);
  * epoch, 6 the output of csrmf_predict.  Writes up to `cap` handles into out
  * and the count into n. */
 int csrmf_mf_handles(const csrmf_ctx* ctx, int32_t which, uint64_t* out, int32_t cap, int32_t* n);
+
+/* ------------------------------------------------------------------------ */
+/* The three-party protocol (Sec. III-B) with message accounting.            */
+/* ------------------------------------------------------------------------ */
+
+/* Initialization phase of the protocol between the users, the recommendation
+ * server (RS) and the crypto service provider (CSP, the key holder; keys from
+ * csrmf_keygen), played on one context with every message serialised and
+ * counted: each user encrypts its CSR row with pk (one rating per slot,
+ * encryption serial 0x50000000 + 64 * user + chunk) and sends it to the RS;
+ * the RS adds a mask per rating (ChaCha20 purpose 12, object = rating index:
+ * ((w mod 2^21) - 2^20) / 2^10) and sends the result to the CSP; the CSP
+ * decrypts the masked ratings, packs them in the CSR block layout of
+ * csrmf_encrypt_csr_rows and encrypts them (serial 0x58000000 + ciphertext
+ * index) for the RS, which removes its masks.  The result replaces the MF
+ * program's rating ciphertexts, as csrmf_encrypt_csr_rows does; n_ct receives
+ * their count.  Errors as csrmf_encrypt_csr_rows. */
+int csrmf_protocol_ingest(csrmf_ctx* ctx, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr,
+                          const int32_t* col_idx, const double* values, int32_t* n_ct);
+
+/* Recommendation phase: the RS masks the encrypted predictions (which = 0:
+ * the last epoch's forward predictions, 1: csrmf_predict's; masks from
+ * ChaCha20 purpose 13 as above) and sends them to the CSP, which decrypts
+ * them and sends the masked plaintext predictions to the users; the RS sends
+ * the users the masks, and the users remove them.  rhat[nnz] receives the
+ * users' predictions in CSR order.  Errors: STATE, INVAL. */
+int csrmf_protocol_recommend(csrmf_ctx* ctx, int32_t which, double* rhat);
+
+/* Messages and bytes per channel since the last csrmf_protocol_ingest,
+ * msgs[8] and bytes[8]: 0 CSP->users (public key), 1 CSP->RS (public and
+ * evaluation keys), 2 users->RS (encrypted rows), 3 RS->CSP (masked rows),
+ * 4 CSP->RS (re-packed rating ciphertexts), 5 RS->CSP (masked encrypted
+ * predictions), 6 CSP->users (masked plaintext predictions, 8 bytes each),
+ * 7 RS->users (prediction masks, 8 bytes each).  A ciphertext message is
+ * 2 (level+1) N 8 bytes.  Errors: INVAL (null pointer). */
+int csrmf_protocol_counters(const csrmf_ctx* ctx, int64_t* msgs, int64_t* bytes);
 
 #ifdef __cplusplus
 }

@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
                 ("n_special", ctypes.c_int32), ("special_bits", ctypes.c_int32),
                 ("dnum", ctypes.c_int32), ("log2_scale", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("lr", ctypes.c_double), ("lam", ctypes.c_double),
-                ("damp", ctypes.c_double), ("rule", ctypes.c_int32), ("refresh_mode", ctypes.c_int32)]
+                ("damp", ctypes.c_double), ("rule", ctypes.c_int32), ("refresh_mode", ctypes.c_int32),
+                ("batch_pairs", ctypes.c_int32)]
 
 
 _p = ctypes.c_void_p
@@ -98,12 +99,25 @@ _SIGS = {
     "csrmf_mf_mac_counts": [_p, ctypes.POINTER(ctypes.c_int64)],
     "csrmf_autotune": [_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32],
     "csrmf_set_ntt_schedule": [_p, ctypes.c_int32],
-    "csrmf_set_baby_budget": [_p, ctypes.c_int32],
-    "csrmf_counters": [_p, ctypes.POINTER(ctypes.c_int64)],
     "csrmf_rotate_noalloc": [_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint64],
+    "csrmf_set_baby_budget": [_p, ctypes.c_int32],
+    "csrmf_set_schedule": [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "csrmf_graph_begin": [_p],
+    "csrmf_graph_end": [_p, _u64p],
+    "csrmf_graph_launch": [_p, ctypes.c_uint64],
+    "csrmf_graph_destroy": [_p, ctypes.c_uint64],
+    "csrmf_get_schedule": [_p, _i32p, _i32p, _i32p],
+    "csrmf_counters": [_p, ctypes.POINTER(ctypes.c_int64)],
+    "csrmf_protocol_ingest": [_p, ctypes.c_int32, ctypes.c_int32, _i64p, _i32p, _dp, _i32p],
+    "csrmf_protocol_recommend": [_p, ctypes.c_int32, _dp],
+    "csrmf_protocol_counters": [_p, _i64p, _i64p],
     "csrmf_server_create": [_p, ctypes.c_int32, ctypes.c_int32, _dp, _dp, ctypes.c_double, ctypes.c_int32,
                             ctypes.POINTER(_p)],
     "csrmf_server_submit": [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _dp, ctypes.c_uint32, _u64p],
+    "csrmf_server_create_int": [_p, ctypes.c_int32, ctypes.c_int32, _i64p, _i64p, _i64p, ctypes.c_double,
+                                ctypes.c_int32, ctypes.POINTER(_p)],
+    "csrmf_server_submit_int": [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _i64p, ctypes.c_uint32,
+                                _u64p],
     "csrmf_server_poll": [_p, ctypes.c_uint64, ctypes.c_int32, _i32p, _u64p, ctypes.c_int32, _i32p, _dp],
     "csrmf_server_stats": [_p, ctypes.c_char_p, ctypes.c_int32],
     "csrmf_server_destroy": [_p],
@@ -123,9 +137,9 @@ def _ptr(a, ct):
 
 
 def params(log2N, base_bits, n_scale, scale_bits, n_special, special_bits, dnum, log2_scale=40,
-           k=0, lr=0.0, lam=0.0, damp=0.0, rule=1, refresh_mode=0):
+           k=0, lr=0.0, lam=0.0, damp=0.0, rule=1, refresh_mode=0, batch_pairs=0):
     return Params(log2N, base_bits, n_scale, scale_bits, n_special, special_bits, dnum, log2_scale,
-                  k, lr, lam, damp, rule, refresh_mode)
+                  k, lr, lam, damp, rule, refresh_mode, batch_pairs)
 
 
 class Context:
@@ -304,6 +318,30 @@ class Context:
         device allocation (the library's static scratch buffer)."""
         self._chk(lib.csrmf_rotate_noalloc(self.h, a, r, out))
 
+    def graph_begin(self):
+        """Capture the following evaluation calls into a HIP graph (see csrmf_graph_begin)."""
+        self._chk(lib.csrmf_graph_begin(self.h))
+
+    def graph_end(self):
+        g = ctypes.c_uint64()
+        self._chk(lib.csrmf_graph_end(self.h, ctypes.byref(g)))
+        return g.value
+
+    def graph_launch(self, g):
+        self._chk(lib.csrmf_graph_launch(self.h, g))
+
+    def graph_destroy(self, g):
+        self._chk(lib.csrmf_graph_destroy(self.h, g))
+
+    def set_schedule(self, ntt_chunk_rows=0, ntt_cached_mid=0, modup_chunk=0):
+        """Fix this context's whole schedule (see csrmf_set_schedule)."""
+        self._chk(lib.csrmf_set_schedule(self.h, int(ntt_chunk_rows), int(ntt_cached_mid), int(modup_chunk)))
+
+    def schedule(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._chk(lib.csrmf_get_schedule(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"ntt_chunk_rows": a.value, "ntt_cached_mid": b.value, "modup_chunk": c.value}
+
     def counters(self):
         """{"key_switches": relinearisations and rotations enqueued so far}."""
         v = ctypes.c_int64()
@@ -422,6 +460,33 @@ class MF:
     def epochs(self, n):
         self.ctx._chk(lib.csrmf_mf_epochs(self.ctx.h, n))
 
+    def protocol_ingest(self, n_rows, n_cols, row_ptr, col_idx, values):
+        """The protocol's initialization phase (users -> RS -> CSP -> RS); returns n_ct."""
+        rp = np.ascontiguousarray(row_ptr, np.int64)
+        ci = np.ascontiguousarray(col_idx, np.int32)
+        v = np.ascontiguousarray(values, np.float64)
+        n = ctypes.c_int32()
+        self.ctx._chk(lib.csrmf_protocol_ingest(self.ctx.h, n_rows, n_cols, _ptr(rp, ctypes.c_int64),
+                                                _ptr(ci, ctypes.c_int32), _ptr(v, ctypes.c_double), ctypes.byref(n)))
+        self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, len(ci)
+        return n.value
+
+    def protocol_recommend(self, which=0):
+        """The recommendation phase: the users' unmasked predictions (CSR order)."""
+        out = np.zeros(self.nnz)
+        self.ctx._chk(lib.csrmf_protocol_recommend(self.ctx.h, which, _ptr(out, ctypes.c_double)))
+        return out
+
+    CHANNELS = ["csp_to_users_pk", "csp_to_rs_keys", "users_to_rs", "rs_to_csp_masked", "csp_to_rs_ratings",
+                "rs_to_csp_predictions", "csp_to_users_predictions", "rs_to_users_masks"]
+
+    def protocol_counters(self):
+        """{channel: (messages, bytes)} of the last protocol run."""
+        msgs = np.zeros(8, np.int64)
+        byts = np.zeros(8, np.int64)
+        self.ctx._chk(lib.csrmf_protocol_counters(self.ctx.h, _ptr(msgs, ctypes.c_int64), _ptr(byts, ctypes.c_int64)))
+        return {n: (int(a), int(b)) for n, a, b in zip(self.CHANNELS, msgs, byts)}
+
     def set_baby_budget(self, max_babies):
         """Block permutations keep at most max_babies baby rotations alive (memory bound)."""
         self.ctx._chk(lib.csrmf_set_baby_budget(self.ctx.h, int(max_babies)))
@@ -452,14 +517,23 @@ class Server:
     """Request server (continuous batching) on a Context; see csrmf_server_*."""
     PREDICT, UPDATE = 0, 1
 
-    def __init__(self, ctx: "Context", U, V, hbm_budget_bytes, max_batch=64):
-        U = np.ascontiguousarray(U, np.float64)
-        V = np.ascontiguousarray(V, np.float64)
+    def __init__(self, ctx: "Context", U, V, hbm_budget_bytes, max_batch=64, plain=None):
+        """U, V: factor matrices (encoded by the library); or plain =
+        (n_users, n_items, utab, vtab, mask_gather) integer plaintexts."""
         self.ctx = ctx
         h = _p()
-        ctx._chk(lib.csrmf_server_create(ctx.h, U.shape[0], V.shape[0], _ptr(U, ctypes.c_double),
-                                         _ptr(V, ctypes.c_double), float(hbm_budget_bytes), max_batch,
-                                         ctypes.byref(h)))
+        if plain is None:
+            U = np.ascontiguousarray(U, np.float64)
+            V = np.ascontiguousarray(V, np.float64)
+            ctx._chk(lib.csrmf_server_create(ctx.h, U.shape[0], V.shape[0], _ptr(U, ctypes.c_double),
+                                             _ptr(V, ctypes.c_double), float(hbm_budget_bytes), max_batch,
+                                             ctypes.byref(h)))
+        else:
+            nu, nv, ut, vt, mg = plain
+            ut, vt, mg = (np.ascontiguousarray(a, np.int64) for a in (ut, vt, mg))
+            ctx._chk(lib.csrmf_server_create_int(ctx.h, nu, nv, _ptr(ut, ctypes.c_int64), _ptr(vt, ctypes.c_int64),
+                                                 _ptr(mg, ctypes.c_int64), float(hbm_budget_bytes), max_batch,
+                                                 ctypes.byref(h)))
         self.h = h
         if not hasattr(ctx, "_servers"):
             ctx._servers = []
@@ -469,15 +543,21 @@ class Server:
         """The context is being destroyed; it stops and frees this server itself."""
         self.h = None
 
-    def submit(self, op, user, items, ratings=None, client_serial=0):
+    def submit(self, op, user, items, ratings=None, client_serial=0, plain=None):
+        """plain: an UPDATE's rating chunks encoded by the caller ([chunks][N] int64)."""
         it = np.ascontiguousarray(items, np.int32)
-        r = None if ratings is None else np.ascontiguousarray(ratings, np.float64)
         rid = ctypes.c_uint64()
-        rc = lib.csrmf_server_submit(self.h, op, user, len(it), _ptr(it, ctypes.c_int32),
-                                     None if r is None else _ptr(r, ctypes.c_double), client_serial,
-                                     ctypes.byref(rid))
+        if plain is not None:
+            pl = np.ascontiguousarray(plain, np.int64)
+            rc = lib.csrmf_server_submit_int(self.h, op, user, len(it), _ptr(it, ctypes.c_int32),
+                                             _ptr(pl, ctypes.c_int64), client_serial, ctypes.byref(rid))
+        else:
+            r = None if ratings is None else np.ascontiguousarray(ratings, np.float64)
+            rc = lib.csrmf_server_submit(self.h, op, user, len(it), _ptr(it, ctypes.c_int32),
+                                         None if r is None else _ptr(r, ctypes.c_double), client_serial,
+                                         ctypes.byref(rid))
         if rc != CSRMF_OK:
-            raise CsrmfError(rc, "submit rejected")
+            raise CsrmfError(rc, lib.csrmf_last_error(None).decode())
         return rid.value
 
     def poll(self, rid, wait=False):

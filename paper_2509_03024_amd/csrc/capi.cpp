@@ -441,6 +441,54 @@ int csrmf_set_ntt_schedule(csrmf_ctx* cx, int32_t chunk_rows) {
     API_END(c)
 }
 
+int csrmf_set_schedule(csrmf_ctx* cx, int32_t ntt_chunk_rows, int32_t ntt_cached_mid, int32_t modup_chunk) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(ntt_chunk_rows >= 0 && modup_chunk >= 0 && (ntt_cached_mid == 0 || ntt_cached_mid == 1), "schedule values");
+    c->tabs.ntt_chunk_rows = ntt_chunk_rows;
+    c->tabs.ntt_cached_mid = ntt_cached_mid;
+    c->modup_chunk = modup_chunk;
+    API_END(c)
+}
+
+int csrmf_get_schedule(const csrmf_ctx* cx, int32_t* ntt_chunk_rows, int32_t* ntt_cached_mid, int32_t* modup_chunk) {
+    const Context* c = reinterpret_cast<const Context*>(cx);
+    if (!c) return CSRMF_E_INVAL;
+    if (ntt_chunk_rows) *ntt_chunk_rows = c->tabs.ntt_chunk_rows;
+    if (ntt_cached_mid) *ntt_cached_mid = c->tabs.ntt_cached_mid;
+    if (modup_chunk) *modup_chunk = c->modup_chunk;
+    return CSRMF_OK;
+}
+
+int csrmf_graph_begin(csrmf_ctx* cx) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    c->graph_begin();
+    API_END(c)
+}
+
+int csrmf_graph_end(csrmf_ctx* cx, uint64_t* graph) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(graph, "graph");
+    *graph = c->graph_end();
+    API_END(c)
+}
+
+int csrmf_graph_launch(csrmf_ctx* cx, uint64_t graph) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    c->graph_launch(graph);
+    API_END(c)
+}
+
+int csrmf_graph_destroy(csrmf_ctx* cx, uint64_t graph) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    c->graph_destroy(graph);
+    API_END(c)
+}
+
 int csrmf_profile_enable(int32_t enable) {
     csrmf::prof_enable(enable != 0);
     return CSRMF_OK;

@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "host_math.h"
+#include "prof.h"
 
 namespace csrmf {
 
@@ -23,6 +24,15 @@ size_t Pool::size_class(size_t bytes) {
 
 void* Pool::get(size_t bytes) {
     bytes = size_class(bytes);
+    if (capture_) {
+        auto ci = cap_free_.find(bytes);
+        if (ci != cap_free_.end()) {   // a block the capture freed earlier
+            void* p = ci->second;
+            cap_free_.erase(ci);
+            in_use_ += bytes;
+            return p;
+        }
+    }
     auto it = free_.find(bytes);
     void* p = nullptr;
     if (it != free_.end()) {
@@ -46,18 +56,59 @@ void* Pool::get(size_t bytes) {
         sizes_[p] = bytes;
     }
     in_use_ += bytes;
+    if (capture_) cap_blocks_[p] = bytes;
     return p;
 }
 
 void Pool::put(void* p) {
     if (!p) return;
+    if (graph_owned_.count(p)) return;   // a graph's block: freed with the graph
     auto it = sizes_.find(p);
     if (it == sizes_.end()) return;
     in_use_ -= it->second;
+    if (capture_) {
+        cap_blocks_[p] = it->second;
+        cap_free_.emplace(it->second, p);
+        return;
+    }
     free_.emplace(it->second, p);
 }
 
+void Pool::begin_capture() {
+    capture_ = true;
+    cap_blocks_.clear();
+    cap_free_.clear();
+}
+
+std::vector<void*> Pool::end_capture() {
+    capture_ = false;
+    std::vector<void*> out;
+    for (auto& kv : cap_blocks_) {
+        out.push_back(kv.first);
+        graph_owned_[kv.first] = kv.second;
+    }
+    // blocks freed during the capture stay out of the free list: the graph uses them
+    for (auto& kv : cap_free_) in_use_ += kv.first;
+    cap_blocks_.clear();
+    cap_free_.clear();
+    return out;
+}
+
+void Pool::free_blocks(const std::vector<void*>& v) {
+    for (void* p : v) {
+        auto g = graph_owned_.find(p);
+        if (g == graph_owned_.end()) continue;
+        in_use_ -= g->second;
+        graph_owned_.erase(g);
+        sizes_.erase(p);
+        (void)hipFree(p);
+    }
+}
+
 void Pool::release_all() {
+    graph_owned_.clear();
+    cap_blocks_.clear();
+    cap_free_.clear();
     for (auto& kv : sizes_) (void)hipFree(kv.first);
     sizes_.clear();
     free_.clear();
@@ -121,6 +172,18 @@ void Staging::release() {
 }
 
 void* Staging::put(const void* src, size_t bytes) {
+    if (arena_host_) {   // graph capture: the graph's own arena
+        const size_t need = (bytes + 255) / 256 * 256;
+        if (arena_used_ + need > arena_cap_) throw Error(CSRMF_E_NOMEM, "graph argument arena full");
+        uint8_t* h = arena_host_ + arena_used_;
+        uint8_t* d = arena_dev_ + arena_used_;
+        arena_used_ += need;
+        if (bytes) {
+            std::memcpy(h, src, bytes);
+            CSRMF_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ops_.stream));
+        }
+        return d;
+    }
     if (!host_) throw Error(CSRMF_E_STATE, "staging ring not initialised");
     const size_t off = ring_.reserve(bytes, ops_);
     if (bytes) {
@@ -130,9 +193,74 @@ void* Staging::put(const void* src, size_t bytes) {
     return dev_ + off;
 }
 
-void Context::sync() {
+void Context::sync(const char* caller) {
+    if (capturing)
+        throw Error(CSRMF_E_STATE, std::string(caller) + " waits for the device and cannot be captured in a graph");
     CSRMF_HIP(hipStreamSynchronize(stream));
     staging.drained();
+}
+
+// ------------------------------------------------------------------ graphs
+void Context::graph_begin() {
+    if (capturing) throw Error(CSRMF_E_STATE, "a capture is already open");
+    if (prof_enabled()) throw Error(CSRMF_E_STATE, "per-kernel profiling records events: disable it to capture");
+    if (!stream) throw Error(CSRMF_E_STATE, "capture needs the context's own stream, not the null stream");
+    sync();
+    CapturedGraph g;
+    CSRMF_HIP(hipHostMalloc((void**)&g.arena_host, kGraphArenaBytes, hipHostMallocDefault));
+    hipError_t e = hipMalloc((void**)&g.arena_dev, kGraphArenaBytes);
+    if (e != hipSuccess) {
+        (void)hipHostFree(g.arena_host);
+        throw Error(CSRMF_E_NOMEM, "graph argument arena");
+    }
+    e = hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        (void)hipHostFree(g.arena_host);
+        (void)hipFree(g.arena_dev);
+        throw Error(CSRMF_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    staging.begin_arena(g.arena_host, g.arena_dev, kGraphArenaBytes);
+    pool.begin_capture();
+    capturing = true;
+    graphs[0] = g;   // slot 0: the capture in progress
+}
+
+uint64_t Context::graph_end() {
+    if (!capturing) throw Error(CSRMF_E_STATE, "no capture is open");
+    capturing = false;
+    staging.end_arena();
+    CapturedGraph g = graphs[0];
+    graphs.erase(0);
+    g.blocks = pool.end_capture();
+    hipError_t e = hipStreamEndCapture(stream, &g.graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    const uint64_t id = next_graph++;
+    graphs[id] = g;
+    if (e != hipSuccess) {
+        graph_destroy(id);
+        throw Error(CSRMF_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    return id;
+}
+
+void Context::graph_launch(uint64_t id) {
+    auto it = graphs.find(id);
+    if (id == 0 || it == graphs.end()) throw Error(CSRMF_E_INVAL, "unknown graph");
+    if (capturing) throw Error(CSRMF_E_STATE, "cannot launch a graph while capturing");
+    CSRMF_HIP(hipGraphLaunch(it->second.exec, stream));
+}
+
+void Context::graph_destroy(uint64_t id) {
+    auto it = graphs.find(id);
+    if (id == 0 || it == graphs.end()) throw Error(CSRMF_E_INVAL, "unknown graph");
+    (void)hipStreamSynchronize(stream);
+    CapturedGraph& g = it->second;
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    pool.free_blocks(g.blocks);
+    if (g.arena_host) (void)hipHostFree(g.arena_host);
+    if (g.arena_dev) (void)hipFree(g.arena_dev);
+    graphs.erase(it);
 }
 
 // ------------------------------------------------------------------ helpers
@@ -151,6 +279,23 @@ static uint64_t* upload_consts(Pool& pool, const std::vector<uint64_t>& v, hipSt
 
 Context::~Context() {
     while (!servers.empty()) destroy_server(servers.back());   // joins the worker threads
+    if (capturing) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        capturing = false;
+        staging.end_arena();
+        graphs[0].blocks = pool.end_capture();
+    }
+    while (!graphs.empty()) {
+        const uint64_t id = graphs.begin()->first;
+        CapturedGraph& g = graphs.begin()->second;
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        if (g.arena_host) (void)hipHostFree(g.arena_host);
+        if (g.arena_dev) (void)hipFree(g.arena_dev);
+        graphs.erase(id);   // the blocks go with release_all below
+    }
     if (stream) (void)hipStreamSynchronize(stream);
     else (void)hipDeviceSynchronize();
     destroy_mf(mf);
@@ -818,31 +963,48 @@ void Context::mod_drop(Ct& c, int level) {
 
 // ModUp of every digit of d (evaluation form, B ciphertext rows of level+1
 // limbs) into ext [B][n_digits][l+1+alpha][N] (evaluation form).
+// Rows of batch elements [b0, b0 + n) of a map.
+static RowMap sub_batch(const RowMap& m, int b0, int n) {
+    RowMap r = m;
+    r.batch = n;
+    if (m.ptrs) r.ptrs = m.ptrs + b0;
+    else r.base = m.base + (int64_t)b0 * m.batch_stride;
+    return r;
+}
+
+// The ModUp runs over sub-batches of `modup_chunk` ciphertexts (0: the whole
+// batch): inverse transform, then per digit the conversion and the forward
+// transform, so that a sub-batch small enough for the last-level cache hands
+// each stage's output to the next from there.
 void Context::ks_modup(const RowMap& d_in, int level, int B, uint64_t* ext, uint64_t* coef) {
     const int nl = level + 1, nr = n_ext(level);
     const LevelConsts& c = lv[level];
     const int nd = (int)c.digits.size();
-    RowMap mc;
-    mc.base = coef;
-    mc.batch = B;
-    mc.batch_stride = (int64_t)nl * N;
-    for (int i = 0; i < nl; ++i) mc.push(i, i);
-    launch_ntt_from(tabs, mc, d_in, true, stream);   // coefficient form of d_in, which stays as it is
-    for (int jj = 0; jj < nd; ++jj) {
-        const DigitConsts& dc = c.digits[jj];
-        RowMap src, dst;
-        src.base = coef;
-        src.batch = B;
-        src.batch_stride = (int64_t)nl * N;
-        for (int i = dc.lo; i < dc.hi; ++i) src.push(i, i);
-        dst.base = ext;
-        dst.batch = B;
-        dst.batch_stride = (int64_t)nd * nr * N;
-        for (int t = 0; t < nr; ++t)
-            if (!(t >= dc.lo && t < dc.hi)) dst.push(jj * nr + t, gmod_ext(level, t));
-        launch_basis_convert(tabs, dst, src, dc.yc, dc.cc, true, stream);   // centred digits
-        launch_ntt(tabs, dst, false, stream);
-        // the digit's own limbs are d_in's: ks_inner reads them there
+    const int mcb = modup_chunk > 0 ? std::min(modup_chunk, B) : B;
+    for (int b0 = 0; b0 < B; b0 += mcb) {
+        const int nb = std::min(mcb, B - b0);
+        RowMap mc;
+        mc.base = coef + (size_t)b0 * nl * N;
+        mc.batch = nb;
+        mc.batch_stride = (int64_t)nl * N;
+        for (int i = 0; i < nl; ++i) mc.push(i, i);
+        launch_ntt_from(tabs, mc, sub_batch(d_in, b0, nb), true, stream);   // coefficient form of d_in, unchanged
+        for (int jj = 0; jj < nd; ++jj) {
+            const DigitConsts& dc = c.digits[jj];
+            RowMap src, dst;
+            src.base = mc.base;
+            src.batch = nb;
+            src.batch_stride = (int64_t)nl * N;
+            for (int i = dc.lo; i < dc.hi; ++i) src.push(i, i);
+            dst.base = ext + (size_t)b0 * nd * nr * N;
+            dst.batch = nb;
+            dst.batch_stride = (int64_t)nd * nr * N;
+            for (int t = 0; t < nr; ++t)
+                if (!(t >= dc.lo && t < dc.hi)) dst.push(jj * nr + t, gmod_ext(level, t));
+            launch_basis_convert(tabs, dst, src, dc.yc, dc.cc, true, stream);   // centred digits
+            launch_ntt(tabs, dst, false, stream);
+            // the digit's own limbs are d_in's: ks_inner reads them there
+        }
     }
 }
 
@@ -1077,30 +1239,72 @@ std::string Context::autotune(int rows) {
     CSRMF_HIP(hipEventCreate(&a));
     CSRMF_HIP(hipEventCreate(&b));
     const int cands[] = {0, 64, 128, 256, 512, 1024, 2048};
-    int best = 0;
+    int best = 0, best_cached = 0;
     float best_ms = 1e30f;
     std::string rep = "{";
-    for (int cnd : cands) {
-        tabs.ntt_chunk_rows = cnd;
-        launch_ntt(tabs, m, false, stream);     // warm
-        launch_ntt(tabs, m, true, stream);
-        CSRMF_HIP(hipEventRecord(a, stream));
-        for (int r = 0; r < 3; ++r) {
-            launch_ntt(tabs, m, false, stream);
+    for (int cached = 0; cached < 2; ++cached) {
+        for (int cnd : cands) {
+            tabs.ntt_chunk_rows = cnd;
+            tabs.ntt_cached_mid = cached;
+            launch_ntt(tabs, m, false, stream);     // warm
             launch_ntt(tabs, m, true, stream);
+            CSRMF_HIP(hipEventRecord(a, stream));
+            for (int r = 0; r < 3; ++r) {
+                launch_ntt(tabs, m, false, stream);
+                launch_ntt(tabs, m, true, stream);
+            }
+            CSRMF_HIP(hipEventRecord(b, stream));
+            CSRMF_HIP(hipEventSynchronize(b));
+            float ms = 0;
+            CSRMF_HIP(hipEventElapsedTime(&ms, a, b));
+            ms /= 3;
+            rep += (rep.size() > 1 ? ", " : "") + std::string("\"ntt_chunk_rows=") + std::to_string(cnd) +
+                   (cached ? ",cached_mid" : "") + "\": " + std::to_string(ms);
+            if (ms < best_ms) { best_ms = ms; best = cnd; best_cached = cached; }
         }
-        CSRMF_HIP(hipEventRecord(b, stream));
-        CSRMF_HIP(hipEventSynchronize(b));
-        float ms = 0;
-        CSRMF_HIP(hipEventElapsedTime(&ms, a, b));
-        ms /= 3;
-        rep += (rep.size() > 1 ? ", " : "") + std::string("\"ntt_chunk_rows=") + std::to_string(cnd) + "\": " + std::to_string(ms);
-        if (ms < best_ms) { best_ms = ms; best = cnd; }
+    }
+    tabs.ntt_chunk_rows = best;
+    tabs.ntt_cached_mid = best_cached;
+    rep += ", \"chosen\": " + std::to_string(best) + ", \"cached_mid\": " + std::to_string(best_cached);
+    // ModUp sub-batch: time one batched rotation of scratch ciphertexts under
+    // each candidate (needs a rotation key; the data does not matter)
+    if (!rot.empty()) {
+        const int nb = std::max(1, std::min(64, rows / (2 * (L + 1))));
+        std::vector<Ct> in(nb), out(nb);
+        std::vector<Ct*> pin, pout;
+        for (int i = 0; i < nb; ++i) {   // zero ciphertexts: the timing does not depend on the residues
+            in[i] = new_ct(L, 1.0);
+            CSRMF_HIP(hipMemsetAsync(in[i].d, 0, ct_words() * 8, stream));
+            pin.push_back(&in[i]);
+        }
+        for (Ct& x : out) pout.push_back(&x);
+        const uint32_t g = rot.begin()->first;
+        const int mcands[] = {0, 8, 16, 32};
+        int best_mc = 0;
+        float best_mc_ms = 1e30f;
+        for (int mc : mcands) {
+            if (mc >= nb) continue;
+            modup_chunk = mc;
+            rotate(pin, g, pout);
+            for (Ct& x : out) pool.put(x.d);
+            CSRMF_HIP(hipEventRecord(a, stream));
+            rotate(pin, g, pout);
+            CSRMF_HIP(hipEventRecord(b, stream));
+            CSRMF_HIP(hipEventSynchronize(b));
+            for (Ct& x : out) pool.put(x.d);
+            float ms = 0;
+            CSRMF_HIP(hipEventElapsedTime(&ms, a, b));
+            rep += ", \"modup_chunk=" + std::to_string(mc) + "\": " + std::to_string(ms);
+            if (ms < best_mc_ms) { best_mc_ms = ms; best_mc = mc; }
+        }
+        modup_chunk = best_mc;
+        rep += ", \"modup_chunk\": " + std::to_string(best_mc);
+        for (Ct& x : in) pool.put(x.d);
+        sync();
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    tabs.ntt_chunk_rows = best;
-    rep += ", \"chosen\": " + std::to_string(best) + "}";
+    rep += "}";
     return rep;
 }
 

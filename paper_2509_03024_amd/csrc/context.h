@@ -63,6 +63,11 @@ struct LevelConsts {
 // allocated.  A block handed back with put() may be handed out again at once:
 // all users run on the context's single stream, so later work is ordered
 // after earlier work on the block.
+//
+// While a HIP graph is being captured, every block the pool hands out or
+// takes back is recorded: blocks freed during the capture are reused only
+// within it, and at its end all recorded blocks leave the pool for the graph
+// (a replay writes them again), which frees them when it is destroyed.
 class Pool {
 public:
     ~Pool();
@@ -71,11 +76,18 @@ public:
     void release_all();
     size_t bytes_in_use() const { return in_use_; }
     static size_t size_class(size_t bytes);
+    void begin_capture();
+    std::vector<void*> end_capture();   // the blocks the graph now owns
+    void free_blocks(const std::vector<void*>& v);
 
 private:
     std::multimap<size_t, void*> free_;
     std::unordered_map<void*, size_t> sizes_;
     size_t in_use_ = 0;
+    bool capture_ = false;
+    std::unordered_map<void*, size_t> cap_blocks_;   // touched during the capture
+    std::multimap<size_t, void*> cap_free_;          // freed during the capture (reusable within it)
+    std::unordered_map<void*, size_t> graph_owned_;  // put() of these is ignored
 };
 
 // Markers of the staging ring: events on the context's stream.
@@ -89,6 +101,10 @@ struct HipMarkers {
 };
 
 // Pinned host ring + device ring for per-launch arguments (see staging.h).
+//
+// During a graph capture put() bump-allocates from the graph's own arena
+// instead (pinned host + device, never reused while the graph exists): the
+// captured copy node reads the host arena at every replay.
 class Staging {
 public:
     static constexpr size_t kBytes = (size_t)64 << 20;
@@ -101,14 +117,35 @@ public:
     // the stream); the device pointer stays valid until work enqueued before
     // the next fence() has completed
     void* put(const void* src, size_t bytes);
-    void fence() { ring_.fence(ops_); }
+    void fence() {
+        if (!arena_host_) ring_.fence(ops_);
+    }
     void drained() { ring_.drained(ops_); }   // after a stream synchronisation
+    void begin_arena(uint8_t* host, uint8_t* dev, size_t bytes) {
+        arena_host_ = host;
+        arena_dev_ = dev;
+        arena_cap_ = bytes;
+        arena_used_ = 0;
+    }
+    void end_arena() { arena_host_ = arena_dev_ = nullptr; }
 
 private:
     uint8_t* host_ = nullptr;
     uint8_t* dev_ = nullptr;
     HipMarkers ops_;
     RingPositions<HipMarkers, hipEvent_t> ring_;
+    uint8_t* arena_host_ = nullptr;
+    uint8_t* arena_dev_ = nullptr;
+    size_t arena_cap_ = 0, arena_used_ = 0;
+};
+
+// A captured HIP graph of a context's evaluation calls and the memory it owns.
+struct CapturedGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void*> blocks;          // pool blocks the graph's kernels use
+    uint8_t* arena_host = nullptr;      // staged launch arguments
+    uint8_t* arena_dev = nullptr;
 };
 
 // Scratch buffer that returns itself to the pool.
@@ -130,6 +167,13 @@ constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
 // Device address of that buffer on the current device (looked up once per
 // device with hipGetSymbolAddress, then cached).
 uint64_t* noalloc_scratch_for_current_device();
+
+// Messages and bytes per channel of the three-party protocol (protocol.cpp).
+struct ProtocolCounters {
+    static constexpr int kChannels = 8;
+    int64_t msgs[kChannels] = {};
+    int64_t bytes[kChannels] = {};
+};
 
 struct MfState;  // encrypted matrix-factorisation program (mf_program.cpp)
 void destroy_mf(MfState* m);
@@ -166,7 +210,17 @@ struct Context {
     Staging staging;
     MfState* mf = nullptr;
     int max_babies = 1024;          // block permutations: baby ciphertexts alive at once
+    int modup_chunk = 0;            // key switching: ciphertexts per ModUp sub-batch (0 = the whole batch)
     int64_t n_key_switches = 0;     // key switches enqueued (relinearisations and rotations)
+    bool capturing = false;         // the stream is being captured into a HIP graph
+    std::map<uint64_t, CapturedGraph> graphs;
+    uint64_t next_graph = 1;
+    static constexpr size_t kGraphArenaBytes = (size_t)32 << 20;
+    void graph_begin();
+    uint64_t graph_end();
+    void graph_launch(uint64_t id);
+    void graph_destroy(uint64_t id);
+    ProtocolCounters proto;         // the last protocol run's message accounting
     std::vector<Server*> servers;   // stopped and freed before the context
 
     Context() = default;
@@ -189,7 +243,9 @@ struct Context {
     // per-launch arguments through the staging ring; fence() after enqueueing their users
     void* stage(const void* src, size_t bytes) { return staging.put(src, bytes); }
     void fence() { staging.fence(); }
-    void sync();   // wait for the stream (and recycle the staging ring)
+    // wait for the stream (and recycle the staging ring); `caller` names the
+    // operation in the error raised while a graph is being captured
+    void sync(const char* caller = __builtin_FUNCTION());
 
     RowMap map_ct(uint64_t* d, int nlimbs, int first = 0) const;
     RowMap map_cts(const std::vector<Ct*>& v, int nlimbs, int first = 0);

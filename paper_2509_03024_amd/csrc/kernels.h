@@ -46,6 +46,7 @@ struct DevTables {
     const uint64_t* tw;          // [n_mod][4][N]: psi^brev, shoup, psi^-brev, shoup
                                  // (FP64 primes: as doubles, w then fl(w/q))
     int ntt_chunk_rows = 0;      // NTT schedule (host side): rows per pair of passes, 0 = the whole batch
+    int ntt_cached_mid = 0;      // NTT schedule: the intermediate between the passes goes through the caches
 };
 
 void launch_ntt(const DevTables& t, const RowMap& rows, bool inverse, hipStream_t s);
@@ -163,7 +164,7 @@ void launch_mask_mac_tasks(const DevTables& t, const MaskTasks& T, const uint64_
 // the 4 KiB kernel-argument limit.
 static_assert(sizeof(RowMap) == 296 && alignof(RowMap) == 8, "RowMap layout");
 static_assert(sizeof(KsArgs) == 624 && offsetof(KsArgs, own) == 320, "KsArgs layout");
-static_assert(sizeof(DevTables) == 32, "DevTables layout");
+static_assert(sizeof(DevTables) == 32, "DevTables layout");   // two ints share the last 8 bytes
 static_assert(sizeof(MaskTasks) == 88, "MaskTasks layout");
 static_assert(sizeof(DevTables) + sizeof(KsArgs) + 4 * sizeof(RowMap) + 32 < 4096, "kernel arguments");
 

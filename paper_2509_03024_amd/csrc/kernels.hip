@@ -145,6 +145,16 @@ __device__ __forceinline__ uint64_t f64_canon(double v, const ModF& m) {
     return (uint64_t)r;
 }
 
+// Streamed load / store: nontemporal (kNt) or through the caches.
+template <bool kNt> __device__ __forceinline__ uint64_t ld_stream(const uint64_t* p) {
+    if constexpr (kNt) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool kNt> __device__ __forceinline__ void st_stream(uint64_t v, uint64_t* p) {
+    if constexpr (kNt) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 template <int NS, bool kInverse, typename T, typename M>
 __device__ __forceinline__ void ntt_round(T (&x)[8], const uint64_t* W, const uint64_t* Wp, int c0, int a,
                                           int blk, const M& md) {
@@ -210,10 +220,14 @@ template <> struct NttIo<double, ModF> {
 };
 
 // `in` is read once, at the start of the pass, and `data` written at its end
-// (the same tile of the same limb): in == data transforms in place.  Both are
-// streamed with nontemporal loads and stores (each residue is touched once per
-// pass), which leaves the cache to the twiddles: 5 % faster passes.
-template <int SL, bool kCols, bool kInverse, typename T, typename M>
+// (the same tile of the same limb): in == data transforms in place.  The
+// transform's input and output are streamed with nontemporal loads and stores
+// (each residue is touched once per pass), which leaves the cache to the
+// twiddles: 5 % faster passes.  The intermediate between the two passes is
+// streamed the same way if kNtMid, else written and read through the caches,
+// so that a sub-batch small enough for the last-level cache can hand it from
+// one pass to the next without a round trip to HBM.
+template <int SL, bool kCols, bool kInverse, bool kNtMid, typename T, typename M>
 __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t* in, uint64_t* data, const uint64_t* W,
                                               const uint64_t* Wp, const M& md, const Modulus& mi, int L1, int L2,
                                               int chunk, int tid) {
@@ -222,6 +236,8 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t*
     constexpr int SPB_L = kNttBlockLog - SL;        // log2(sub-transforms per block)
     constexpr int R0 = (SL % 3) ? (SL % 3) : 3;
     constexpr bool kFirstPass = kCols != kInverse;   // forward starts with columns, inverse with rows
+    constexpr bool kNtLd = kFirstPass || kNtMid;     // the second pass loads the intermediate
+    constexpr bool kNtSt = !kFirstPass || kNtMid;    // the first pass stores it
     int sub, tt;
     if (kCols) { sub = tid & ((1 << SPB_L) - 1); tt = tid >> SPB_L; }
     else       { sub = tid >> TPS_L;              tt = tid & ((1 << TPS_L) - 1); }
@@ -248,7 +264,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t*
         ld = SL - 3;
         j0 = tt;
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(__builtin_nontemporal_load(&in[gaddr(tt + (kk << ld))]), kFirstPass, md);
+        for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(ld_stream<kNtLd>(&in[gaddr(tt + (kk << ld))]), kFirstPass, md);
         ntt_round<R0, false>(x, W, Wp, c0, 0, 0, md);
 #pragma unroll
         for (int a = R0; a < SL; a += 3) {
@@ -264,7 +280,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t*
         }
         if (kCols) {
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) __builtin_nontemporal_store(Io::out_mid(x[kk], md), &data[gaddr(j0 + (kk << ld))]);
+            for (int kk = 0; kk < 8; ++kk) st_stream<kNtSt>(Io::out_mid(x[kk], md), &data[gaddr(j0 + (kk << ld))]);
         } else {
             // the last round leaves each thread 8 adjacent residues; one more
             // exchange lets consecutive lanes store consecutive residues
@@ -273,20 +289,20 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t*
             __syncthreads();
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk)
-                __builtin_nontemporal_store(Io::out_fwd_end(lds[lbase(tt) + loff(kk, SL - 3)], md), &data[gaddr(tt + (kk << (SL - 3)))]);
+                st_stream<kNtSt>(Io::out_fwd_end(lds[lbase(tt) + loff(kk, SL - 3)], md), &data[gaddr(tt + (kk << (SL - 3)))]);
         }
     } else {
         ld = 0;
         j0 = tt << 3;
         if (kCols) {
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(__builtin_nontemporal_load(&in[gaddr(j0 + kk)]), kFirstPass, md);
+            for (int kk = 0; kk < 8; ++kk) x[kk] = Io::in(ld_stream<kNtLd>(&in[gaddr(j0 + kk)]), kFirstPass, md);
         } else {
             // consecutive lanes load consecutive residues; an exchange hands
             // each thread the 8 adjacent residues of the first round
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk)
-                lds[lbase(tt) + loff(kk, SL - 3)] = Io::in(__builtin_nontemporal_load(&in[gaddr(tt + (kk << (SL - 3)))]), kFirstPass, md);
+                lds[lbase(tt) + loff(kk, SL - 3)] = Io::in(ld_stream<kNtLd>(&in[gaddr(tt + (kk << (SL - 3)))]), kFirstPass, md);
             __syncthreads();
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) x[kk] = lds[lbase(j0) + loff(kk, 0)];
@@ -317,19 +333,19 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t*
             if constexpr (std::is_same<T, double>::value) {
                 const double ninv = (double)mi.n_inv, ninvq = ninv / (double)mi.q;
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) __builtin_nontemporal_store(Io::out_inv_end(x[kk], md, ninv, ninvq), &data[gaddr(j0 + (kk << ld))]);
+                for (int kk = 0; kk < 8; ++kk) st_stream<kNtSt>(Io::out_inv_end(x[kk], md, ninv, ninvq), &data[gaddr(j0 + (kk << ld))]);
             } else {
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) __builtin_nontemporal_store(NttIo<uint64_t, Modulus>::out_inv_end((uint64_t)x[kk], mi), &data[gaddr(j0 + (kk << ld))]);
+                for (int kk = 0; kk < 8; ++kk) st_stream<kNtSt>(NttIo<uint64_t, Modulus>::out_inv_end((uint64_t)x[kk], mi), &data[gaddr(j0 + (kk << ld))]);
             }
         } else {
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) __builtin_nontemporal_store(Io::out_mid(x[kk], md), &data[gaddr(j0 + (kk << ld))]);
+            for (int kk = 0; kk < 8; ++kk) st_stream<kNtSt>(Io::out_mid(x[kk], md), &data[gaddr(j0 + (kk << ld))]);
         }
     }
 }
 
-template <int SL, bool kCols, bool kInverse>
+template <int SL, bool kCols, bool kInverse, bool kNtMid>
 __global__ void __launch_bounds__(kNttThreads) k_ntt_pass(DevTables t, RowMap m, RowMap src) {
     __shared__ uint64_t lds[kNttBlockElems + kNttBlockElems / 16];   // rows passes pad 1 word in 16
     constexpr int SPB_L = kNttBlockLog - SL;
@@ -346,22 +362,29 @@ __global__ void __launch_bounds__(kNttThreads) k_ntt_pass(DevTables t, RowMap m,
     const uint64_t* Wp = W + N;
     if (md.q < kFp64PrimeBound) {
         const ModF mf{(double)md.q, 1.0 / (double)md.q};
-        ntt_pass_body<SL, kCols, kInverse, double, ModF>(lds, in, data, W, Wp, mf, md, L1, L2, chunk, threadIdx.x);
+        ntt_pass_body<SL, kCols, kInverse, kNtMid, double, ModF>(lds, in, data, W, Wp, mf, md, L1, L2, chunk, threadIdx.x);
     } else {
-        ntt_pass_body<SL, kCols, kInverse, uint64_t, Modulus>(lds, in, data, W, Wp, md, md, L1, L2, chunk, threadIdx.x);
+        ntt_pass_body<SL, kCols, kInverse, kNtMid, uint64_t, Modulus>(lds, in, data, W, Wp, md, md, L1, L2, chunk, threadIdx.x);
+    }
+}
+
+template <int SL, bool kNtMid>
+void launch_ntt_pass(const DevTables& t, const RowMap& m, const RowMap& src, bool cols, bool inverse, int blocks,
+                     hipStream_t s) {
+    if (cols) {
+        if (inverse) hipLaunchKernelGGL((k_ntt_pass<SL, true, true, kNtMid>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
+        else hipLaunchKernelGGL((k_ntt_pass<SL, true, false, kNtMid>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
+    } else {
+        if (inverse) hipLaunchKernelGGL((k_ntt_pass<SL, false, true, kNtMid>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
+        else hipLaunchKernelGGL((k_ntt_pass<SL, false, false, kNtMid>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
     }
 }
 
 template <int SL>
 void launch_ntt_pass(const DevTables& t, const RowMap& m, const RowMap& src, bool cols, bool inverse, int blocks,
                      hipStream_t s) {
-    if (cols) {
-        if (inverse) hipLaunchKernelGGL((k_ntt_pass<SL, true, true>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
-        else hipLaunchKernelGGL((k_ntt_pass<SL, true, false>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
-    } else {
-        if (inverse) hipLaunchKernelGGL((k_ntt_pass<SL, false, true>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
-        else hipLaunchKernelGGL((k_ntt_pass<SL, false, false>), dim3(blocks), dim3(kNttThreads), 0, s, t, m, src);
-    }
+    if (t.ntt_cached_mid) launch_ntt_pass<SL, false>(t, m, src, cols, inverse, blocks, s);
+    else launch_ntt_pass<SL, true>(t, m, src, cols, inverse, blocks, s);
 }
 
 void dispatch_ntt_pass(const DevTables& t, const RowMap& m, const RowMap& src, bool cols, bool inverse, int blocks,

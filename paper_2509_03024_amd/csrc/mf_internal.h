@@ -21,6 +21,15 @@ struct MfState {
     // doubles in the rows of primes below 2^44 (the masked MAC's FP64 form)
     uint64_t* mask0 = nullptr;      // at the scatter mask scale
     uint64_t* maskg = nullptr;      // at the gather mask scale
+    // Alg. 2 (params.batch_pairs): the user-item batch pairs in order, each
+    // with its user table ub, item table vb, rating ciphertexts [ct0, ct1)
+    // and ratings (CSR indices, in CSR order)
+    struct Pair {
+        int ub = 0, vb = 0, ct0 = 0, ct1 = 0;
+        std::vector<int32_t> ratings;
+    };
+    bool pairs = false;
+    std::vector<Pair> pair_list;
     int epochs_done = 0;
     int refresh_round = 0;
     double refresh_seconds = 0;     // wall time spent in refreshes (host + device)
@@ -72,6 +81,7 @@ struct SelfTerm {
 // (source index, baby step beta) -> HRot_{beta B}(source) at the permutation's level
 typedef std::map<std::pair<int, int>, Ct> BabyCache;
 
+MfState& state(Context* c);   // the context's MF state (STATE error if none)
 void free_handles(Context* c, std::vector<uint64_t>& v);
 void release(Context* c, std::vector<Ct>& v);
 std::vector<Ct*> ptrs(std::vector<Ct>& v);
@@ -102,6 +112,14 @@ std::vector<Ct> block_permute_cached(Context* c, MfState& m, const std::vector<C
 int choose_G(const std::vector<std::vector<Move>>& dests, int D);
 std::vector<Ct> dot_products(Context* c, MfState& m, const std::vector<Ct*>& ug, const std::vector<Ct*>& vg,
                              double* sp_out);
+// Validate the CSR arrays, compute the layout, generate the program's
+// rotation keys and install it as the context's MF state (replacing one).
+void install_layout(Context* c, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr, const int32_t* col_idx);
+// Slot vectors of the rating-layout ciphertexts (which: 0 ratings, 1 users, 2 items).
+void fill_rating_slots(const MfState& m, int which, const double* values, const double* U, const double* V,
+                       std::vector<std::vector<double>>& zs);
+// Encrypt count integer plaintexts at the top level (running serials).
+std::vector<uint64_t> encrypt_list(Context* c, const int64_t* m, int count, double scale);
 
 }  // namespace mfp
 }  // namespace csrmf

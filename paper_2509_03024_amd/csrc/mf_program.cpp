@@ -16,8 +16,9 @@
 //   tables <- BlockPermute(G -> tables, learning-rate weights) + self term;
 //   gathered factors <- BlockPermute(tables -> rating layout, weight 1).
 // BlockPermute (move: source c, block a -> destination block b, weight w;
-// (a - b) mod D = gamma*G + beta, G = 2^ceil(log2(D)/2)):
-//   acc_d = sum_gamma Rot_{gamma G B}( sum_{c,beta} HRot_{beta B}(src_c) (.) M_{d,c,gamma,beta} )
+// (a - b) mod D = gamma*G + beta with the baby-step size G of the call chosen
+// by choose_G, babies built in blocks of kBabyBlock by rotation trees):
+//   acc_d = sum_gamma Rot_{gamma G B}( sum_{c,beta} Rot_{beta B}(src_c) (.) M_{d,c,gamma,beta} )
 //   M = sum_moves W * tau_{g_p}(I0), p = (b + gamma G) mod D, g_p = 5^((-pB) mod N/2),
 //   W = rint((w * S_t * q_ell) / (S_src * S_I)); one rescale per destination.
 //   Scatter: S_I = 2^24, S_t = 2^50 (the tables' scale), self term as a constant
@@ -114,6 +115,36 @@ MfState* make_layout(Context* c, int32_t n_rows, int32_t n_cols, const int64_t* 
     m->n_ct = ct + 1;
     m->n_utab = (n_rows + m->D - 1) / m->D;
     m->n_vtab = (n_cols + m->D - 1) / m->D;
+    if (c->prm.batch_pairs) {
+        // Alg. 2: group by (user batch, item batch) with a batch of D profiles,
+        // pairs in the order of their first rating; each pair's ratings (CSR
+        // order) fill rating ciphertexts of their own
+        std::map<std::pair<int, int>, int> index;
+        for (int64_t p = 0; p < nnz; ++p) {
+            const std::pair<int, int> key{m->rows[p] / m->D, col_idx[p] / m->D};
+            auto it = index.find(key);
+            if (it == index.end()) {
+                it = index.emplace(key, (int)m->pair_list.size()).first;
+                m->pair_list.emplace_back();
+                m->pair_list.back().ub = key.first;
+                m->pair_list.back().vb = key.second;
+            }
+            m->pair_list[it->second].ratings.push_back((int32_t)p);
+        }
+        int c0 = 0;
+        for (auto& pr : m->pair_list) {
+            const int n = (int)pr.ratings.size();
+            pr.ct0 = c0;
+            pr.ct1 = c0 + (n + m->D - 1) / m->D;
+            for (int q = 0; q < n; ++q) {
+                m->ct_of[pr.ratings[q]] = c0 + q / m->D;
+                m->blk_of[pr.ratings[q]] = q % m->D;
+            }
+            c0 = pr.ct1;
+        }
+        m->n_ct = c0;
+        m->pairs = true;
+    }
     return m;
 }
 
@@ -985,6 +1016,103 @@ void run_epoch(Context* c, MfState& m) {
     m.epochs_done++;
 }
 
+// One Alg. 2 epoch: the batch pairs in turn (see csrmf_mf_epochs).
+void run_pair_epoch(Context* c, MfState& m) {
+    const double a_t = c->prm.lr / (1.0 + c->prm.damp * (double)m.epochs_done);
+    const double lam = c->prm.lambda;
+    if (m.Sdot.size() != (size_t)m.n_ct) {
+        free_handles(c, m.Sdot);
+        m.Sdot.assign(m.n_ct, 0);
+    }
+    // the initial gathered copies are not used: every pair gathers from the tables
+    free_handles(c, m.Ug);
+    free_handles(c, m.Vg);
+    std::vector<Ct*> R = cts_of(c, m.R);
+    for (const MfState::Pair& pr : m.pair_list) {
+        if (std::min(c->get(m.Utab[pr.ub]).level, c->get(m.Vtab[pr.vb]).level) < kRefreshLevel) {
+            if (!c->prm.refresh_mode) throw Error(CSRMF_E_LEVEL, "level budget exhausted (refresh_mode = 0)");
+            refresh_tables(c, m);
+        }
+        const int nct = pr.ct1 - pr.ct0;
+        // gathers from one user table and one item table into the pair's ciphertexts
+        std::vector<std::vector<Move>> mu(nct), mv(nct);
+        for (int32_t r : pr.ratings) {
+            const int t = m.ct_of[r] - pr.ct0;
+            mu[t].push_back({0, m.rows[r] % m.D, m.blk_of[r], 1.0});
+            mv[t].push_back({0, m.col_idx[r] % m.D, m.blk_of[r], 1.0});
+        }
+        std::vector<Ct*> su{&c->get(m.Utab[pr.ub])}, sv{&c->get(m.Vtab[pr.vb])};
+        std::vector<Ct> ug = block_permute(c, m, su, mu, nullptr, su[0]->level, true);
+        std::vector<Ct> vg = block_permute(c, m, sv, mv, nullptr, sv[0]->level, true);
+        std::vector<Ct*> pu = ptrs(ug), pv = ptrs(vg);
+        double sp = 0;
+        std::vector<Ct> S = dot_products(c, m, pu, pv, &sp);
+        const int slv = S[0].level;
+        std::vector<Ct*> Rp(R.begin() + pr.ct0, R.begin() + pr.ct1);
+        const double q_R = (double)c->moduli[Rp[0]->level];
+        const int64_t WR = (int64_t)std::nearbyint((sp * q_R) / Rp[0]->scale);
+        std::vector<Ct> Re(nct);
+        for (int i = 0; i < nct; ++i) c->mul_int(*Rp[i], WR, Re[i]);
+        std::vector<Ct*> pre = ptrs(Re);
+        c->rescale(pre);
+        for (auto& x : Re) x.level = slv;
+        std::vector<Ct*> ps = ptrs(S);
+        std::vector<Ct> E = add_all(c, pre, ps, true);
+        release(c, Re);
+        const int elv = E[0].level;
+        std::vector<Ct*> pe = ptrs(E);
+        std::vector<Ct> vgd = dropped(pv, elv), ugd = dropped(pu, elv);
+        std::vector<Ct*> pvgd = ptrs(vgd), pugd = ptrs(ugd);
+        std::vector<Ct> GU = hmult_all(c, pe, pvgd);
+        std::vector<Ct> GV = hmult_all(c, pe, pugd);
+        release(c, E);
+        release(c, ug);
+        release(c, vg);
+        const int glv = GU[0].level;
+        // scatter into the pair's two tables: weight a_t per rating, self term
+        // 1 - a_t lambda c_e (c_e = the entity's ratings in this pair)
+        for (int side = 0; side < 2; ++side) {
+            const bool users = side == 0;
+            const int tab = users ? pr.ub : pr.vb;
+            const int n_ent = users ? m.n_users : m.n_items;
+            std::vector<uint64_t>& tabs = users ? m.Utab : m.Vtab;
+            std::vector<std::vector<Move>> mvs(1);
+            std::map<int, double> cnt;
+            for (int32_t r : pr.ratings) {
+                const int e = users ? m.rows[r] : m.col_idx[r];
+                mvs[0].push_back({m.ct_of[r] - pr.ct0, m.blk_of[r], e % m.D, a_t});
+                cnt[e] += 1.0;
+            }
+            std::vector<SelfTerm> selfs(1);
+            selfs[0].t = &c->get(tabs[tab]);
+            std::vector<std::pair<int, double>> ws;
+            for (int b = 0; b < m.D; ++b) {
+                const int e = tab * m.D + b;
+                if (e >= n_ent) break;
+                auto it = cnt.find(e);
+                ws.push_back({b, 1.0 - a_t * lam * (it == cnt.end() ? 0.0 : it->second)});
+            }
+            std::vector<double> srt;
+            for (auto& bw : ws) srt.push_back(bw.second);
+            std::sort(srt.begin(), srt.end());
+            selfs[0].c = srt[(srt.size() - 1) / 2];
+            for (auto& bw : ws)
+                if (bw.second != selfs[0].c) selfs[0].corr.push_back({bw.first, bw.second - selfs[0].c});
+            std::vector<Ct*> pg = ptrs(users ? GU : GV);
+            std::vector<Ct> nt = block_permute(c, m, pg, mvs, &selfs, glv, false);
+            c->free_ct(tabs[tab]);
+            tabs[tab] = c->put(nt[0]);
+        }
+        release(c, GU);
+        release(c, GV);
+        for (int i = 0; i < nct; ++i) {
+            if (m.Sdot[pr.ct0 + i]) c->free_ct(m.Sdot[pr.ct0 + i]);
+            m.Sdot[pr.ct0 + i] = c->put(S[i]);
+        }
+    }
+    m.epochs_done++;
+}
+
 void decrypt_slots(Context* c, uint64_t h, std::vector<double>& z) {
     const Ct& ct = c->get(h);
     std::vector<int64_t> mm(c->N);
@@ -1021,7 +1149,8 @@ using csrmf::MfState;
         return CSRMF_E_DEVICE;         \
     }
 
-static void install_layout(Context* c, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr, const int32_t* col_idx) {
+void csrmf::mfp::install_layout(Context* c, int32_t n_rows, int32_t n_cols, const int64_t* row_ptr,
+                                const int32_t* col_idx) {
     if (!c->have_keys) throw Error(CSRMF_E_STATE, "keygen first");
     MfState* m = csrmf::mfp::make_layout(c, n_rows, n_cols, row_ptr, col_idx);
     // rotation keys the program uses: windowed sum 1, 2, .., B/2 and -k'; the
@@ -1059,7 +1188,7 @@ int csrmf_encrypt_csr_rows(csrmf_ctx* cx, int32_t n_rows, int32_t n_cols, const 
     if (!values) throw Error(CSRMF_E_INVAL, "values");
     for (int64_t p = 0; row_ptr && n_rows > 0 && p < row_ptr[n_rows]; ++p)
         if (!std::isfinite(values[p])) throw Error(CSRMF_E_INVAL, "non-finite rating");
-    install_layout(c, n_rows, n_cols, row_ptr, col_idx);
+    csrmf::mfp::install_layout(c, n_rows, n_cols, row_ptr, col_idx);
     MfState& m = *c->mf;
     std::vector<std::vector<double>> zs(m.n_ct, std::vector<double>(c->N / 2));
     csrmf::mfp::fill_rating_slots(m, 0, values, nullptr, nullptr, zs);
@@ -1075,7 +1204,7 @@ int csrmf_encrypt_csr_rows_int(csrmf_ctx* cx, int32_t n_rows, int32_t n_cols, co
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
     if (!plain) throw Error(CSRMF_E_INVAL, "plaintexts");
-    install_layout(c, n_rows, n_cols, row_ptr, col_idx);
+    csrmf::mfp::install_layout(c, n_rows, n_cols, row_ptr, col_idx);
     MfState& m = *c->mf;
     if (n_plain != m.n_ct) throw Error(CSRMF_E_INVAL, "number of plaintexts differs from the layout's ciphertexts");
     m.R = csrmf::mfp::encrypt_list(c, plain, m.n_ct, std::ldexp(1.0, c->prm.log2_scale));
@@ -1172,6 +1301,12 @@ int csrmf_mf_epochs(csrmf_ctx* cx, int32_t n_epochs) {
     if (!m.factors) throw Error(CSRMF_E_STATE, "init_factors first");
     if (n_epochs < 0) throw Error(CSRMF_E_INVAL, "n_epochs");
     if (n_epochs == 0) API_END_EARLY;
+    if (m.pairs) {
+        if (c->L < csrmf::mfp::kRefreshLevel) throw Error(CSRMF_E_LEVEL, "a batch pair needs 4 levels");
+        for (int t = 0; t < n_epochs; ++t) csrmf::mfp::run_pair_epoch(c, m);
+        if (!c->capturing) c->sync();
+        API_END_EARLY;
+    }
     // Level budget: an epoch on gathered factors uses 3 levels, every further
     // one 4 (its gather included).  Without refresh the whole request must fit;
     // with refresh, tables below kRefreshLevel are refreshed before a gather.
@@ -1186,7 +1321,7 @@ int csrmf_mf_epochs(csrmf_ctx* cx, int32_t n_epochs) {
         if (t > 0 || !have_g) csrmf::mfp::prepare_epoch(c, m);
         csrmf::mfp::run_epoch(c, m);
     }
-    c->sync();
+    if (!c->capturing) c->sync();   // a captured epoch runs when its graph is launched
     API_END(c)
 }
 

@@ -18,7 +18,9 @@ std::mutex g_mu;
 bool g_on = false;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_free;
-Rec g_open{nullptr, nullptr, nullptr, 0.0};
+// the scope being timed on this thread (scopes open and close on one thread;
+// the serving worker and the caller's thread may time launches at once)
+thread_local Rec g_open{nullptr, nullptr, nullptr, 0.0};
 
 hipEvent_t take() {
     if (!g_free.empty()) {

@@ -18,11 +18,21 @@
 // Every step is a deterministic function of the request and the resident
 // state, and batching only groups launches, so a result is the same alone
 // and in any mix.
+//
+// Continuous batching: the worker admits queued requests while their
+// ciphertext footprint fits the budget left by every batch still on the
+// device, enqueues the batch's launches on the context's stream and records
+// a completion event, without waiting; up to max_inflight batches are
+// pipelined, so the host prepares (encodes, encrypts, plans) the next batch
+// while earlier ones run and the device never idles between batches.  A
+// request is done, and its footprint returned, when its batch's event has
+// completed.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <thread>
+#include <unordered_set>
 
 #include "host_math.h"
 #include "mf_internal.h"
@@ -42,6 +52,7 @@ struct ServeRequest {
     uint32_t client_serial = 0;
     std::vector<int32_t> items;
     std::vector<double> ratings;
+    std::vector<int64_t> plain;     // UPDATE: encoded rating chunks [n_chunks][N] (else empty: encode ratings)
     int status = 0;             // 0 queued, 1 running, 2 done, < 0 error code
     std::string error;
     std::vector<uint64_t> result;
@@ -58,19 +69,29 @@ struct Server {
     double lr = 0, lam = 0;
     size_t budget = 0, in_flight = 0;
     int max_batch = 64;
+    int max_inflight = 4;                  // batches enqueued and not yet complete
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv, done_cv;
     bool stop = false;
     std::deque<ServeRequest*> pending;
     std::map<uint64_t, ServeRequest*> reqs;
+    std::unordered_set<uint32_t> update_serials;   // client serials of admitted UPDATEs (encryption randomness)
     uint64_t next_id = 1;
-    long batches = 0, processed = 0, max_seen_batch = 0;
+    long batches = 0, processed = 0, max_seen_batch = 0, overlapped = 0, max_seen_inflight = 0;
     std::string fatal;
+
+    struct InFlight {
+        std::vector<ServeRequest*> batch;
+        hipEvent_t done = nullptr;
+    };
+    std::deque<InFlight> inflight;         // worker thread only (under mu)
+    std::vector<hipEvent_t> spare_events;
 
     ~Server();
     void run();
     void process(std::vector<ServeRequest*>& batch);
+    void retire_locked(bool wait_all);
 };
 
 namespace {
@@ -120,6 +141,7 @@ Server::~Server() {
     cv.notify_all();
     if (worker.joinable()) worker.join();
     std::lock_guard<std::recursive_mutex> lk(c->mu);
+    for (hipEvent_t e : spare_events) (void)hipEventDestroy(e);
     for (size_t i = 0; i < c->servers.size(); ++i)
         if (c->servers[i] == this) {
             c->servers.erase(c->servers.begin() + (long)i);
@@ -133,50 +155,110 @@ Server::~Server() {
     mfp::free_masks(c, lay);
 }
 
+// Batches whose completion event has fired are done (oldest first; one
+// stream, so they complete in order).  wait_all: wait for every batch.
+void Server::retire_locked(bool wait_all) {
+    while (!inflight.empty()) {
+        InFlight& f = inflight.front();
+        if (wait_all) {
+            (void)hipEventSynchronize(f.done);
+        } else {
+            const hipError_t q = hipEventQuery(f.done);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess)
+                for (ServeRequest* r : f.batch)
+                    if (r->status == 1) { r->status = CSRMF_E_DEVICE; r->error = hipGetErrorString(q); }
+        }
+        const double t = now_s();
+        for (ServeRequest* r : f.batch) {
+            if (r->status == 1) r->status = 2;
+            r->t_done = t;
+            in_flight -= r->footprint;
+        }
+        spare_events.push_back(f.done);
+        inflight.pop_front();
+        done_cv.notify_all();
+    }
+}
+
 void Server::run() {
     for (;;) {
         std::vector<ServeRequest*> batch;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv.wait(lk, [&] { return stop || !pending.empty(); });
-            if (stop) return;
-            // admit while the ciphertext footprint fits the budget
-            while (!pending.empty() && (int)batch.size() < max_batch &&
-                   in_flight + pending.front()->footprint <= budget) {
-                ServeRequest* r = pending.front();
-                pending.pop_front();
-                in_flight += r->footprint;
-                r->status = 1;
-                r->t_start = now_s();
-                batch.push_back(r);
+            retire_locked(false);
+            if (stop) {
+                retire_locked(true);
+                return;
             }
+            // admit while the footprint fits the budget left by the batches in flight
+            if ((int)inflight.size() < max_inflight) {
+                while (!pending.empty() && (int)batch.size() < max_batch &&
+                       in_flight + pending.front()->footprint <= budget) {
+                    ServeRequest* r = pending.front();
+                    pending.pop_front();
+                    in_flight += r->footprint;
+                    r->status = 1;
+                    r->t_start = now_s();
+                    batch.push_back(r);
+                }
+            }
+            if (batch.empty()) {
+                if (inflight.empty()) cv.wait(lk, [&] { return stop || !pending.empty(); });
+                else cv.wait_for(lk, std::chrono::microseconds(200));   // poll the device
+                continue;
+            }
+            if (!inflight.empty()) overlapped++;
         }
-        if (batch.empty()) continue;
+        hipEvent_t ev = nullptr;
+        bool failed = false;
         try {
             std::lock_guard<std::recursive_mutex> lk(c->mu);
             process(batch);
-            c->sync();
+            {
+                std::lock_guard<std::mutex> lk2(mu);
+                if (!spare_events.empty()) {
+                    ev = spare_events.back();
+                    spare_events.pop_back();
+                }
+            }
+            if (!ev) CSRMF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            CSRMF_HIP(hipEventRecord(ev, c->stream));
         } catch (const Error& e) {
+            failed = true;
             std::lock_guard<std::mutex> lk(mu);
             for (ServeRequest* r : batch) { r->status = e.code; r->error = e.what(); }
         } catch (const std::exception& e) {
+            failed = true;
             std::lock_guard<std::mutex> lk(mu);
             for (ServeRequest* r : batch) { r->status = CSRMF_E_DEVICE; r->error = e.what(); }
         }
+        if (failed) {
+            // let queued work drain before the footprint is given back
+            try {
+                std::lock_guard<std::recursive_mutex> lk(c->mu);
+                c->sync();
+            } catch (...) {
+            }
+        }
         {
             std::lock_guard<std::mutex> lk(mu);
-            const double t = now_s();
-            for (ServeRequest* r : batch) {
-                if (r->status == 1) r->status = 2;
-                r->t_done = t;
-                in_flight -= r->footprint;
+            if (failed || !ev) {
+                const double t = now_s();
+                for (ServeRequest* r : batch) {
+                    r->t_done = t;
+                    in_flight -= r->footprint;
+                }
+                if (ev) spare_events.push_back(ev);
+                done_cv.notify_all();
+            } else {
+                inflight.push_back({batch, ev});
+                if ((long)inflight.size() > max_seen_inflight) max_seen_inflight = (long)inflight.size();
             }
             batches++;
             processed += (long)batch.size();
             if ((long)batch.size() > max_seen_batch) max_seen_batch = (long)batch.size();
         }
-        done_cv.notify_all();
-        cv.notify_all();
     }
 }
 
@@ -219,21 +301,29 @@ void Server::process(std::vector<ServeRequest*>& batch) {
         }
     }
     if (!upd.empty()) {
-        // encrypt the rating chunks (client side; randomness from the client serial)
+        // encrypt the rating chunks (client side; randomness from the client
+        // serial): the client's encoded plaintexts, or the ratings encoded here
         const int nu = (int)upd.size();
-        std::vector<std::vector<double>> zs(nu, std::vector<double>(c->N / 2, 0.0));
+        const size_t N = c->N;
+        std::vector<int64_t> pt((size_t)nu * N);
         std::vector<uint32_t> serials;
         for (int u = 0; u < nu; ++u) {
             const Chunk& ch = chunks[upd[u]];
             const ServeRequest* r = batch[ch.req];
-            for (int t = ch.s; t < ch.e; ++t)
-                for (int f = 0; f < k; ++f) zs[u][(size_t)(t - ch.s) * B + f] = r->ratings[t];
             int idx = 0;
             for (int i = 0; i < upd[u]; ++i) idx += chunks[i].req == ch.req;
             serials.push_back(chunk_serial(r->client_serial, idx));
+            if (!r->plain.empty()) {
+                std::memcpy(pt.data() + (size_t)u * N, r->plain.data() + (size_t)idx * N, N * 8);
+            } else {
+                std::vector<std::vector<double>> zs(1, std::vector<double>(N / 2, 0.0));
+                for (int t = ch.s; t < ch.e; ++t)
+                    for (int f = 0; f < k; ++f) zs[0][(size_t)(t - ch.s) * B + f] = r->ratings[t];
+                std::vector<int64_t> one = mfp::encode_all(c, zs, std::ldexp(1.0, c->prm.log2_scale));
+                std::memcpy(pt.data() + (size_t)u * N, one.data(), N * 8);
+            }
         }
         const double scale = std::ldexp(1.0, c->prm.log2_scale);
-        std::vector<int64_t> pt = mfp::encode_all(c, zs, scale);
         std::vector<Ct> R;
         c->encrypt_int_batch(pt.data(), nu, L, scale, R, serials.data());
         // E = drop(Rescale(R * W_R)) - Sdot
@@ -313,18 +403,27 @@ using csrmf::Error;
 using csrmf::Server;
 using csrmf::ServeRequest;
 
-extern "C" {
+namespace {
 
-int csrmf_server_create(csrmf_ctx* cx, int32_t n_users, int32_t n_items, const double* U, const double* V,
-                        double hbm_budget_bytes, int32_t max_batch, csrmf_server** out) {
-    Context* c = reinterpret_cast<Context*>(cx);
-    if (!c || !out) return CSRMF_E_INVAL;
+// Shared by the float and the integer-plaintext forms: tables from U, V
+// (encoded here) or from the caller's encodings utab/vtab with the gather
+// indicator mask_g (I_0 at 2^30); table encryptions take the context's
+// running serials, U tables first.
+int create_server(Context* c, int32_t n_users, int32_t n_items, const double* U, const double* V,
+                  const int64_t* utab, const int64_t* vtab, const int64_t* mask_g_in, double hbm_budget_bytes,
+                  int32_t max_batch, csrmf_server** out) {
+    if (!c || !out) {
+        csrmf::last_error() = "server: null argument";
+        return CSRMF_E_INVAL;
+    }
     *out = nullptr;
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     Server* s = nullptr;
     try {
         if (!c->have_keys) throw Error(CSRMF_E_STATE, "keygen first");
-        if (n_users <= 0 || n_items <= 0 || !U || !V || !(hbm_budget_bytes > 0) || max_batch <= 0)
+        const bool from_int = utab != nullptr;
+        if (n_users <= 0 || n_items <= 0 || !(hbm_budget_bytes > 0) || max_batch <= 0 ||
+            (from_int ? (!vtab || !mask_g_in) : (!U || !V)))
             throw Error(CSRMF_E_INVAL, "server arguments");
         const int k = c->prm.k;
         if (k <= 0) throw Error(CSRMF_E_INVAL, "params.k must be positive");
@@ -355,10 +454,25 @@ int csrmf_server_create(csrmf_ctx* cx, int32_t n_users, int32_t n_items, const d
         for (int q = m.B; q < m.B * m.D; q *= 2) steps.push_back(q);
         c->keygen(steps.data(), (int)steps.size(), false);
         std::vector<int64_t> mask_s, mask_g;
-        csrmf::mfp::encode_masks(c, k, mask_s, mask_g);
+        if (from_int) {
+            mask_g.assign(mask_g_in, mask_g_in + c->N);
+            mask_s = mask_g;   // serving gathers only; the scatter mask is not used
+        } else {
+            csrmf::mfp::encode_masks(c, k, mask_s, mask_g);
+        }
         csrmf::mfp::upload_masks(c, m, mask_s.data(), mask_g.data());
-        csrmf::encrypt_tables(c, m, n_users, U, s->Utab);
-        csrmf::encrypt_tables(c, m, n_items, V, s->Vtab);
+        if (from_int) {
+            const double scale = std::ldexp(1.0, c->prm.log2_scale);
+            const int nu = (n_users + m.D - 1) / m.D, nv = (n_items + m.D - 1) / m.D;
+            std::vector<csrmf::Ct> cu, cv;
+            c->encrypt_int_batch(utab, nu, c->L, scale, cu);
+            c->encrypt_int_batch(vtab, nv, c->L, scale, cv);
+            s->Utab = csrmf::mfp::put_all(c, cu);
+            s->Vtab = csrmf::mfp::put_all(c, cv);
+        } else {
+            csrmf::encrypt_tables(c, m, n_users, U, s->Utab);
+            csrmf::encrypt_tables(c, m, n_items, V, s->Vtab);
+        }
         csrmf::cache_babies(c, m, s->Utab, s->ucache);
         csrmf::cache_babies(c, m, s->Vtab, s->vcache);
         c->sync();
@@ -373,41 +487,94 @@ int csrmf_server_create(csrmf_ctx* cx, int32_t n_users, int32_t n_items, const d
         delete s;
         return CSRMF_E_DEVICE;
     }
+    csrmf::last_error().clear();
     *out = reinterpret_cast<csrmf_server*>(s);
     return CSRMF_OK;
 }
 
-int csrmf_server_submit(csrmf_server* sv, int32_t op, int32_t user, int32_t n, const int32_t* items,
-                        const double* ratings, uint32_t client_serial, uint64_t* id) {
-    Server* s = reinterpret_cast<Server*>(sv);
-    if (!s || !id || n <= 0 || !items || (op != 0 && op != 1) || (op == 1 && !ratings)) return CSRMF_E_INVAL;
-    if (user < 0 || user >= s->lay.n_users || client_serial >= (1u << 27)) return CSRMF_E_INVAL;
-    if (op == 1 && s->c->L < 4) return CSRMF_E_LEVEL;
+int submit(Server* s, int32_t op, int32_t user, int32_t n, const int32_t* items, const double* ratings,
+           const int64_t* plain, uint32_t client_serial, uint64_t* id) {
+    auto fail = [](int code, const char* msg) {
+        csrmf::last_error() = msg;
+        return code;
+    };
+    if (!s || !id || n <= 0 || !items || (op != 0 && op != 1)) return fail(CSRMF_E_INVAL, "submit: bad arguments");
+    if (op == 1 && !ratings && !plain) return fail(CSRMF_E_INVAL, "submit: an UPDATE needs its ratings");
+    if (user < 0 || user >= s->lay.n_users) return fail(CSRMF_E_INVAL, "submit: user out of range");
+    if (client_serial >= (1u << 27)) return fail(CSRMF_E_INVAL, "submit: client serial must be below 2^27");
+    if (op == 1 && s->c->L < 4) return fail(CSRMF_E_LEVEL, "an UPDATE needs 4 levels");
     for (int32_t i = 0; i < n; ++i) {
-        if (items[i] < 0 || items[i] >= s->lay.n_items) return CSRMF_E_INVAL;
-        if (i > 0 && items[i] <= items[i - 1]) return CSRMF_E_INVAL;   // sorted, distinct (a CSR row)
-        if (op == 1 && !std::isfinite(ratings[i])) return CSRMF_E_INVAL;
+        if (items[i] < 0 || items[i] >= s->lay.n_items) return fail(CSRMF_E_INVAL, "submit: item out of range");
+        if (i > 0 && items[i] <= items[i - 1]) return fail(CSRMF_E_INVAL, "submit: items must increase (a CSR row)");
+        if (op == 1 && ratings && !std::isfinite(ratings[i])) return fail(CSRMF_E_INVAL, "submit: rating not finite");
     }
+    const int n_chunks = (n + s->lay.D - 1) / s->lay.D;
+    if (n_chunks > 8) return fail(CSRMF_E_INVAL, "submit: a row may span at most 8 chunks of D items");
+    const size_t fp = csrmf::request_footprint(s->c, n_chunks);
+    if (fp > s->budget) return fail(CSRMF_E_NOMEM, "submit: the request alone exceeds the memory budget");
     ServeRequest* r = new ServeRequest();
     r->op = op;
     r->user = user;
     r->client_serial = client_serial;
     r->items.assign(items, items + n);
-    if (op == 1) r->ratings.assign(ratings, ratings + n);
-    r->n_chunks = (n + s->lay.D - 1) / s->lay.D;
-    if (r->n_chunks > 8) { delete r; return CSRMF_E_INVAL; }
-    r->footprint = csrmf::request_footprint(s->c, r->n_chunks);
-    if (r->footprint > s->budget) { delete r; return CSRMF_E_NOMEM; }
+    if (op == 1) {
+        if (plain) r->plain.assign(plain, plain + (size_t)n_chunks * s->c->N);
+        else r->ratings.assign(ratings, ratings + n);
+    }
+    r->n_chunks = n_chunks;
+    r->footprint = fp;
     r->t_submit = csrmf::now_s();
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        // an UPDATE's encryption randomness derives from its serial: a reused
+        // serial would encrypt different ratings with the same randomness
+        if (op == 1 && !s->update_serials.insert(client_serial).second) {
+            delete r;
+            return fail(CSRMF_E_INVAL, "submit: client serial already used by an UPDATE on this server");
+        }
         r->id = s->next_id++;
         s->reqs[r->id] = r;
         s->pending.push_back(r);
         *id = r->id;
     }
     s->cv.notify_all();
+    csrmf::last_error().clear();
     return CSRMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int csrmf_server_create(csrmf_ctx* cx, int32_t n_users, int32_t n_items, const double* U, const double* V,
+                        double hbm_budget_bytes, int32_t max_batch, csrmf_server** out) {
+    return create_server(reinterpret_cast<Context*>(cx), n_users, n_items, U, V, nullptr, nullptr, nullptr,
+                         hbm_budget_bytes, max_batch, out);
+}
+
+int csrmf_server_create_int(csrmf_ctx* cx, int32_t n_users, int32_t n_items, const int64_t* utab,
+                            const int64_t* vtab, const int64_t* mask_gather, double hbm_budget_bytes,
+                            int32_t max_batch, csrmf_server** out) {
+    if (!utab) {
+        csrmf::last_error() = "server: null table plaintexts";
+        return CSRMF_E_INVAL;
+    }
+    return create_server(reinterpret_cast<Context*>(cx), n_users, n_items, nullptr, nullptr, utab, vtab,
+                         mask_gather, hbm_budget_bytes, max_batch, out);
+}
+
+int csrmf_server_submit(csrmf_server* sv, int32_t op, int32_t user, int32_t n, const int32_t* items,
+                        const double* ratings, uint32_t client_serial, uint64_t* id) {
+    return submit(reinterpret_cast<Server*>(sv), op, user, n, items, ratings, nullptr, client_serial, id);
+}
+
+int csrmf_server_submit_int(csrmf_server* sv, int32_t op, int32_t user, int32_t n, const int32_t* items,
+                            const int64_t* plain, uint32_t client_serial, uint64_t* id) {
+    if (op == 1 && !plain) {
+        csrmf::last_error() = "submit: an UPDATE needs its encoded rating chunks";
+        return CSRMF_E_INVAL;
+    }
+    return submit(reinterpret_cast<Server*>(sv), op, user, n, items, nullptr, plain, client_serial, id);
 }
 
 int csrmf_server_poll(csrmf_server* sv, uint64_t id, int32_t wait, int32_t* status, uint64_t* results, int32_t cap,
@@ -437,7 +604,10 @@ int csrmf_server_stats(csrmf_server* sv, char* buf, int32_t cap) {
         o = "{\"batches\": " + std::to_string(s->batches) + ", \"processed\": " + std::to_string(s->processed) +
             ", \"max_batch\": " + std::to_string(s->max_seen_batch) + ", \"queued\": " +
             std::to_string(s->pending.size()) + ", \"in_flight_bytes\": " + std::to_string(s->in_flight) +
-            ", \"budget_bytes\": " + std::to_string(s->budget) + "}";
+            ", \"budget_bytes\": " + std::to_string(s->budget) +
+            ", \"overlapped_batches\": " + std::to_string(s->overlapped) +
+            ", \"max_batches_in_flight\": " + std::to_string(s->max_seen_inflight) +
+            ", \"batches_in_flight\": " + std::to_string(s->inflight.size()) + "}";
     }
     if (buf && cap > 0) {
         const size_t n = std::min<size_t>(o.size(), (size_t)cap - 1);

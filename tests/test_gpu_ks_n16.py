@@ -112,3 +112,22 @@ def test_mf_chain_dnum7():
     _check(ctx, ctx.hmult_batch([a], [b])[0], golden[("hmult", 0)], "HMult, dnum 7")
     _check(ctx, ctx.rotate(a, gold.ROT_STEP), golden[("rotate", 0)], "rotation, dnum 7")
     ctx.close()
+
+
+@pytest.mark.parametrize("sched", [(2048, 1, 16), (256, 1, 8), (0, 0, 32)])
+def test_schedules_give_the_same_bits(kb, sched):
+    """Cached or streamed NTT intermediates, NTT chunks and ModUp sub-batches
+    change only the order of the launches: the batched rotation and HMult of
+    the 64 ciphertexts keep the oracle's bits."""
+    ctx, cts, golden = kb
+    ctx.set_schedule(*sched)
+    try:
+        rots = ctx.rotate_batch(cts, gold.ROT_STEP)
+        prods = ctx.hmult_batch(cts, cts[1:] + cts[:1])
+        for i in gold.SAMPLES:
+            _check(ctx, rots[i], golden[("rotate", i)], f"rotation {i} under {sched}")
+            _check(ctx, prods[i], golden[("hmult", i)], f"HMult {i} under {sched}")
+        for h in rots + prods:
+            ctx.free(h)
+    finally:
+        ctx.set_schedule(2048, 0, 0)

@@ -1,7 +1,9 @@
-"""Serving loop on the GPU (N = 2^12 chain, k = 4): PREDICT and UPDATE results
-against plaintext arithmetic, a row cut into two chunks, and the same request
+"""Serving loop on the GPU (N = 2^12 chain): PREDICT and UPDATE results
+against plaintext arithmetic, a row cut into two chunks, the same request
 giving bit-identical result ciphertexts alone and inside a mix of other
-requests (continuous batching changes only how launches are grouped)."""
+requests whose batches overlap on the device (continuous batching changes
+only how launches are grouped), sampled requests bit-exact against the
+oracle's serving functions, and the refusal of a reused UPDATE serial."""
 import numpy as np
 import pytest
 
@@ -18,12 +20,12 @@ def _params():
     return pk.params(12, 60, 5, 40, 2, 60, 3, 40, k=K, lr=LR, lam=LAM, rule=2)
 
 
-def _server(n_users=32, n_items=600, sigma=0.1):
+def _server(n_users=32, n_items=600, sigma=0.1, max_batch=32):
     import paper_2509_03024_amd as pk
     U0, V0 = workloads.init_factors(n_users, n_items, K, seed=5, sigma=sigma)
     ctx = pk.Context(_params(), workloads.CRYPTO_SEED)
     ctx.keygen([])
-    srv = pk.Server(ctx, U0, V0, hbm_budget_bytes=8e9, max_batch=32)
+    srv = pk.Server(ctx, U0, V0, hbm_budget_bytes=8e9, max_batch=max_batch)
     return ctx, srv, U0, V0
 
 
@@ -67,7 +69,7 @@ def test_result_identical_alone_and_in_a_mix():
     ya = srv_a.submit(srv_a.PREDICT, 9, y_items, client_serial=78)
     ra = srv_a.poll(xa, wait=True)[1] + srv_a.poll(ya, wait=True)[1]
 
-    ctx_b, srv_b, _, _ = _server()
+    ctx_b, srv_b, _, _ = _server(max_batch=4)
     ids = []
     for n, ((it, rr), user, op) in enumerate(others[:6]):
         ids.append(srv_b.submit(op, user, it, rr if op else None, client_serial=1000 + n))
@@ -78,7 +80,9 @@ def test_result_identical_alone_and_in_a_mix():
     rb = srv_b.poll(xb, wait=True)[1] + srv_b.poll(yb, wait=True)[1]
     for i in ids:
         assert srv_b.poll(i, wait=True)[0] == 2
-    assert srv_b.stats()["max_batch"] > 1, "the mix was never batched"
+    st_b = srv_b.stats()
+    assert st_b["max_batch"] > 1, "the mix was never batched"
+    assert st_b["overlapped_batches"] >= 1, "no batch was admitted while another was on the device"
     for ha, hb in zip(ra, rb):
         ea, la, sa = ctx_a.export_ct(ha)
         eb, lb, sb = ctx_b.export_ct(hb)
@@ -99,5 +103,59 @@ def test_admission_rejects_oversized_request():
     assert e.value.name == "NOMEM"
     with pytest.raises(pk.CsrmfError):
         srv.submit(srv.PREDICT, 0, np.array([3, 2], dtype=np.int32))   # unsorted row
+    srv.close()
+    ctx.close()
+
+
+def test_sampled_requests_bit_exact_against_oracle_while_batches_overlap():
+    """Five requests (PREDICT and UPDATE, one UPDATE over two chunks) served
+    from tables and rating chunks encoded by the oracle, submitted back to back
+    with at most two requests per batch, so batches are pipelined on the
+    device: every result ciphertext equals the oracle's serving result."""
+    import paper_2509_03024_amd as pk
+    from tests import test_oracle_serving as osv
+    k = osv.K
+    U0, V0 = workloads.init_factors(osv.N_USERS, osv.N_ITEMS, k, seed=5)
+    octx, st, (ut, vt, mask) = osv.make_state(U0, V0)
+    ctx = pk.Context(pk.params(12, 60, 5, 40, 2, 60, 3, 40, k=k, lr=osv.LR, lam=osv.LAM, rule=2),
+                     workloads.CRYPTO_SEED)
+    ctx.keygen([])
+    srv = pk.Server(ctx, None, None, hbm_budget_bytes=8e9, max_batch=2,
+                    plain=(osv.N_USERS, osv.N_ITEMS, np.stack(ut), np.stack(vt), mask))
+    rng = np.random.default_rng(12)
+    reqs = []
+    for n, (op, d) in enumerate([(0, 20), (1, 12), (1, 70), (0, 9), (1, 5)]):
+        items = np.sort(rng.choice(osv.N_ITEMS, size=d, replace=False)).astype(np.int32)
+        r = np.rint(np.clip(rng.normal(3.5, 1.1, d), 1, 5))
+        user = int(rng.integers(0, osv.N_USERS))
+        pt = osv.rating_plaintexts(octx, r, st.D, st.B, k) if op else None
+        rid = srv.submit(op, user, items, client_serial=500 + n, plain=None if pt is None else np.stack(pt))
+        reqs.append((rid, op, user, items, pt, 500 + n))
+    got = [srv.poll(rid, wait=True) for rid, *_ in reqs]
+    stats = srv.stats()
+    assert stats["overlapped_batches"] >= 1 and stats["max_batches_in_flight"] >= 2, stats
+    for (rid, op, user, items, pt, cs), (status, res, lat) in zip(reqs, got):
+        assert status == 2
+        want = st.update(user, items, pt, cs) if op else st.predict(user, items)
+        want = [want] if op else want
+        assert len(res) == len(want)
+        for h, o in zip(res, want):
+            e, lvl, sc = ctx.export_ct(h)
+            assert lvl == o.level and sc == o.scale
+            assert np.array_equal(e[0], o.c0) and np.array_equal(e[1], o.c1), (op, len(items))
+    srv.close()
+    ctx.close()
+
+
+def test_update_serial_reuse_is_refused():
+    import paper_2509_03024_amd as pk
+    ctx, srv, U0, V0 = _server(n_users=8, n_items=64)
+    rng = np.random.default_rng(2)
+    items, r = _row(rng, 64, 10)
+    srv.submit(srv.UPDATE, 1, items, r, client_serial=42)
+    srv.submit(srv.PREDICT, 1, items, client_serial=42)            # a PREDICT encrypts nothing
+    with pytest.raises(pk.CsrmfError) as e:
+        srv.submit(srv.UPDATE, 2, items, r, client_serial=42)
+    assert e.value.name == "INVAL" and "serial" in str(e.value)
     srv.close()
     ctx.close()
