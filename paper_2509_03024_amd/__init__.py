@@ -29,6 +29,16 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                       "(python -m paper_2509_03024_amd.build)")
 
+# One HIP runtime per process.  PyTorch ships its own libamdhip64 (soname
+# libamdhip64.so.7, loaded under the file name libamdhip64.so); when it is
+# loaded first, this library binds to it by soname.  Loaded the other way
+# round, the process would hold two HIP runtimes and PyTorch's would see no
+# device.  So PyTorch, when installed, is loaded before the library.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 lib = ctypes.CDLL(LIB_PATH)
 
 

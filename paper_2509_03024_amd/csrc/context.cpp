@@ -266,6 +266,41 @@ void Context::graph_destroy(uint64_t id) {
 // ------------------------------------------------------------------ helpers
 static uint64_t mm(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
 
+// Constant records of a basis conversion (layout: launch_basis_convert):
+// hats[i * targets.size() + t] = Qhat_i mod targets[t]; r_mod[t] = 2^64 mod targets[t].
+static std::vector<uint64_t> bc_records(const std::vector<uint64_t>& hats, int ns,
+                                        const std::vector<uint64_t>& targets, const std::vector<uint64_t>& r_mod) {
+    const int R = kBcRecordWords(ns), nt = (int)targets.size();
+    std::vector<uint64_t> rec((size_t)nt * R, 0);
+    auto put = [&](size_t at, double v) { std::memcpy(&rec[at], &v, 8); };
+    for (int t = 0; t < nt; ++t) {
+        const uint64_t q = targets[t];
+        const size_t base = (size_t)t * R;
+        for (int i = 0; i < ns; ++i) {
+            const uint64_t h = hats[(size_t)i * nt + t];
+            if (q < kBcFp64Bound) {
+                const int64_t lo = (int64_t)((h + (1u << 19)) & ((1u << 20) - 1)) - (1 << 19);
+                put(base + 2 * i, (double)lo);
+                put(base + 2 * i + 1, (double)(((int64_t)h - lo) >> 20));
+            } else {
+                rec[base + i] = mm(h, r_mod[t], q);
+            }
+        }
+        if (q < kBcFp64Bound) {
+            const double qd = (double)q;
+            put(base + 2 * ns, qd);
+            put(base + 2 * ns + 1, 1.0 / qd);
+            const int sh[3] = {20, 30, 50};
+            for (int k = 0; k < 3; ++k) {
+                const uint64_t w = (1ull << sh[k]) % q;
+                put(base + 2 * ns + 2 + 2 * k, (double)w);
+                put(base + 2 * ns + 3 + 2 * k, (double)w / qd);
+            }
+        }
+    }
+    return rec;
+}
+
 static void upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
     CSRMF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
     CSRMF_HIP(hipStreamSynchronize(s));   // the host buffer may be reused on return
@@ -421,14 +456,17 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
                 yc.push_back(w);
                 yc.push_back(shoup_pre(w, qi));
             }
+            std::vector<uint64_t> hats, tq, trm;
+            for (int tm : tg) { tq.push_back(moduli[tm]); trm.push_back(mh[tm].r_mod); }
             for (int i = lo; i < hi; ++i) {
                 for (int tm : tg) {
                     const uint64_t qt = moduli[tm];
                     uint64_t hat = 1;
                     for (int k = lo; k < hi; ++k) if (k != i) hat = mm(hat, moduli[k] % qt, qt);
-                    cc.push_back(mm(hat, mh[tm].r_mod, qt));
+                    hats.push_back(hat);
                 }
             }
+            cc = bc_records(hats, hi - lo, tq, trm);
             dc.yc = upload_consts(pool, yc, stream);
             dc.cc = upload_consts(pool, cc, stream);
             c.digits.push_back(dc);
@@ -442,14 +480,17 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
             y.push_back(w);
             y.push_back(shoup_pre(w, pk_));
         }
+        std::vector<uint64_t> md_hats, md_tq, md_trm;
+        for (int i = 0; i <= l; ++i) { md_tq.push_back(moduli[i]); md_trm.push_back(mh[i].r_mod); }
         for (int k = 0; k < alpha; ++k) {
             for (int i = 0; i <= l; ++i) {
                 const uint64_t qi = moduli[i];
                 uint64_t hat = 1;
                 for (int kk = 0; kk < alpha; ++kk) if (kk != k) hat = mm(hat, moduli[L + 1 + kk] % qi, qi);
-                cv.push_back(mm(hat, mh[i].r_mod, qi));
+                md_hats.push_back(hat);
             }
         }
+        cv = bc_records(md_hats, alpha, md_tq, md_trm);
         for (int i = 0; i <= l; ++i) {
             const uint64_t qi = moduli[i];
             uint64_t P = 1;

@@ -47,13 +47,13 @@ struct Key {
 struct DigitConsts {
     int lo, hi;                 // limbs [lo, hi) of the digit at this level
     uint64_t* yc = nullptr;     // [|D|][2]
-    uint64_t* cc = nullptr;     // [|D|][n_tgt]  Qhat_i * 2^64 mod target
+    uint64_t* cc = nullptr;     // [n_tgt][kBcRecordWords(|D|)]  conversion records (launch_basis_convert)
 };
 
 struct LevelConsts {
     std::vector<DigitConsts> digits;
     uint64_t* md_y = nullptr;       // [alpha][2]  (P/p_k)^-1 mod p_k
-    uint64_t* md_c = nullptr;       // [alpha][l+1]  (P/p_k) * 2^64 mod q_i
+    uint64_t* md_c = nullptr;       // [l+1][kBcRecordWords(alpha)]  records of the conversion P -> Q_l
     uint64_t* md_pinv = nullptr;    // [l+1][2]  P^-1 mod q_i
     uint64_t* rs = nullptr;         // [l][4]  h mod q_i, q_l^-1 mod q_i, shoup, 0
 };

@@ -37,6 +37,11 @@ struct RowMap {
 // Primes below this bound use the exact FP64 transform; their twiddle tables
 // hold doubles: w and fl(w/q) in place of w and shoup(w).
 constexpr uint64_t kFp64PrimeBound = 1ull << 44;
+// Basis-conversion targets below this bound sum their products in exact FP64
+// (the 40-bit scale primes); see launch_basis_convert for their constants.
+constexpr uint64_t kBcFp64Bound = 1ull << 40;
+// Words of a basis-conversion target's constant record for ns sources.
+constexpr int kBcRecordWords(int ns) { return 2 * ns + 8; }
 
 // Device-resident tables of the modulus chain.
 struct DevTables {
@@ -92,7 +97,11 @@ void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, cons
 //   y_i = x_i * [Qhat_i^-1]_{q_i},   out_t = sum_i y_i * [Qhat_i]_t  (mod t)
 // src map: n_src (1..16) rows; dst map: n_tgt rows.  Device constants:
 //   yc[2i], yc[2i+1]            = Qhat_i^-1 mod src_i and its shoup
-//   cc[i*n_tgt+t]               = Qhat_i * 2^64 mod tgt_t (Montgomery form)
+//   cc[t*R .. t*R + R-1]        = target t's record, R = kBcRecordWords(n_src) words:
+//     target below kBcFp64Bound: doubles (bit patterns) c_0, d_0, .., c_{n-1}, d_{n-1}
+//       (Qhat_i mod t = c_i + d_i 2^20, c_i in [-2^19, 2^19)), then t, 1/t,
+//       2^20 mod t, (2^20 mod t)/t, 2^30 mod t, (2^30 mod t)/t, 2^50 mod t, (2^50 mod t)/t;
+//     other targets: Qhat_i * 2^64 mod t (Montgomery form) for i < n_src, then zeros
 // centered: y_i taken in (-q_i/2, q_i/2] (ModUp of key-switching digits), so
 // the result is the centred representative mod Q plus a small multiple of Q.
 void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src,

@@ -501,68 +501,137 @@ __global__ void __launch_bounds__(kThreads) k_automorphism(DevTables t, uint32_t
     }
 }
 
-// Basis conversion: two coefficients per thread.  y_i = x_i * [Qhat_i^-1]_{q_i}
-// (Shoup, canonical), then for every target t the products y_i * (Qhat_i 2^64
-// mod t) are summed exactly in 128 bits and reduced once by Montgomery REDC:
-// sum < NS * 2^60 * t <= t * 2^64, so REDC returns sum * 2^-64 mod t in [0, 2t).
-// kCentered (ModUp): y_s is taken in (-q_s/2, q_s/2]: a term with 2 y_s > q_s
-// contributes (q_s - y_s) * (t - c) = -(q_s - y_s) * c (mod t), and every
-// term stays below 2^59 * t.
+// Basis conversion, one coefficient per thread.  y_s = x_s * [Qhat_s^-1]_{q_s}
+// (Shoup, canonical), then for every target t the sum of y_s * [Qhat_s]_t.
+// kCentered (ModUp): y_s is taken in (-q_s/2, q_s/2].
+//
+// Targets t < 2^40 (the scale primes) take an exact FP64 form: y_s is split
+// into balanced 30-bit halves y_s = a_s + b_s 2^30 (|a_s|, |b_s| <= 2^29) and
+// C = [Qhat_s]_t into balanced 20-bit halves C = c_s + d_s 2^20
+// (|c_s| <= 2^19, 0 <= d_s <= 2^20), so every partial product is an integer
+// of magnitude at most 2^49 and each of the four sums
+//   A0 = sum a c,  A1 = sum a d (weight 2^20),  A2 = sum b c (2^30),
+//   A3 = sum b d (2^50)
+// of at most 16 sources stays within 2^53: exact in doubles, one FMA per
+// product and no reduction inside the sum.  The weights are then applied by
+// exact products modulo t (fmul_wide) and the total (below 11 t in magnitude)
+// is reduced once.  Without centring a 60-bit y_s has |b_s| <= 2^30, so that
+// form is used for at most 8 sources (ModDown converts the special limbs).
+//
+// Other targets (the 60-bit primes) sum the products |y_s| * (Qhat_s 2^64 mod t)
+// exactly in 128 bits and reduce once by Montgomery REDC:
+// sum < NS * 2^60 * t <= t * 2^64, so REDC returns sum * 2^-64 mod t in [0, 2t);
+// a term with y_s < 0 contributes |y_s| * (t - c) = y_s * c (mod t), every
+// term below 2^59 * t.
+//
+// The constants are the same for every thread: one record of 2 NS + 8 words
+// per target (layout in kernels.h), read with scalar loads.
+
+// y * w mod q for an integer-valued double |y| <= 2^53 and an integer
+// 0 <= w < q < 2^44 with wq within two roundings of w/q: h = fl(y w) and
+// l = y w - h (exact, FMA), t = rint(fl(y wq)) is within 3.5 of y w / q (at
+// most three roundings of relative size 2^-53 on a quotient below 2^53), so
+// h - t q = y w - t q - l is an integer below 2^45 in magnitude and the FMA
+// forms it exactly; the result y w - t q is exact, with |r| <= 3.5 q.
+__device__ __forceinline__ double fmul_wide(double y, double w, double wq, double q) {
+    const double h = y * w;
+    const double l = fma(y, w, -h);
+    const double t = rint(y * wq);
+    return fma(-t, q, h) + l;
+}
+
+// One 60-bit target of the basis conversion from the signed y_s.
+template <int NS>
+__device__ __forceinline__ void convert_int_target(const DevTables& t, int mod, const int64_t (&y)[NS],
+                                                   const uint64_t* __restrict__ r, uint64_t* o, int i) {
+    const Modulus md = t.mods[mod];
+    uint64_t lo = 0, hi = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const bool neg = y[s] < 0;
+        const uint64_t ym = neg ? (uint64_t)(-y[s]) : (uint64_t)y[s];
+        const uint64_t c0 = r[s];
+        const uint64_t c = (neg && c0) ? md.q - c0 : c0;
+        const uint64_t pl = ym * c;
+        const uint64_t ph = mulhi64(ym, c);
+        lo += pl;
+        hi += ph + (lo < pl ? 1u : 0u);
+    }
+    const uint64_t m = lo * md.qneg_inv;
+    const uint64_t res = hi + mulhi64(m, md.q) + (lo != 0 ? 1u : 0u);
+    o[i] = res >= md.q ? res - md.q : res;
+}
+
 template <int NS, bool kCentered>
 __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap dst, RowMap src, const uint64_t* yc,
-                                                            const uint64_t* cc) {
+                                                            const uint64_t* __restrict__ rec) {
     const int logN = t.logN;
     const int N = 1 << logN;
-    const int chunks = N / (2 * kThreads);
+    const int chunks = N / kThreads;
     const int chunk = blockIdx.x % chunks;
     const int b = blockIdx.x / chunks;
-    // two adjacent coefficients per thread: 16-byte loads and stores, and each
-    // constant read from LDS serves two products (5-9 % faster than one)
-    const int i = 2 * (chunk * kThreads + threadIdx.x);
+    const int i = chunk * kThreads + threadIdx.x;
     const int nt = dst.n;
-    // the constants are the same for every thread: stage them in LDS once, so
-    // the NS * nt multiply-accumulates below do not wait on global loads
-    __shared__ uint64_t s_cc[16 * kMaxMapRows];
-    for (int idx = threadIdx.x; idx < NS * nt; idx += kThreads) s_cc[idx] = cc[idx];
-    __syncthreads();
-    uint64_t y[2][NS];
-    bool neg[2][NS];
+    constexpr bool kFp64Sum = kCentered ? NS <= 16 : NS <= 8;
+    constexpr int R = kBcRecordWords(NS);
+    // y_s as a signed integer (centred or not)
+    int64_t y[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         int mod;
         const uint64_t* p = map_row(src, b, s, logN, mod);
         const uint64_t qs = t.mods[mod].q;
-        const ulonglong2 xv = *reinterpret_cast<const ulonglong2*>(p + i);
-        const uint64_t xs[2] = {xv.x, xv.y};
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const uint64_t v = mul_shoup(xs[e], yc[2 * s], yc[2 * s + 1], qs);
-            neg[e][s] = kCentered && 2 * v > qs;
-            y[e][s] = neg[e][s] ? qs - v : v;
+        const uint64_t v = mul_shoup(p[i], yc[2 * s], yc[2 * s + 1], qs);
+        y[s] = (kCentered && 2 * v > qs) ? (int64_t)v - (int64_t)qs : (int64_t)v;
+    }
+    if (!kFp64Sum) {
+        for (int tt = 0; tt < nt; ++tt) {
+            int mod;
+            uint64_t* o = map_row(dst, b, tt, logN, mod);
+            convert_int_target<NS>(t, mod, y, rec + (size_t)tt * R, o, i);
         }
+        return;
+    }
+    double ya[NS], yb[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int64_t lo = (int64_t)(((uint64_t)y[s] + (1u << 29)) & ((1u << 30) - 1)) - (1 << 29);
+        ya[s] = (double)(int32_t)lo;
+        yb[s] = (double)(int32_t)((y[s] - lo) >> 30);
+    }
+    // the targets below 2^40
+    for (int tt = 0; tt < nt; ++tt) {
+        int mod;
+        uint64_t* o = map_row(dst, b, tt, logN, mod);
+        if (t.mods[mod].q >= kBcFp64Bound) continue;
+        const double* r = reinterpret_cast<const double*>(rec + (size_t)tt * R);
+        double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            A0 = fma(ya[s], r[2 * s], A0);
+            A1 = fma(ya[s], r[2 * s + 1], A1);
+            A2 = fma(yb[s], r[2 * s], A2);
+            A3 = fma(yb[s], r[2 * s + 1], A3);
+        }
+        const double* f = r + 2 * NS;   // q, 1/q, then (2^20, 2^30, 2^50 mod q) with their quotients by q
+        const ModF mf{f[0], f[1]};
+        const double v = fma(-rint(A0 * mf.qinv), mf.q, A0) + fmul_wide(A1, f[2], f[3], mf.q) +
+                         fmul_wide(A2, f[4], f[5], mf.q) + fmul_wide(A3, f[6], f[7], mf.q);
+        o[i] = f64_canon(v, mf);
+    }
+    // then the 60-bit targets, with y_s formed again from its halves (an empty
+    // asm keeps the compiler from holding y_s itself through the loop above)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        double ha = ya[s], hb = yb[s];
+        asm volatile("" : "+v"(ha), "+v"(hb));
+        y[s] = (int64_t)ha + (int64_t)hb * (1ll << 30);
     }
     for (int tt = 0; tt < nt; ++tt) {
         int mod;
         uint64_t* o = map_row(dst, b, tt, logN, mod);
-        const Modulus md = t.mods[mod];
-        uint64_t r2[2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            uint64_t lo = 0, hi = 0;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const uint64_t c0 = s_cc[s * nt + tt];
-                const uint64_t c = (neg[e][s] && c0) ? md.q - c0 : c0;
-                const uint64_t pl = y[e][s] * c;
-                const uint64_t ph = mulhi64(y[e][s], c);
-                lo += pl;
-                hi += ph + (lo < pl ? 1u : 0u);
-            }
-            const uint64_t m = lo * md.qneg_inv;
-            const uint64_t r = hi + mulhi64(m, md.q) + (lo != 0 ? 1u : 0u);
-            r2[e] = r >= md.q ? r - md.q : r;
-        }
-        *reinterpret_cast<ulonglong2*>(o + i) = make_ulonglong2(r2[0], r2[1]);
+        if (t.mods[mod].q < kBcFp64Bound) continue;
+        convert_int_target<NS>(t, mod, y, rec + (size_t)tt * R, o, i);
     }
 }
 
@@ -925,7 +994,7 @@ static void launch_bc(const DevTables& t, const RowMap& dst, const RowMap& src, 
 void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src, const uint64_t* yc,
                           const uint64_t* cc, bool centered, hipStream_t s) {
     if (!dst.n || !src.n) return;
-    const int blocks = dst.batch * ((1 << t.logN) / (2 * kThreads));
+    const int blocks = dst.batch * ((1 << t.logN) / kThreads);
     ProfScope ps_("k_basis_convert", s, NB(dst.batch) * (src.n + dst.n));
     const bool ce = centered;
     switch (src.n) {
