@@ -42,8 +42,9 @@ FP64_FMA_PER_S = 78.6e12 / 2
 # Modular-multiply rates measured on an MI355X by a register-resident
 # microbenchmark (4 independent dependent chains per thread, 8192 x 256
 # threads, every result stored; method and figures in the design doc), in
-# operations per second.
-MODMUL_RATE = {"shoup_u64": 1.912e12, "montgomery_u64": 1.319e12, "fp64_exact": 6.346e12, "mac_64x64_128": 2.303e12}
+# operations per second (fp64_split_mac: conversion terms of four FMAs).
+MODMUL_RATE = {"shoup_u64": 1.927e12, "montgomery_u64": 1.318e12, "fp64_exact": 6.164e12, "mac_64x64_128": 2.301e12,
+               "fp64_split_mac": 9.624e12}
 # HBM bytes per launch of a kernel in the timed step (average over the step's
 # launches), from rocprofv3 FETCH_SIZE + WRITE_SIZE counters scaled by a 512 MiB
 # copy (profiles/), with the NTT schedule (rows per pair of passes) of that run
@@ -55,7 +56,8 @@ TRAFFIC = {
     "k_ntt_pass<cols,fwd>": {"bytes": 1.472e+09, "alg_bytes": 7.356e+08, "schedule": 2048},
     "k_ntt_pass<rows,inv>": {"bytes": 1.065e+09, "alg_bytes": 5.251e+08, "schedule": 2048},
     "k_ntt_pass<cols,inv>": {"bytes": 1.051e+09, "alg_bytes": 5.251e+08, "schedule": 2048},
-    "k_ks_combine": {"bytes": 7.802e+09, "alg_bytes": 8.319e+09, "schedule": None},
+    "k_basis_convert": {"bytes": 1.175e+09, "alg_bytes": 1.174e+09, "schedule": None},
+    "k_ks_combine": {"bytes": 7.801e+09, "alg_bytes": 8.319e+09, "schedule": None},
     "k_ks_inner": {"bytes": 5.128e+08, "alg_bytes": 5.128e+08, "schedule": None},
 }
 # Counter bytes (FETCH_SIZE + WRITE_SIZE, scaled as above) of a whole step of
@@ -124,23 +126,29 @@ def ks_model(N, nl, alpha, dnum_digits, key_share):
     int_limbs = 1 + len(dnum_digits) * alpha + (len(dnum_digits) - 1) + 2 * alpha + 2
     bfly = ntt_limbs * (N // 2) * logN
     conv = N * (sum(d * (nr - d) for d in dnum_digits) + 2 * alpha * nl)
+    # conversion terms into 60-bit targets (the special primes in ModUp, q_0 in
+    # the digits that do not hold it and in ModDown); the others sum in FP64
+    conv_int = N * (sum(d * alpha for d in dnum_digits) + sum(dnum_digits[1:]) + 2 * alpha)
     inner = N * len(dnum_digits) * nr * 2
     scal = N * 2 * nl
     return {"alg_bytes": alg_bytes, "limb_ntts": ntt_limbs, "int_limb_ntts": int_limbs, "butterflies": bfly,
-            "conv_macs": conv, "inner_mults": inner, "scale_mults": scal, "modmuls": bfly + conv + inner + scal}
+            "conv_macs": conv, "conv_macs_int": conv_int, "inner_mults": inner, "scale_mults": scal,
+            "modmuls": bfly + conv + inner + scal}
 
 
 def valu_bound(model, q_is_fp64):
     """Seconds per rotation if only the measured modular-multiply rates
     limited it: butterflies of the 40-bit limbs in the exact FP64 form, the
-    60-bit ones with Shoup multiplies, conversion terms as 64x64->128-bit
+    60-bit ones with Shoup multiplies, conversion terms into 40-bit targets as
+    exact FP64 split sums (four FMAs), into 60-bit targets as 64x64->128-bit
     multiply-accumulates, inner products and scalings as Montgomery multiplies."""
     r = MODMUL_RATE
     if any(v is None for v in r.values()):
         return None
     f = q_is_fp64
+    ci = model["conv_macs_int"]
     return (model["butterflies"] * f / r["fp64_exact"] + model["butterflies"] * (1 - f) / r["shoup_u64"]
-            + model["conv_macs"] / r["mac_64x64_128"]
+            + (model["conv_macs"] - ci) / r["fp64_split_mac"] + ci / r["mac_64x64_128"]
             + (model["inner_mults"] + model["scale_mults"]) / r["montgomery_u64"])
 
 

@@ -63,6 +63,9 @@ def test_rotation_model_hand_counts():
     assert m["butterflies"] == 135 * (1 << 15) * 16
     assert m["conv_macs"] == (1 << 16) * (9 * 18 + 9 * 18 + 6 * 21 + 2 * 3 * 24)
     assert m["inner_mults"] == (1 << 16) * 3 * 27 * 2
+    # terms into 60-bit targets: every digit into the 3 special primes, digits 1
+    # and 2 into q_0, and ModDown's 3 special limbs into q_0 for both polynomials
+    assert m["conv_macs_int"] == (1 << 16) * ((9 + 9 + 6) * 3 + (9 + 6) + 2 * 3)
 
 
 def test_traffic_of_an_unmeasured_kernel_is_null():
