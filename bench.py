@@ -52,18 +52,14 @@ MODMUL_RATE = {"shoup_u64": 1.927e12, "montgomery_u64": 1.318e12, "fp64_exact": 
 # counters were taken on.  Under another schedule the launches differ in size
 # and the measured bytes are scaled by the algorithmic bytes (traffic_basis).
 TRAFFIC = {
-    "k_ntt_pass<rows,fwd>": {"bytes": 1.494e+09, "alg_bytes": 7.356e+08, "schedule": 2048},
     "k_ntt_pass<cols,fwd>": {"bytes": 1.472e+09, "alg_bytes": 7.356e+08, "schedule": 2048},
-    "k_ntt_pass<rows,inv>": {"bytes": 1.065e+09, "alg_bytes": 5.251e+08, "schedule": 2048},
     "k_ntt_pass<cols,inv>": {"bytes": 1.051e+09, "alg_bytes": 5.251e+08, "schedule": 2048},
     "k_basis_convert": {"bytes": 1.175e+09, "alg_bytes": 1.174e+09, "schedule": None},
-    "k_ks_combine": {"bytes": 7.801e+09, "alg_bytes": 8.319e+09, "schedule": None},
-    "k_ks_inner": {"bytes": 5.128e+08, "alg_bytes": 5.128e+08, "schedule": None},
 }
 # Counter bytes (FETCH_SIZE + WRITE_SIZE, scaled as above) of a whole step of
 # the kernel-batch workload (transform phase, HMult phase and rotation phase),
 # from the same counter runs; None once the kernels have changed.
-KS_COUNTER_BYTES_PER_STEP = 575.8e9
+KS_COUNTER_BYTES_PER_STEP = None
 
 
 def traffic_of(name, schedule, alg_bytes):
@@ -131,9 +127,13 @@ def ks_model(N, nl, alpha, dnum_digits, key_share):
     conv_int = N * (sum(d * alpha for d in dnum_digits) + sum(dnum_digits[1:]) + 2 * alpha)
     inner = N * len(dnum_digits) * nr * 2
     scal = N * 2 * nl
+    # inner-product and scaling multiplies on 60-bit limbs (the special primes
+    # and q_0; the 40-bit limbs use the exact FP64 form)
+    inner_int = N * len(dnum_digits) * (alpha + 1) * 2
+    scal_int = N * 2
     return {"alg_bytes": alg_bytes, "limb_ntts": ntt_limbs, "int_limb_ntts": int_limbs, "butterflies": bfly,
-            "conv_macs": conv, "conv_macs_int": conv_int, "inner_mults": inner, "scale_mults": scal,
-            "modmuls": bfly + conv + inner + scal}
+            "conv_macs": conv, "conv_macs_int": conv_int, "inner_mults": inner, "inner_mults_int": inner_int,
+            "scale_mults": scal, "scale_mults_int": scal_int, "modmuls": bfly + conv + inner + scal}
 
 
 def valu_bound(model, q_is_fp64):
@@ -141,15 +141,18 @@ def valu_bound(model, q_is_fp64):
     limited it: butterflies of the 40-bit limbs in the exact FP64 form, the
     60-bit ones with Shoup multiplies, conversion terms into 40-bit targets as
     exact FP64 split sums (four FMAs), into 60-bit targets as 64x64->128-bit
-    multiply-accumulates, inner products and scalings as Montgomery multiplies."""
+    multiply-accumulates, inner products and scalings in the exact FP64 form on
+    the 40-bit limbs and as Montgomery multiplies on the 60-bit ones."""
     r = MODMUL_RATE
     if any(v is None for v in r.values()):
         return None
     f = q_is_fp64
     ci = model["conv_macs_int"]
+    mi = model["inner_mults_int"] + model["scale_mults_int"]
+    mf = model["inner_mults"] + model["scale_mults"] - mi
     return (model["butterflies"] * f / r["fp64_exact"] + model["butterflies"] * (1 - f) / r["shoup_u64"]
             + (model["conv_macs"] - ci) / r["fp64_split_mac"] + ci / r["mac_64x64_128"]
-            + (model["inner_mults"] + model["scale_mults"]) / r["montgomery_u64"])
+            + mf / r["fp64_exact"] + mi / r["montgomery_u64"])
 
 
 # ---------------------------------------------------------------- CPU oracle legs
@@ -273,6 +276,7 @@ def run_cpu_legs(legs):
 
 # ---------------------------------------------------------------- accuracy (RMSE per iteration)
 ACC_ITERS, ACC_LR, ACC_LAM, ACC_DAMP = 20, 0.001, 0.02, 0.1
+ACC_PREC_ITERS, ACC_DELTA_BITS = 15, (26, 32, 40)
 
 
 def run_accuracy(iters=ACC_ITERS):
@@ -319,6 +323,25 @@ def run_accuracy(iters=ACC_ITERS):
     for name in ("without_batching", "with_batching_alg2"):
         out[name]["iterations_to_slower_final_rmse"] = next(
             i + 1 for i, x in enumerate(out[name]["rmse"]) if x <= target)
+    # precision: the same run without batching at smaller scales Delta (scale
+    # primes of log2(Delta) bits; the program's masks scale with Delta)
+    prec = {}
+    for bits in ACC_DELTA_BITS:
+        ctx = pk.Context(pk.params(15, 60, 16, bits, 3, 60, 5, bits, k=K, lr=ACC_LR, lam=ACC_LAM, rule=1,
+                                   refresh_mode=1), workloads.CRYPTO_SEED)
+        ctx.keygen([])
+        m = pk.MF(ctx)
+        m.encrypt_csr_rows(csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx, csr.values)
+        m.init_factors(U0, V0)
+        curve = []
+        for it in range(ACC_PREC_ITERS):
+            m.epochs(1)
+            U, V = m.decrypt_factors()
+            curve.append(round(rmse(U, V), 6))
+        prec[f"delta_2^{bits}"] = {"rmse": curve, "refreshes": m.stats()["refreshes"]}
+        log(f"accuracy Delta 2^{bits}: RMSE {curve[0]} -> {curve[-1]}")
+        ctx.close()
+    out["precision_without_batching"] = prec
     out.update({"metric": "RMSE (Eq. 10) per iteration, encrypted MF", "value": out["without_batching"]["rmse"][-1],
                 "unit": "rmse", "higher_is_better": False,
                 "config": {"workload": f"encrypted MF, MovieLens-100K-shaped 943 x 1682, {csr.nnz} ratings, k={K}, "
@@ -536,6 +559,8 @@ def bench_serve(args):
             srv = servers["n15" if len(items) <= 512 else "n16"][1]
             serial += 1
             ids.append((srv, srv.submit(op, user, items, r if op else None, client_serial=serial), len(items)))
+            if len(ids) % 250 == 0:
+                log(f"rate {rate}: {len(ids)} requests submitted")
         lats = []
         n_ratings = 0
         for srv, rid, d in ids:
@@ -789,6 +814,9 @@ def main():
             for name, curve in ref.items():
                 enc = out[name]["rmse"]
                 out[name]["max_abs_diff_vs_fp64"] = round(max(abs(a - b) for a, b in zip(enc, curve)), 6)
+            for v in out.get("precision_without_batching", {}).values():
+                ref0 = ref.get("without_batching", [])
+                v["max_abs_diff_vs_fp64"] = round(max(abs(a - b) for a, b in zip(v["rmse"], ref0)), 6)
         print(json.dumps(out), flush=True)
         return
     if args.workload in ("mf100k", "mf1m"):

@@ -289,7 +289,7 @@ int csrmf_server_create(csrmf_ctx* ctx, int32_t n_users, int32_t n_items, const 
  * results bit for bit): utab[ceil(n_users/D)][N], vtab[ceil(n_items/D)][N]
  * (entity a*D + b at block b, k factors in slots bB..bB+k-1, scale
  * 2^log2_scale) and mask_gather[N], the indicator of slots 0..k-1 encoded at
- * 2^30.  The tables are encrypted at the top level with the context's running
+ * 2^(log2_scale - 10).  The tables are encrypted at the top level with the context's running
  * serial numbers, the U tables first.  Errors as csrmf_server_create. */
 int csrmf_server_create_int(csrmf_ctx* ctx, int32_t n_users, int32_t n_items, const int64_t* utab,
                             const int64_t* vtab, const int64_t* mask_gather, double hbm_budget_bytes,
@@ -442,7 +442,8 @@ int csrmf_init_factors(csrmf_ctx* ctx, const double* U0, const double* V0);
 /* Integer-plaintext form of csrmf_init_factors plus the block indicator masks:
  * utab[n_utab][N], vtab[n_vtab][N], ug[n_ct][N], vg[n_ct][N];
  * mask_scatter[N] and mask_gather[N] = encodings of the indicator of slots
- * 0..k-1 at scales 2^24 (scatters) and 2^30 (gathers, whose weights are all 1).
+ * 0..k-1 at scales 2^(log2_scale - 16) (scatters) and 2^(log2_scale - 10)
+ * (gathers, whose weights are all 1): 2^24 and 2^30 at log2_scale = 40.
  * Counts are reported by csrmf_mf_layout.  Errors: INVAL (null pointer), STATE. */
 int csrmf_init_factors_int(csrmf_ctx* ctx, const int64_t* utab, const int64_t* vtab,
                            const int64_t* ug, const int64_t* vg, const int64_t* mask_scatter,
@@ -466,7 +467,7 @@ int csrmf_mf_layout(const csrmf_ctx* ctx, int32_t* n_ct, int32_t* n_utab, int32_
  * Run n_epochs synchronous encrypted gradient-descent epochs.  Each epoch
  * computes for every rating ciphertext P = Ug*Vg, the block dot products by a
  * windowed rotate-and-sum, E = R - <u,v>, the gradient terms E*Vg and E*Ug,
- * scatters them into the factor tables (held at scale 2^50) with the
+ * scatters them into the factor tables (held at scale 2^(log2_scale + 10)) with the
  * learning-rate weights and the (1 - alpha*lambda*...) self term; every
  * further epoch first gathers the factors back into the rating layout.  The
  * first epoch on gathered factors costs 3 levels, each further one 4.

@@ -679,9 +679,20 @@ void Context::make_switching_key(Key& key, const uint64_t* sprime, uint32_t key_
     Scratch pcd(pool, pc.size());
     upload(pcd.p, pc.data(), pc.size() * 8, stream);
     std::vector<uint64_t> rc;
-    for (int i = 0; i < nall; ++i) { rc.push_back(mh[i].r_mod); rc.push_back(mh[i].r_mod_shoup); }
-    Scratch rcd(pool, rc.size());
-    upload(rcd.p, rc.data(), rc.size() * 8, stream);
+    RowMap mk_int, mk_f64;   // key rows by form (both polynomials of mk_int through poly_stride)
+    mk_int.base = key.d;
+    mk_int.poly_stride = (int64_t)rows_words;
+    for (int i = 0; i < nall; ++i) {
+        if (moduli[i] < kFp64PrimeBound) {
+            mk_f64.push(i, i);
+        } else {
+            mk_int.push(i, i);
+            rc.push_back(mh[i].r_mod);
+            rc.push_back(mh[i].r_mod_shoup);
+        }
+    }
+    Scratch rci(pool, std::max<size_t>(1, rc.size()));
+    if (!rc.empty()) upload(rci.p, rc.data(), rc.size() * 8, stream);
     std::vector<uint64_t> av(rows_words);
     std::vector<int64_t> ev(N);
     Scratch es(pool, N), tmp(pool, rows_words);
@@ -707,11 +718,15 @@ void Context::make_switching_key(Key& key, const uint64_t* sprime, uint32_t key_
         for (int i = lo; i < hi; ++i) { dq.push(i, i); sq.push(i, i); tq.push(i, i); }
         launch_mul_const(tabs, tq, sq, pcd.p + 2 * lo, false, stream);   // P * s'
         launch_ew(tabs, EW_ADD, dq, dq, tq, stream);
-        // store times 2^64
-        RowMap mk = ma;
-        mk.base = kb;
-        mk.poly_stride = (int64_t)rows_words;
-        launch_mul_const(tabs, mk, mk, rcd.p, true, stream);
+        mk_int.base = kb;
+        // store the 60-bit rows times 2^64 (Montgomery form), the rows of
+        // primes below 2^44 as centred doubles (the inner products' FP64 form)
+        if (mk_int.n) launch_mul_const(tabs, mk_int, mk_int, rci.p, true, stream);
+        for (uint64_t* base : {kb, ka}) {
+            RowMap mf = mk_f64;
+            mf.base = base;
+            if (mf.n) launch_ew(tabs, EW_F64C, mf, mf, mf, stream);
+        }
     }
     sync();
 }
@@ -860,12 +875,15 @@ void Context::export_key(int which, uint32_t g, uint64_t* out) {
     if (!have_keys) throw Error(CSRMF_E_STATE, "keygen first");
     const int nall = L + 1 + alpha;
     std::vector<uint64_t> h;
-    auto pull = [&](const uint64_t* d, int rows, const std::vector<int>& mods, bool mont) {
+    // mont: rows stored times 2^64; f64: rows of primes below 2^44 stored as
+    // centred doubles (switching keys)
+    auto pull = [&](const uint64_t* d, int rows, const std::vector<int>& mods, bool mont, bool f64 = false) {
         Scratch x(pool, (size_t)rows * N);
         CSRMF_HIP(hipMemcpyAsync(x.p, d, (size_t)rows * N * 8, hipMemcpyDeviceToDevice, stream));
         RowMap m;
         m.base = x.p;
         for (int r = 0; r < rows; ++r) m.push(r, mods[r]);
+        if (f64) launch_ew(tabs, EW_F64U, m, m, m, stream);
         launch_ntt(tabs, m, true, stream);
         std::vector<uint64_t> v((size_t)rows * N);
         CSRMF_HIP(hipMemcpyAsync(v.data(), x.p, v.size() * 8, hipMemcpyDeviceToHost, stream));
@@ -873,6 +891,7 @@ void Context::export_key(int which, uint32_t g, uint64_t* out) {
         if (mont) {
             for (int r = 0; r < rows; ++r) {
                 const uint64_t q = moduli[mods[r]];
+                if (f64 && q < kFp64PrimeBound) continue;
                 const uint64_t rinv = inv_mod(mh[mods[r]].r_mod, q);
                 for (uint64_t n = 0; n < N; ++n) v[(size_t)r * N + n] = mm(v[(size_t)r * N + n], rinv, q);
             }
@@ -891,8 +910,8 @@ void Context::export_key(int which, uint32_t g, uint64_t* out) {
     } else if (which == 2 || which == 3) {
         const Key& k = which == 2 ? relin : key_for(g);
         for (int j = 0; j < k.n_digits; ++j) {
-            pull(k.d + (size_t)j * 2 * nall * N, nall, all_mods, true);
-            pull(k.d + (size_t)j * 2 * nall * N + (size_t)nall * N, nall, all_mods, true);
+            pull(k.d + (size_t)j * 2 * nall * N, nall, all_mods, true, true);
+            pull(k.d + (size_t)j * 2 * nall * N + (size_t)nall * N, nall, all_mods, true, true);
         }
     } else {
         throw Error(CSRMF_E_INVAL, "unknown key selector");
@@ -901,8 +920,12 @@ void Context::export_key(int which, uint32_t g, uint64_t* out) {
 }
 
 // ------------------------------------------------------------------ evaluation
+// Operands of an addition must carry the same scale up to the rounding of the
+// integer weights that produced them: 2^-30 relative, or 2^-(log2_scale - 4)
+// on chains with a smaller scale (their weights are integers of about
+// log2_scale bits).
 void Context::check_scales(double a, double b) const {
-    if (std::fabs(a / b - 1.0) > std::ldexp(1.0, -30))
+    if (std::fabs(a / b - 1.0) > std::ldexp(1.0, std::max(-30, 4 - prm.log2_scale)))
         throw Error(CSRMF_E_SCALE, "operand scales differ: " + std::to_string(a) + " vs " + std::to_string(b));
 }
 

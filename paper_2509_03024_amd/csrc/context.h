@@ -38,7 +38,8 @@ struct Ct {
     double scale = 1.0;
 };
 
-// A switching key: [n_digits][2 (b, a)][L+1+alpha][N], stored times 2^64 mod q.
+// A switching key: [n_digits][2 (b, a)][L+1+alpha][N]; rows of 60-bit primes are
+// stored times 2^64 mod q, rows of primes below 2^44 as centred doubles (bit patterns).
 struct Key {
     uint64_t* d = nullptr;
     int n_digits = 0;

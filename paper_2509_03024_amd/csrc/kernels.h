@@ -65,10 +65,10 @@ void launch_ntt_from(const DevTables& t, const RowMap& rows, const RowMap& src, 
 void launch_expand_signed(const DevTables& t, const RowMap& out, const int64_t* src, int n_src,
                           int64_t src_batch_stride, hipStream_t s);
 
-enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_NEG = 2, EW_COPY = 3, EW_F64C = 4 };
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_NEG = 2, EW_COPY = 3, EW_F64C = 4, EW_F64U = 5 };
 // out = a (op) b (EW_NEG: out = -a; EW_COPY: out = a; EW_F64C: rows of primes
 // below 2^44 become their centred values as raw doubles, the others are
-// copied); maps share (n, batch).
+// copied; EW_F64U: the inverse of EW_F64C); maps share (n, batch).
 void launch_ew(const DevTables& t, EwOp op, const RowMap& out, const RowMap& a, const RowMap& b,
                hipStream_t s);
 

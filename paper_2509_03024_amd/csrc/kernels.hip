@@ -227,12 +227,30 @@ template <> struct NttIo<double, ModF> {
 // streamed the same way if kNtMid, else written and read through the caches,
 // so that a sub-batch small enough for the last-level cache can hand it from
 // one pass to the next without a round trip to HBM.
+// Barrier between the LDS exchanges of a pass.  A rows pass's sub-transform
+// (2^SL residues, 8 per thread, SL <= 9) is held by 2^(SL-3) consecutive
+// lanes of one wave and owns its own LDS range, so its exchanges only need
+// that wave's LDS accesses kept in order (a wavefront-scope fence); the
+// columns passes interleave their sub-transforms across the block's waves
+// and need the block barrier.
+template <bool kCols>
+__device__ __forceinline__ void pass_sync() {
+    if constexpr (kCols) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 template <int SL, bool kCols, bool kInverse, bool kNtMid, typename T, typename M>
 __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t* in, uint64_t* data, const uint64_t* W,
                                               const uint64_t* Wp, const M& md, const Modulus& mi, int L1, int L2,
                                               int chunk, int tid) {
     T* lds = reinterpret_cast<T*>(lds_raw);
     constexpr int TPS_L = SL - 3;
+    static_assert(kCols || TPS_L <= 6, "a rows sub-transform is held by the lanes of one wave (pass_sync)");
     constexpr int SPB_L = kNttBlockLog - SL;        // log2(sub-transforms per block)
     constexpr int R0 = (SL % 3) ? (SL % 3) : 3;
     constexpr bool kFirstPass = kCols != kInverse;   // forward starts with columns, inverse with rows
@@ -270,12 +288,12 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t*
         for (int a = R0; a < SL; a += 3) {
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) lds[lbase(j0) + loff(kk, ld)] = x[kk];
-            __syncthreads();
+            pass_sync<kCols>();
             ld = SL - a - 3;
             j0 = ((tt >> ld) << (ld + 3)) | (tt & ((1 << ld) - 1));
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) x[kk] = lds[lbase(j0) + loff(kk, ld)];
-            __syncthreads();
+            pass_sync<kCols>();
             ntt_round<3, false>(x, W, Wp, c0, a, tt >> ld, md);
         }
         if (kCols) {
@@ -286,7 +304,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t*
             // exchange lets consecutive lanes store consecutive residues
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) lds[lbase(j0) + loff(kk, ld)] = x[kk];
-            __syncthreads();
+            pass_sync<kCols>();
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk)
                 st_stream<kNtSt>(Io::out_fwd_end(lds[lbase(tt) + loff(kk, SL - 3)], md), &data[gaddr(tt + (kk << (SL - 3)))]);
@@ -303,27 +321,27 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t*
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk)
                 lds[lbase(tt) + loff(kk, SL - 3)] = Io::in(ld_stream<kNtLd>(&in[gaddr(tt + (kk << (SL - 3)))]), kFirstPass, md);
-            __syncthreads();
+            pass_sync<kCols>();
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) x[kk] = lds[lbase(j0) + loff(kk, 0)];
-            __syncthreads();
+            pass_sync<kCols>();
         }
         ntt_round<3, true>(x, W, Wp, c0, SL - 3, tt, md);
 #pragma unroll
         for (int a = SL - 6; a >= R0; a -= 3) {
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) lds[lbase(j0) + loff(kk, ld)] = x[kk];
-            __syncthreads();
+            pass_sync<kCols>();
             ld = SL - a - 3;
             j0 = ((tt >> ld) << (ld + 3)) | (tt & ((1 << ld) - 1));
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) x[kk] = lds[lbase(j0) + loff(kk, ld)];
-            __syncthreads();
+            pass_sync<kCols>();
             ntt_round<3, true>(x, W, Wp, c0, a, tt >> ld, md);
         }
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) lds[lbase(j0) + loff(kk, ld)] = x[kk];
-        __syncthreads();
+        pass_sync<kCols>();
         ld = SL - 3;
         j0 = tt;
 #pragma unroll
@@ -434,7 +452,10 @@ __global__ void __launch_bounds__(kThreads) k_ew(DevTables t, int op, RowMap out
         else if (op == EW_SUB) r = sub_mod(x, pb[i], q);
         else if (op == EW_NEG) r = neg_mod(x, q);
         else if (op == EW_F64C && q < kFp64PrimeBound) r = f64_bits(x > q / 2 ? -(double)(q - x) : (double)x);
-        else r = x;
+        else if (op == EW_F64U && q < kFp64PrimeBound) {
+            const double v = as_f64(x);
+            r = v < 0.0 ? q - (uint64_t)(-v) : (uint64_t)v;
+        } else r = x;
         o[i] = r;
     }
 }
@@ -658,16 +679,51 @@ __device__ __forceinline__ void ks_dot(const KsArgs& a, int b, int kl, int i, ui
     }
 }
 
+// The same inner product for a limb whose prime is below 2^44: the key rows
+// of such a limb hold centred doubles (switching keys are stored that way),
+// every product is exact (fmul_centred, |x| < q < 2^44), and the sums of at
+// most 16 terms (each below 0.6 q in magnitude) stay centred doubles.
+__device__ __forceinline__ void ks_dot_f64(const KsArgs& a, int b, int kl, int i, uint32_t src, int logN,
+                                           const ModF& mf, double& acc0, double& acc1) {
+    const int64_t krow = (int64_t)kl << logN;
+    const uint64_t* pe0 = a.ext + (int64_t)b * a.ext_batch_stride + ((int64_t)kl << logN);
+    const int jown = a.digit_of[kl];
+    int omod;
+    const uint64_t* pown = map_row(a.own, b, kl, logN, omod);
+    acc0 = acc1 = 0.0;
+    for (int j = 0; j < a.n_digits; ++j) {
+        const double x = (double)(j == jown ? __builtin_nontemporal_load(&pown[src])
+                                            : __builtin_nontemporal_load(&pe0[(int64_t)j * a.ext_digit_stride + src]));
+        const uint64_t* pk = a.key + (int64_t)j * a.key_digit_stride + krow;
+        const double w0 = as_f64(pk[i]), w1 = as_f64(pk[i + a.key_poly_stride]);
+        acc0 += fmul_centred(x, w0, w0 * mf.qinv, mf.q);
+        acc1 += fmul_centred(x, w1, w1 * mf.qinv, mf.q);
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) k_ks_inner(DevTables t, RowMap u, KsArgs a, uint32_t g) {
     EW_PROLOGUE(u)
     int mod;
     uint64_t* pu = map_row(u, b, k, logN, mod);
     const Modulus md = t.mods[mod];
+    const int kl = k + a.row0;
+    if (kl < a.n_q && md.q < kFp64PrimeBound) {   // a Q limb with FP64 key rows
+        const ModF mf{(double)md.q, 1.0 / (double)md.q};
+        for (int uu = 0; uu < kEwPerThread; ++uu) {
+            const int i = base_i + uu * kThreads;
+            const uint32_t src = (g == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g, logN);
+            double acc0, acc1;
+            ks_dot_f64(a, b, kl, i, src, logN, mf, acc0, acc1);
+            __builtin_nontemporal_store(f64_canon(acc0, mf), &pu[i]);
+            __builtin_nontemporal_store(f64_canon(acc1, mf), &pu[i + u.poly_stride]);
+        }
+        return;
+    }
     for (int uu = 0; uu < kEwPerThread; ++uu) {
         const int i = base_i + uu * kThreads;
         const uint32_t src = (g == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g, logN);
         uint64_t acc0, acc1;
-        ks_dot(a, b, k + a.row0, i, src, logN, md, acc0, acc1);
+        ks_dot(a, b, kl, i, src, logN, md, acc0, acc1);
         __builtin_nontemporal_store(acc0, &pu[i]);
         __builtin_nontemporal_store(acc1, &pu[i + u.poly_stride]);
     }
@@ -685,6 +741,31 @@ __global__ void __launch_bounds__(kThreads) k_ks_combine(DevTables t, RowMap out
     const Modulus md = t.mods[mod];
     const uint64_t q = md.q;
     const uint64_t c = consts[2 * k], cp = consts[2 * k + 1];
+    if (q < kFp64PrimeBound) {
+        // exact FP64 form: (u - conv) P^-1 with centred doubles, one reduction at the end
+        const ModF mf{(double)q, 1.0 / (double)q};
+        const double cd = (double)c, cq = cd * mf.qinv;
+        for (int uu = 0; uu < kEwPerThread; ++uu) {
+            const int i = base_i + uu * kThreads;
+            const uint32_t src = (g == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g, logN);
+            double u0, u1;
+            ks_dot_f64(a, b, k, i, src, logN, mf, u0, u1);
+            const uint32_t sa = (g_add == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g_add, logN);
+            double r0 = fmul_centred(u0 - (double)__builtin_nontemporal_load(&pc[i]), cd, cq, mf.q);
+            double r1 = fmul_centred(u1 - (double)__builtin_nontemporal_load(&pc[i + conv.poly_stride]), cd, cq, mf.q);
+            if (pa) {
+                r0 += (double)pa[sa];
+                if (add_both) r1 += (double)pa[sa + add.poly_stride];
+            }
+            if (pacc) {
+                r0 += (double)pacc[i];
+                r1 += (double)pacc[i + acc.poly_stride];
+            }
+            __builtin_nontemporal_store(f64_canon(r0, mf), &o[i]);
+            __builtin_nontemporal_store(f64_canon(r1, mf), &o[i + out.poly_stride]);
+        }
+        return;
+    }
     for (int uu = 0; uu < kEwPerThread; ++uu) {
         const int i = base_i + uu * kThreads;
         const uint32_t src = (g == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g, logN);

@@ -1,5 +1,6 @@
 // Internal pieces of the encrypted MF program shared with the serving loop.
 #pragma once
+#include <cmath>
 #include <map>
 #include <utility>
 #include <vector>
@@ -43,21 +44,22 @@ struct MfState {
 
 namespace mfp {
 
-// Scales of the block indicator I0.  Rounding I0's coefficients puts an error
-// of about sqrt(N/24)/S_I on every slot of every mask; a gather (all weights 1)
-// sums D masks, so it takes the larger scale and declares the exact scale of
-// its terms instead of rounding a weight; a scatter needs room for small
-// integer weights (learning rate over degree): 2^24 with the 2^50 table scale,
-// and the self term's common weight applied as a constant so only
-// corrections are masked.
-constexpr double kMaskScale = 16777216.0;          // 2^24, scatter
-constexpr double kGatherMaskScale = 1073741824.0;  // 2^30, gather
-constexpr double kTargetScale = 1099511627776.0;   // 2^40, scale of gathered factors
-// Scale the factor tables are held at (target of a scatter): the scatter
-// weights alpha/d are ~1e-5; their integers are W ~ w 2^26 here, where a 2^40
-// target with 2^20 masks gives W ~ w 2^20 ~ 10, rounded by up to 5 percent
-// the same way every epoch.
-constexpr double kTableScale = 1125899906842624.0; // 2^50
+// Scales of the program, relative to the chain's scale Delta = 2^log2_scale
+// (the values in brackets are those at Delta = 2^40).  Rounding the block
+// indicator I0's coefficients puts an error of about sqrt(N/24)/S_I on every
+// slot of every mask; a gather (all weights 1) sums D masks, so it takes the
+// larger mask scale Delta / 2^10 [2^30] and declares the exact scale of its
+// terms instead of rounding a weight; a scatter needs room for small integer
+// weights (learning rate over degree): masks at Delta / 2^16 [2^24] with the
+// factor tables held at Delta 2^10 [2^50], and the self term's common weight
+// applied as a constant so only corrections are masked.  The scatter weights
+// alpha/d are ~1e-5; their integers are W ~ w 2^26 at any Delta (a target of
+// Delta with masks at Delta / 2^20 would give W ~ 10, rounded by up to 5
+// percent the same way every epoch).  Gathered factors are at Delta.
+inline double mask_scale(const Context* c) { return std::ldexp(1.0, c->prm.log2_scale - 16); }
+inline double gather_mask_scale(const Context* c) { return std::ldexp(1.0, c->prm.log2_scale - 10); }
+inline double target_scale(const Context* c) { return std::ldexp(1.0, c->prm.log2_scale); }
+inline double table_scale(const Context* c) { return std::ldexp(1.0, c->prm.log2_scale + 10); }
 // Refresh of level-exhausted tables: tables below this level are refreshed
 // before the next gather; masks have integer coefficients in [-2^50, 2^50);
 // refreshed table j of round r is encrypted with serial kRefreshSerial + r*1024 + j.

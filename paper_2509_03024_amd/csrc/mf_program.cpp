@@ -211,8 +211,8 @@ void encode_masks(Context* c, int k, std::vector<int64_t>& mask_scatter, std::ve
     for (int f = 0; f < k; ++f) ind[f] = 1.0;
     mask_scatter.assign(c->N, 0);
     mask_gather.assign(c->N, 0);
-    ckks_encode(ind.data(), (int)ind.size(), c->logN, kMaskScale, mask_scatter.data());
-    ckks_encode(ind.data(), (int)ind.size(), c->logN, kGatherMaskScale, mask_gather.data());
+    ckks_encode(ind.data(), (int)ind.size(), c->logN, mask_scale(c), mask_scatter.data());
+    ckks_encode(ind.data(), (int)ind.size(), c->logN, gather_mask_scale(c), mask_gather.data());
 }
 
 void free_masks(Context* c, MfState& m) {
@@ -411,8 +411,8 @@ std::vector<Ct> block_permute_cached(Context* c, MfState& m, const std::vector<C
     const int nl = level + 1;
     const double s_src = srcs.empty() ? 1.0 : srcs[0]->scale;
     const double q_acc = (double)c->moduli[level];
-    const double mask_scale = unit ? kGatherMaskScale : kMaskScale;
-    const double target = unit ? kTargetScale : kTableScale;
+    const double mask_scale = unit ? gather_mask_scale(c) : csrmf::mfp::mask_scale(c);
+    const double target = unit ? target_scale(c) : table_scale(c);
     const uint64_t* mask = unit ? m.maskg : m.mask0;
     if (!mask) throw Error(CSRMF_E_STATE, "block masks not uploaded");
     double acc_scale = target * q_acc;
@@ -659,8 +659,8 @@ std::vector<Ct> block_permute(Context* c, MfState& m, const std::vector<Ct*>& sr
     const int nl = level + 1;
     const double s_src = srcs.empty() ? 1.0 : srcs[0]->scale;
     const double q_acc = (double)c->moduli[level];
-    const double mask_scale = unit ? kGatherMaskScale : kMaskScale;
-    const double target = unit ? kTargetScale : kTableScale;
+    const double mask_scale = unit ? gather_mask_scale(c) : csrmf::mfp::mask_scale(c);
+    const double target = unit ? target_scale(c) : table_scale(c);
     const uint64_t* mask = unit ? m.maskg : m.mask0;
     if (!mask) throw Error(CSRMF_E_STATE, "block masks not uploaded");
     double acc_scale = target * q_acc;

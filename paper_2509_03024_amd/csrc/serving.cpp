@@ -367,12 +367,12 @@ void Server::process(std::vector<ServeRequest*>& batch) {
             }
             const int lvl = tot.level;
             const double q_acc = (double)c->moduli[lvl];
-            const double target = mfp::kTargetScale * q_acc;
+            const double target = mfp::target_scale(c) * q_acc;
             const double d = (double)r->items.size();
             Ct self = Ug[upd[kv.second[0]]];
             self.level = lvl;
-            const int64_t Ws = (int64_t)std::nearbyint(((1.0 - lr * lam) * mfp::kTargetScale * q_acc) / self.scale);
-            const int64_t Wg = (int64_t)std::nearbyint(((lr / d) * mfp::kTargetScale * q_acc) / tot.scale);
+            const int64_t Ws = (int64_t)std::nearbyint(((1.0 - lr * lam) * mfp::target_scale(c) * q_acc) / self.scale);
+            const int64_t Wg = (int64_t)std::nearbyint(((lr / d) * mfp::target_scale(c) * q_acc) / tot.scale);
             Ct a, b, out;
             c->mul_int(self, Ws, a, target);
             c->mul_int(tot, Wg, b, target);

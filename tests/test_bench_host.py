@@ -66,6 +66,9 @@ def test_rotation_model_hand_counts():
     # terms into 60-bit targets: every digit into the 3 special primes, digits 1
     # and 2 into q_0, and ModDown's 3 special limbs into q_0 for both polynomials
     assert m["conv_macs_int"] == (1 << 16) * ((9 + 9 + 6) * 3 + (9 + 6) + 2 * 3)
+    # inner products on the 3 special limbs and q_0, both key polynomials, 3 digits
+    assert m["inner_mults_int"] == (1 << 16) * 3 * 4 * 2
+    assert m["scale_mults_int"] == (1 << 16) * 2
 
 
 def test_traffic_of_an_unmeasured_kernel_is_null():

@@ -46,3 +46,42 @@ def test_rmse_per_iteration_follows_fp64(pairs):
     assert np.max(np.abs(np.array(enc) - np.array(ref))) < 1e-3
     assert enc[-1] < enc[0] < r0
     ctx.close()
+
+
+def _curve_at_scale(bits, iters, csr, U0, V0):
+    import paper_2509_03024_amd as pk
+    ctx = pk.Context(pk.params(15, 60, 16, bits, 3, 60, 5, bits, k=K, lr=LR, lam=LAM, rule=1, refresh_mode=1),
+                     workloads.CRYPTO_SEED)
+    ctx.keygen([])
+    m = pk.MF(ctx)
+    m.encrypt_csr_rows(csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx, csr.values)
+    m.init_factors(U0, V0)
+    out = []
+    for _ in range(iters):
+        m.epochs(1)
+        U, V = m.decrypt_factors()
+        out.append(mf.rmse(mf.predict(U, V, csr.row_ptr, csr.col_idx), csr.values))
+    ctx.close()
+    return np.array(out)
+
+
+def test_precision_effect_of_the_scale():
+    """The precision experiment of Sec. IV-D (Fig. 8's question, at the scales
+    this program supports): without batching, the chain's scale Delta =
+    2^26, 2^32, 2^40 with scale primes of that size (the program's masks and
+    tables scale with Delta).  The RMSE after every iteration is ordered by
+    precision (a smaller Delta never does better), Delta = 2^40 stays within
+    1e-3 of FP64 and Delta = 2^32 within 2e-2."""
+    csr = workloads.movielens100k_shaped()
+    U0, V0 = workloads.init_factors(csr.n_rows, csr.n_cols, K)
+    iters = 10
+    Uf, Vf, ref = U0, V0, []
+    for t in range(iters):
+        Uf, Vf, _ = mf.epoch(Uf, Vf, csr.row_ptr, csr.col_idx, csr.values, LR, LAM, t, 0.0, "R1")
+        ref.append(mf.rmse(mf.predict(Uf, Vf, csr.row_ptr, csr.col_idx), csr.values))
+    ref = np.array(ref)
+    c26, c32, c40 = (_curve_at_scale(b, iters, csr, U0, V0) for b in (26, 32, 40))
+    print("Delta 2^26", np.round(c26, 6), "2^32", np.round(c32, 6), "2^40", np.round(c40, 6))
+    assert np.max(np.abs(c40 - ref)) < 1e-3
+    assert np.max(np.abs(c32 - ref)) < 2e-2
+    assert np.all(c32 >= c40 - 1e-5) and np.all(c26 >= c32 - 1e-5)
