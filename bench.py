@@ -52,14 +52,18 @@ MODMUL_RATE = {"shoup_u64": 1.927e12, "montgomery_u64": 1.318e12, "fp64_exact": 
 # counters were taken on.  Under another schedule the launches differ in size
 # and the measured bytes are scaled by the algorithmic bytes (traffic_basis).
 TRAFFIC = {
+    "k_ntt_pass<rows,fwd>": {"bytes": 1.494e+09, "alg_bytes": 7.355e+08, "schedule": 2048},
     "k_ntt_pass<cols,fwd>": {"bytes": 1.472e+09, "alg_bytes": 7.356e+08, "schedule": 2048},
+    "k_ntt_pass<rows,inv>": {"bytes": 1.065e+09, "alg_bytes": 5.251e+08, "schedule": 2048},
     "k_ntt_pass<cols,inv>": {"bytes": 1.051e+09, "alg_bytes": 5.251e+08, "schedule": 2048},
     "k_basis_convert": {"bytes": 1.175e+09, "alg_bytes": 1.174e+09, "schedule": None},
+    "k_ks_combine": {"bytes": 7.798e+09, "alg_bytes": 8.319e+09, "schedule": None},
+    "k_ks_inner": {"bytes": 5.128e+08, "alg_bytes": 5.128e+08, "schedule": None},
 }
 # Counter bytes (FETCH_SIZE + WRITE_SIZE, scaled as above) of a whole step of
 # the kernel-batch workload (transform phase, HMult phase and rotation phase),
 # from the same counter runs; None once the kernels have changed.
-KS_COUNTER_BYTES_PER_STEP = None
+KS_COUNTER_BYTES_PER_STEP = 575.7e9
 
 
 def traffic_of(name, schedule, alg_bytes):
@@ -718,6 +722,20 @@ def bench_ks(args):
     ctx.sync()
     plain_rate = PLAIN_CT * (len(CHAIN) + 1) / (time.perf_counter() - t_pl)
     log(f"plain path {plain_rate:.1f} rotations/s")
+    # hoisted fan-out: one ModUp per source, then its 15 rotations by 2^0..2^14
+    # (16 sources, one call each)
+    ctx.sync()
+    t0 = time.perf_counter()
+    fan = []
+    for i in range(16):
+        fan += ctx.rotate_hoisted(cts[i], CHAIN)
+    ctx.sync()
+    t_fan = time.perf_counter() - t0
+    for h in fan:
+        ctx.free(h)
+    hoisted = {"what": "16 sources, each rotated by 2^0..2^14 from one ModUp (csrmf_rotate_hoisted)",
+               "rotations_per_s": round(len(fan) / t_fan, 2)}
+    log(f"hoisted fan-out {hoisted['rotations_per_s']} rotations/s")
     torch.cuda.synchronize()
     ctx.sync()
     pk.profile_enable(True)
@@ -786,6 +804,7 @@ def bench_ks(args):
                            "what": "same rotate-and-sum chain, one ciphertext per call",
                            "batched_rotation_phase_speedup": round(rot_rate / plain_rate, 2)},
         "graph_path": graph,
+        "hoisted_fan_out": hoisted,
         "roofline": dominant_roofline(prof, schedule),
         "ks_roofline": ks_roof,
         "kernels": kernel_table(prof),

@@ -21,9 +21,10 @@
 //   acc_d = sum_gamma Rot_{gamma G B}( sum_{c,beta} Rot_{beta B}(src_c) (.) M_{d,c,gamma,beta} )
 //   M = sum_moves W * tau_{g_p}(I0), p = (b + gamma G) mod D, g_p = 5^((-pB) mod N/2),
 //   W = rint((w * S_t * q_ell) / (S_src * S_I)); one rescale per destination.
-//   Scatter: S_I = 2^24, S_t = 2^50 (the tables' scale), self term as a constant
-//   plus masked corrections; gather: S_I = 2^30, S_t = 2^40, the accumulator
-//   declared at the exact scale of its terms (all weights are 1).
+//   With Delta the chain's scale: scatter S_I = Delta / 2^16, S_t = Delta 2^10
+//   (the tables' scale), self term as a constant plus masked corrections;
+//   gather S_I = Delta / 2^10, S_t = Delta, the accumulator declared at the
+//   exact scale of its terms (all weights are 1).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
