@@ -88,9 +88,10 @@ typedef struct csrmf_params {
                             /* 1 = user-item batch pairs (Alg. 2, Sec. III-D)   */
 } csrmf_params;
 
-/* Create a context: derives the prime chain and roots, uploads the transform
- * tables to the current HIP device.  seed is the 32-byte ChaCha20 master key
- * from which every random polynomial is drawn.
+/* Create a context (the "encryption context" Alg. 1 takes as input; the CKKS
+ * scheme of Sec. II-A.2): derives the prime chain and roots, uploads the
+ * transform tables to the current HIP device.  seed is the 32-byte ChaCha20
+ * master key from which every random polynomial is drawn.
  * Errors: INVAL (N out of range, not enough primes, k' = 2^ceil(log2 k) too
  * large for the slots), NOMEM, DEVICE. */
 int csrmf_create(const csrmf_params* p, const uint8_t seed[32], csrmf_ctx** out);
@@ -492,15 +493,19 @@ int csrmf_mf_epochs(csrmf_ctx* ctx, int32_t n_epochs);
 int csrmf_set_baby_budget(csrmf_ctx* ctx, int32_t max_babies);
 
 /* Encrypted predictions r_hat = <u_i, v_j> on the observed ratings from the
- * current factor tables (gather + product + windowed sum).  Errors: LEVEL. */
+ * current factor tables (gather + product + windowed sum): Alg. 1's encrypted
+ * R_hat = U V^T restricted to the rated cells, the set Eq. 10 is evaluated on.
+ * Errors: LEVEL. */
 int csrmf_predict(csrmf_ctx* ctx);
 
-/* Decrypt the factor tables: U[n_rows*k], V[n_cols*k] row-major. */
+/* Decrypt the factor tables (the key holder's decryption, Sec. III-B,
+ * recommendation phase): U[n_rows*k], V[n_cols*k] row-major.  Errors: STATE. */
 int csrmf_decrypt_factors(csrmf_ctx* ctx, double* U, double* V);
 
-/* Decrypt predictions on the observed ratings, in CSR order, into rhat[nnz]:
+/* Decrypt predictions on the observed ratings (Sec. III-B, recommendation
+ * phase; the r_hat of Eq. 10), in CSR order, into rhat[nnz]:
  * which = 0: the forward predictions of the last epoch (epoch-start factors);
- * which = 1: the output of csrmf_predict. */
+ * which = 1: the output of csrmf_predict.  Errors: STATE, INVAL. */
 int csrmf_decrypt_predictions(csrmf_ctx* ctx, double* rhat, int32_t which);
 
 /* Progress of the MF program since csrmf_init_factors: epochs run, table

@@ -233,3 +233,19 @@ def test_choose_G_counts():
     assert program.choose_G(gather, D) == 16
     # scatter: G=1 costs 0 + 63, G=2 costs 32 + 31 (tie -> smaller), G=4 costs 96 + 15
     assert program.choose_G(scatter, D) == 1
+
+
+def test_layout_of_the_degenerate_matrix():
+    """workloads.edge_ratings() at N = 2^12, k = 1 (B = 2, D = 1024): the
+    single rating of user 1 opens ciphertext 0, user 2's 1030 ratings do not
+    fit beside it and are cut into a chunk of 1024 (ciphertext 1) and one of 6
+    (ciphertext 2, which users 4, 5 and 7 then fill to 12 blocks); empty rows
+    take no blocks; one user table, two item tables."""
+    csr = workloads.edge_ratings()
+    lay = program.make_layout(1 << 12, 1, csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx)
+    assert (lay.B, lay.D, lay.n_ct, lay.n_utab, lay.n_vtab) == (2, 1024, 3, 1, 2)
+    ct = np.asarray(lay.ct_of)
+    blk = np.asarray(lay.blk_of)
+    assert ct[0] == 0 and blk[0] == 0                                  # user 1
+    assert np.all(ct[1:1025] == 1) and np.array_equal(blk[1:1025], np.arange(1024))
+    assert np.all(ct[1025:] == 2) and np.array_equal(blk[1025:], np.arange(12))

@@ -44,6 +44,21 @@ def tiny_ratings(seed=0, n=32, m=64, density=0.10):
     return _csr_from_cells(n, m, cells // m, cells % m, vals)
 
 
+def edge_ratings():
+    """8 users x 1100 items with the degenerate shapes of a CSR matrix: empty
+    rows (users 0, 3, 6), single-rating rows (1, 7), a row of 1030 ratings
+    (longer than the 1024 blocks of one ciphertext at N = 2^12, k = 1, so it is
+    cut in chunks of 1024 and 6), short rows (4, 5), empty columns
+    (1030..1097), and the first and last item; ratings uniform integers 1..5
+    (numpy PCG64 seed 3)."""
+    rng = np.random.default_rng(3)
+    rows_items = {1: [5], 2: list(range(1030)), 4: [7, 1098, 1099], 5: [17, 1029], 7: [1099]}
+    rows = np.concatenate([np.full(len(v), u) for u, v in rows_items.items()])
+    cols = np.concatenate([np.asarray(v) for v in rows_items.values()])
+    vals = rng.integers(1, 6, size=len(rows)).astype(np.float64)
+    return _csr_from_cells(8, 1100, rows, cols, vals)
+
+
 def init_factors(n, m, k, seed=1, sigma=0.1):
     rng = np.random.default_rng(seed)
     return rng.normal(0.0, sigma, (n, k)), rng.normal(0.0, sigma, (m, k))
