@@ -47,15 +47,17 @@ MODMUL_RATE = {"shoup_u64": 1.927e12, "montgomery_u64": 1.318e12, "fp64_exact": 
                "fp64_split_mac": 9.624e12}
 # HBM bytes per launch of a kernel in the timed step (average over the step's
 # launches), from rocprofv3 FETCH_SIZE + WRITE_SIZE counters scaled by a 512 MiB
-# copy (profiles/), with the NTT schedule (rows per pair of passes) of that run
-# and the algorithmic bytes of its launches; only valid for the kernel code the
-# counters were taken on.  Under another schedule the launches differ in size
-# and the measured bytes are scaled by the algorithmic bytes (traffic_basis).
+# copy (profiles/), with the NTT schedule (rows per pair of passes) and the
+# split of the transform's stages between its passes of that run, and the
+# algorithmic bytes of its launches; only valid for the kernel code the
+# counters were taken on.  Under another number of rows the launches differ in
+# size and the measured bytes are scaled by the algorithmic bytes
+# (traffic_basis); under another split they were not measured (None).
 TRAFFIC = {
-    "k_ntt_pass<rows,fwd>": {"bytes": 1.494e+09, "alg_bytes": 7.355e+08, "schedule": 2048},
-    "k_ntt_pass<cols,fwd>": {"bytes": 1.472e+09, "alg_bytes": 7.356e+08, "schedule": 2048},
-    "k_ntt_pass<rows,inv>": {"bytes": 1.065e+09, "alg_bytes": 5.251e+08, "schedule": 2048},
-    "k_ntt_pass<cols,inv>": {"bytes": 1.051e+09, "alg_bytes": 5.251e+08, "schedule": 2048},
+    "k_ntt_pass<rows,fwd>": {"bytes": 1.494e+09, "alg_bytes": 7.355e+08, "schedule": 2048, "split": 8},
+    "k_ntt_pass<cols,fwd>": {"bytes": 1.472e+09, "alg_bytes": 7.356e+08, "schedule": 2048, "split": 8},
+    "k_ntt_pass<rows,inv>": {"bytes": 1.065e+09, "alg_bytes": 5.251e+08, "schedule": 2048, "split": 8},
+    "k_ntt_pass<cols,inv>": {"bytes": 1.051e+09, "alg_bytes": 5.251e+08, "schedule": 2048, "split": 8},
     "k_basis_convert": {"bytes": 1.175e+09, "alg_bytes": 1.174e+09, "schedule": None},
     "k_ks_combine": {"bytes": 7.798e+09, "alg_bytes": 8.319e+09, "schedule": None},
     "k_ks_inner": {"bytes": 5.128e+08, "alg_bytes": 5.128e+08, "schedule": None},
@@ -67,15 +69,20 @@ KS_COUNTER_BYTES_PER_STEP = 575.7e9
 
 
 def traffic_of(name, schedule, alg_bytes):
+    """Measured HBM bytes per launch of kernel `name` under `schedule`
+    ((NTT rows per pair of passes, column-pass stages)), with their basis."""
     t = TRAFFIC.get(name)
     if t is None:
         return None, None
     if t["schedule"] is None:
         return t["bytes"], "rocprofv3 counters"
-    if t["schedule"] == schedule:
-        return t["bytes"], f"rocprofv3 counters at NTT schedule {schedule}"
+    rows, split = schedule
+    if split != t["split"]:
+        return None, f"not measured at NTT split {split} (counters taken at split {t['split']})"
+    if t["schedule"] == rows:
+        return t["bytes"], f"rocprofv3 counters at NTT schedule {rows}"
     return round(t["bytes"] / t["alg_bytes"] * alg_bytes), \
-        f"rocprofv3 counters at NTT schedule {t['schedule']}, scaled by algorithmic bytes to schedule {schedule}"
+        f"rocprofv3 counters at NTT schedule {t['schedule']}, scaled by algorithmic bytes to schedule {rows}"
 
 
 def parse():
@@ -93,6 +100,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--ntt-chunk", type=int, default=None,
                     help="fix the NTT schedule (rows per pair of passes) instead of autotuning (for profiles)")
+    ap.add_argument("--ntt-split", type=int, default=None,
+                    help="with --ntt-chunk: butterfly stages of the NTT's column pass (default log2 N / 2)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the HIP-graph replay, so that the timed steps end the run (profiles)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -387,7 +396,7 @@ def kernel_table(prof):
             for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
 
 
-def dominant_roofline(prof, schedule=None):
+def dominant_roofline(prof, schedule):
     """Roofline entry of the kernel with the largest total time: algorithmic
     bytes per launch over its average launch duration (HIP events on the
     library's stream), against the HBM peak."""
@@ -440,6 +449,7 @@ def run_mf(which, epochs, ntt_chunk=None):
         ctx.set_ntt_schedule(ntt_chunk)
     else:
         ctx.autotune()
+    sched = ctx.schedule()
     m = pk.MF(ctx)
     n_ct = m.encrypt_csr_rows(csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx, csr.values)
     m.init_factors(U0, V0)
@@ -474,7 +484,7 @@ def run_mf(which, epochs, ntt_chunk=None):
                                f"{n_ct} rating ciphertexts, rule R2, {epochs} epochs "
                                f"({st['refreshes']} table refreshes)"},
         "rmse_last_forward": round(rmse, 5),
-        "roofline": dominant_roofline(prof),
+        "roofline": dominant_roofline(prof, (sched["ntt_chunk_rows"], sched["ntt_split"])),
         "kernels": kernel_table(prof),
         "masked_mac": mac_summary(mac, prof, 1 << prm.log2N),
     }
@@ -640,12 +650,12 @@ def bench_ks(args):
     ctx.keygen(CHAIN, conj=True)
     log(f"context + keys {time.perf_counter() - t0:.1f} s")
     if args.ntt_chunk is not None:
-        ctx.set_ntt_schedule(args.ntt_chunk)
+        ctx.set_schedule(args.ntt_chunk, 0, 0, args.ntt_split or 0)
         tune = {"fixed": args.ntt_chunk}
-        schedule = args.ntt_chunk
     else:
         tune = ctx.autotune()
-        schedule = tune["chosen"]
+    sched = ctx.schedule()
+    schedule = (sched["ntt_chunk_rows"], sched["ntt_split"])
     log(f"schedule {tune}")
     N = ctx.N
     L = ctx.L

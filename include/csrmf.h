@@ -339,7 +339,8 @@ void csrmf_server_destroy(csrmf_server* s);
 /* ------------------------------------------------------------------------ */
 
 /* Time the candidate NTT schedules (rows transformed per pair of passes, the
- * intermediate cached or streamed) on `rows` limbs of this context's ring
+ * intermediate cached or streamed, the split of the stages between the two
+ * passes) on `rows` limbs of this context's ring
  * (0: 64 ciphertexts x 2 x (L+1) limbs, the batched key-switching shape) and,
  * if the context has a rotation key, the ModUp sub-batch sizes on one batched
  * rotation of up to 64 zero ciphertexts, with HIP events, and keep the
@@ -358,11 +359,18 @@ int csrmf_set_ntt_schedule(csrmf_ctx* ctx, int32_t chunk_rows);
  * the caches (1) or is streamed past them (0), and ciphertexts per ModUp
  * sub-batch of a key switch (0: the whole batch; a sub-batch runs its inverse
  * transform, conversions and forward transforms before the next, so a small
- * one keeps each stage's output in the last-level cache).  Results do not
- * depend on the schedule.  csrmf_autotune chooses all three (the ModUp
- * sub-batch only when the context has a rotation key).  Errors: INVAL. */
-int csrmf_set_schedule(csrmf_ctx* ctx, int32_t ntt_chunk_rows, int32_t ntt_cached_mid, int32_t modup_chunk);
-int csrmf_get_schedule(const csrmf_ctx* ctx, int32_t* ntt_chunk_rows, int32_t* ntt_cached_mid, int32_t* modup_chunk);
+ * one keeps each stage's output in the last-level cache), and the split of
+ * the transform into its two passes: ntt_split of the log2 N butterfly
+ * stages in the column pass, the rest in the row pass, each pass taking 6 to
+ * 9 (0: log2 N / 2; a column pass of s stages reads runs of 2^(12-s)
+ * consecutive residues).  Results do not depend on the schedule.
+ * csrmf_autotune chooses all four (the ModUp sub-batch only when the context
+ * has a rotation key).  Errors: INVAL (a negative value, a split outside
+ * that range). */
+int csrmf_set_schedule(csrmf_ctx* ctx, int32_t ntt_chunk_rows, int32_t ntt_cached_mid, int32_t modup_chunk,
+                       int32_t ntt_split);
+int csrmf_get_schedule(const csrmf_ctx* ctx, int32_t* ntt_chunk_rows, int32_t* ntt_cached_mid, int32_t* modup_chunk,
+                       int32_t* ntt_split);
 
 /* ------------------------------------------------------------------------ */
 /* HIP graphs of evaluation sequences.                                       */

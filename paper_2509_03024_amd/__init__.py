@@ -111,12 +111,12 @@ _SIGS = {
     "csrmf_set_ntt_schedule": [_p, ctypes.c_int32],
     "csrmf_rotate_noalloc": [_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint64],
     "csrmf_set_baby_budget": [_p, ctypes.c_int32],
-    "csrmf_set_schedule": [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "csrmf_set_schedule": [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "csrmf_graph_begin": [_p],
     "csrmf_graph_end": [_p, _u64p],
     "csrmf_graph_launch": [_p, ctypes.c_uint64],
     "csrmf_graph_destroy": [_p, ctypes.c_uint64],
-    "csrmf_get_schedule": [_p, _i32p, _i32p, _i32p],
+    "csrmf_get_schedule": [_p, _i32p, _i32p, _i32p, _i32p],
     "csrmf_counters": [_p, ctypes.POINTER(ctypes.c_int64)],
     "csrmf_protocol_ingest": [_p, ctypes.c_int32, ctypes.c_int32, _i64p, _i32p, _dp, _i32p],
     "csrmf_protocol_recommend": [_p, ctypes.c_int32, _dp],
@@ -343,14 +343,15 @@ class Context:
     def graph_destroy(self, g):
         self._chk(lib.csrmf_graph_destroy(self.h, g))
 
-    def set_schedule(self, ntt_chunk_rows=0, ntt_cached_mid=0, modup_chunk=0):
+    def set_schedule(self, ntt_chunk_rows=0, ntt_cached_mid=0, modup_chunk=0, ntt_split=0):
         """Fix this context's whole schedule (see csrmf_set_schedule)."""
-        self._chk(lib.csrmf_set_schedule(self.h, int(ntt_chunk_rows), int(ntt_cached_mid), int(modup_chunk)))
+        self._chk(lib.csrmf_set_schedule(self.h, int(ntt_chunk_rows), int(ntt_cached_mid), int(modup_chunk),
+                                         int(ntt_split)))
 
     def schedule(self):
-        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        self._chk(lib.csrmf_get_schedule(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return {"ntt_chunk_rows": a.value, "ntt_cached_mid": b.value, "modup_chunk": c.value}
+        a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._chk(lib.csrmf_get_schedule(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        return {"ntt_chunk_rows": a.value, "ntt_cached_mid": b.value, "modup_chunk": c.value, "ntt_split": d.value}
 
     def counters(self):
         """{"key_switches": relinearisations and rotations enqueued so far}."""

@@ -441,22 +441,28 @@ int csrmf_set_ntt_schedule(csrmf_ctx* cx, int32_t chunk_rows) {
     API_END(c)
 }
 
-int csrmf_set_schedule(csrmf_ctx* cx, int32_t ntt_chunk_rows, int32_t ntt_cached_mid, int32_t modup_chunk) {
+int csrmf_set_schedule(csrmf_ctx* cx, int32_t ntt_chunk_rows, int32_t ntt_cached_mid, int32_t modup_chunk,
+                       int32_t ntt_split) {
     Context* c = reinterpret_cast<Context*>(cx);
     API_BEGIN(c)
     NEED(ntt_chunk_rows >= 0 && modup_chunk >= 0 && (ntt_cached_mid == 0 || ntt_cached_mid == 1), "schedule values");
+    const int l1 = ntt_split ? ntt_split : c->tabs.logN / 2;
+    NEED(csrmf::ntt_split_valid(c->tabs.logN, l1), "NTT split: both passes need 6 to 9 stages");
     c->tabs.ntt_chunk_rows = ntt_chunk_rows;
     c->tabs.ntt_cached_mid = ntt_cached_mid;
+    c->tabs.L1 = l1;
     c->modup_chunk = modup_chunk;
     API_END(c)
 }
 
-int csrmf_get_schedule(const csrmf_ctx* cx, int32_t* ntt_chunk_rows, int32_t* ntt_cached_mid, int32_t* modup_chunk) {
+int csrmf_get_schedule(const csrmf_ctx* cx, int32_t* ntt_chunk_rows, int32_t* ntt_cached_mid, int32_t* modup_chunk,
+                       int32_t* ntt_split) {
     const Context* c = reinterpret_cast<const Context*>(cx);
     if (!c) return CSRMF_E_INVAL;
     if (ntt_chunk_rows) *ntt_chunk_rows = c->tabs.ntt_chunk_rows;
     if (ntt_cached_mid) *ntt_cached_mid = c->tabs.ntt_cached_mid;
     if (modup_chunk) *modup_chunk = c->modup_chunk;
+    if (ntt_split) *ntt_split = c->tabs.L1;
     return CSRMF_OK;
 }
 

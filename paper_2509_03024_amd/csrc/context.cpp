@@ -1303,33 +1303,41 @@ std::string Context::autotune(int rows) {
     CSRMF_HIP(hipEventCreate(&a));
     CSRMF_HIP(hipEventCreate(&b));
     const int cands[] = {0, 64, 128, 256, 512, 1024, 2048};
-    int best = 0, best_cached = 0;
+    const int half = logN / 2;
+    int best = 0, best_cached = 0, best_split = half;
     float best_ms = 1e30f;
     std::string rep = "{";
-    for (int cached = 0; cached < 2; ++cached) {
-        for (int cnd : cands) {
-            tabs.ntt_chunk_rows = cnd;
-            tabs.ntt_cached_mid = cached;
-            launch_ntt(tabs, m, false, stream);     // warm
-            launch_ntt(tabs, m, true, stream);
-            CSRMF_HIP(hipEventRecord(a, stream));
-            for (int r = 0; r < 3; ++r) {
-                launch_ntt(tabs, m, false, stream);
+    for (int split = half - 1; split <= half + 1; ++split) {
+        if (!ntt_split_valid(logN, split)) continue;
+        tabs.L1 = split;
+        for (int cached = 0; cached < 2; ++cached) {
+            for (int cnd : cands) {
+                tabs.ntt_chunk_rows = cnd;
+                tabs.ntt_cached_mid = cached;
+                launch_ntt(tabs, m, false, stream);     // warm
                 launch_ntt(tabs, m, true, stream);
+                CSRMF_HIP(hipEventRecord(a, stream));
+                for (int r = 0; r < 3; ++r) {
+                    launch_ntt(tabs, m, false, stream);
+                    launch_ntt(tabs, m, true, stream);
+                }
+                CSRMF_HIP(hipEventRecord(b, stream));
+                CSRMF_HIP(hipEventSynchronize(b));
+                float ms = 0;
+                CSRMF_HIP(hipEventElapsedTime(&ms, a, b));
+                ms /= 3;
+                rep += (rep.size() > 1 ? ", " : "") + std::string("\"ntt_split=") + std::to_string(split) +
+                       ",ntt_chunk_rows=" + std::to_string(cnd) + (cached ? ",cached_mid" : "") + "\": " +
+                       std::to_string(ms);
+                if (ms < best_ms) { best_ms = ms; best = cnd; best_cached = cached; best_split = split; }
             }
-            CSRMF_HIP(hipEventRecord(b, stream));
-            CSRMF_HIP(hipEventSynchronize(b));
-            float ms = 0;
-            CSRMF_HIP(hipEventElapsedTime(&ms, a, b));
-            ms /= 3;
-            rep += (rep.size() > 1 ? ", " : "") + std::string("\"ntt_chunk_rows=") + std::to_string(cnd) +
-                   (cached ? ",cached_mid" : "") + "\": " + std::to_string(ms);
-            if (ms < best_ms) { best_ms = ms; best = cnd; best_cached = cached; }
         }
     }
     tabs.ntt_chunk_rows = best;
     tabs.ntt_cached_mid = best_cached;
-    rep += ", \"chosen\": " + std::to_string(best) + ", \"cached_mid\": " + std::to_string(best_cached);
+    tabs.L1 = best_split;
+    rep += ", \"chosen\": " + std::to_string(best) + ", \"cached_mid\": " + std::to_string(best_cached) +
+           ", \"ntt_split\": " + std::to_string(best_split);
     // ModUp sub-batch: time one batched rotation of scratch ciphertexts under
     // each candidate (needs a rotation key; the data does not matter)
     if (!rot.empty()) {

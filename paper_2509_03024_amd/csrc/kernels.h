@@ -46,13 +46,18 @@ constexpr int kBcRecordWords(int ns) { return 2 * ns + 8; }
 // Device-resident tables of the modulus chain.
 struct DevTables {
     int logN;
-    int L1;                      // stages done by the column pass
+    int L1;                      // stages done by the column pass (NTT schedule; ntt_split_valid)
     const Modulus* mods;         // [n_mod]
     const uint64_t* tw;          // [n_mod][4][N]: psi^brev, shoup, psi^-brev, shoup
                                  // (FP64 primes: as doubles, w then fl(w/q))
     int ntt_chunk_rows = 0;      // NTT schedule (host side): rows per pair of passes, 0 = the whole batch
     int ntt_cached_mid = 0;      // NTT schedule: the intermediate between the passes goes through the caches
 };
+
+// A pass holds 2^6 to 2^9-point sub-transforms (a rows sub-transform within
+// one wave), so the column pass may take L1 stages when both L1 and
+// logN - L1 lie in 6..9.  The transform's output does not depend on L1.
+inline bool ntt_split_valid(int logN, int L1) { return L1 >= 6 && L1 <= 9 && logN - L1 >= 6 && logN - L1 <= 9; }
 
 void launch_ntt(const DevTables& t, const RowMap& rows, bool inverse, hipStream_t s);
 // The same transform of rows that are read from `src` (same shape; its first

@@ -412,7 +412,8 @@ void dispatch_ntt_pass(const DevTables& t, const RowMap& m, const RowMap& src, b
         case 6: launch_ntt_pass<6>(t, m, src, cols, inverse, blocks, s); break;
         case 7: launch_ntt_pass<7>(t, m, src, cols, inverse, blocks, s); break;
         case 8: launch_ntt_pass<8>(t, m, src, cols, inverse, blocks, s); break;
-        default: break;   // log2N is validated to [12, 16] at context creation
+        case 9: launch_ntt_pass<9>(t, m, src, cols, inverse, blocks, s); break;
+        default: break;   // both passes are validated to 6..9 stages (ntt_split_valid)
     }
 }
 

@@ -15,7 +15,7 @@ def _bench():
     return mod
 
 
-_T = {"k_ntt_pass<rows,fwd>": {"schedule": 2048, "bytes": 1500.0e6, "alg_bytes": 1471.1e6},
+_T = {"k_ntt_pass<rows,fwd>": {"schedule": 2048, "split": 8, "bytes": 1500.0e6, "alg_bytes": 1471.1e6},
       "k_basis_convert": {"schedule": None, "bytes": 1174.6e6, "alg_bytes": 1174.4e6}}
 
 
@@ -24,10 +24,10 @@ def test_traffic_at_the_measured_schedule_is_the_measurement():
     b.TRAFFIC = dict(_T)
     for name, t in b.TRAFFIC.items():
         if t["schedule"] is None:
-            val, basis = b.traffic_of(name, 512, t["alg_bytes"])
+            val, basis = b.traffic_of(name, (512, 8), t["alg_bytes"])
             assert val == t["bytes"] and basis == "rocprofv3 counters"
         else:
-            val, basis = b.traffic_of(name, t["schedule"], t["alg_bytes"])
+            val, basis = b.traffic_of(name, (t["schedule"], t["split"]), t["alg_bytes"])
             assert val == t["bytes"] and str(t["schedule"]) in basis
 
 
@@ -37,16 +37,26 @@ def test_traffic_under_another_schedule_scales_with_the_launch():
     name, t = next((n, t) for n, t in b.TRAFFIC.items() if t["schedule"] is not None)
     other = 64 if t["schedule"] != 64 else 128
     half = t["alg_bytes"] / 2
-    val, basis = b.traffic_of(name, other, half)
+    val, basis = b.traffic_of(name, (other, t["split"]), half)
     assert abs(val - t["bytes"] / 2) <= 1.0
     assert "scaled" in basis and str(other) in basis
+
+
+def test_traffic_under_another_split_is_not_measured():
+    """A different split of the transform's stages changes the passes' access
+    pattern: their counters do not carry over."""
+    b = _bench()
+    b.TRAFFIC = dict(_T)
+    t = b.TRAFFIC["k_ntt_pass<rows,fwd>"]
+    val, basis = b.traffic_of("k_ntt_pass<rows,fwd>", (t["schedule"], t["split"] + 1), t["alg_bytes"])
+    assert val is None and "not measured" in basis
 
 
 def test_measured_traffic_entries_are_consistent():
     b = _bench()
     for name, t in b.TRAFFIC.items():
         assert t["bytes"] > 0 and t["alg_bytes"] > 0
-        assert t["schedule"] is None or t["schedule"] > 0
+        assert t["schedule"] is None or (t["schedule"] > 0 and 6 <= t["split"] <= 9)
 
 
 def test_rotation_model_hand_counts():
@@ -73,7 +83,7 @@ def test_rotation_model_hand_counts():
 
 def test_traffic_of_an_unmeasured_kernel_is_null():
     b = _bench()
-    assert b.traffic_of("k_not_measured", 2048, 1e9) == (None, None)
+    assert b.traffic_of("k_not_measured", (2048, 8), 1e9) == (None, None)
 
 
 def test_mac_summary_rates():

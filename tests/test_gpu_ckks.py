@@ -49,6 +49,8 @@ def test_chain_matches_oracle(pair):
 
 @pytest.mark.parametrize("logN", [12, 15, 16])
 def test_forward_ntt_is_evaluation_in_bit_reversed_order(logN):
+    """Every split of the butterfly stages between the two passes (6 to 9
+    stages each) gives the oracle's transform, and the inverse undoes it."""
     import paper_2509_03024_amd as pk
     prm = {12: params.config_tiny, 15: params.config_mf_n15, 16: params.config_kernel_batch}[logN]()
     lp = {12: pk.tiny_params(), 15: pk.mf_n15_params(), 16: pk.kernel_batch_params()}[logN]
@@ -57,16 +59,23 @@ def test_forward_ntt_is_evaluation_in_bit_reversed_order(logN):
     mods = prm.moduli
     limbs = [0, 1, len(prm.q) - 1, len(mods) - 1]
     x = workloads.random_residues([mods[i] for i in limbs], N, 2, seed=logN)   # [2][4][N]
-    t = to_device_u64(x.reshape(-1, N))
-    lib.ntt_rows(t.data_ptr(), 8, limbs, inverse=False)
-    y = from_device_u64(t).reshape(2, 4, N)
     perm = np.array([brev(i, logN) for i in range(N)])
-    for b in range(2):
-        for r, li in enumerate(limbs):
-            want = ring.ntt(x[b, r], mods[li], prm.psi[li])
-            assert np.array_equal(y[b, r], want[perm]), (b, li)
-    lib.ntt_rows(t.data_ptr(), 8, limbs, inverse=True)
-    assert np.array_equal(from_device_u64(t).reshape(2, 4, N), x)
+    want = np.array([[ring.ntt(x[b, r], mods[li], prm.psi[li])[perm] for r, li in enumerate(limbs)]
+                     for b in range(2)])
+    splits = [s for s in range(6, 10) if 6 <= logN - s <= 9]
+    assert lib.schedule()["ntt_split"] == logN // 2
+    for split in splits:
+        lib.set_schedule(0, 0, 0, split)
+        t = to_device_u64(x.reshape(-1, N))
+        lib.ntt_rows(t.data_ptr(), 8, limbs, inverse=False)
+        y = from_device_u64(t).reshape(2, 4, N)
+        for b in range(2):
+            for r, li in enumerate(limbs):
+                assert np.array_equal(y[b, r], want[b, r]), (split, b, li)
+        lib.ntt_rows(t.data_ptr(), 8, limbs, inverse=True)
+        assert np.array_equal(from_device_u64(t).reshape(2, 4, N), x), split
+    with pytest.raises(RuntimeError):
+        lib.set_schedule(0, 0, 0, logN - 5)       # a row pass of 5 stages
     lib.close()
 
 

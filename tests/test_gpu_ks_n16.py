@@ -114,11 +114,12 @@ def test_mf_chain_dnum7():
     ctx.close()
 
 
-@pytest.mark.parametrize("sched", [(2048, 1, 16), (256, 1, 8), (0, 0, 32)])
+@pytest.mark.parametrize("sched", [(2048, 1, 16, 7), (256, 1, 8, 9), (0, 0, 32, 8)])
 def test_schedules_give_the_same_bits(kb, sched):
-    """Cached or streamed NTT intermediates, NTT chunks and ModUp sub-batches
-    change only the order of the launches: the batched rotation and HMult of
-    the 64 ciphertexts keep the oracle's bits."""
+    """Cached or streamed NTT intermediates, NTT chunks, ModUp sub-batches and
+    the split of the transform's stages between its passes change only the
+    order and shape of the launches: the batched rotation and HMult of the 64
+    ciphertexts keep the oracle's bits."""
     ctx, cts, golden = kb
     ctx.set_schedule(*sched)
     try:
