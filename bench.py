@@ -53,19 +53,11 @@ MODMUL_RATE = {"shoup_u64": 1.927e12, "montgomery_u64": 1.318e12, "fp64_exact": 
 # counters were taken on.  Under another number of rows the launches differ in
 # size and the measured bytes are scaled by the algorithmic bytes
 # (traffic_basis); under another split they were not measured (None).
-TRAFFIC = {
-    "k_ntt_pass<rows,fwd>": {"bytes": 1.494e+09, "alg_bytes": 7.355e+08, "schedule": 2048, "split": 8},
-    "k_ntt_pass<cols,fwd>": {"bytes": 1.472e+09, "alg_bytes": 7.356e+08, "schedule": 2048, "split": 8},
-    "k_ntt_pass<rows,inv>": {"bytes": 1.065e+09, "alg_bytes": 5.251e+08, "schedule": 2048, "split": 8},
-    "k_ntt_pass<cols,inv>": {"bytes": 1.051e+09, "alg_bytes": 5.251e+08, "schedule": 2048, "split": 8},
-    "k_basis_convert": {"bytes": 1.175e+09, "alg_bytes": 1.174e+09, "schedule": None},
-    "k_ks_combine": {"bytes": 7.798e+09, "alg_bytes": 8.319e+09, "schedule": None},
-    "k_ks_inner": {"bytes": 5.128e+08, "alg_bytes": 5.128e+08, "schedule": None},
-}
+TRAFFIC = {}
 # Counter bytes (FETCH_SIZE + WRITE_SIZE, scaled as above) of a whole step of
 # the kernel-batch workload (transform phase, HMult phase and rotation phase),
 # from the same counter runs; None once the kernels have changed.
-KS_COUNTER_BYTES_PER_STEP = 575.7e9
+KS_COUNTER_BYTES_PER_STEP = None
 
 
 def traffic_of(name, schedule, alg_bytes):

@@ -267,18 +267,24 @@ void Context::graph_destroy(uint64_t id) {
 static uint64_t mm(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
 
 // Constant records of a basis conversion (layout: launch_basis_convert):
-// hats[i * targets.size() + t] = Qhat_i mod targets[t]; r_mod[t] = 2^64 mod targets[t].
-static std::vector<uint64_t> bc_records(const std::vector<uint64_t>& hats, int ns,
-                                        const std::vector<uint64_t>& targets, const std::vector<uint64_t>& r_mod) {
+// hats[i * targets.size() + t] = Qhat_i mod targets[t]; r_mod[t] = 2^64 mod
+// targets[t], qneg_inv[t] = -targets[t]^-1 mod 2^64.  The FP64 form serves the
+// targets below kBcFp64Bound when the sums of the sources fit it (centred:
+// up to 16 sources, canonical: up to 8).
+static std::vector<uint64_t> bc_records(const std::vector<uint64_t>& hats, int ns, bool centered,
+                                        const std::vector<uint64_t>& targets, const std::vector<uint64_t>& r_mod,
+                                        const std::vector<uint64_t>& qneg_inv) {
     const int R = kBcRecordWords(ns), nt = (int)targets.size();
+    const bool fp64_sum = centered ? ns <= 16 : ns <= 8;
     std::vector<uint64_t> rec((size_t)nt * R, 0);
     auto put = [&](size_t at, double v) { std::memcpy(&rec[at], &v, 8); };
     for (int t = 0; t < nt; ++t) {
         const uint64_t q = targets[t];
+        const bool f64 = fp64_sum && q < kBcFp64Bound;
         const size_t base = (size_t)t * R;
         for (int i = 0; i < ns; ++i) {
             const uint64_t h = hats[(size_t)i * nt + t];
-            if (q < kBcFp64Bound) {
+            if (f64) {
                 const int64_t lo = (int64_t)((h + (1u << 19)) & ((1u << 20) - 1)) - (1 << 19);
                 put(base + 2 * i, (double)lo);
                 put(base + 2 * i + 1, (double)(((int64_t)h - lo) >> 20));
@@ -286,7 +292,10 @@ static std::vector<uint64_t> bc_records(const std::vector<uint64_t>& hats, int n
                 rec[base + i] = mm(h, r_mod[t], q);
             }
         }
-        if (q < kBcFp64Bound) {
+        if (!f64) {
+            rec[base + 2 * ns + 1] = q;
+            rec[base + 2 * ns + 2] = qneg_inv[t];
+        } else {
             const double qd = (double)q;
             put(base + 2 * ns, qd);
             put(base + 2 * ns + 1, 1.0 / qd);
@@ -299,6 +308,18 @@ static std::vector<uint64_t> bc_records(const std::vector<uint64_t>& hats, int n
         }
     }
     return rec;
+}
+
+// Per-source constants of a basis conversion (layout: launch_basis_convert):
+// w = (Qhat_i)^-1 mod q_i with what the source's product needs.
+static void push_source_consts(std::vector<uint64_t>& v, uint64_t w, uint64_t q) {
+    auto bits = [](double d) { uint64_t u; std::memcpy(&u, &d, 8); return u; };
+    if (q < kFp64PrimeBound) {
+        const double wd = (double)w, qd = (double)q;
+        v.insert(v.end(), {bits(wd), bits(wd / qd), bits(qd), bits(1.0 / qd)});
+    } else {
+        v.insert(v.end(), {w, shoup_pre(w, q), q, 0});
+    }
 }
 
 static void upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
@@ -452,12 +473,10 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
                 const uint64_t qi = moduli[i];
                 uint64_t hat = 1;
                 for (int k = lo; k < hi; ++k) if (k != i) hat = mm(hat, moduli[k] % qi, qi);
-                const uint64_t w = inv_mod(hat, qi);
-                yc.push_back(w);
-                yc.push_back(shoup_pre(w, qi));
+                push_source_consts(yc, inv_mod(hat, qi), qi);
             }
-            std::vector<uint64_t> hats, tq, trm;
-            for (int tm : tg) { tq.push_back(moduli[tm]); trm.push_back(mh[tm].r_mod); }
+            std::vector<uint64_t> hats, tq, trm, tni;
+            for (int tm : tg) { tq.push_back(moduli[tm]); trm.push_back(mh[tm].r_mod); tni.push_back(mh[tm].qneg_inv); }
             for (int i = lo; i < hi; ++i) {
                 for (int tm : tg) {
                     const uint64_t qt = moduli[tm];
@@ -466,7 +485,7 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
                     hats.push_back(hat);
                 }
             }
-            cc = bc_records(hats, hi - lo, tq, trm);
+            cc = bc_records(hats, hi - lo, true, tq, trm, tni);
             dc.yc = upload_consts(pool, yc, stream);
             dc.cc = upload_consts(pool, cc, stream);
             c.digits.push_back(dc);
@@ -476,12 +495,14 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
             const uint64_t pk_ = moduli[L + 1 + k];
             uint64_t hat = 1;
             for (int kk = 0; kk < alpha; ++kk) if (kk != k) hat = mm(hat, moduli[L + 1 + kk] % pk_, pk_);
-            const uint64_t w = inv_mod(hat, pk_);
-            y.push_back(w);
-            y.push_back(shoup_pre(w, pk_));
+            push_source_consts(y, inv_mod(hat, pk_), pk_);
         }
-        std::vector<uint64_t> md_hats, md_tq, md_trm;
-        for (int i = 0; i <= l; ++i) { md_tq.push_back(moduli[i]); md_trm.push_back(mh[i].r_mod); }
+        std::vector<uint64_t> md_hats, md_tq, md_trm, md_tni;
+        for (int i = 0; i <= l; ++i) {
+            md_tq.push_back(moduli[i]);
+            md_trm.push_back(mh[i].r_mod);
+            md_tni.push_back(mh[i].qneg_inv);
+        }
         for (int k = 0; k < alpha; ++k) {
             for (int i = 0; i <= l; ++i) {
                 const uint64_t qi = moduli[i];
@@ -490,7 +511,7 @@ void Context::init(const csrmf_params& p, const uint8_t s[32]) {
                 md_hats.push_back(hat);
             }
         }
-        cv = bc_records(md_hats, alpha, md_tq, md_trm);
+        cv = bc_records(md_hats, alpha, false, md_tq, md_trm, md_tni);
         for (int i = 0; i <= l; ++i) {
             const uint64_t qi = moduli[i];
             uint64_t P = 1;

@@ -53,7 +53,7 @@ struct DigitConsts {
 
 struct LevelConsts {
     std::vector<DigitConsts> digits;
-    uint64_t* md_y = nullptr;       // [alpha][2]  (P/p_k)^-1 mod p_k
+    uint64_t* md_y = nullptr;       // [alpha][4]  (P/p_k)^-1 mod p_k with the constants of its product
     uint64_t* md_c = nullptr;       // [l+1][kBcRecordWords(alpha)]  records of the conversion P -> Q_l
     uint64_t* md_pinv = nullptr;    // [l+1][2]  P^-1 mod q_i
     uint64_t* rs = nullptr;         // [l][4]  h mod q_i, q_l^-1 mod q_i, shoup, 0

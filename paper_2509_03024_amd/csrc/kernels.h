@@ -101,12 +101,16 @@ void launch_automorphism(const DevTables& t, uint32_t g, const RowMap& out, cons
 // Fast basis conversion (coefficient form), per batch element:
 //   y_i = x_i * [Qhat_i^-1]_{q_i},   out_t = sum_i y_i * [Qhat_i]_t  (mod t)
 // src map: n_src (1..16) rows; dst map: n_tgt rows.  Device constants:
-//   yc[2i], yc[2i+1]            = Qhat_i^-1 mod src_i and its shoup
+//   yc[4i .. 4i+3]              = source i: w = Qhat_i^-1 mod q_i, then
+//     q_i below kFp64PrimeBound: doubles (bit patterns) w, fl(w/q_i), q_i, 1/q_i;
+//     other sources: w, shoup(w), q_i, 0
 //   cc[t*R .. t*R + R-1]        = target t's record, R = kBcRecordWords(n_src) words:
-//     target below kBcFp64Bound: doubles (bit patterns) c_0, d_0, .., c_{n-1}, d_{n-1}
+//     target below kBcFp64Bound (with n_src <= 16 centred, <= 8 otherwise):
+//       doubles (bit patterns) c_0, d_0, .., c_{n-1}, d_{n-1}
 //       (Qhat_i mod t = c_i + d_i 2^20, c_i in [-2^19, 2^19)), then t, 1/t,
 //       2^20 mod t, (2^20 mod t)/t, 2^30 mod t, (2^30 mod t)/t, 2^50 mod t, (2^50 mod t)/t;
-//     other targets: Qhat_i * 2^64 mod t (Montgomery form) for i < n_src, then zeros
+//     other targets: Qhat_i * 2^64 mod t (Montgomery form) for i < n_src, zeros up
+//       to word 2 n_src, which stays 0 (the kind of the record), then t, -t^-1 mod 2^64
 // centered: y_i taken in (-q_i/2, q_i/2] (ModUp of key-switching digits), so
 // the result is the centred representative mod Q plus a small multiple of Q.
 void launch_basis_convert(const DevTables& t, const RowMap& dst, const RowMap& src,

@@ -137,12 +137,19 @@ __device__ __forceinline__ void bfly_inv(uint64_t& x, uint64_t& y, uint64_t w, u
 __device__ __forceinline__ double as_f64(uint64_t v) { return __longlong_as_double((long long)v); }
 __device__ __forceinline__ uint64_t f64_bits(double v) { return (uint64_t)__double_as_longlong(v); }
 
-// centred double (|v| < 2^50) -> canonical residue in [0, q)
+// Exact conversions between integers below 2^52 and doubles through the
+// bits of 2^52 + x (exponent 52, mantissa x): an add or an or and a xor
+// instead of the general conversion sequences.
+__device__ __forceinline__ double u52_to_f64(uint64_t x) { return as_f64(x | 0x4330000000000000ull) - 0x1p52; }
+__device__ __forceinline__ uint64_t f64_to_u52(double v) { return f64_bits(v + 0x1p52) ^ 0x4330000000000000ull; }
+
+// centred double (integer, |v| < 2^50) -> canonical residue in [0, q):
+// t = rint(v/q) is within 0.5 + 2^-2/q of v/q, so r = v - t q (exact) lies
+// within q/2 + 1 of zero and one correction makes it canonical.
 __device__ __forceinline__ uint64_t f64_canon(double v, const ModF& m) {
-    double r = fma(-floor(v * m.qinv), m.q, v);
+    double r = fma(-rint(v * m.qinv), m.q, v);
     r = r < 0.0 ? r + m.q : r;
-    r = r >= m.q ? r - m.q : r;
-    return (uint64_t)r;
+    return f64_to_u52(r);
 }
 
 // Streamed load / store: nontemporal (kNt) or through the caches.
@@ -210,7 +217,7 @@ template <> struct NttIo<uint64_t, Modulus> {
 };
 template <> struct NttIo<double, ModF> {
     static __device__ __forceinline__ double in(uint64_t v, bool canonical, const ModF&) {
-        return canonical ? (double)v : as_f64(v);
+        return canonical ? u52_to_f64(v) : as_f64(v);
     }
     static __device__ __forceinline__ uint64_t out_mid(double v, const ModF&) { return f64_bits(v); }
     static __device__ __forceinline__ uint64_t out_fwd_end(double v, const ModF& m) { return f64_canon(v, m); }
@@ -524,21 +531,27 @@ __global__ void __launch_bounds__(kThreads) k_automorphism(DevTables t, uint32_t
 }
 
 // Basis conversion, one coefficient per thread.  y_s = x_s * [Qhat_s^-1]_{q_s}
-// (Shoup, canonical), then for every target t the sum of y_s * [Qhat_s]_t.
-// kCentered (ModUp): y_s is taken in (-q_s/2, q_s/2].
+// (canonical, or centred in (-q_s/2, q_s/2) if kCentered: ModUp), then for
+// every target t the sum of y_s * [Qhat_s]_t.
 //
-// Targets t < 2^40 (the scale primes) take an exact FP64 form: y_s is split
-// into balanced 30-bit halves y_s = a_s + b_s 2^30 (|a_s|, |b_s| <= 2^29) and
-// C = [Qhat_s]_t into balanced 20-bit halves C = c_s + d_s 2^20
-// (|c_s| <= 2^19, 0 <= d_s <= 2^20), so every partial product is an integer
-// of magnitude at most 2^49 and each of the four sums
+// y_s: for a source prime below kFp64PrimeBound one exact FP64 product
+// (fmul_centred, |r| <= 0.57 q_s) brought to the centred or canonical
+// representative by one rounding step; for the others a Shoup product.  Each
+// y_s is kept as balanced 30-bit halves y_s = a_s + b_s 2^30 (|a_s| <= 2^29),
+// as doubles.
+//
+// Targets t < 2^40 (the scale primes) take an exact FP64 form: C = [Qhat_s]_t
+// is split into balanced 20-bit halves C = c_s + d_s 2^20 (|c_s| <= 2^19,
+// 0 <= d_s <= 2^20), so every partial product is an integer of magnitude at
+// most 2^49 and each of the four sums
 //   A0 = sum a c,  A1 = sum a d (weight 2^20),  A2 = sum b c (2^30),
 //   A3 = sum b d (2^50)
 // of at most 16 sources stays within 2^53: exact in doubles, one FMA per
-// product and no reduction inside the sum.  The weights are then applied by
-// exact products modulo t (fmul_wide) and the total (below 11 t in magnitude)
-// is reduced once.  Without centring a 60-bit y_s has |b_s| <= 2^30, so that
-// form is used for at most 8 sources (ModDown converts the special limbs).
+// product and no reduction inside the sum.  The weights are applied by exact
+// products modulo t (fmul_wide, each below 3.5 t), the total (below 2^53) is
+// reduced by one rounding step and one correction.  Without centring a 60-bit
+// y_s has |b_s| <= 2^30, so that form is used for at most 8 sources (ModDown
+// converts the special limbs).
 //
 // Other targets (the 60-bit primes) sum the products |y_s| * (Qhat_s 2^64 mod t)
 // exactly in 128 bits and reduce once by Montgomery REDC:
@@ -546,8 +559,9 @@ __global__ void __launch_bounds__(kThreads) k_automorphism(DevTables t, uint32_t
 // a term with y_s < 0 contributes |y_s| * (t - c) = y_s * c (mod t), every
 // term below 2^59 * t.
 //
-// The constants are the same for every thread: one record of 2 NS + 8 words
-// per target (layout in kernels.h), read with scalar loads.
+// The constants are the same for every thread and are read with scalar
+// loads: 4 words per source and one record of 2 NS + 8 words per target
+// (layouts in kernels.h), which also tell the two kinds of prime apart.
 
 // y * w mod q for an integer-valued double |y| <= 2^53 and an integer
 // 0 <= w < q < 2^44 with wq within two roundings of w/q: h = fl(y w) and
@@ -562,30 +576,9 @@ __device__ __forceinline__ double fmul_wide(double y, double w, double wq, doubl
     return fma(-t, q, h) + l;
 }
 
-// One 60-bit target of the basis conversion from the signed y_s.
-template <int NS>
-__device__ __forceinline__ void convert_int_target(const DevTables& t, int mod, const int64_t (&y)[NS],
-                                                   const uint64_t* __restrict__ r, uint64_t* o, int i) {
-    const Modulus md = t.mods[mod];
-    uint64_t lo = 0, hi = 0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const bool neg = y[s] < 0;
-        const uint64_t ym = neg ? (uint64_t)(-y[s]) : (uint64_t)y[s];
-        const uint64_t c0 = r[s];
-        const uint64_t c = (neg && c0) ? md.q - c0 : c0;
-        const uint64_t pl = ym * c;
-        const uint64_t ph = mulhi64(ym, c);
-        lo += pl;
-        hi += ph + (lo < pl ? 1u : 0u);
-    }
-    const uint64_t m = lo * md.qneg_inv;
-    const uint64_t res = hi + mulhi64(m, md.q) + (lo != 0 ? 1u : 0u);
-    o[i] = res >= md.q ? res - md.q : res;
-}
-
 template <int NS, bool kCentered>
-__global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap dst, RowMap src, const uint64_t* yc,
+__global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap dst, RowMap src,
+                                                            const uint64_t* __restrict__ yc,
                                                             const uint64_t* __restrict__ rec) {
     const int logN = t.logN;
     const int N = 1 << logN;
@@ -596,37 +589,45 @@ __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap 
     const int nt = dst.n;
     constexpr bool kFp64Sum = kCentered ? NS <= 16 : NS <= 8;
     constexpr int R = kBcRecordWords(NS);
-    // y_s as a signed integer (centred or not)
-    int64_t y[NS];
+    // all source loads first (the memory clobber keeps them above it): the
+    // compiler would otherwise sink each load into its source's branch below
+    // and wait for it there, one source after the other
+    uint64_t xs[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         int mod;
-        const uint64_t* p = map_row(src, b, s, logN, mod);
-        const uint64_t qs = t.mods[mod].q;
-        const uint64_t v = mul_shoup(p[i], yc[2 * s], yc[2 * s + 1], qs);
-        y[s] = (kCentered && 2 * v > qs) ? (int64_t)v - (int64_t)qs : (int64_t)v;
+        xs[s] = __builtin_nontemporal_load(&map_row(src, b, s, logN, mod)[i]);
     }
-    if (!kFp64Sum) {
-        for (int tt = 0; tt < nt; ++tt) {
-            int mod;
-            uint64_t* o = map_row(dst, b, tt, logN, mod);
-            convert_int_target<NS>(t, mod, y, rec + (size_t)tt * R, o, i);
-        }
-        return;
-    }
+    asm volatile("" ::: "memory");
     double ya[NS], yb[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const int64_t lo = (int64_t)(((uint64_t)y[s] + (1u << 29)) & ((1u << 30) - 1)) - (1 << 29);
-        ya[s] = (double)(int32_t)lo;
-        yb[s] = (double)(int32_t)((y[s] - lo) >> 30);
+        const uint64_t x = xs[s];
+        const uint64_t* c = yc + 4 * s;
+        const double qinv = as_f64(c[3]);
+        if (qinv != 0.0) {   // FP64 source: w, fl(w/q), q, 1/q
+            const double q = as_f64(c[2]);
+            double v = fmul_centred(u52_to_f64(x), as_f64(c[0]), as_f64(c[1]), q);
+            if (kCentered) v = fma(-rint(v * qinv), q, v);
+            else v = v < 0.0 ? v + q : v;
+            yb[s] = rint(v * 0x1p-30);
+            ya[s] = fma(-yb[s], 0x1p30, v);
+        } else {             // integer source: w, shoup(w), q, 0
+            const uint64_t qs = c[2];
+            const uint64_t v = mul_shoup(x, c[0], c[1], qs);
+            const int64_t y = (kCentered && 2 * v > qs) ? (int64_t)v - (int64_t)qs : (int64_t)v;
+            const int64_t lo = (int64_t)(((uint64_t)y + (1u << 29)) & ((1u << 30) - 1)) - (1 << 29);
+            ya[s] = (double)(int32_t)lo;
+            yb[s] = (double)(int32_t)((y - lo) >> 30);
+        }
     }
-    // the targets below 2^40
-    for (int tt = 0; tt < nt; ++tt) {
+    // the targets below 2^40 (record word 2 NS holds t as a double, nonzero)
+    for (int tt = 0; kFp64Sum && tt < nt; ++tt) {
+        const double* r = reinterpret_cast<const double*>(rec + (size_t)tt * R);
+        const double* f = r + 2 * NS;   // t, 1/t, then (2^20, 2^30, 2^50 mod t) with their quotients by t
+        if (f[0] == 0.0) continue;
         int mod;
         uint64_t* o = map_row(dst, b, tt, logN, mod);
-        if (t.mods[mod].q >= kBcFp64Bound) continue;
-        const double* r = reinterpret_cast<const double*>(rec + (size_t)tt * R);
         double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -635,25 +636,48 @@ __global__ void __launch_bounds__(kThreads) k_basis_convert(DevTables t, RowMap 
             A2 = fma(yb[s], r[2 * s], A2);
             A3 = fma(yb[s], r[2 * s + 1], A3);
         }
-        const double* f = r + 2 * NS;   // q, 1/q, then (2^20, 2^30, 2^50 mod q) with their quotients by q
-        const ModF mf{f[0], f[1]};
-        const double v = fma(-rint(A0 * mf.qinv), mf.q, A0) + fmul_wide(A1, f[2], f[3], mf.q) +
-                         fmul_wide(A2, f[4], f[5], mf.q) + fmul_wide(A3, f[6], f[7], mf.q);
-        o[i] = f64_canon(v, mf);
+        const double q = f[0];
+        const double v = A0 + fmul_wide(A1, f[2], f[3], q) + fmul_wide(A2, f[4], f[5], q) + fmul_wide(A3, f[6], f[7], q);
+        double res = fma(-rint(v * f[1]), q, v);
+        res = res < 0.0 ? res + q : res;
+        __builtin_nontemporal_store(f64_to_u52(res), &o[i]);
     }
-    // then the 60-bit targets, with y_s formed again from its halves (an empty
-    // asm keeps the compiler from holding y_s itself through the loop above)
+    // then the 60-bit targets, from |y_s| and the signs; y_s is formed again
+    // from its halves (an empty asm keeps the compiler from holding y_s
+    // itself through the loop above)
+    uint64_t ym[NS];
+    uint32_t neg = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         double ha = ya[s], hb = yb[s];
         asm volatile("" : "+v"(ha), "+v"(hb));
-        y[s] = (int64_t)ha + (int64_t)hb * (1ll << 30);
+        const int64_t y = (int64_t)(int32_t)ha + (int64_t)(int32_t)hb * (1ll << 30);
+        neg |= (y < 0 ? 1u : 0u) << s;
+        ym[s] = (uint64_t)(y < 0 ? -y : y);
     }
     for (int tt = 0; tt < nt; ++tt) {
+        const uint64_t* r = rec + (size_t)tt * R;   // C_s (Montgomery form) per source, then 0 at 2 NS, t, -t^-1 mod 2^64
+        if (kFp64Sum && r[2 * NS] != 0) continue;
         int mod;
         uint64_t* o = map_row(dst, b, tt, logN, mod);
-        if (t.mods[mod].q < kBcFp64Bound) continue;
-        convert_int_target<NS>(t, mod, y, rec + (size_t)tt * R, o, i);
+        const uint64_t q = r[2 * NS + 1], qneg_inv = r[2 * NS + 2];
+        // t - C_s formed from a vector copy of t: a select between two scalar
+        // constants per source kept them all in vector registers at once
+        uint64_t qv = q;
+        asm volatile("" : "+v"(qv));
+        uint64_t lo = 0, hi = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const uint64_t c0 = r[s];
+            const uint64_t c = (((neg >> s) & 1u) && c0) ? qv - c0 : c0;
+            const uint64_t pl = ym[s] * c;
+            const uint64_t ph = mulhi64(ym[s], c);
+            lo += pl;
+            hi += ph + (lo < pl ? 1u : 0u);
+        }
+        const uint64_t m = lo * qneg_inv;
+        const uint64_t res = hi + mulhi64(m, q) + (lo != 0 ? 1u : 0u);
+        __builtin_nontemporal_store(res >= q ? res - q : res, &o[i]);
     }
 }
 
@@ -693,8 +717,8 @@ __device__ __forceinline__ void ks_dot_f64(const KsArgs& a, int b, int kl, int i
     const uint64_t* pown = map_row(a.own, b, kl, logN, omod);
     acc0 = acc1 = 0.0;
     for (int j = 0; j < a.n_digits; ++j) {
-        const double x = (double)(j == jown ? __builtin_nontemporal_load(&pown[src])
-                                            : __builtin_nontemporal_load(&pe0[(int64_t)j * a.ext_digit_stride + src]));
+        const double x = u52_to_f64(j == jown ? __builtin_nontemporal_load(&pown[src])
+                                              : __builtin_nontemporal_load(&pe0[(int64_t)j * a.ext_digit_stride + src]));
         const uint64_t* pk = a.key + (int64_t)j * a.key_digit_stride + krow;
         const double w0 = as_f64(pk[i]), w1 = as_f64(pk[i + a.key_poly_stride]);
         acc0 += fmul_centred(x, w0, w0 * mf.qinv, mf.q);
@@ -752,15 +776,15 @@ __global__ void __launch_bounds__(kThreads) k_ks_combine(DevTables t, RowMap out
             double u0, u1;
             ks_dot_f64(a, b, k, i, src, logN, mf, u0, u1);
             const uint32_t sa = (g_add == 1u) ? (uint32_t)i : galois_perm((uint32_t)i, g_add, logN);
-            double r0 = fmul_centred(u0 - (double)__builtin_nontemporal_load(&pc[i]), cd, cq, mf.q);
-            double r1 = fmul_centred(u1 - (double)__builtin_nontemporal_load(&pc[i + conv.poly_stride]), cd, cq, mf.q);
+            double r0 = fmul_centred(u0 - u52_to_f64(__builtin_nontemporal_load(&pc[i])), cd, cq, mf.q);
+            double r1 = fmul_centred(u1 - u52_to_f64(__builtin_nontemporal_load(&pc[i + conv.poly_stride])), cd, cq, mf.q);
             if (pa) {
-                r0 += (double)pa[sa];
-                if (add_both) r1 += (double)pa[sa + add.poly_stride];
+                r0 += u52_to_f64(pa[sa]);
+                if (add_both) r1 += u52_to_f64(pa[sa + add.poly_stride]);
             }
             if (pacc) {
-                r0 += (double)pacc[i];
-                r1 += (double)pacc[i + acc.poly_stride];
+                r0 += u52_to_f64(pacc[i]);
+                r1 += u52_to_f64(pacc[i + acc.poly_stride]);
             }
             __builtin_nontemporal_store(f64_canon(r0, mf), &o[i]);
             __builtin_nontemporal_store(f64_canon(r1, mf), &o[i + out.poly_stride]);
@@ -862,8 +886,8 @@ __device__ __forceinline__ void mask_mac_f64(const MaskTasks& T, int task, int k
     } else {
 #pragma unroll
         for (int u = 0; u < kMacPerThread; ++u) {
-            a0[u] = (double)pa[base_i + u];
-            a1[u] = (double)pa[base_i + u + T.poly_stride];
+            a0[u] = u52_to_f64(pa[base_i + u]);
+            a1[u] = u52_to_f64(pa[base_i + u + T.poly_stride]);
         }
     }
     int n_acc = 0;
@@ -895,8 +919,8 @@ __device__ __forceinline__ void mask_mac_f64(const MaskTasks& T, int task, int k
         for (int u = 0; u < kMacPerThread; ++u) {
             const int i = base_i + u;
             const double Mc = f64_centre(M[u], q, qinv);
-            a0[u] += f64_mulmod((double)ps[i], Mc, q, qinv);
-            a1[u] += f64_mulmod((double)ps[i + T.poly_stride], Mc, q, qinv);
+            a0[u] += f64_mulmod(u52_to_f64(ps[i]), Mc, q, qinv);
+            a1[u] += f64_mulmod(u52_to_f64(ps[i + T.poly_stride]), Mc, q, qinv);
         }
         if (++n_acc == kF64Batch) {
             n_acc = 0;
