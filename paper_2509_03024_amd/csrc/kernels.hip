@@ -252,10 +252,23 @@ __device__ __forceinline__ void pass_sync() {
 }
 
 template <int SL, bool kCols, bool kInverse, bool kNtMid, typename T, typename M>
-__device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t* in, uint64_t* data, const uint64_t* W,
-                                              const uint64_t* Wp, const M& md, const Modulus& mi, int L1, int L2,
-                                              int chunk, int tid) {
+__device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, uint64_t* twl, const uint64_t* in, uint64_t* data,
+                                              const uint64_t* W, const uint64_t* Wp, const M& md, const Modulus& mi,
+                                              int L1, int L2, int chunk, int tid) {
     T* lds = reinterpret_cast<T*>(lds_raw);
+    if constexpr (kCols) {
+        // The columns pass uses twiddle indices below 2^SL only, the same in
+        // every block: staged in LDS once per block, its rounds read them
+        // there instead of issuing per-lane vector loads (the vector memory
+        // path is the transform passes' busiest unit).
+        for (int k = tid; k < (1 << SL); k += kNttThreads) {
+            twl[k] = W[k];
+            twl[(1 << SL) + k] = Wp[k];
+        }
+        __syncthreads();
+        W = twl;
+        Wp = twl + (1 << SL);
+    }
     constexpr int TPS_L = SL - 3;
     static_assert(kCols || TPS_L <= 6, "a rows sub-transform is held by the lanes of one wave (pass_sync)");
     constexpr int SPB_L = kNttBlockLog - SL;        // log2(sub-transforms per block)
@@ -373,6 +386,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* lds_raw, const uint64_t*
 template <int SL, bool kCols, bool kInverse, bool kNtMid>
 __global__ void __launch_bounds__(kNttThreads) k_ntt_pass(DevTables t, RowMap m, RowMap src) {
     __shared__ uint64_t lds[kNttBlockElems + kNttBlockElems / 16];   // rows passes pad 1 word in 16
+    __shared__ uint64_t twl[kCols ? (2 << SL) : 1];                    // columns passes: their twiddles
     constexpr int SPB_L = kNttBlockLog - SL;
     const int logN = t.logN, L1 = t.L1, L2 = logN - L1;
     const size_t N = (size_t)1 << logN;
@@ -387,9 +401,9 @@ __global__ void __launch_bounds__(kNttThreads) k_ntt_pass(DevTables t, RowMap m,
     const uint64_t* Wp = W + N;
     if (md.q < kFp64PrimeBound) {
         const ModF mf{(double)md.q, 1.0 / (double)md.q};
-        ntt_pass_body<SL, kCols, kInverse, kNtMid, double, ModF>(lds, in, data, W, Wp, mf, md, L1, L2, chunk, threadIdx.x);
+        ntt_pass_body<SL, kCols, kInverse, kNtMid, double, ModF>(lds, twl, in, data, W, Wp, mf, md, L1, L2, chunk, threadIdx.x);
     } else {
-        ntt_pass_body<SL, kCols, kInverse, kNtMid, uint64_t, Modulus>(lds, in, data, W, Wp, md, md, L1, L2, chunk, threadIdx.x);
+        ntt_pass_body<SL, kCols, kInverse, kNtMid, uint64_t, Modulus>(lds, twl, in, data, W, Wp, md, md, L1, L2, chunk, threadIdx.x);
     }
 }
 
