@@ -342,9 +342,10 @@ void csrmf_server_destroy(csrmf_server* s);
  * intermediate cached or streamed, the split of the stages between the two
  * passes) on `rows` limbs of this context's ring
  * (0: 64 ciphertexts x 2 x (L+1) limbs, the batched key-switching shape) and,
- * if the context has a rotation key, the ModUp sub-batch sizes on one batched
- * rotation of up to 64 zero ciphertexts, with HIP events, and keep the
- * fastest for all later work of this context.  Writes a JSON report of the timings into
+ * if the context has a rotation key, rank the four fastest of them again and
+ * then the ModUp sub-batch sizes on batched rotations of up to 64 zero
+ * ciphertexts, with HIP events, and keep the fastest for all later work of
+ * this context.  Writes a JSON report of the timings into
  * report (NUL-terminated, truncated to cap bytes; may be NULL).
  * Errors: NOMEM, DEVICE. */
 int csrmf_autotune(csrmf_ctx* ctx, int32_t rows, char* report, int32_t cap);
