@@ -53,11 +53,19 @@ MODMUL_RATE = {"shoup_u64": 1.927e12, "montgomery_u64": 1.318e12, "fp64_exact": 
 # counters were taken on.  Under another number of rows the launches differ in
 # size and the measured bytes are scaled by the algorithmic bytes
 # (traffic_basis); under another split they were not measured (None).
-TRAFFIC = {}
+TRAFFIC = {
+    "k_ntt_pass<rows,fwd>": {"bytes": 1.4945e+09, "alg_bytes": 7.355e+08, "schedule": 2048, "split": 7},
+    "k_ntt_pass<cols,fwd>": {"bytes": 1.4716e+09, "alg_bytes": 7.356e+08, "schedule": 2048, "split": 7},
+    "k_ntt_pass<rows,inv>": {"bytes": 1.0653e+09, "alg_bytes": 5.251e+08, "schedule": 2048, "split": 7},
+    "k_ntt_pass<cols,inv>": {"bytes": 1.0506e+09, "alg_bytes": 5.251e+08, "schedule": 2048, "split": 7},
+    "k_basis_convert": {"bytes": 1.1746e+09, "alg_bytes": 1.174e+09, "schedule": None},
+    "k_ks_combine": {"bytes": 7.7946e+09, "alg_bytes": 8.319e+09, "schedule": None},
+    "k_ks_inner": {"bytes": 5.128e+08, "alg_bytes": 5.128e+08, "schedule": None},
+}
 # Counter bytes (FETCH_SIZE + WRITE_SIZE, scaled as above) of a whole step of
 # the kernel-batch workload (transform phase, HMult phase and rotation phase),
 # from the same counter runs; None once the kernels have changed.
-KS_COUNTER_BYTES_PER_STEP = None
+KS_COUNTER_BYTES_PER_STEP = 575.6e9
 
 
 def traffic_of(name, schedule, alg_bytes):
@@ -437,14 +445,16 @@ def run_mf(which, epochs, ntt_chunk=None):
     t0 = time.perf_counter()
     ctx = pk.Context(prm, workloads.CRYPTO_SEED)
     ctx.keygen([], conj=False)
+    m = pk.MF(ctx)
+    n_ct = m.encrypt_csr_rows(csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx, csr.values)
+    m.init_factors(U0, V0)
+    # tuned once the program's rotation keys exist, so that the transform
+    # schedules are ranked on batched rotations too
     if ntt_chunk is not None:
         ctx.set_ntt_schedule(ntt_chunk)
     else:
         ctx.autotune()
     sched = ctx.schedule()
-    m = pk.MF(ctx)
-    n_ct = m.encrypt_csr_rows(csr.n_rows, csr.n_cols, csr.row_ptr, csr.col_idx, csr.values)
-    m.init_factors(U0, V0)
     ctx.sync()
     log(f"{which}: set-up (keys, encryption of {n_ct} rating ciphertexts) {time.perf_counter() - t0:.1f} s")
     ks0 = ctx.counters()["key_switches"]

@@ -48,6 +48,16 @@ def _lastn(argv):
     return out
 
 
+def _steps(argv):
+    """Timed steps of the bench.py JSON line among the arguments, or None."""
+    for a in argv:
+        if a.endswith(".json"):
+            import json
+            line = [x for x in open(a).read().splitlines() if x.startswith("{")][-1]
+            return int(json.loads(line).get("steps", 0)) or None
+    return None
+
+
 def trace(path, last):
     per = defaultdict(list)
     for r in csv.DictReader(open(path)):
@@ -77,20 +87,24 @@ def _counters(path, cname):
     return per, calib
 
 
-def hbm(fetch_path, write_path, last):
+def hbm(fetch_path, write_path, last, steps=None):
     f, fc = _counters(fetch_path, "FETCH_SIZE")
     w, wc = _counters(write_path, "WRITE_SIZE")
     sf, sw = CALIB_KIB / fc, CALIB_KIB / wc
     print(f"calibration copy (512 MiB): FETCH_SIZE {fc:.1f} KiB -> scale {sf:.3f}; "
           f"WRITE_SIZE {wc:.1f} KiB -> scale {sw:.3f}")
+    total = 0.0
     for k, (n, _) in last.items():
         fv = [v for _, v in sorted(f.get(k, []))[-n:]]
         wv = [v for _, v in sorted(w.get(k, []))[-n:]]
         if fv and wv:
             fb = sum(fv) / len(fv) * sf * 1024
             wb = sum(wv) / len(wv) * sw * 1024
+            total += (fb + wb) * n
             print(f"timed steps: {k} over its last {len(fv)} dispatches: fetch {fb / 1e6:.1f} MB, "
                   f"write {wb / 1e6:.1f} MB, traffic {(fb + wb) / 1e6:.1f} MB per launch")
+    if steps:
+        print(f"timed steps: all listed kernels, traffic {total / steps / 1e9:.1f} GB per step ({steps} steps)")
 
 
 def counters(path, last):
@@ -113,4 +127,4 @@ if __name__ == "__main__":
     elif sys.argv[1] == "counters":
         counters(sys.argv[2], _lastn(sys.argv[3:]))
     else:
-        hbm(sys.argv[2], sys.argv[3], _lastn(sys.argv[4:]))
+        hbm(sys.argv[2], sys.argv[3], _lastn(sys.argv[4:]), _steps(sys.argv[4:]))
