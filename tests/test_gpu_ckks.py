@@ -194,6 +194,23 @@ def test_batched_equals_single(pair):
         _same(lib, conj[i], orc.conjugate(hs[i][1]))
 
 
+def test_autotune_installs_its_choice(pair):
+    """The tuner keeps the schedule its report names (transform schedules
+    ranked again on batched rotations, the context having rotation keys), and
+    results under it keep the oracle's bits."""
+    lib, orc = pair
+    rep = lib.autotune()
+    s = lib.schedule()
+    assert (s["ntt_chunk_rows"], s["ntt_cached_mid"], s["ntt_split"], s["modup_chunk"]) == \
+        (rep["chosen"], rep["cached_mid"], rep["ntt_split"], rep["modup_chunk"])
+    ranked = [k for k in rep if k.startswith("rotation ")]
+    assert 1 <= len(ranked) <= 4
+    assert list(rep["chosen_by_rotation"]) == [s["ntt_split"], s["ntt_chunk_rows"], s["ntt_cached_mid"]]
+    h, o, _ = _enc_pair(lib, orc, 60)
+    _same(lib, lib.rotate(h, 3), orc.rotate(o, 3))
+    lib.set_schedule(0, 0, 0)
+
+
 def test_import_export_roundtrip(pair):
     lib, orc = pair
     h, o, z = _enc_pair(lib, orc, 50)
