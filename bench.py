@@ -482,6 +482,11 @@ def run_mf(which, epochs, ntt_chunk=None):
         "refresh_s": round(st["refresh_seconds"], 3),
         "ratings_per_s_excluding_refresh": round(csr.nnz * epochs / (elapsed - st["refresh_seconds"]), 2),
         "key_switches_per_epoch": round(n_ks / epochs),
+        "key_switches_per_s": round(n_ks / elapsed, 1),
+        # share of the timed kernels' time in the key-switching kernels
+        "key_switch_kernel_share": round(sum(v[1] for k, v in prof.items()
+                                             if k.startswith(("k_ntt_pass", "k_basis_convert", "k_ks_")))
+                                         / max(1e-9, sum(v[1] for v in prof.values())), 3),
         "config": {"workload": f"encrypted MF, {name}, {csr.nnz} ratings, k={k}, N=2^{prm.log2N}, "
                                f"{n_ct} rating ciphertexts, rule R2, {epochs} epochs "
                                f"({st['refreshes']} table refreshes)"},
@@ -810,6 +815,10 @@ def bench_ks(args):
                                "64 HMult, 64 x 16 rotate-and-sum key switches",
                    "ciphertexts": N_CT, "log2N": LOGN, "limbs": L + 1, "special": ctx.alpha, "dnum": 3},
         "phase_ms_per_step": {k: round(1e3 * v / args.steps, 3) for k, v in phase.items()},
+        # the transform phase runs the forward and the inverse transform of every
+        # limb of the 64 ciphertexts; the HMult phase 64 HMult + relin + rescale
+        "ntt_limbs_per_s": round(2 * ntt_buf.shape[0] * args.steps / phase["ntt_intt"]),
+        "hmults_per_s": round(N_CT * args.steps / phase["hmult"], 1),
         "autotune_ms": tune,
         "rotation_phase_rotations_per_s": round(rot_rate, 2),
         "plain_gpu_path": {"rotations_per_s": round(plain_rate, 2), "ciphertexts": PLAIN_CT,
