@@ -873,6 +873,14 @@ __global__ void __launch_bounds__(kThreads) k_rescale_combine(DevTables t, RowMa
 // [term_begin[g], term_begin[g+1]).  If first[t] != 0 the accumulator starts at 0.
 
 
+// The MAC's per-task metadata (group and term tables, weights, source
+// pointers) is written by the host before the launch and only read here:
+// read through the constant address space, uniform loads of it become scalar
+// loads, which wait on their own counter instead of behind the vector loads
+// of the mask rows and sources.
+template <typename T> using ConstPtr = const __attribute__((address_space(4))) T*;
+template <typename T> __device__ __forceinline__ ConstPtr<T> as_const(const T* p) { return (ConstPtr<T>)p; }
+
 // FP64 form of the masked MAC for a limb whose prime is below 2^44 (the mask
 // row and the weight rows of such a limb hold centred doubles: the mask value,
 // and w with fl(w/q)).  Every product is exact (FMA two-product, reduced by
@@ -905,15 +913,28 @@ __device__ __forceinline__ void mask_mac_f64(const MaskTasks& T, int task, int k
         }
     }
     int n_acc = 0;
+    const ConstPtr<int32_t> term_begin = as_const(T.term_begin), wi = as_const(T.wi);
+    const ConstPtr<uint32_t> gs = as_const(T.gs);
+    const ConstPtr<uint64_t> cw = as_const(T.cw);
+    const ConstPtr<const uint64_t*> srcs = as_const(T.src);
     for (int g = g0; g < g1; ++g) {
+        // the group's source rows first: their loads overlap the mask gathers
+        const uint64_t* ps = srcs[g] + ((size_t)k << logN);
+        double s0[kMacPerThread], s1[kMacPerThread];
+#pragma unroll
+        for (int u = 0; u < kMacPerThread; ++u) {
+            s0[u] = u52_to_f64(ps[base_i + u]);
+            s1[u] = u52_to_f64(ps[base_i + u + T.poly_stride]);
+        }
+        asm volatile("" ::: "memory");   // issued here, not sunk below the term loop
         double M[kMacPerThread];
 #pragma unroll
         for (int u = 0; u < kMacPerThread; ++u) M[u] = 0.0;
-        const int m0 = T.term_begin[g], m1 = T.term_begin[g + 1];
+        const int m0 = term_begin[g], m1 = term_begin[g + 1];
         for (int m = m0; m < m1; ++m) {
-            const uint64_t* c = T.cw + 2 * ((size_t)T.wi[m] * T.cw_stride + k);
+            const ConstPtr<uint64_t> c = cw + 2 * ((size_t)wi[m] * T.cw_stride + k);
             const double w = as_f64(c[0]), wq = as_f64(c[1]);
-            const uint32_t gm = T.gs[m];
+            const uint32_t gm = gs[m];
             // Galois element 0 marks a constant term (the plaintext W, no mask)
             if (gm) {
 #pragma unroll
@@ -928,13 +949,11 @@ __device__ __forceinline__ void mask_mac_f64(const MaskTasks& T, int task, int k
                 for (int u = 0; u < kMacPerThread; ++u) M[u] = f64_centre(M[u], q, qinv);
             }
         }
-        const uint64_t* ps = T.src[g] + ((size_t)k << logN);
 #pragma unroll
         for (int u = 0; u < kMacPerThread; ++u) {
-            const int i = base_i + u;
             const double Mc = f64_centre(M[u], q, qinv);
-            a0[u] += f64_mulmod(u52_to_f64(ps[i]), Mc, q, qinv);
-            a1[u] += f64_mulmod(u52_to_f64(ps[i + T.poly_stride]), Mc, q, qinv);
+            a0[u] += f64_mulmod(s0[u], Mc, q, qinv);
+            a1[u] += f64_mulmod(s1[u], Mc, q, qinv);
         }
         if (++n_acc == kF64Batch) {
             n_acc = 0;
@@ -992,15 +1011,27 @@ __global__ void __launch_bounds__(kThreads) k_mask_mac_tasks(DevTables t, MaskTa
             a1[u] = pa[base_i + u + T.poly_stride];
         }
     }
+    const ConstPtr<int32_t> term_begin = as_const(T.term_begin), wi = as_const(T.wi);
+    const ConstPtr<uint32_t> gs = as_const(T.gs);
+    const ConstPtr<uint64_t> cw = as_const(T.cw);
+    const ConstPtr<const uint64_t*> srcs = as_const(T.src);
     for (int g = g0; g < g1; ++g) {
+        const uint64_t* ps = srcs[g] + ((size_t)k << logN);
+        uint64_t s0[kMacPerThread], s1[kMacPerThread];
+#pragma unroll
+        for (int u = 0; u < kMacPerThread; ++u) {
+            s0[u] = ps[base_i + u];
+            s1[u] = ps[base_i + u + T.poly_stride];
+        }
+        asm volatile("" ::: "memory");
         uint64_t M[kMacPerThread];
 #pragma unroll
         for (int u = 0; u < kMacPerThread; ++u) M[u] = 0;
-        const int m1 = T.term_begin[g + 1];
-        for (int m = T.term_begin[g]; m < m1; ++m) {
-            const uint64_t* c = T.cw + 2 * ((size_t)T.wi[m] * T.cw_stride + k);
+        const int m1 = term_begin[g + 1];
+        for (int m = term_begin[g]; m < m1; ++m) {
+            const ConstPtr<uint64_t> c = cw + 2 * ((size_t)wi[m] * T.cw_stride + k);
             const uint64_t w = c[0], ws = c[1];
-            const uint32_t gm = T.gs[m];
+            const uint32_t gm = gs[m];
             // Galois element 0 marks a constant term (the plaintext W, no mask)
             if (gm) {
 #pragma unroll
@@ -1012,12 +1043,10 @@ __global__ void __launch_bounds__(kThreads) k_mask_mac_tasks(DevTables t, MaskTa
                 for (int u = 0; u < kMacPerThread; ++u) M[u] = add_mod(M[u], w, md.q);
             }
         }
-        const uint64_t* ps = T.src[g] + ((size_t)k << logN);
 #pragma unroll
         for (int u = 0; u < kMacPerThread; ++u) {
-            const int i = base_i + u;
-            a0[u] = add_mod(a0[u], mul_mont(ps[i], M[u], md.q, md.qneg_inv), md.q);
-            a1[u] = add_mod(a1[u], mul_mont(ps[i + T.poly_stride], M[u], md.q, md.qneg_inv), md.q);
+            a0[u] = add_mod(a0[u], mul_mont(s0[u], M[u], md.q, md.qneg_inv), md.q);
+            a1[u] = add_mod(a1[u], mul_mont(s1[u], M[u], md.q, md.qneg_inv), md.q);
         }
     }
 #pragma unroll
