@@ -1,0 +1,100 @@
+"""Writes boot_n12.txt: SHA-256 digests of the oracle's bootstrapped ciphertexts
+(oracle.bootstrap) on the N = 2^12 test chain (q_0 60-bit + 18 x 40-bit,
+3 x 60-bit special primes, dnum 5: 4-limb digits; scale 2^40).
+
+Inputs: two ciphertexts encrypted at level 0 (serials 0 and 1 after keygen),
+slot values V[i] tiled with period N_SLOTS over the N/2 slots, V[i] drawn
+uniformly from [-1, 1) by numpy's default_rng(100 + i).  Both are bootstrapped
+with n = 4 slots, r = 9 squarings, a degree-11 series, pre-multiplication by
+2^12; the file holds the inputs' and the outputs' digests, the outputs' level
+and scale, and the largest slot error of the oracle's own decryption.
+
+Only oracle/ and the seeded inputs below are used.  Run from the repository
+root (about four minutes on one core):
+    python tests/golden/make_boot_n12.py
+"""
+import hashlib
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import bootstrap, ckks, params  # noqa: E402
+import workloads  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+N_SLOTS, SQUARINGS, DEGREE, PRE_BITS = 4, 9, 11, 12
+N_CT = 2
+SCALE = 2.0 ** 40
+CHAIN = (12, 60, 18, 40, 3, 60, 5, 40)      # logN, base, L, scale bits, alpha, special bits, dnum, log2 scale
+
+
+def chain():
+    return params.make_params(*CHAIN, name="boot_n12")
+
+
+def config():
+    return bootstrap.BootConfig(n=N_SLOTS, r=SQUARINGS, d=DEGREE, pre_bits=PRE_BITS)
+
+
+def values(i, N):
+    v = np.random.default_rng(100 + i).uniform(-1.0, 1.0, N_SLOTS)
+    return np.tile(v, N // 2 // N_SLOTS)
+
+
+def digest(c0, c1):
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(np.asarray(c0, dtype=np.uint64), dtype="<u8").tobytes())
+    h.update(np.ascontiguousarray(np.asarray(c1, dtype=np.uint64), dtype="<u8").tobytes())
+    return h.hexdigest()
+
+
+def read(path):
+    """{(kind, index): (level, scale, digest)} and {key: float} of the '#=' lines."""
+    out, meta = {}, {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#="):
+                k, v = line[2:].split()
+                meta[k] = float(v)
+                continue
+            if line.startswith("#") or not line.strip():
+                continue
+            kind, i, lvl, sc, dg = line.split()
+            out[(kind, int(i))] = (int(lvl), float(sc), dg)
+    return out, meta
+
+
+def main():
+    prm = chain()
+    orc = ckks.Context(prm, workloads.CRYPTO_SEED)
+    bootstrap.keygen_for(orc, config())
+    print("keys done", flush=True)
+    rows, err = [], 0.0
+    cts = [orc.encrypt(values(i, prm.N), level=0, scale=SCALE) for i in range(N_CT)]
+    for i, ct in enumerate(cts):
+        rows.append(("input", i, ct))
+    for i, ct in enumerate(cts):
+        out = bootstrap.bootstrap(orc, ct, config())
+        err = max(err, float(np.max(np.abs(orc.decrypt(out) - values(i, prm.N)))))
+        rows.append(("boot", i, out))
+        print("bootstrap", i, "done, error so far", err, flush=True)
+    lines = ["# Oracle bootstrapping on the N = 2^12 test chain (q_0 + 18 x 40-bit, 3 x 60-bit special, dnum 5);",
+             f"# n = {N_SLOTS}, r = {SQUARINGS}, d = {DEGREE}, pre_bits = {PRE_BITS}; inputs encrypted at level 0",
+             "# (serials 0, 1), slot values default_rng(100 + i).uniform(-1, 1, n) tiled; written by",
+             "# tests/golden/make_boot_n12.py.",
+             "# kind index level scale sha256(c0 || c1 as little-endian uint64 [level+1][N])",
+             f"#=max_abs_error {err!r}"]
+    for kind, i, c in rows:
+        lines.append(f"{kind} {i} {c.level} {c.scale!r} {digest(c.c0, c.c1)}")
+    path = os.path.join(HERE, "boot_n12.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", path, flush=True)
+
+
+if __name__ == "__main__":
+    main()
