@@ -16,11 +16,13 @@ Default run (one JSON line):
   (943 x 1682, 99,926 ratings, k = 10, N = 2^15, two table refreshes);
 * "tiny": the latency of one encrypted MF epoch at the tiny configuration
   (32 x 64, 205 ratings, k = 4, N = 2^12);
+* "bootstrap": bootstrapping a batch of 8 ciphertexts at N = 2^16 (MF chain,
+  16-periodic slots, 18 levels) back from level 0, ciphertexts per second;
 * "cpu_baseline" legs: the oracle on bounded samples of each workload, run
   in parallel processes after the GPU work.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-       [--no-mf] [--workload ks|mf100k|mf1m|serve]
+       [--no-mf] [--workload ks|mf100k|mf1m|serve|accuracy|boot]
 """
 import argparse
 import json
@@ -92,9 +94,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mf", action="store_true", help="default run: skip the MF-100K and tiny sub-objects")
-    ap.add_argument("--workload", default="ks", choices=["ks", "mf100k", "mf1m", "serve", "accuracy"],
-                    help="ks: batched key switching with the MF sub-objects (default); mf100k / mf1m: "
-                         "encrypted MF epochs alone; serve: the request stream")
+    ap.add_argument("--workload", default="ks", choices=["ks", "mf100k", "mf1m", "serve", "accuracy", "boot"],
+                    help="ks: batched key switching with the MF and bootstrapping sub-objects (default); "
+                         "mf100k / mf1m: encrypted MF epochs alone; serve: the request stream; boot: "
+                         "bootstrapping alone")
     ap.add_argument("--epochs", type=int, default=None, help="MF workloads: epochs (100K: 10, 1M: 5)")
     ap.add_argument("--rates", default="10,20,50,100,200,500", help="serve: Poisson arrival rates (requests/s)")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
@@ -530,6 +533,68 @@ def run_tiny(reps=3):
             "config": {"workload": "tiny: 32 x 64, 205 ratings, k=4, N=2^12, rule R1, 1 epoch"}}
 
 
+# ---------------------------------------------------------------- bootstrapping
+BOOT_CFG = (16, 10, 16, 13)     # n slots, squarings r, series degree d, pre-multiplication bits
+BOOT_BATCH = 8
+
+
+def run_boot(batch=BOOT_BATCH, reps=3):
+    """Bootstrapping at N = 2^16 on the MF chain (q_0 + 24 x 40-bit, 3 x 60-bit
+    special, dnum 7): a batch of level-0 ciphertexts with 16-periodic slots back
+    to level L - 18, every step on the device; ciphertexts per second over the
+    timed batches, the key switches they ran, and the largest slot error of the
+    outputs against the inputs."""
+    import numpy as np
+    import torch
+    import paper_2509_03024_amd as pk
+    import workloads
+    ctx = pk.Context(pk.mf_n16_params(), workloads.CRYPTO_SEED)
+    cfg = pk.BootConfig(*BOOT_CFG)
+    n = BOOT_CFG[0]
+    t0 = time.perf_counter()
+    ctx.keygen(ctx.boot_rotation_steps(cfg), conj=True)
+    vals = [np.tile(np.random.default_rng(300 + i).uniform(-1, 1, n), ctx.N // (2 * n)) for i in range(batch)]
+    cts = [ctx.encrypt(v, level=0, scale=2.0 ** 40) for v in vals]
+    ctx.sync()
+    log(f"bootstrap: keys and inputs {time.perf_counter() - t0:.1f} s")
+    for h in ctx.bootstrap(cts, cfg):          # warm-up
+        ctx.free(h)
+    ctx.sync()
+    ks0 = ctx.counters()["key_switches"]
+    pk.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = []
+    for r in range(reps):
+        if outs:
+            for h in outs:
+                ctx.free(h)
+        outs = ctx.bootstrap(cts, cfg)
+    ctx.sync()
+    elapsed = time.perf_counter() - t0
+    prof = pk.profile_report()
+    pk.profile_enable(False)
+    n_ks = ctx.counters()["key_switches"] - ks0
+    err = max(float(np.max(np.abs(ctx.decrypt(h) - v))) for h, v in zip(outs, vals))
+    lvl = ctx.info(outs[0])[0]
+    sched = ctx.schedule()
+    out = {
+        "metric": "bootstraps/s", "value": round(batch * reps / elapsed, 2), "unit": "ciphertexts/s",
+        "ms_per_batch": round(1e3 * elapsed / reps, 2), "batch": batch,
+        "levels_used": pk.boot_levels(cfg), "output_level": lvl,
+        "key_switches_per_bootstrap": round(n_ks / (batch * reps), 1),
+        "key_switches_per_s": round(n_ks / elapsed, 1),
+        "max_abs_error": err,
+        "config": {"workload": f"bootstrapping, N=2^16, q_0 + 24 x 40-bit, dnum 7, n={n} slots, "
+                               f"r={BOOT_CFG[1]}, degree {BOOT_CFG[2]}, pre-multiplication 2^{BOOT_CFG[3]}, "
+                               f"batch of {batch}, |values| <= 1"},
+        "roofline": dominant_roofline(prof, (sched["ntt_chunk_rows"], sched["ntt_split"])),
+        "kernels": kernel_table(prof),
+    }
+    ctx.close()
+    return out
+
+
 # ---------------------------------------------------------------- serving
 def bench_serve(args):
     """Poisson stream of encrypted per-user PREDICT / UPDATE requests (50/50) over the
@@ -859,6 +924,13 @@ def main():
                 v["max_abs_diff_vs_fp64"] = round(max(abs(a - b) for a, b in zip(v["rmse"], ref0)), 6)
         print(json.dumps(out), flush=True)
         return
+    if args.workload == "boot":
+        out = run_boot()
+        out.update({"n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": out["ms_per_batch"],
+                    "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+                    "data": "synthetic"})
+        print(json.dumps(out), flush=True)
+        return
     if args.workload in ("mf100k", "mf1m"):
         epochs = args.epochs or (10 if args.workload == "mf100k" else 5)
         out = run_mf(args.workload, epochs, args.ntt_chunk)
@@ -877,6 +949,9 @@ def main():
         log(f"MF-100K {out['mf100k']['value']} ratings/s")
         out["tiny"] = run_tiny()
         log(f"tiny epoch {out['tiny']['value']} ms")
+        log("bootstrapping at N = 2^16 ...")
+        out["bootstrap"] = run_boot()
+        log(f"bootstrap {out['bootstrap']['value']} ciphertexts/s, error {out['bootstrap']['max_abs_error']:.2e}")
     if not args.no_cpu_baseline:
         log("cpu baselines (oracle, parallel processes) ...")
         legs = {"ks": (cpu_leg_ks, (max(1, min(8, (os.cpu_count() or 2) - 3)),))}

@@ -251,6 +251,56 @@ int csrmf_rotate_add_batch(csrmf_ctx* ctx, const uint64_t* a, const uint64_t* ac
 int csrmf_conjugate_batch(csrmf_ctx* ctx, const uint64_t* a, int32_t n, uint64_t* out);
 
 /* ------------------------------------------------------------------------ */
+/* Bootstrapping (renews the levels of a ciphertext without decrypting it).   */
+/* ------------------------------------------------------------------------ */
+
+/* Sec. IV-C claims that the factorisation runs without communication; the
+ * epochs use levels the paper gives no way to renew.  Bootstrapping renews
+ * them on the device by the published method for approximate homomorphic
+ * encryption (Cheon, Han, Kim, Kim, Song, EUROCRYPT 2018), sparse packing:
+ * ModRaise, SubSum (the trace onto Z[X^(N/2n)]), CoeffToSlot, EvalMod
+ * (exp(i theta) by a Taylor series of degree `degree`, squared `squarings`
+ * times, minus its conjugate) and SlotToCoeff.
+ *   n_slots    n: the message's slots repeat with period n (power of two,
+ *              1..N/2); the output's slots repeat with the same period;
+ *   squarings  r: the series' argument is 2 pi (m/q_0 + I) / 2^r, where
+ *              |I| (about sqrt(N/18) for the dense ternary secret) must stay
+ *              below K with 2 pi (K + 1/2) / 2^r below about 0.8;
+ *   degree     d (1..18): the series' degree (11 keeps its error below 2^-32
+ *              for arguments up to 0.8);
+ *   pre_bits   the level-0 input is multiplied by 2^pre_bits before ModRaise,
+ *              so that the message uses about 2^-8 of q_0 (precision against
+ *              the linearisation sin x ~ x). */
+typedef struct csrmf_boot_config {
+    int32_t n_slots;
+    int32_t squarings;
+    int32_t degree;
+    int32_t pre_bits;
+} csrmf_boot_config;
+
+/* Levels one bootstrap consumes: 2 + ceil(log2 degree) + 1 + squarings + 1.
+ * Errors: INVAL (null arguments). */
+int csrmf_boot_levels(const csrmf_boot_config* cfg, int32_t* levels);
+
+/* The rotation steps whose keys csrmf_bootstrap needs (1 .. 2n-1 and n 2^j
+ * below N/2), ascending, into steps[cap]; *count receives their number (also
+ * when cap is too small, then with CSRMF_E_INVAL).  Relinearisation and
+ * conjugation keys are needed too (csrmf_keygen with conj = 1). */
+int csrmf_boot_rotation_steps(csrmf_ctx* ctx, const csrmf_boot_config* cfg, int32_t* steps, int32_t cap,
+                              int32_t* count);
+
+/* Bootstrap the ciphertexts in[0..n) (one scale shared by all, any level; the
+ * top limbs above level 0 are ignored) into new handles out[0..n), at level
+ * L - csrmf_boot_levels(cfg) and a scale of about 2^log2_scale, every step on
+ * the whole batch in the library's kernels.  The outputs decrypt to the
+ * inputs' slot values up to the method's error (about 4e-4 for |values| <= 1
+ * on the N = 2^12 test chain).  Errors: INVAL (configuration, handles),
+ * LEVEL (chain too short), SCALE (scales differ), STATE (no keys), KEY (a
+ * needed key is absent: nothing is enqueued). */
+int csrmf_bootstrap(csrmf_ctx* ctx, const csrmf_boot_config* cfg, const uint64_t* in, int32_t n,
+                    uint64_t* out);
+
+/* ------------------------------------------------------------------------ */
 /* Raw transforms on caller device memory (test and benchmark hooks).        */
 /* ------------------------------------------------------------------------ */
 

@@ -52,6 +52,11 @@ class Params(ctypes.Structure):
                 ("batch_pairs", ctypes.c_int32)]
 
 
+class BootConfig(ctypes.Structure):
+    """Bootstrapping parameters (csrmf_boot_config)."""
+    _fields_ = [("n_slots", ctypes.c_int32), ("squarings", ctypes.c_int32),
+                ("degree", ctypes.c_int32), ("pre_bits", ctypes.c_int32)]
+
 _p = ctypes.c_void_p
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -94,6 +99,9 @@ _SIGS = {
     "csrmf_rotate_batch": [_p, _u64p, ctypes.c_int32, ctypes.c_int32, _u64p],
     "csrmf_rotate_add_batch": [_p, _u64p, _u64p, ctypes.c_int32, ctypes.c_int32, _u64p],
     "csrmf_conjugate_batch": [_p, _u64p, ctypes.c_int32, _u64p],
+    "csrmf_boot_levels": [ctypes.POINTER(BootConfig), _i32p],
+    "csrmf_boot_rotation_steps": [_p, ctypes.POINTER(BootConfig), _i32p, ctypes.c_int32, _i32p],
+    "csrmf_bootstrap": [_p, ctypes.POINTER(BootConfig), _u64p, ctypes.c_int32, _u64p],
     "csrmf_ntt_rows": [_p, _p, ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_int32],
     "csrmf_encrypt_csr_rows": [_p, ctypes.c_int32, ctypes.c_int32, _i64p, _i32p, _dp, _i32p],
     "csrmf_encrypt_csr_rows_int": [_p, ctypes.c_int32, ctypes.c_int32, _i64p, _i32p, _i64p, ctypes.c_int32, _i32p],
@@ -400,6 +408,24 @@ class Context:
         self._chk(lib.csrmf_conjugate_batch(self.h, _ptr(a, ctypes.c_uint64), len(a), _ptr(out, ctypes.c_uint64)))
         return [int(x) for x in out]
 
+    def boot_rotation_steps(self, cfg):
+        """Rotation steps whose keys bootstrap(cfg) needs (plus conjugation)."""
+        cnt = ctypes.c_int32()
+        lib.csrmf_boot_rotation_steps(self.h, ctypes.byref(cfg), None, 0, ctypes.byref(cnt))
+        st = np.zeros(max(cnt.value, 1), np.int32)
+        self._chk(lib.csrmf_boot_rotation_steps(self.h, ctypes.byref(cfg), _ptr(st, ctypes.c_int32), len(st),
+                                                ctypes.byref(cnt)))
+        return [int(x) for x in st[: cnt.value]]
+
+    def bootstrap(self, handles, cfg):
+        """Bootstrap a batch of ciphertexts (one scale); new handles at level
+        L - boot_levels(cfg)."""
+        a = np.asarray(list(handles), np.uint64)
+        out = np.zeros(len(a), np.uint64)
+        self._chk(lib.csrmf_bootstrap(self.h, ctypes.byref(cfg), _ptr(a, ctypes.c_uint64), len(a),
+                                      _ptr(out, ctypes.c_uint64)))
+        return [int(x) for x in out]
+
     def autotune(self, rows=0):
         """Pick the fastest NTT schedule for this ring on `rows` limbs; returns the timings."""
         import json
@@ -618,6 +644,21 @@ def profile_report():
             break
         cap = 2 * n
     return {k: (int(v[0]), float(v[1]), float(v[2])) for k, v in json.loads(buf.value.decode()).items()}
+
+
+def boot_levels(cfg):
+    """Levels one bootstrap with this configuration consumes."""
+    v = ctypes.c_int32()
+    rc = lib.csrmf_boot_levels(ctypes.byref(cfg), ctypes.byref(v))
+    if rc != CSRMF_OK:
+        raise CsrmfError(rc, "invalid bootstrapping configuration")
+    return v.value
+
+
+def boot_n12_params():
+    """N = 2^12, q_0 60-bit + 18 x 40-bit, 3 x 60-bit special primes, dnum 5 (4-limb digits),
+    scale 2^40: room for one bootstrap (17 levels at r = 9, d = 11) and one level after it."""
+    return params(12, 60, 18, 40, 3, 60, 5, 40)
 
 
 def tiny_params(k=4, lr=0.01, lam=0.02, rule=1):

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcsrmf.so")
 SOURCES = ["kernels.hip", "context.cpp", "capi.cpp", "host_math.cpp", "mf_program.cpp", "prof.cpp", "serving.cpp",
-           "noalloc.cpp", "protocol.cpp"]
+           "noalloc.cpp", "protocol.cpp", "bootstrap.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

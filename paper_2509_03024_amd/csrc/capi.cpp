@@ -3,6 +3,7 @@
 #include <cstring>
 #include <new>
 
+#include "bootstrap.h"
 #include "context.h"
 #include "host_math.h"
 #include "prof.h"
@@ -408,6 +409,49 @@ int csrmf_rotate_hoisted(csrmf_ctx* cx, uint64_t a, const int32_t* r, int32_t n,
     std::vector<Ct*> vo;
     for (auto& x : res) vo.push_back(&x);
     c->rotate_hoisted(c->get(a), gs, vo);
+    for (int i = 0; i < n; ++i) out[i] = c->put(res[i]);
+    API_END(c)
+}
+
+static csrmf::BootCfg boot_cfg(const csrmf_boot_config* cfg) {
+    NEED(cfg, "configuration");
+    csrmf::BootCfg b;
+    b.n = cfg->n_slots;
+    b.r = cfg->squarings;
+    b.d = cfg->degree;
+    b.pre_bits = cfg->pre_bits;
+    return b;
+}
+
+int csrmf_boot_levels(const csrmf_boot_config* cfg, int32_t* levels) {
+    if (!cfg || !levels || cfg->degree < 1) return CSRMF_E_INVAL;
+    *levels = csrmf::boot_levels(boot_cfg(cfg));
+    return CSRMF_OK;
+}
+
+int csrmf_boot_rotation_steps(csrmf_ctx* cx, const csrmf_boot_config* cfg, int32_t* steps, int32_t cap,
+                              int32_t* count) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(count && (steps || cap == 0) && cap >= 0, "arguments");
+    const csrmf::BootCfg b = boot_cfg(cfg);
+    csrmf::boot_check(c, b);
+    const std::vector<int32_t> s = csrmf::boot_rotation_steps(c->N, b.n);
+    *count = (int32_t)s.size();
+    NEED((int32_t)s.size() <= cap, "steps array too small");
+    std::copy(s.begin(), s.end(), steps);
+    API_END(c)
+}
+
+int csrmf_bootstrap(csrmf_ctx* cx, const csrmf_boot_config* cfg, const uint64_t* in, int32_t n, uint64_t* out) {
+    Context* c = reinterpret_cast<Context*>(cx);
+    API_BEGIN(c)
+    NEED(in && out && n > 0, "arguments");
+    const csrmf::BootCfg b = boot_cfg(cfg);
+    std::vector<Ct*> v;
+    for (int i = 0; i < n; ++i) v.push_back(&c->get(in[i]));
+    std::vector<Ct> res;
+    csrmf::bootstrap(c, b, v, res);
     for (int i = 0; i < n; ++i) out[i] = c->put(res[i]);
     API_END(c)
 }

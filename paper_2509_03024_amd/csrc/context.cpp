@@ -1041,6 +1041,65 @@ void Context::mul_int(const Ct& a, int64_t w, Ct& out, double declared) {
     fence();
 }
 
+void Context::mul_plain_batch(const std::vector<Ct*>& a, const int64_t* m, double pt_scale, std::vector<Ct*>& out) {
+    const int B = (int)a.size();
+    if (B == 0) return;
+    const int lvl = a[0]->level;
+    for (Ct* c : a)
+        if (c->level != lvl) throw Error(CSRMF_E_INVAL, "batch operands must share a level");
+    const int nl = lvl + 1;
+    Scratch ex(pool, (size_t)nl * N);
+    const int64_t* src = (const int64_t*)stage(m, N * 8);
+    RowMap me;
+    me.base = ex.p;
+    for (int i = 0; i < nl; ++i) me.push(i, i);
+    launch_expand_signed(tabs, me, src, 1, 0, stream);
+    launch_ntt(tabs, me, false, stream);
+    std::vector<uint64_t> rc;
+    for (int i = 0; i < nl; ++i) { rc.push_back(mh[i].r_mod); rc.push_back(mh[i].r_mod_shoup); }
+    const uint64_t* rcd = (const uint64_t*)stage(rc.data(), rc.size() * 8);
+    launch_mul_const(tabs, me, me, rcd, false, stream);   // plaintext times 2^64
+    for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, a[i]->scale * pt_scale);
+    RowMap ma = map_cts(a, nl), mo = map_cts(out, nl);
+    RowMap mb = me;                                        // one plaintext for every batch element
+    mb.batch = B;
+    mb.batch_stride = 0;
+    launch_mul_mont(tabs, mo, ma, mb, false, stream);
+    for (int i = 0; i < nl; ++i) {
+        ma.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+        mo.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+    }
+    launch_mul_mont(tabs, mo, ma, mb, false, stream);
+    fence();
+}
+
+void Context::mod_raise(const std::vector<Ct*>& in, double scale, std::vector<Ct*>& out) {
+    const int B = (int)in.size();
+    if (B == 0) return;
+    for (Ct* c : in)
+        if (c->level != 0) throw Error(CSRMF_E_INVAL, "ModRaise takes ciphertexts at level 0");
+    // limb 0 of c0 and c1 back to coefficient form: [B][2][N]
+    Scratch coef(pool, 2 * (size_t)B * N);
+    RowMap src = map_cts(in, 1, 0);
+    src.push(L + 1, 0);
+    RowMap mc;
+    mc.base = coef.p;
+    mc.batch = B;
+    mc.batch_stride = 2 * (int64_t)N;
+    mc.poly_stride = (int64_t)N;
+    mc.push(0, 0);
+    mc.push(1, 0);
+    launch_ntt_from(tabs, mc, src, true, stream);
+    for (int i = 0; i < B; ++i) *out[i] = new_ct(L, scale);
+    RowMap o0 = map_cts(out, L + 1), o1 = o0;
+    for (int i = 0; i <= L; ++i) o1.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
+    launch_lift_centred(tabs, o0, coef.p, 2 * (int64_t)N, moduli[0], stream);
+    launch_lift_centred(tabs, o1, coef.p + N, 2 * (int64_t)N, moduli[0], stream);
+    launch_ntt(tabs, o0, false, stream);
+    launch_ntt(tabs, o1, false, stream);
+    fence();
+}
+
 void Context::mod_drop(Ct& c, int level) {
     if (level > c.level) throw Error(CSRMF_E_LEVEL, "cannot raise the level");
     c.level = level;

@@ -70,6 +70,11 @@ void launch_ntt_from(const DevTables& t, const RowMap& rows, const RowMap& src, 
 void launch_expand_signed(const DevTables& t, const RowMap& out, const int64_t* src, int n_src,
                           int64_t src_batch_stride, hipStream_t s);
 
+// out row (b, k) = the residue mod the row's prime of the centred integer of
+// src[b*src_batch_stride + i] (residues mod q0, coefficient form): ModRaise.
+void launch_lift_centred(const DevTables& t, const RowMap& out, const uint64_t* src, int64_t src_batch_stride,
+                         uint64_t q0, hipStream_t s);
+
 enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_NEG = 2, EW_COPY = 3, EW_F64C = 4, EW_F64U = 5 };
 // out = a (op) b (EW_NEG: out = -a; EW_COPY: out = a; EW_F64C: rows of primes
 // below 2^44 become their centred values as raw doubles, the others are

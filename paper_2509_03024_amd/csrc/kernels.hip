@@ -459,6 +459,23 @@ __global__ void __launch_bounds__(kThreads) k_expand_signed(DevTables t, RowMap 
     }
 }
 
+// ModRaise: residues x mod q_0 (coefficient form) read as the centred integer
+// in (-q_0/2, q_0/2] and taken modulo the row's prime.
+__global__ void __launch_bounds__(kThreads) k_lift_centred(DevTables t, RowMap out, const uint64_t* src, int64_t sbs,
+                                                            uint64_t q0) {
+    EW_PROLOGUE(out)
+    int mod;
+    uint64_t* o = map_row(out, b, k, logN, mod);
+    const uint64_t q = t.mods[mod].q;
+    const uint64_t* s = src + (int64_t)b * sbs;
+    const uint64_t half = q0 >> 1;
+    for (int u = 0; u < kEwPerThread; ++u) {
+        const int i = base_i + u * kThreads;
+        const uint64_t x = s[i];
+        o[i] = x > half ? from_signed(-(int64_t)(q0 - x), q) : from_signed((int64_t)x, q);
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) k_ew(DevTables t, int op, RowMap out, RowMap a, RowMap bm) {
     EW_PROLOGUE(out)
     int mod, ma, mb;
@@ -1106,6 +1123,12 @@ void launch_expand_signed(const DevTables& t, const RowMap& out, const int64_t* 
                           hipStream_t s) {
     if (!out.rows()) return;
     { ProfScope ps_("k_expand_signed", s, NB(out.rows()) * 2); hipLaunchKernelGGL(k_expand_signed, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, src, n_src, sbs); }
+}
+
+void launch_lift_centred(const DevTables& t, const RowMap& out, const uint64_t* src, int64_t sbs, uint64_t q0,
+                         hipStream_t s) {
+    if (!out.rows()) return;
+    { ProfScope ps_("k_lift_centred", s, NB(out.rows()) * 2); hipLaunchKernelGGL(k_lift_centred, dim3(ew_blocks(t, out)), dim3(kThreads), 0, s, t, out, src, sbs, q0); }
 }
 
 void launch_ew(const DevTables& t, EwOp op, const RowMap& out, const RowMap& a, const RowMap& b, hipStream_t s) {
