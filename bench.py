@@ -16,7 +16,7 @@ Default run (one JSON line):
   (943 x 1682, 99,926 ratings, k = 10, N = 2^15, two table refreshes);
 * "tiny": the latency of one encrypted MF epoch at the tiny configuration
   (32 x 64, 205 ratings, k = 4, N = 2^12);
-* "bootstrap": bootstrapping a batch of 8 ciphertexts at N = 2^16 (MF chain,
+* "bootstrap": bootstrapping a batch of 16 ciphertexts at N = 2^16 (MF chain,
   16-periodic slots, 18 levels) back from level 0, ciphertexts per second;
 * "cpu_baseline" legs: the oracle on bounded samples of each workload, run
   in parallel processes after the GPU work.
@@ -535,7 +535,7 @@ def run_tiny(reps=3):
 
 # ---------------------------------------------------------------- bootstrapping
 BOOT_CFG = (16, 10, 16, 13)     # n slots, squarings r, series degree d, pre-multiplication bits
-BOOT_BATCH = 8
+BOOT_BATCH = 16
 
 
 def run_boot(batch=BOOT_BATCH, reps=3):
@@ -553,10 +553,11 @@ def run_boot(batch=BOOT_BATCH, reps=3):
     n = BOOT_CFG[0]
     t0 = time.perf_counter()
     ctx.keygen(ctx.boot_rotation_steps(cfg), conj=True)
+    ctx.autotune()
     vals = [np.tile(np.random.default_rng(300 + i).uniform(-1, 1, n), ctx.N // (2 * n)) for i in range(batch)]
     cts = [ctx.encrypt(v, level=0, scale=2.0 ** 40) for v in vals]
     ctx.sync()
-    log(f"bootstrap: keys and inputs {time.perf_counter() - t0:.1f} s")
+    log(f"bootstrap: keys, schedule and inputs {time.perf_counter() - t0:.1f} s")
     for h in ctx.bootstrap(cts, cfg):          # warm-up
         ctx.free(h)
     ctx.sync()

@@ -209,7 +209,9 @@ Batch hmult(Context* c, Batch& a, Batch& b) {
     return out;
 }
 
-// acc += rot(in, d) x diag_d for d < count, the rotations hoisted (one ModUp)
+// acc += rot(in, d) x diag_d for d < count, the rotations hoisted (one ModUp),
+// each product accumulated by the multiply kernel itself (modular sums are
+// exact, so the bits are those of separate products and additions)
 void hoisted_mac(Context* c, Batch& in, int count, const std::vector<std::vector<int64_t>>& pts, double pt_scale,
                  Batch& acc, bool& have) {
     Context::Hoist h;
@@ -218,20 +220,19 @@ void hoisted_mac(Context* c, Batch& in, int count, const std::vector<std::vector
         c->hoist_begin(h, pi);
     }
     for (int d = 0; d < count; ++d) {
-        Batch t(c, 0);
-        if (d == 0) {
-            t = mul_plain(c, in, pts[0], pt_scale);
-        } else {
-            Batch rot(c, in.size());
+        Batch rot(c, 0);
+        if (d > 0) {
+            rot = Batch(c, in.size());
             std::vector<Ct*> po = rot.ptrs();
             c->hoist_rotate(h, c->galois_for_step(d), po);
-            t = mul_plain(c, rot, pts[d], pt_scale);
         }
+        Batch& src = d == 0 ? in : rot;
         if (!have) {
-            acc = std::move(t);
+            acc = mul_plain(c, src, pts[d], pt_scale);
             have = true;
         } else {
-            acc = add(c, acc, t);
+            std::vector<Ct*> ps = src.ptrs(), pa = acc.ptrs();
+            c->mul_plain_batch(ps, pts[d].data(), pt_scale, pa, true);
         }
     }
 }

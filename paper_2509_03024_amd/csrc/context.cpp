@@ -1041,12 +1041,18 @@ void Context::mul_int(const Ct& a, int64_t w, Ct& out, double declared) {
     fence();
 }
 
-void Context::mul_plain_batch(const std::vector<Ct*>& a, const int64_t* m, double pt_scale, std::vector<Ct*>& out) {
+void Context::mul_plain_batch(const std::vector<Ct*>& a, const int64_t* m, double pt_scale, std::vector<Ct*>& out,
+                              bool accumulate) {
     const int B = (int)a.size();
     if (B == 0) return;
     const int lvl = a[0]->level;
     for (Ct* c : a)
         if (c->level != lvl) throw Error(CSRMF_E_INVAL, "batch operands must share a level");
+    if (accumulate)
+        for (int i = 0; i < B; ++i) {
+            if (out[i]->level != lvl) throw Error(CSRMF_E_INVAL, "accumulator must have the operand's level");
+            check_scales(out[i]->scale, a[i]->scale * pt_scale);
+        }
     const int nl = lvl + 1;
     Scratch ex(pool, (size_t)nl * N);
     const int64_t* src = (const int64_t*)stage(m, N * 8);
@@ -1059,17 +1065,18 @@ void Context::mul_plain_batch(const std::vector<Ct*>& a, const int64_t* m, doubl
     for (int i = 0; i < nl; ++i) { rc.push_back(mh[i].r_mod); rc.push_back(mh[i].r_mod_shoup); }
     const uint64_t* rcd = (const uint64_t*)stage(rc.data(), rc.size() * 8);
     launch_mul_const(tabs, me, me, rcd, false, stream);   // plaintext times 2^64
-    for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, a[i]->scale * pt_scale);
+    if (!accumulate)
+        for (int i = 0; i < B; ++i) *out[i] = new_ct(lvl, a[i]->scale * pt_scale);
     RowMap ma = map_cts(a, nl), mo = map_cts(out, nl);
     RowMap mb = me;                                        // one plaintext for every batch element
     mb.batch = B;
     mb.batch_stride = 0;
-    launch_mul_mont(tabs, mo, ma, mb, false, stream);
+    launch_mul_mont(tabs, mo, ma, mb, accumulate, stream);
     for (int i = 0; i < nl; ++i) {
         ma.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
         mo.e[i] = ((uint32_t)(L + 1 + i) << 8) | (uint32_t)i;
     }
-    launch_mul_mont(tabs, mo, ma, mb, false, stream);
+    launch_mul_mont(tabs, mo, ma, mb, accumulate, stream);
     fence();
 }
 

@@ -281,8 +281,11 @@ struct Context {
     // ModRaise of level-0 ciphertexts: out[i] (level L, scale `scale`) holds the
     // centred residues of in[i] mod q_0 taken modulo every q_j
     void mod_raise(const std::vector<Ct*>& in, double scale, std::vector<Ct*>& out);
-    // out[i] = a[i] x m for one plaintext m (signed coefficients) shared by the batch
-    void mul_plain_batch(const std::vector<Ct*>& a, const int64_t* m, double pt_scale, std::vector<Ct*>& out);
+    // out[i] = a[i] x m for one plaintext m (signed coefficients) shared by the batch;
+    // with accumulate, out[i] += a[i] x m into existing ciphertexts of a[i]'s level
+    // and scale a[i].scale * pt_scale (their scale is kept)
+    void mul_plain_batch(const std::vector<Ct*>& a, const int64_t* m, double pt_scale, std::vector<Ct*>& out,
+                         bool accumulate = false);
     // out[i] = tau_g(in[i]) key-switched; with acc, out[i] = acc[i] + that (fused)
     void rotate(const std::vector<Ct*>& in, uint32_t g, std::vector<Ct*>& out, const std::vector<Ct*>* acc = nullptr);
     void rotate_hoisted(const Ct& in, const std::vector<uint32_t>& gs, std::vector<Ct*>& out);
