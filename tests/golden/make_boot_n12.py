@@ -7,10 +7,13 @@ slot values V[i] tiled with period N_SLOTS over the N/2 slots, V[i] drawn
 uniformly from [-1, 1) by numpy's default_rng(100 + i).  Both are bootstrapped
 with n = 4 slots, r = 9 squarings, a degree-11 series, pre-multiplication by
 2^12; the file holds the inputs' and the outputs' digests, the outputs' level
-and scale, and the largest slot error of the oracle's own decryption.
+and scale, and the largest slot error of the oracle's own decryption.  Edge
+case: a third ciphertext (serial 2), one value default_rng(99) in every slot,
+encrypted at level 2, bootstrapped with n = 1 (no rotation in CoeffToSlot,
+log2(N/2) steps of SubSum) under the same keys.
 
 Only oracle/ and the seeded inputs below are used.  Run from the repository
-root (about four minutes on one core):
+root (about six minutes on one core):
     python tests/golden/make_boot_n12.py
 """
 import hashlib
@@ -38,6 +41,17 @@ def chain():
 
 def config():
     return bootstrap.BootConfig(n=N_SLOTS, r=SQUARINGS, d=DEGREE, pre_bits=PRE_BITS)
+
+
+def edge_config():
+    return bootstrap.BootConfig(n=1, r=SQUARINGS, d=DEGREE, pre_bits=PRE_BITS)
+
+
+EDGE_LEVEL = 2
+
+
+def edge_values(N):
+    return np.full(N // 2, np.random.default_rng(99).uniform(-1.0, 1.0))
 
 
 def values(i, N):
@@ -82,12 +96,20 @@ def main():
         err = max(err, float(np.max(np.abs(orc.decrypt(out) - values(i, prm.N)))))
         rows.append(("boot", i, out))
         print("bootstrap", i, "done, error so far", err, flush=True)
+    edge = orc.encrypt(edge_values(prm.N), level=EDGE_LEVEL, scale=SCALE)
+    rows.append(("edge_input", 0, edge))
+    out = bootstrap.bootstrap(orc, edge, edge_config())
+    edge_err = float(np.max(np.abs(orc.decrypt(out) - edge_values(prm.N))))
+    rows.append(("edge_boot", 0, out))
+    print("edge bootstrap done, error", edge_err, flush=True)
     lines = ["# Oracle bootstrapping on the N = 2^12 test chain (q_0 + 18 x 40-bit, 3 x 60-bit special, dnum 5);",
              f"# n = {N_SLOTS}, r = {SQUARINGS}, d = {DEGREE}, pre_bits = {PRE_BITS}; inputs encrypted at level 0",
              "# (serials 0, 1), slot values default_rng(100 + i).uniform(-1, 1, n) tiled; written by",
              "# tests/golden/make_boot_n12.py.",
              "# kind index level scale sha256(c0 || c1 as little-endian uint64 [level+1][N])",
-             f"#=max_abs_error {err!r}"]
+             "# edge_*: n = 1, input at level 2 (serial 2), one value in every slot;",
+             f"#=max_abs_error {err!r}",
+             f"#=edge_max_abs_error {edge_err!r}"]
     for kind, i, c in rows:
         lines.append(f"{kind} {i} {c.level} {c.scale!r} {digest(c.c0, c.c1)}")
     path = os.path.join(HERE, "boot_n12.txt")

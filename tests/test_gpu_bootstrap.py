@@ -32,20 +32,22 @@ def n12():
     cfg = pk.BootConfig(gold.N_SLOTS, gold.SQUARINGS, gold.DEGREE, gold.PRE_BITS)
     ctx.keygen(ctx.boot_rotation_steps(cfg), conj=True)
     cts = [ctx.encrypt(gold.values(i, ctx.N), level=0, scale=gold.SCALE) for i in range(gold.N_CT)]
-    yield pk, ctx, cfg, cts, golden
+    edge = ctx.encrypt(gold.edge_values(ctx.N), level=gold.EDGE_LEVEL, scale=gold.SCALE)   # serial 2
+    yield pk, ctx, cfg, cts + [edge], golden
     ctx.close()
 
 
 def test_inputs_equal_the_oracles(n12):
     pk, ctx, cfg, cts, golden = n12
-    for i, h in enumerate(cts):
+    for i, h in enumerate(cts[:2]):
         assert _digest_of(ctx, h) == golden[("input", i)], f"input {i}"
+    assert _digest_of(ctx, cts[2]) == golden[("edge_input", 0)]
 
 
 def test_bootstrap_batch_matches_the_oracle(n12):
     pk, ctx, cfg, cts, golden = n12
     assert pk.boot_levels(cfg) == 17
-    out = ctx.bootstrap(cts, cfg)
+    out = ctx.bootstrap(cts[:2], cfg)
     for i, h in enumerate(out):
         lvl, scale, dg = _digest_of(ctx, h)
         want = golden[("boot", i)]
@@ -64,6 +66,16 @@ def test_bootstrap_of_one_ciphertext_matches_the_oracle(n12):
     ctx.free(out[0])
 
 
+def test_bootstrap_one_slot_from_level_2_matches_the_oracle(n12):
+    """n = 1 (CoeffToSlot without rotations, the longest SubSum), the input given
+    at level 2 (the bootstrap drops it to level 0 itself)."""
+    pk, ctx, cfg, cts, golden = n12
+    out = ctx.bootstrap([cts[2]], pk.BootConfig(1, gold.SQUARINGS, gold.DEGREE, gold.PRE_BITS))
+    assert _digest_of(ctx, out[0]) == golden[("edge_boot", 0)]
+    assert np.max(np.abs(ctx.decrypt(out[0]) - gold.edge_values(ctx.N))) < 1e-3
+    ctx.free(out[0])
+
+
 def test_bootstrap_argument_errors(n12):
     pk, ctx, cfg, cts, golden = n12
     with pytest.raises(pk.CsrmfError):
@@ -75,6 +87,8 @@ def test_bootstrap_argument_errors(n12):
     other = ctx.mul_int(cts[0], 3)
     with pytest.raises(pk.CsrmfError):
         ctx.bootstrap([cts[1], other], cfg)                                                   # scales differ
+    with pytest.raises(pk.CsrmfError):
+        ctx.bootstrap([], cfg)                                                                # empty batch
     ctx.free(other)
 
 

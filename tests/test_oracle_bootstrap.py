@@ -226,6 +226,7 @@ def test_golden_records_an_accurate_bootstrap():
     from tests.golden import make_boot_n12 as gold
     _, meta = gold.read(os.path.join(HERE, "golden", "boot_n12.txt"))
     assert 0 < meta["max_abs_error"] < 1e-3
+    assert 0 < meta["edge_max_abs_error"] < 1e-3
 
 
 @pytest.mark.slow
