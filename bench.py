@@ -72,19 +72,26 @@ KS_COUNTER_BYTES_PER_STEP = 575.6e9
 
 def traffic_of(name, schedule, alg_bytes):
     """Measured HBM bytes per launch of kernel `name` under `schedule`
-    ((NTT rows per pair of passes, column-pass stages)), with their basis."""
+    ((NTT rows per pair of passes, column-pass stages)), with their basis.
+    Launches of another size (another schedule, or another workload's batch)
+    get the measured bytes scaled by their algorithmic bytes."""
     t = TRAFFIC.get(name)
     if t is None:
         return None, None
+    same_size = abs(alg_bytes / t["alg_bytes"] - 1.0) <= 0.01
     if t["schedule"] is None:
-        return t["bytes"], "rocprofv3 counters"
+        if same_size:
+            return t["bytes"], "rocprofv3 counters"
+        return round(t["bytes"] / t["alg_bytes"] * alg_bytes), \
+            "rocprofv3 counters on the kernel-batch launches, scaled by algorithmic bytes"
     rows, split = schedule
     if split != t["split"]:
         return None, f"not measured at NTT split {split} (counters taken at split {t['split']})"
-    if t["schedule"] == rows:
+    if t["schedule"] == rows and same_size:
         return t["bytes"], f"rocprofv3 counters at NTT schedule {rows}"
     return round(t["bytes"] / t["alg_bytes"] * alg_bytes), \
-        f"rocprofv3 counters at NTT schedule {t['schedule']}, scaled by algorithmic bytes to schedule {rows}"
+        f"rocprofv3 counters at NTT schedule {t['schedule']}, scaled by algorithmic bytes to launches of " \
+        f"{round(alg_bytes / 1e6, 1)} MB at schedule {rows}"
 
 
 def parse():

@@ -42,6 +42,18 @@ def test_traffic_under_another_schedule_scales_with_the_launch():
     assert "scaled" in basis and str(other) in basis
 
 
+def test_traffic_of_smaller_launches_is_scaled():
+    """Another workload's launches (a smaller batch) at the measured schedule:
+    the counters are scaled by the algorithmic bytes, not reported as measured."""
+    b = _bench()
+    b.TRAFFIC = dict(_T)
+    for name, t in b.TRAFFIC.items():
+        sched = (512, 8) if t["schedule"] is None else (t["schedule"], t["split"])
+        val, basis = b.traffic_of(name, sched, t["alg_bytes"] / 4)
+        assert abs(val - t["bytes"] / 4) <= 1.0
+        assert "scaled" in basis
+
+
 def test_traffic_under_another_split_is_not_measured():
     """A different split of the transform's stages changes the passes' access
     pattern: their counters do not carry over."""
