@@ -21,6 +21,9 @@ evaluated by a Taylor series and repeated squaring:
   EvalMod     exp(i theta) by its Taylor series of degree d, squared r times:
               exp(2 pi i t'/q_0), whose imaginary part sin(2 pi m/q_0) no longer
               sees q_0 I;
+  (arcsine)   optionally D - D^3/24 in place of D = 2 i sin: (s + s^3/6) 2 i, the
+              first two terms of arcsin, so that a larger message (more of q_0)
+              keeps the linearisation error small;
   SlotToCoeff the linear map from those 2n values back to the n slots, with the
               factor q_0 / (2 pi) folded in.
 
@@ -60,12 +63,13 @@ class BootConfig:
     r: int           # squarings of the exponential
     d: int           # degree of the Taylor series of exp
     pre_bits: int    # the level-0 input is multiplied by 2^pre_bits before ModRaise
+    arcsine: bool = False   # add the cubic term of arcsin after EvalMod (2 more levels)
 
 
 def levels_used(cfg):
     """Levels one bootstrap consumes: 2 (CoeffToSlot) + ceil(log2 d) + 1 (series)
-    + r (squarings) + 1 (SlotToCoeff)."""
-    return 2 + (cfg.d - 1).bit_length() + 1 + cfg.r + 1
+    + r (squarings) + 2 with the arcsine term + 1 (SlotToCoeff)."""
+    return 2 + (cfg.d - 1).bit_length() + 1 + cfg.r + (2 if cfg.arcsine else 0) + 1
 
 
 def rotation_steps(N, n):
@@ -245,6 +249,18 @@ def eval_mod(ctx, x, d, r, target):
     return ctx.sub(e, ctx.conjugate(e))
 
 
+def arcsine_term(ctx, D):
+    """D - D^3 / 24 for D = 2 i s: 2 i (s + s^3 / 6).  D^2 = D D; the constant
+    -1/24 multiplies D with the plaintext scale q_l q_{l-1} / scale(D^2), so that
+    D^2 times it lands on D's scale; the sum keeps D's scale."""
+    q = ctx.prm.q
+    d2 = ctx.hmult(D, D)
+    delta = (float(q[D.level]) * float(q[D.level - 1])) / d2.scale
+    t = ctx.rescale(ctx.mul_plain(D, encode_const(ctx.N, (-1.0 / 24.0, 0.0), delta), delta))
+    d3 = ctx.hmult(d2, t)
+    return ctx.add(ctx.mod_drop(D, d3.level), d3)
+
+
 def slot_to_coeff(ctx, ct, n, gamma, target):
     """Sum over d < 2n of rot(ct, d) times diagonal d of gamma B', one rescale onto
     `target`: the integers carry gamma, the declared plaintext scale does not."""
@@ -281,6 +297,8 @@ def bootstrap(ctx, ct, cfg, target=None):
     c = sub_sum(ctx, c, cfg.n)
     c = coeff_to_slot(ctx, c, cfg.n, target)
     c = eval_mod(ctx, c, cfg.d, cfg.r, target)
+    if cfg.arcsine:
+        c = arcsine_term(ctx, c)
     return slot_to_coeff(ctx, c, cfg.n, gamma, target)
 
 

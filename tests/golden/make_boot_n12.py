@@ -10,10 +10,13 @@ with n = 4 slots, r = 9 squarings, a degree-11 series, pre-multiplication by
 and scale, and the largest slot error of the oracle's own decryption.  Edge
 case: a third ciphertext (serial 2), one value default_rng(99) in every slot,
 encrypted at level 2, bootstrapped with n = 1 (no rotation in CoeffToSlot,
-log2(N/2) steps of SubSum) under the same keys.
+log2(N/2) steps of SubSum) under the same keys.  Arcsine case: a fourth
+ciphertext (serial 3, values default_rng(98).uniform(-1, 1, 4) tiled) at
+level 0 bootstrapped with the arcsine term, r = 8, a degree-16 series and
+2^15 pre-multiplication (18 levels: the whole chain).
 
 Only oracle/ and the seeded inputs below are used.  Run from the repository
-root (about six minutes on one core):
+root (about eight minutes on one core):
     python tests/golden/make_boot_n12.py
 """
 import hashlib
@@ -48,6 +51,14 @@ def edge_config():
 
 
 EDGE_LEVEL = 2
+
+
+def arcsine_config():
+    return bootstrap.BootConfig(n=N_SLOTS, r=8, d=16, pre_bits=15, arcsine=True)
+
+
+def arcsine_values(N):
+    return np.tile(np.random.default_rng(98).uniform(-1.0, 1.0, N_SLOTS), N // 2 // N_SLOTS)
 
 
 def edge_values(N):
@@ -102,6 +113,12 @@ def main():
     edge_err = float(np.max(np.abs(orc.decrypt(out) - edge_values(prm.N))))
     rows.append(("edge_boot", 0, out))
     print("edge bootstrap done, error", edge_err, flush=True)
+    asn = orc.encrypt(arcsine_values(prm.N), level=0, scale=SCALE)
+    rows.append(("arcsine_input", 0, asn))
+    out = bootstrap.bootstrap(orc, asn, arcsine_config())
+    asn_err = float(np.max(np.abs(orc.decrypt(out) - arcsine_values(prm.N))))
+    rows.append(("arcsine_boot", 0, out))
+    print("arcsine bootstrap done, error", asn_err, flush=True)
     lines = ["# Oracle bootstrapping on the N = 2^12 test chain (q_0 + 18 x 40-bit, 3 x 60-bit special, dnum 5);",
              f"# n = {N_SLOTS}, r = {SQUARINGS}, d = {DEGREE}, pre_bits = {PRE_BITS}; inputs encrypted at level 0",
              "# (serials 0, 1), slot values default_rng(100 + i).uniform(-1, 1, n) tiled; written by",
@@ -109,7 +126,9 @@ def main():
              "# kind index level scale sha256(c0 || c1 as little-endian uint64 [level+1][N])",
              "# edge_*: n = 1, input at level 2 (serial 2), one value in every slot;",
              f"#=max_abs_error {err!r}",
-             f"#=edge_max_abs_error {edge_err!r}"]
+             "# arcsine_*: n = 4, r = 8, d = 16, pre_bits = 15 with the arcsine term (serial 3);",
+             f"#=edge_max_abs_error {edge_err!r}",
+             f"#=arcsine_max_abs_error {asn_err!r}"]
     for kind, i, c in rows:
         lines.append(f"{kind} {i} {c.level} {c.scale!r} {digest(c.c0, c.c1)}")
     path = os.path.join(HERE, "boot_n12.txt")

@@ -10,7 +10,7 @@ mathematics fixes rather than against the oracle itself:
   level-0 plaintext plus q_0 times small integers;
 * SubSum: the decryption is N/2n times the coefficients at multiples of N/2n;
 * the series and EvalMod against the same recipe in plain complex numbers and
-  against 2 i sin(2^r theta);
+  against 2 i sin(2^r theta); the arcsine term against 2 i (s + s^3/6);
 * the whole bootstrap (slow: minutes) decrypts to its input within 1e-3."""
 import math
 import os
@@ -128,6 +128,7 @@ def test_slot_to_coeff_diagonals(n):
 def test_levels_and_rotation_steps():
     assert bs.levels_used(bs.BootConfig(n=4, r=9, d=11, pre_bits=12)) == 17
     assert bs.levels_used(bs.BootConfig(n=1, r=0, d=1, pre_bits=0)) == 4
+    assert bs.levels_used(bs.BootConfig(n=4, r=8, d=16, pre_bits=15, arcsine=True)) == 18
     assert bs.rotation_steps(4096, 4) == [1, 2, 3, 4, 5, 6, 7, 8, 16, 32, 64, 128, 256, 512, 1024]
     assert bs.rotation_steps(64, 16) == list(range(1, 32))
     assert bs.raise_scale(64, 97, 4, 3) == (64.0 * 97.0 * 8.0) / (4.0 * math.pi * 4.0)
@@ -200,6 +201,19 @@ def test_exp_series_and_eval_mod(tiny2):
     assert np.max(np.abs(got - 2j * np.sin(4 * theta))) < 1e-4
 
 
+def test_arcsine_term(tiny2):
+    c = tiny2
+    sv = np.random.default_rng(8).uniform(-0.3, 0.3, c.N // 2)
+    ct = c.encrypt(sv)
+    S = c.prm.scale
+    D = c.rescale(c.mul_plain(ct, bs.encode_const(c.N, (0.0, 2.0), S), S))    # 2 i s
+    out = bs.arcsine_term(c, D)
+    assert out.level == D.level - 2 and abs(out.scale / D.scale - 1) < 1e-12
+    got = _decrypt_complex(c, out)
+    assert np.max(np.abs(got - 2j * (sv + sv ** 3 / 6))) < 1e-6
+    assert np.max(np.abs(got - 2j * np.arcsin(sv))) < 2 * (np.arcsin(0.3) - 0.3 - 0.3 ** 3 / 6) + 1e-6
+
+
 def test_coeff_to_slot_and_slot_to_coeff_values(tiny2):
     c = tiny2
     n = 4
@@ -227,6 +241,7 @@ def test_golden_records_an_accurate_bootstrap():
     _, meta = gold.read(os.path.join(HERE, "golden", "boot_n12.txt"))
     assert 0 < meta["max_abs_error"] < 1e-3
     assert 0 < meta["edge_max_abs_error"] < 1e-3
+    assert 0 < meta["arcsine_max_abs_error"] < 1e-3
 
 
 @pytest.mark.slow
