@@ -17,7 +17,7 @@ Default run (one JSON line):
 * "tiny": the latency of one encrypted MF epoch at the tiny configuration
   (32 x 64, 205 ratings, k = 4, N = 2^12);
 * "bootstrap": bootstrapping a batch of 16 ciphertexts at N = 2^16 (MF chain,
-  16-periodic slots, 18 levels) back from level 0, ciphertexts per second;
+  16-periodic slots, 20 levels) back from level 0, ciphertexts per second;
 * "cpu_baseline" legs: the oracle on bounded samples of each workload, run
   in parallel processes after the GPU work.
 
@@ -541,14 +541,14 @@ def run_tiny(reps=3):
 
 
 # ---------------------------------------------------------------- bootstrapping
-BOOT_CFG = (16, 10, 16, 13)     # n slots, squarings r, series degree d, pre-multiplication bits
+BOOT_CFG = (16, 10, 16, 15, 1)  # n slots, squarings r, series degree d, pre-multiplication bits, arcsine term
 BOOT_BATCH = 16
 
 
 def run_boot(batch=BOOT_BATCH, reps=3):
     """Bootstrapping at N = 2^16 on the MF chain (q_0 + 24 x 40-bit, 3 x 60-bit
     special, dnum 7): a batch of level-0 ciphertexts with 16-periodic slots back
-    to level L - 18, every step on the device; ciphertexts per second over the
+    to level L - 20, every step on the device; ciphertexts per second over the
     timed batches, the key switches they ran, and the largest slot error of the
     outputs against the inputs."""
     import numpy as np
@@ -595,6 +595,7 @@ def run_boot(batch=BOOT_BATCH, reps=3):
         "max_abs_error": err,
         "config": {"workload": f"bootstrapping, N=2^16, q_0 + 24 x 40-bit, dnum 7, n={n} slots, "
                                f"r={BOOT_CFG[1]}, degree {BOOT_CFG[2]}, pre-multiplication 2^{BOOT_CFG[3]}, "
+                               f"{'with' if BOOT_CFG[4] else 'without'} the arcsine term, "
                                f"batch of {batch}, |values| <= 1"},
         "roofline": dominant_roofline(prof, (sched["ntt_chunk_rows"], sched["ntt_split"])),
         "kernels": kernel_table(prof),

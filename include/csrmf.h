@@ -269,16 +269,20 @@ int csrmf_conjugate_batch(csrmf_ctx* ctx, const uint64_t* a, int32_t n, uint64_t
  *   degree     d (1..18): the series' degree (11 keeps its error below 2^-32
  *              for arguments up to 0.8);
  *   pre_bits   the level-0 input is multiplied by 2^pre_bits before ModRaise,
- *              so that the message uses about 2^-8 of q_0 (precision against
- *              the linearisation sin x ~ x). */
+ *              so that the message uses about 2^-8 of q_0 (2^-6 with arcsine;
+ *              precision against the linearisation sin x ~ x);
+ *   arcsine    1: after EvalMod, D - D^3/24 (D = 2 i sin), the cubic term of
+ *              arcsin, two more levels; 0: none. */
 typedef struct csrmf_boot_config {
     int32_t n_slots;
     int32_t squarings;
     int32_t degree;
     int32_t pre_bits;
+    int32_t arcsine;
 } csrmf_boot_config;
 
-/* Levels one bootstrap consumes: 2 + ceil(log2 degree) + 1 + squarings + 1.
+/* Levels one bootstrap consumes: 2 + ceil(log2 degree) + 1 + squarings
+ * (+ 2 with arcsine) + 1.
  * Errors: INVAL (null arguments). */
 int csrmf_boot_levels(const csrmf_boot_config* cfg, int32_t* levels);
 

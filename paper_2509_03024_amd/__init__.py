@@ -55,7 +55,7 @@ class Params(ctypes.Structure):
 class BootConfig(ctypes.Structure):
     """Bootstrapping parameters (csrmf_boot_config)."""
     _fields_ = [("n_slots", ctypes.c_int32), ("squarings", ctypes.c_int32),
-                ("degree", ctypes.c_int32), ("pre_bits", ctypes.c_int32)]
+                ("degree", ctypes.c_int32), ("pre_bits", ctypes.c_int32), ("arcsine", ctypes.c_int32)]
 
 _p = ctypes.c_void_p
 _u64p = ctypes.POINTER(ctypes.c_uint64)

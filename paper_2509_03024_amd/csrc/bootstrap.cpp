@@ -14,7 +14,9 @@
 //                theta = 2 pi t' / (q_0 2^r) (one conjugation, two hoisted
 //                fan-outs of n rotations, two rescales);
 //   EvalMod      exp(i theta) = sum_{k<=d} (i theta)^k / k!, squared r times,
-//                minus its conjugate: 2 i sin(2 pi m / q_0), free of q_0 I;
+//                minus its conjugate: D = 2 i sin(2 pi m / q_0), free of q_0 I;
+//   (arcsine)    optionally D - D^3/24 = 2 i (s + s^3/6), the first two terms of
+//                arcsin, so that the message may use more of q_0;
 //   SlotToCoeff  back to the n slots with q_0 / (4 pi i) folded in (one hoisted
 //                fan-out of 2n rotations, one rescale).
 //
@@ -240,7 +242,7 @@ void hoisted_mac(Context* c, Batch& in, int count, const std::vector<std::vector
 }  // namespace
 
 int boot_levels(const BootCfg& cfg) {
-    return 2 + log2_exact((uint64_t)cfg.d) + 1 + cfg.r + 1;
+    return 2 + log2_exact((uint64_t)cfg.d) + 1 + cfg.r + (cfg.arcsine ? 2 : 0) + 1;
 }
 
 std::vector<int32_t> boot_rotation_steps(uint64_t N, int n) {
@@ -372,6 +374,16 @@ void bootstrap(Context* c, const BootCfg& cfg, const std::vector<Ct*>& in, std::
     {
         Batch ej = rotate(c, e, g_conj);
         e = add(c, e, ej, true);
+    }
+    if (cfg.arcsine) {
+        // D^2; D times -1/24 at plaintext scale q_l q_{l-1} / scale(D^2), so that
+        // the product of the two lands on D's scale; D + that keeps D's scale
+        Batch d2 = hmult(c, e, e);
+        const double delta = ((double)c->moduli[e.level()] * (double)c->moduli[e.level() - 1]) / d2.scale();
+        Batch t = mul_plain(c, e, encode_const(N, Cplx{-1.0 / 24.0, 0.0}, delta), delta);
+        rescale(c, t);
+        Batch d3 = hmult(c, d2, t);
+        e = add(c, e, d3);
     }
 
     // SlotToCoeff: integers carry gamma, the declared plaintext scale does not

@@ -13,9 +13,11 @@ struct BootCfg {
     int r = 0;          // squarings of the exponential
     int d = 0;          // degree of exp's Taylor series (1..18)
     int pre_bits = 0;   // the level-0 input is multiplied by 2^pre_bits
+    bool arcsine = false;   // add the cubic term of arcsin after EvalMod (2 more levels)
 };
 
-// Levels one bootstrap consumes: 2 + ceil(log2 d) + 1 + r + 1.
+// Levels one bootstrap consumes: 2 + ceil(log2 d) + 1 + r (+ 2 with the arcsine
+// term) + 1.
 int boot_levels(const BootCfg& cfg);
 // Rotation steps whose keys a bootstrap needs (besides relinearisation and
 // conjugation), ascending.

@@ -420,11 +420,13 @@ static csrmf::BootCfg boot_cfg(const csrmf_boot_config* cfg) {
     b.r = cfg->squarings;
     b.d = cfg->degree;
     b.pre_bits = cfg->pre_bits;
+    NEED(cfg->arcsine == 0 || cfg->arcsine == 1, "arcsine must be 0 or 1");
+    b.arcsine = cfg->arcsine != 0;
     return b;
 }
 
 int csrmf_boot_levels(const csrmf_boot_config* cfg, int32_t* levels) {
-    if (!cfg || !levels || cfg->degree < 1) return CSRMF_E_INVAL;
+    if (!cfg || !levels || cfg->degree < 1 || (cfg->arcsine != 0 && cfg->arcsine != 1)) return CSRMF_E_INVAL;
     *levels = csrmf::boot_levels(boot_cfg(cfg));
     return CSRMF_OK;
 }
