@@ -262,7 +262,8 @@ int csrmf_conjugate_batch(csrmf_ctx* ctx, const uint64_t* a, int32_t n, uint64_t
  * (exp(i theta) by a Taylor series of degree `degree`, squared `squarings`
  * times, minus its conjugate) and SlotToCoeff.
  *   n_slots    n: the message's slots repeat with period n (power of two,
- *              1..N/2); the output's slots repeat with the same period;
+ *              1..N/4: the linear maps use 2n-periodic vectors); the
+ *              output's slots repeat with the same period;
  *   squarings  r: the series' argument is 2 pi (m/q_0 + I) / 2^r, where
  *              |I| (about sqrt(N/18) for the dense ternary secret) must stay
  *              below K with 2 pi (K + 1/2) / 2^r below about 0.8;

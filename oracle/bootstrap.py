@@ -59,7 +59,7 @@ from .ckks import Ciphertext, galois_for_step
 
 @dataclass(frozen=True)
 class BootConfig:
-    n: int           # slots of the sparse packing (power of two, 1 <= n <= N/2)
+    n: int           # slots of the sparse packing (power of two, 1 <= n <= N/4)
     r: int           # squarings of the exponential
     d: int           # degree of the Taylor series of exp
     pre_bits: int    # the level-0 input is multiplied by 2^pre_bits before ModRaise
@@ -284,7 +284,7 @@ def raise_scale(N, q0, n, r):
 def bootstrap(ctx, ct, cfg, target=None):
     """Bootstrap ct (any level, its slots n-periodic) onto level L - levels_used."""
     N = ctx.N
-    assert cfg.n & (cfg.n - 1) == 0 and 1 <= cfg.n <= N // 2
+    assert cfg.n & (cfg.n - 1) == 0 and 1 <= cfg.n <= N // 4     # 2n-periodic vectors fit N/2 slots
     if levels_used(cfg) > ctx.prm.L:
         raise ValueError("not enough levels for this bootstrap")
     target = ctx.prm.scale if target is None else target

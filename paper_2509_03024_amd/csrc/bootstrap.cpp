@@ -261,8 +261,8 @@ std::vector<int32_t> boot_rotation_steps(uint64_t N, int n) {
 
 void boot_check(const Context* c, const BootCfg& cfg) {
     const int64_t n = cfg.n;
-    if (n < 1 || (n & (n - 1)) || (uint64_t)n > c->N / 2)
-        throw Error(CSRMF_E_INVAL, "bootstrap: n_slots must be a power of two in [1, N/2]");
+    if (n < 1 || (n & (n - 1)) || (uint64_t)n > c->N / 4)
+        throw Error(CSRMF_E_INVAL, "bootstrap: n_slots must be a power of two in [1, N/4]");
     if (cfg.d < 1 || cfg.d > 18) throw Error(CSRMF_E_INVAL, "bootstrap: degree must be in [1, 18]");
     if (cfg.r < 0 || cfg.r > 40) throw Error(CSRMF_E_INVAL, "bootstrap: squarings must be in [0, 40]");
     if (cfg.pre_bits < 0 || cfg.pre_bits > 30) throw Error(CSRMF_E_INVAL, "bootstrap: pre_bits must be in [0, 30]");

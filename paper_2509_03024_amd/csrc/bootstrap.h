@@ -9,7 +9,7 @@
 namespace csrmf {
 
 struct BootCfg {
-    int n = 0;          // slots of the sparse packing (power of two, 1..N/2)
+    int n = 0;          // slots of the sparse packing (power of two, 1..N/4)
     int r = 0;          // squarings of the exponential
     int d = 0;          // degree of exp's Taylor series (1..18)
     int pre_bits = 0;   // the level-0 input is multiplied by 2^pre_bits

@@ -95,6 +95,8 @@ def test_bootstrap_argument_errors(n12):
     with pytest.raises(pk.CsrmfError):
         ctx.bootstrap(cts, pk.BootConfig(3, gold.SQUARINGS, gold.DEGREE, gold.PRE_BITS))     # n not a power of 2
     with pytest.raises(pk.CsrmfError):
+        ctx.bootstrap(cts[:1], pk.BootConfig(ctx.N // 2, 0, 1, 0))                          # n above N/4
+    with pytest.raises(pk.CsrmfError):
         ctx.bootstrap(cts, pk.BootConfig(gold.N_SLOTS, 12, gold.DEGREE, gold.PRE_BITS))      # 20 levels > 18
     with pytest.raises(pk.CsrmfError):
         ctx.bootstrap(cts, pk.BootConfig(64, gold.SQUARINGS, gold.DEGREE, gold.PRE_BITS))    # keys for n = 64 absent

@@ -125,6 +125,13 @@ def test_slot_to_coeff_diagonals(n):
     assert np.allclose(out, np.tile(want, 2), atol=1e-12)
 
 
+def test_more_slots_than_a_quarter_ring_are_refused(tiny):
+    """The linear maps use 2n-periodic vectors, which must fit the N/2 slots."""
+    ct = tiny.encrypt(np.zeros(tiny.N // 2), level=0)
+    with pytest.raises(AssertionError):
+        bs.bootstrap(tiny, ct, bs.BootConfig(n=tiny.N // 2, r=0, d=1, pre_bits=0))
+
+
 def test_levels_and_rotation_steps():
     assert bs.levels_used(bs.BootConfig(n=4, r=9, d=11, pre_bits=12)) == 17
     assert bs.levels_used(bs.BootConfig(n=1, r=0, d=1, pre_bits=0)) == 4
