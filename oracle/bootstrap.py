@@ -17,7 +17,8 @@ evaluated by a Taylor series and repeated squaring:
               keeps the 2n coefficients t'_i = t_{i N/2n}, times N/2n;
   CoeffToSlot the linear map from the n slots to the 2n real coefficients,
               laid out 2n-periodically as [t'_0..t'_{n-1} | t'_n..t'_{2n-1}], read
-              as theta = 2 pi t' / (q_0 2^r);
+              as theta = 2 pi t' / (q_0 2^r): A + conj(A) for one diagonal sum A
+              over n rotations, then two rescales;
   EvalMod     exp(i theta) by its Taylor series of degree d, squared r times:
               exp(2 pi i t'/q_0), whose imaginary part sin(2 pi m/q_0) no longer
               sees q_0 I;
@@ -192,22 +193,23 @@ def _rescale_to(ctx, ct, times):
 
 def coeff_to_slot(ctx, ct, n, target):
     """[theta_lo | theta_hi] in 2n-periodic real slots, scale about `target`,
-    two levels lower.  The plaintext scale puts the scale after the two rescales
+    two levels lower.  The map on conj(x) has the conjugate diagonals
+    (D2_d = conj(D1_d)) and conjugation commutes with rotation, so the whole
+    map is A + conj(A) with A = sum_d D1_d rot(x, d): one fan-out of rotations
+    and one conjugation, the latter before the two rescales (at A's scale its
+    key-switching noise is negligible; after them the squarings of EvalMod
+    would amplify it).  The plaintext scale puts the scale after the rescales
     at target: Delta = (target q_l) q_{l-1} / scale."""
     lv = ct.level
     q = ctx.prm.q
     delta = ((target * float(q[lv])) * float(q[lv - 1])) / ct.scale
-    D1, D2 = cts_diagonals(n)
-    cj = ctx.conjugate(ct)
-    steps = list(range(n))
-    R = ctx.hoisted_rotations(ct, steps)
-    Rc = ctx.hoisted_rotations(cj, steps)
+    D1, _ = cts_diagonals(n)
+    R = ctx.hoisted_rotations(ct, list(range(n)))
     acc = None
     for d in range(n):
-        for rot, diag in ((R[d], D1[d]), (Rc[d], D2[d])):
-            t = ctx.mul_plain(rot, encode_periodic(ctx.N, diag, delta), delta)
-            acc = t if acc is None else ctx.add(acc, t)
-    return _rescale_to(ctx, acc, 2)
+        t = ctx.mul_plain(R[d], encode_periodic(ctx.N, D1[d], delta), delta)
+        acc = t if acc is None else ctx.add(acc, t)
+    return _rescale_to(ctx, ctx.add(acc, ctx.conjugate(acc)), 2)
 
 
 def _power_split(k):

@@ -114,6 +114,15 @@ def test_coeff_to_slot_diagonals(n):
 
 
 @pytest.mark.parametrize("n", [1, 2, 4, 8])
+def test_conjugate_map_has_the_conjugate_diagonals(n):
+    """What lets CoeffToSlot be A + conj(A): D2_d = conj(D1_d), exactly."""
+    D1, D2 = bs.cts_diagonals(n)
+    for d in range(n):
+        for (r1, i1), (r2, i2) in zip(D1[d], D2[d]):
+            assert r2 == r1 and i2 == -i1
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8])
 def test_slot_to_coeff_diagonals(n):
     rng = np.random.default_rng(20 + n)
     D = rng.uniform(-1, 1, 2 * n) + 1j * rng.uniform(-1, 1, 2 * n)
