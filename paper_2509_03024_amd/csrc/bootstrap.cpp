@@ -11,8 +11,8 @@
 //   SubSum       sum of rotations by n 2^j: N/2n times the coefficients
 //                t'_i = t_{i N/2n} of the trace onto Z[X^(N/2n)];
 //   CoeffToSlot  the 2n real t'_i into 2n-periodic slots, read as
-//                theta = 2 pi t' / (q_0 2^r) (one conjugation, two hoisted
-//                fan-outs of n rotations, two rescales);
+//                theta = 2 pi t' / (q_0 2^r): A + conj(A) for the diagonal sum A
+//                over one hoisted fan-out of n rotations, then two rescales;
 //   EvalMod      exp(i theta) = sum_{k<=d} (i theta)^k / k!, squared r times,
 //                minus its conjugate: D = 2 i sin(2 pi m / q_0), free of q_0 I;
 //   (arcsine)    optionally D - D^3/24 = 2 i (s + s^3/6), the first two terms of
@@ -131,14 +131,14 @@ std::vector<int64_t> encode_const(uint64_t N, Cplx c, double scale) {
     return m;
 }
 
-// CoeffToSlot's diagonals d < n on x (D1) and on conj(x) (D2), 2n-periodic:
-// with a_{j,c} = e(-2 5^c j)/n (P2 = 4n), the entries of the inverse of the
-// embedding restricted to Z[X^(N/2n)], slot j < n receives Re(sum_c a_{j,c} x_c)
-// and slot n + j receives Im(sum_c a_{j,c} x_c).
-void cts_diagonals(int n, std::vector<std::vector<Cplx>>& D1, std::vector<std::vector<Cplx>>& D2) {
+// CoeffToSlot's diagonals d < n (on x), 2n-periodic: with a_{j,c} = e(-2 5^c j)/n
+// (P2 = 4n), the entries of the inverse of the embedding restricted to
+// Z[X^(N/2n)], D_d[j] = a_{j mod n, (j+d) mod n} / 2 times 1 (j < n) or -i
+// (j >= n), so that A + conj(A), A = sum_d D_d rot(x, d), puts
+// Re(sum_c a_{j,c} x_c) in slot j < n and Im(sum_c a_{j,c} x_c) in slot n + j.
+std::vector<std::vector<Cplx>> cts_diagonals(int n) {
     const double inv = 1.0 / (2.0 * n);
-    D1.assign(n, std::vector<Cplx>(2 * n));
-    D2.assign(n, std::vector<Cplx>(2 * n));
+    std::vector<std::vector<Cplx>> D(n, std::vector<Cplx>(2 * n));
     for (int d = 0; d < n; ++d)
         for (int j = 0; j < 2 * n; ++j) {
             const int c = (j + d) % n;
@@ -146,14 +146,9 @@ void cts_diagonals(int n, std::vector<std::vector<Cplx>>& D1, std::vector<std::v
             root(-2 * pow5_mod(c, 8 * n) * (j % n), 4 * n, co, si);
             co = co * inv;
             si = si * inv;
-            if (j < n) {
-                D1[d][j] = {co, si};
-                D2[d][j] = {co, -si};
-            } else {
-                D1[d][j] = {si, -co};
-                D2[d][j] = {si, co};
-            }
+            D[d][j] = j < n ? Cplx{co, si} : Cplx{si, -co};
         }
+    return D;
 }
 
 // SlotToCoeff's diagonals d < 2n of B'_{j,c} = e(2 5^(j mod n) (c mod n)) times
@@ -318,17 +313,16 @@ void bootstrap(Context* c, const BootCfg& cfg, const std::vector<Ct*>& in, std::
     {
         const int lv = y.level();
         const double delta = ((target * (double)c->moduli[lv]) * (double)c->moduli[lv - 1]) / y.scale();
-        std::vector<std::vector<Cplx>> D1, D2;
-        cts_diagonals(n, D1, D2);
-        std::vector<std::vector<int64_t>> p1, p2;
-        for (int d = 0; d < n; ++d) {
-            p1.push_back(encode_periodic(N, D1[d], delta));
-            p2.push_back(encode_periodic(N, D2[d], delta));
-        }
-        Batch cj = rotate(c, y, g_conj);
+        // the map on conj(x) has the conjugate diagonals and conjugation
+        // commutes with rotation: the map is A + conj(A), A = sum_d D_d rot(x, d)
+        const std::vector<std::vector<Cplx>> D = cts_diagonals(n);
+        std::vector<std::vector<int64_t>> p1;
+        for (int d = 0; d < n; ++d) p1.push_back(encode_periodic(N, D[d], delta));
         bool have = false;
         hoisted_mac(c, y, n, p1, delta, theta, have);
-        hoisted_mac(c, cj, n, p2, delta, theta, have);
+        // the conjugation at A's scale, where its key-switching noise is negligible
+        Batch tj = rotate(c, theta, g_conj);
+        theta = add(c, theta, tj);
         rescale(c, theta);
         rescale(c, theta);
     }
