@@ -18,7 +18,7 @@ evaluated by a Taylor series and repeated squaring:
   CoeffToSlot the linear map from the n slots to the 2n real coefficients,
               laid out 2n-periodically as [t'_0..t'_{n-1} | t'_n..t'_{2n-1}], read
               as theta = 2 pi t' / (q_0 2^r): A + conj(A) for one diagonal sum A
-              over n rotations, then two rescales;
+              over n rotations (baby-step giant-step), then two rescales;
   EvalMod     exp(i theta) by its Taylor series of degree d, squared r times:
               exp(2 pi i t'/q_0), whose imaginary part sin(2 pi m/q_0) no longer
               sees q_0 I;
@@ -191,6 +191,37 @@ def _rescale_to(ctx, ct, times):
     return ct
 
 
+def bsgs_split(count):
+    """Baby steps B = 2^ceil(log2(count) / 2) and giant steps G = ceil(count / B)."""
+    B = 1 << (((count - 1).bit_length() + 1) // 2)
+    return B, -(-count // B)
+
+
+def linear_map(ctx, ct, diags, enc_scale, pt_scale):
+    """sum_{d < count} diag_d (.) rot(ct, d), no rescale, by baby-step giant-step:
+    with d = g B + b, diag_d (.) rot(x, d) = rot(rot(diag_d, -g B) (.) rot(x, b), g B),
+    so the B baby rotations share one ModUp (hoisted) and each giant step g > 0
+    rotates the sum of its B products once.  The diagonals are P-periodic complex
+    vectors; rot(v, -k)_j = v_{(j - k) mod P}."""
+    count, P = len(diags), len(diags[0])
+    B, G = bsgs_split(count)
+    R = ctx.hoisted_rotations(ct, list(range(B)))
+    acc = None
+    for g in range(G):
+        part = None
+        for b in range(B):
+            d = g * B + b
+            if d >= count:
+                break
+            shifted = [diags[d][(j - g * B) % P] for j in range(P)]
+            t = ctx.mul_plain(R[b], encode_periodic(ctx.N, shifted, enc_scale), pt_scale)
+            part = t if part is None else ctx.add(part, t)
+        if g > 0:
+            part = ctx.rotate(part, g * B)
+        acc = part if acc is None else ctx.add(acc, part)
+    return acc
+
+
 def coeff_to_slot(ctx, ct, n, target):
     """[theta_lo | theta_hi] in 2n-periodic real slots, scale about `target`,
     two levels lower.  The map on conj(x) has the conjugate diagonals
@@ -204,11 +235,7 @@ def coeff_to_slot(ctx, ct, n, target):
     q = ctx.prm.q
     delta = ((target * float(q[lv])) * float(q[lv - 1])) / ct.scale
     D1, _ = cts_diagonals(n)
-    R = ctx.hoisted_rotations(ct, list(range(n)))
-    acc = None
-    for d in range(n):
-        t = ctx.mul_plain(R[d], encode_periodic(ctx.N, D1[d], delta), delta)
-        acc = t if acc is None else ctx.add(acc, t)
+    acc = linear_map(ctx, ct, D1, delta, delta)
     return _rescale_to(ctx, ctx.add(acc, ctx.conjugate(acc)), 2)
 
 
@@ -269,12 +296,7 @@ def slot_to_coeff(ctx, ct, n, gamma, target):
     q = ctx.prm.q
     delta = (target * float(q[ct.level])) / ct.scale
     dg = delta * gamma
-    R = ctx.hoisted_rotations(ct, list(range(2 * n)))
-    acc = None
-    for d, diag in enumerate(stc_diagonals(n)):
-        t = ctx.mul_plain(R[d], encode_periodic(ctx.N, diag, dg), delta)
-        acc = t if acc is None else ctx.add(acc, t)
-    return ctx.rescale(acc)
+    return ctx.rescale(linear_map(ctx, ct, stc_diagonals(n), dg, delta))
 
 
 def raise_scale(N, q0, n, r):

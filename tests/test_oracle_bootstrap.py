@@ -148,6 +148,9 @@ def test_levels_and_rotation_steps():
     assert bs.rotation_steps(4096, 4) == [1, 2, 3, 4, 5, 6, 7, 8, 16, 32, 64, 128, 256, 512, 1024]
     assert bs.rotation_steps(64, 16) == list(range(1, 32))
     assert bs.raise_scale(64, 97, 4, 3) == (64.0 * 97.0 * 8.0) / (4.0 * math.pi * 4.0)
+    # baby-step giant-step split: B = 2^ceil(log2(count)/2), B * G >= count
+    assert [bs.bsgs_split(c) for c in (1, 2, 4, 8, 16, 32, 64)] == \
+        [(1, 1), (2, 1), (2, 2), (4, 2), (4, 4), (8, 4), (8, 8)]
 
 
 # ----------------------------------------------------------------- the steps
