@@ -12,13 +12,13 @@
 //                t'_i = t_{i N/2n} of the trace onto Z[X^(N/2n)];
 //   CoeffToSlot  the 2n real t'_i into 2n-periodic slots, read as
 //                theta = 2 pi t' / (q_0 2^r): A + conj(A) for the diagonal sum A
-//                over one hoisted fan-out of n rotations, then two rescales;
+//                over n rotations (baby-step giant-step), then two rescales;
 //   EvalMod      exp(i theta) = sum_{k<=d} (i theta)^k / k!, squared r times,
 //                minus its conjugate: D = 2 i sin(2 pi m / q_0), free of q_0 I;
 //   (arcsine)    optionally D - D^3/24 = 2 i (s + s^3/6), the first two terms of
 //                arcsin, so that the message may use more of q_0;
-//   SlotToCoeff  back to the n slots with q_0 / (4 pi i) folded in (one hoisted
-//                fan-out of 2n rotations, one rescale).
+//   SlotToCoeff  back to the n slots with q_0 / (4 pi i) folded in (2n diagonals
+//                by baby-step giant-step, one rescale).
 //
 // Every operation runs in the library's kernels on the whole batch.  The
 // sequence of operations, the plaintext encodings and the scale bookkeeping
@@ -206,30 +206,51 @@ Batch hmult(Context* c, Batch& a, Batch& b) {
     return out;
 }
 
-// acc += rot(in, d) x diag_d for d < count, the rotations hoisted (one ModUp),
-// each product accumulated by the multiply kernel itself (modular sums are
-// exact, so the bits are those of separate products and additions)
-void hoisted_mac(Context* c, Batch& in, int count, const std::vector<std::vector<int64_t>>& pts, double pt_scale,
-                 Batch& acc, bool& have) {
+// acc (+)= sum_{d < count} diag_d (.) rot(in, d) by baby-step giant-step: with
+// d = g B + b, diag_d (.) rot(x, d) = rot(rot(diag_d, -g B) (.) rot(x, b), g B), so
+// the B baby rotations share one ModUp (hoisted) and each giant step g > 0
+// rotates the sum of its B products once.  Each product is accumulated by the
+// multiply kernel itself (modular sums are exact, so the bits are those of
+// separate products and additions).
+void bsgs_mac(Context* c, Batch& in, const std::vector<std::vector<Cplx>>& diags, double enc_scale, double pt_scale,
+              Batch& acc, bool& have) {
+    const uint64_t N = c->N;
+    const int count = (int)diags.size(), P = (int)diags[0].size();
+    const int B = 1 << ((log2_exact((uint64_t)count) + 1) / 2), G = (count + B - 1) / B;
     Context::Hoist h;
-    if (count > 1) {
+    std::vector<Batch> R;
+    if (B > 1) {
         std::vector<Ct*> pi = in.ptrs();
         c->hoist_begin(h, pi);
-    }
-    for (int d = 0; d < count; ++d) {
-        Batch rot(c, 0);
-        if (d > 0) {
-            rot = Batch(c, in.size());
-            std::vector<Ct*> po = rot.ptrs();
-            c->hoist_rotate(h, c->galois_for_step(d), po);
+        for (int b = 1; b < B; ++b) {
+            R.emplace_back(c, in.size());
+            std::vector<Ct*> po = R.back().ptrs();
+            c->hoist_rotate(h, c->galois_for_step(b), po);
         }
-        Batch& src = d == 0 ? in : rot;
+    }
+    std::vector<Cplx> shifted(P);
+    for (int g = 0; g < G; ++g) {
+        Batch part(c, 0);
+        bool hp = false;
+        for (int b = 0; b < B && g * B + b < count; ++b) {
+            const auto& dg = diags[g * B + b];
+            for (int j = 0; j < P; ++j) shifted[j] = dg[((j - g * B) % P + P) % P];
+            const std::vector<int64_t> pt = encode_periodic(N, shifted, enc_scale);
+            Batch& src = b == 0 ? in : R[b - 1];
+            if (!hp) {
+                part = mul_plain(c, src, pt, pt_scale);
+                hp = true;
+            } else {
+                std::vector<Ct*> ps = src.ptrs(), pa = part.ptrs();
+                c->mul_plain_batch(ps, pt.data(), pt_scale, pa, true);
+            }
+        }
+        if (g > 0) part = rotate(c, part, c->galois_for_step((int64_t)g * B));
         if (!have) {
-            acc = mul_plain(c, src, pts[d], pt_scale);
+            acc = std::move(part);
             have = true;
         } else {
-            std::vector<Ct*> ps = src.ptrs(), pa = acc.ptrs();
-            c->mul_plain_batch(ps, pts[d].data(), pt_scale, pa, true);
+            acc = add(c, acc, part);
         }
     }
 }
@@ -315,11 +336,8 @@ void bootstrap(Context* c, const BootCfg& cfg, const std::vector<Ct*>& in, std::
         const double delta = ((target * (double)c->moduli[lv]) * (double)c->moduli[lv - 1]) / y.scale();
         // the map on conj(x) has the conjugate diagonals and conjugation
         // commutes with rotation: the map is A + conj(A), A = sum_d D_d rot(x, d)
-        const std::vector<std::vector<Cplx>> D = cts_diagonals(n);
-        std::vector<std::vector<int64_t>> p1;
-        for (int d = 0; d < n; ++d) p1.push_back(encode_periodic(N, D[d], delta));
         bool have = false;
-        hoisted_mac(c, y, n, p1, delta, theta, have);
+        bsgs_mac(c, y, cts_diagonals(n), delta, delta, theta, have);
         // the conjugation at A's scale, where its key-switching noise is negligible
         Batch tj = rotate(c, theta, g_conj);
         theta = add(c, theta, tj);
@@ -385,10 +403,8 @@ void bootstrap(Context* c, const BootCfg& cfg, const std::vector<Ct*>& in, std::
     {
         const double delta = (target * (double)c->moduli[e.level()]) / e.scale();
         const double dg = delta * gamma;
-        std::vector<std::vector<int64_t>> pts;
-        for (const auto& diag : stc_diagonals(n)) pts.push_back(encode_periodic(N, diag, dg));
         bool have = false;
-        hoisted_mac(c, e, 2 * n, pts, delta, out, have);
+        bsgs_mac(c, e, stc_diagonals(n), dg, delta, out, have);
         rescale(c, out);
     }
     result = out.take();
