@@ -114,6 +114,14 @@ def test_mac_summary_rates():
     assert "source_and_accumulator_GBps" not in out and out["groups"] == 40
 
 
+def test_bootstrap_cpu_baseline_extrapolates_the_rotation():
+    b = _bench()
+    leg = {"value": 1.0 / 30.0, "unit": "key-switch rotations/s", "cores": 1}
+    out = b.boot_cpu_baseline(leg, 56.0)
+    assert abs(out["value"] - 1.0 / (30.0 * 56.0)) < 1e-15
+    assert out["cores"] == 1 and out["kind"] == "oracle" and "56.0 key switches" in out["sample"]
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=300)
