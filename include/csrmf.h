@@ -298,8 +298,10 @@ int csrmf_boot_rotation_steps(csrmf_ctx* ctx, const csrmf_boot_config* cfg, int3
  * top limbs above level 0 are ignored) into new handles out[0..n), at level
  * L - csrmf_boot_levels(cfg) and a scale of about 2^log2_scale, every step on
  * the whole batch in the library's kernels.  The outputs decrypt to the
- * inputs' slot values up to the method's error (about 4e-4 for |values| <= 1
- * on the N = 2^12 test chain).  Errors: INVAL (configuration, handles),
+ * inputs' slot values up to the method's error, for |values| <= 1: about
+ * 4e-4 on the N = 2^12 test chain (r = 9, pre_bits 12), 3e-5 there with the
+ * arcsine term (r = 8, pre_bits 15), about 5e-3 at N = 2^16 (r = 10,
+ * pre_bits 15, arcsine term).  Errors: INVAL (configuration, handles),
  * LEVEL (chain too short), SCALE (scales differ), STATE (no keys), KEY (a
  * needed key is absent: nothing is enqueued). */
 int csrmf_bootstrap(csrmf_ctx* ctx, const csrmf_boot_config* cfg, const uint64_t* in, int32_t n,
