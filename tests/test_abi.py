@@ -46,3 +46,20 @@ def test_create_rejects_bad_params_without_gpu_work():
     assert b"log2N must be in [12, 16]" in pk.lib.csrmf_last_error(None)    # the failed create's message
     assert pk.lib.csrmf_create(None, bytes(32), ctypes.byref(h)) == -1
     assert b"null argument" in pk.lib.csrmf_last_error(None)
+
+
+def test_boot_levels_through_the_abi_match_the_oracle():
+    """csrmf_boot_levels is host arithmetic: the library's level count of a
+    bootstrap equals the oracle's for every degree, squaring count and flag,
+    and an invalid configuration is refused."""
+    import paper_2509_03024_amd as pk
+    from oracle import bootstrap as bs
+    for d in range(1, 19):
+        for r in (0, 1, 8, 12):
+            for asn in (0, 1):
+                cfg = pk.BootConfig(4, r, d, 12, asn)
+                want = bs.levels_used(bs.BootConfig(n=4, r=r, d=d, pre_bits=12, arcsine=bool(asn)))
+                assert pk.boot_levels(cfg) == want, (d, r, asn)
+    v = ctypes.c_int32()
+    assert pk.lib.csrmf_boot_levels(ctypes.byref(pk.BootConfig(4, 9, 0, 12, 0)), ctypes.byref(v)) == -1
+    assert pk.lib.csrmf_boot_levels(ctypes.byref(pk.BootConfig(4, 9, 11, 12, 2)), ctypes.byref(v)) == -1
